@@ -1,0 +1,71 @@
+"""The plain definitions, by enumeration (TEST INFRASTRUCTURE ONLY).
+
+These functions write the discrete-HMM quantities out as sums over every
+hidden state path, with no recursion at all, so that the forward / backward
+oracle in hmm_oracle.c can be checked against something other than itself.
+They accept Python floats or fractions.Fraction (exact arithmetic); they are
+exponential in T and meant for N <= 3, T <= 6.
+
+  P(O | lambda) = sum_Q pi[q_1] B[q_1][o_1] prod_{t>=2} A[q_{t-1}][q_t] B[q_t][o_t]
+
+Expected counts under the posterior P(Q | O) = P(Q, O) / P(O):
+  n_pi[i]   = E[ [q_1 = i] ]
+  n_A[i][j] = E[ #{t < T : q_t = i, q_{t+1} = j} ]
+  n_B[i][o] = E[ #{t : q_t = i, o_t = o} ]
+These are the gradient of log P(O | lambda) with respect to ln pi, ln A, ln B.
+"""
+from __future__ import annotations
+
+import itertools
+
+
+def joint(pi, A, B, q, o):
+    """P(Q = q, O = o | lambda) for one state path q."""
+    p = pi[q[0]] * B[q[0]][o[0]]
+    for t in range(1, len(o)):
+        p = p * A[q[t - 1]][q[t]] * B[q[t]][o[t]]
+    return p
+
+
+def likelihood(pi, A, B, o):
+    """P(O = o | lambda) as the sum over all N^T state paths (1 for T = 0)."""
+    N = len(pi)
+    T = len(o)
+    if T == 0:
+        return 1 if not isinstance(pi[0], float) else 1.0
+    total = 0
+    for q in itertools.product(range(N), repeat=T):
+        total = total + joint(pi, A, B, q, o)
+    return total
+
+
+def total_over_strings(pi, A, B, M, T):
+    """sum over all M^T symbol strings of P(O | lambda) (equals 1 for a proper model)."""
+    total = 0
+    for o in itertools.product(range(M), repeat=T):
+        total = total + likelihood(pi, A, B, o)
+    return total
+
+
+def expected_counts(pi, A, B, o):
+    """(P(O), n_pi[N], n_A[N][N], n_B[N][M]) by enumerating every state path."""
+    N = len(pi)
+    M = len(B[0])
+    T = len(o)
+    zero = 0 * pi[0]
+    n_pi = [zero] * N
+    n_A = [[zero] * N for _ in range(N)]
+    n_B = [[zero] * M for _ in range(N)]
+    P = zero
+    for q in itertools.product(range(N), repeat=T):
+        w = joint(pi, A, B, q, o)
+        P = P + w
+        n_pi[q[0]] = n_pi[q[0]] + w
+        for t in range(T):
+            n_B[q[t]][o[t]] = n_B[q[t]][o[t]] + w
+            if t + 1 < T:
+                n_A[q[t]][q[t + 1]] = n_A[q[t]][q[t + 1]] + w
+    n_pi = [x / P for x in n_pi]
+    n_A = [[x / P for x in row] for row in n_A]
+    n_B = [[x / P for x in row] for row in n_B]
+    return P, n_pi, n_A, n_B
