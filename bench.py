@@ -1,0 +1,217 @@
+"""Benchmark of the discrete-HMM bank on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+A step is one pass of the recognition path over one batch: the length-sorted
+plan, the batched MFMA forward over every (sequence, model) pair, and the
+arg-max over models (hmm_classify), on the 64-model bank (N=32 states, M=256
+symbols) and 65,536 ragged sequences (log-uniform lengths in [16, 2048]) with
+inputs resident in HBM.  The metric is state-steps/s = N^2 * sum(T) * models /
+time.  Printed as one JSON line, with:
+  roofline      the batched forward kernel's own HIP-event time against the
+                FP32 MFMA peak (2 algorithmic FLOPs per state-step);
+  cpu_baseline  the FP64 oracle on the host cores, on a stratified sample of the
+                same workload, in the same unit;
+  plain         the plain per-pair kernel on the same workload (batched / plain speedup);
+  fwd_bwd       forward + adjoint (expected counts) on the gradient workload
+                (8 models, N=64, M=512, 8192 sequences, T in [100, 1000]),
+                6 algorithmic FLOPs per state-step.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "HMM state-steps/s (N²·ΣT·models) fwd and fwd+bwd, batched vs plain, FP32"
+FP32_PEAK_TFLOPS = 157.3
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+KERNEL_SOURCES = ["paper_1310_3322_amd/csrc/fwd_mfma.hip", "paper_1310_3322_amd/csrc/fwd_step.cuh",
+                  "paper_1310_3322_amd/csrc/common.cuh"]
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source; else None."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            data = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    rec = data.get(workload)
+    if not rec or rec.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def to_dev(w, torch, own):
+    from paper_1310_3322_amd import hmm
+
+    def d(a):
+        return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+    return hmm.Problem(d(w.pi), d(w.A), d(w.B), d(w.symbols), d(w.offsets), d(w.lengths),
+                       d(w.owner) if own else None, max_len=w.max_len, total_symbols=w.total_symbols)
+
+
+def time_steps(fn, steps, warmup, torch):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / max(steps, 1)
+
+
+def cpu_baseline(w, target_s: float = 15.0):
+    """FP64 oracle on a stratified sample: every stride-th sequence in length order, all models."""
+    from oracle import oracle as O
+    order = np.argsort(-w.lengths, kind="stable")
+    threads = O.max_threads()
+    # calibrate on a small sample, then size the sample to about target_s seconds
+    probe = w.subset(order[::1024])
+    t0 = time.perf_counter()
+    O.forward(probe.pi, probe.A, probe.B, probe.symbols, probe.offsets, probe.lengths, None)
+    dt = max(time.perf_counter() - t0, 1e-3)
+    rate = probe.units() / dt
+    stride = int(np.clip(np.ceil(w.units() / (rate * target_s)), 1, 1024))
+    sample = w.subset(order[::stride])
+    t0 = time.perf_counter()
+    O.forward(sample.pi, sample.A, sample.B, sample.symbols, sample.offsets, sample.lengths, None)
+    dt = time.perf_counter() - t0
+    return {"value": sample.units() / dt, "unit": "state-steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"every {stride}th sequence in length order ({sample.S} of {w.S}) x all {w.K} models, "
+                      f"{sample.units():.3e} state-steps in {dt:.1f} s, FP64, OpenMP over pairs"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extra", action="store_true", help="skip the plain and fwd+bwd legs")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(sharding over sequences is described in DESIGN.md).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1310_3322_amd import hmm, workloads
+
+    torch.cuda.set_device(0)
+    hmm.load_library()
+
+    log("generating the recognition workload (64 models, N=32, M=256, 65536 sequences)")
+    w = workloads.make_workload("c3")
+    units = w.units()
+    p = to_dev(w, torch, own=False)
+    b = p.batch_without_models()
+    ws = p.workspace(hmm.OP_CLASSIFY, b)
+    labels = torch.empty(w.S, dtype=torch.int32, device="cuda")
+    ll = torch.empty((w.S, w.K), dtype=torch.float32, device="cuda")
+
+    hmm.select_kernel(hmm.KERNEL_BATCHED)
+
+    def step():
+        hmm.classify(p, labels=labels, loglik=ll, ws=ws)
+
+    log(f"timing {args.steps} steps after {args.warmup} warmup")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    hmm.profile_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / args.steps
+    kern_ms, launches = hmm.profile_read(hmm.PROF_FWD_BATCHED)
+    hmm.profile_enable(False)
+    kern_s = kern_ms / 1e3 / max(launches, 1)
+    flops = 2.0 * units
+    achieved = flops / kern_s / 1e12
+    traffic = measured_traffic("c3_classify")
+    roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / FP32_PEAK_TFLOPS, 4), "traffic": traffic,
+                "kernel": "k_fwd_mfma<R=2> (batched forward)", "kernel_ms": round(kern_s * 1e3, 4),
+                "launches": launches}
+    result = {"metric": METRIC, "value": units / sec, "unit": "state-steps/s", "n_gpus": 1, "steps": args.steps,
+              "warmup": args.warmup, "ms_per_step": sec * 1e3, "higher_is_better": True, "scaling": "weak",
+              "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+              "config": {"workload": "c3 recognition: 64 HMMs N=32 M=256 Dirichlet(0.5), 65536 sequences, "
+                                     "log-uniform T in [16,2048], all pairs + arg-max (hmm_classify)",
+                         "models": w.K, "states": w.N, "symbols": w.M, "sequences": w.S,
+                         "sum_T": int(w.lengths.sum()), "state_steps_per_step": units},
+              "roofline": roofline}
+
+    if not args.no_extra:
+        log("plain per-pair kernel on the same workload")
+        hmm.select_kernel(hmm.KERNEL_PLAIN)
+        psec = time_steps(step, 2, 1, torch)
+        hmm.select_kernel(hmm.KERNEL_BATCHED)
+        result["plain"] = {"value": units / psec, "ms_per_step": psec * 1e3,
+                           "speedup_batched_over_plain": psec / sec}
+        log("forward + adjoint on the gradient workload (8 models, N=64, M=512, 8192 sequences)")
+        w4 = workloads.make_workload("c4")
+        p4 = to_dev(w4, torch, own=True)
+        ws4 = p4.workspace(hmm.OP_GRAD)
+        ll4 = torch.empty(w4.S, dtype=torch.float32, device="cuda")
+        cnt = (torch.empty((w4.K, w4.N), device="cuda"), torch.empty((w4.K, w4.N, w4.N), device="cuda"),
+               torch.empty((w4.K, w4.N, w4.M), device="cuda"))
+
+        def gstep():
+            hmm.forward_backward_grad(p4, phase=0, loglik=ll4, counts=cnt, ws=ws4)
+
+        for _ in range(2):
+            gstep()
+        torch.cuda.synchronize()
+        hmm.profile_enable(True)
+        gsteps = 10
+        t0 = time.perf_counter()
+        for _ in range(gsteps):
+            gstep()
+        torch.cuda.synchronize()
+        gsec = (time.perf_counter() - t0) / gsteps
+        f_ms, f_n = hmm.profile_read(hmm.PROF_FWD_BATCHED)
+        a_ms, a_n = hmm.profile_read(hmm.PROF_ADJ_BATCHED)
+        hmm.profile_enable(False)
+        u4 = w4.units()
+        result["fwd_bwd"] = {"workload": "c4 gradient: 8 HMMs N=64 M=512, 8192 sequences, T in [100,1000], "
+                                         "own model, fused forward + adjoint",
+                             "value": u4 / gsec, "unit": "state-steps/s", "ms_per_step": gsec * 1e3,
+                             "fwd_kernel_ms": f_ms / max(f_n, 1), "adj_kernel_ms": a_ms / max(a_n, 1),
+                             "frac_fp32_peak": 6.0 * u4 / gsec / 1e12 / FP32_PEAK_TFLOPS}
+
+    if not args.no_cpu:
+        log("CPU oracle baseline on a stratified sample")
+        result["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,183 @@
+/*
+ * hmm.h — C ABI of libhmm_mi355x.so: a bank of discrete-observation hidden
+ * Markov models evaluated over many ragged symbol sequences on one MI355X
+ * (gfx950).
+ *
+ * What is computed.  The paper's activity-recognition stage (Sec. 2.7) keeps
+ * one discrete HMM per activity class and provides the Forward, Viterbi and
+ * Baum-Welch functions; the HMMs of the different actions are independent and
+ * evaluated in parallel (Sec. 3, item 3); an observation is a discretised
+ * feature symbol (Sec. 2.5); the configuration knobs are the number of hidden
+ * states, the feature-vector size and the number of actions (Sec. 4.1).  The
+ * paper prints no formulas; the textbook discrete HMM is used:
+ *
+ *   pi[k][i]    = P(q_1 = i)                          model k, state i
+ *   A[k][i][j]  = P(q_{t+1} = j | q_t = i)            rows sum to 1
+ *   B[k][i][o]  = P(o_t = o | q_t = i)                rows sum to 1
+ *   alpha_1     = pi o B[:, o_1],   alpha_t = (alpha_{t-1} A) o B[:, o_t]
+ *   log P(O | lambda_k) = ln sum_i alpha_T(i)
+ *
+ * The recursion is renormalised every step (power-of-two rescaling, exact in
+ * floating point); the result equals sum_t ln c_t with c_t the per-step sums.
+ * Recognition takes the arg-max over models.  The gradient entry point runs the
+ * scaled backward (beta) recursion and returns the Baum-Welch E-step expected
+ * counts, which are the gradient of sum_s w_s log P(O_s | lambda_{m(s)}) with
+ * respect to ln pi, ln A and ln B.
+ *
+ * Conventions shared by every entry point.
+ *  - All array pointers are DEVICE pointers on the current HIP device, owned
+ *    by the caller, dense and row-major as declared.  Probabilities are FP32.
+ *  - Calls only enqueue work on `stream` and return; results are valid once
+ *    the caller synchronises that stream.  No call allocates device memory,
+ *    synchronises, or reads device memory back, except hmm_workspace_error.
+ *    Calls may therefore be captured into a HIP graph.
+ *  - Scratch memory is the caller's workspace `ws` of `ws_bytes` bytes, at
+ *    least hmm_workspace_size(...) for the same bank, batch and op, 256-byte
+ *    aligned.  Two calls in flight at once need two workspaces.
+ *  - Host-checkable problems (null pointer, shape out of range, workspace too
+ *    small) return a negative status and enqueue nothing.
+ *  - Data problems found on the device (a symbol outside [0, M), a negative
+ *    length or one above max_len, offset + length outside [0, total_symbols],
+ *    a model index outside [0, K)) never cause an out-of-bounds access: the
+ *    affected sequence gets NaN log-likelihoods, label -1 and no counts, and
+ *    the workspace records the smallest such sequence index
+ *    (hmm_workspace_error).
+ *  - An impossible observation (a zero per-step sum) gives -inf and no counts.
+ *    A sequence of length 0 gives 0 and no counts.
+ */
+#ifndef HMM_MI355X_H
+#define HMM_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HMM_OK = 0,
+    HMM_ERR_NULL = -1,        /* a required pointer is NULL                        */
+    HMM_ERR_SHAPE = -2,       /* K, N, M, S, max_len or total_symbols out of range */
+    HMM_ERR_WORKSPACE = -3,   /* workspace NULL, misaligned or too small           */
+    HMM_ERR_UNSUPPORTED = -4, /* valid request this build cannot run               */
+    HMM_ERR_HIP = -5,         /* a HIP runtime call or kernel launch failed        */
+    HMM_ERR_ARG = -6          /* an enumerated argument has an unknown value       */
+} hmm_status;
+
+/* A bank of K discrete HMMs with N states and M symbols, FP32 probabilities.
+ * 1 <= K <= 65536, 1 <= N <= HMM_MAX_STATES, 1 <= M <= HMM_MAX_SYMBOLS. */
+typedef struct {
+    int32_t K, N, M;
+    const float *pi;   /* [K][N]                                  */
+    const float *A;    /* [K][N][N], A[k][i][j] = P(j | i)         */
+    const float *B;    /* [K][N][M], B[k][i][o] = P(o | i)         */
+} hmm_bank;
+
+/* S ragged int32 symbol sequences.  Sequence s is
+ * symbols[offsets[s] .. offsets[s] + lengths[s]).  Sequences may overlap or
+ * leave gaps in `symbols`.  max_len (>= every length) and total_symbols (the
+ * element count of `symbols`) are host-side promises used to size work; the
+ * device checks every sequence against them. */
+typedef struct {
+    int32_t S;                    /* 0 <= S <= 2^30                                    */
+    const int32_t *symbols;       /* [total_symbols], values in [0, M)                 */
+    const int64_t *offsets;       /* [S]                                               */
+    const int32_t *lengths;       /* [S], 0 <= lengths[s] <= max_len                   */
+    const int32_t *model_of_seq;  /* [S] model of each sequence, or NULL = all K models */
+    int32_t max_len;              /* 0 <= max_len <= HMM_MAX_LEN                       */
+    int64_t total_symbols;        /* >= 0                                              */
+} hmm_batch;
+
+#define HMM_MAX_STATES 256
+#define HMM_MAX_SYMBOLS 1048576
+#define HMM_MAX_LEN 1048576
+
+/* Operation selector for hmm_workspace_size. */
+#define HMM_OP_FORWARD 0
+#define HMM_OP_CLASSIFY 1
+#define HMM_OP_GRAD 2
+
+/* Kernel family selector (process-wide; affects later calls). */
+#define HMM_KERNEL_AUTO 0     /* batched where supported, else plain               */
+#define HMM_KERNEL_PLAIN 1    /* one workgroup per (sequence, model) pair           */
+#define HMM_KERNEL_BATCHED 2  /* length-sorted persistent MFMA kernels              */
+
+/* Bytes of workspace the call `op` needs for this bank and batch (host only,
+ * reads no device memory; pointers in bank/batch may be NULL here).
+ * Returns 0 if the shapes are out of range. */
+size_t hmm_workspace_size(const hmm_bank *bank, const hmm_batch *batch, int op);
+
+/* Forward log-likelihoods (Sec. 2.7 "Forward"; Sec. 3 item 3).
+ * loglik: [S][K] (sequence-major) when batch->model_of_seq == NULL, else [S];
+ * natural log, FP32. */
+hmm_status hmm_forward_loglik(const hmm_bank *bank, const hmm_batch *batch, float *loglik,
+                              void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Recognition (Sec. 2.7; Fig. 1 output "recognized activity"): every sequence
+ * is scored against all K models (model_of_seq is ignored) and
+ * labels[s] = smallest k attaining max_k loglik[s][k]; NaN entries are skipped
+ * and an all-NaN row gives -1.  loglik_opt: [S][K] or NULL. */
+hmm_status hmm_classify(const hmm_bank *bank, const hmm_batch *batch, int32_t *labels,
+                        float *loglik_opt, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Gradient / Baum-Welch E-step (Sec. 2.7 "BalmWelch") for each sequence with
+ * its own model (batch->model_of_seq is required).
+ * seq_weight: [S] weight w_s of sequence s (dL/dloglik_s), or NULL = all ones.
+ * loglik:     [S] log P(O_s | lambda_{m(s)}).
+ * cnt_pi [K][N], cnt_A [K][N][N], cnt_B [K][N][M]: overwritten with
+ *   sum_s w_s E[ [q_1 = i] ], sum_s w_s E[ #(i -> j) ], sum_s w_s E[ #(i emits o) ]
+ * (the gradient of sum_s w_s loglik_s w.r.t. ln pi, ln A, ln B).
+ * phase: 0 = forward and backward in one call;
+ *        1 = forward only, writing loglik and keeping alpha checkpoints in ws
+ *            (counts untouched, may be NULL);
+ *        2 = backward only, from the checkpoints a phase-1 call with the same
+ *            bank, batch and ws left behind (loglik untouched, may be NULL).
+ * The forward pass keeps alpha every ceil(sqrt(T)) steps (T the longest
+ * sequence of the length-sorted tile of 16 sequences) and the backward pass
+ * recomputes each segment, so memory grows with sqrt(T). */
+hmm_status hmm_forward_backward_grad(const hmm_bank *bank, const hmm_batch *batch,
+                                     const float *seq_weight, float *loglik, float *cnt_pi,
+                                     float *cnt_A, float *cnt_B, int32_t phase, void *ws,
+                                     size_t ws_bytes, hipStream_t stream);
+
+/* Row-wise softmax of FP32 logits: probs[r][c] = exp(z[r][c]) / sum_c' exp(z[r][c']).
+ * The parameterisation of the gradient entry point's logits. */
+hmm_status hmm_softmax_rows(const float *logits, float *probs, int64_t rows, int32_t cols,
+                            hipStream_t stream);
+
+/* Logit gradient from log-probability gradient n and probabilities p
+ * (row-wise softmax):  grad[r][c] = n[r][c] - p[r][c] * sum_c' n[r][c']. */
+hmm_status hmm_logit_grad(const float *n, const float *probs, float *grad, int64_t rows,
+                          int32_t cols, hipStream_t stream);
+
+/* Synchronises `stream`, then reads the workspace error word: *first_bad_seq
+ * is the smallest sequence index the last call flagged, or -1 if none. */
+hmm_status hmm_workspace_error(const void *ws, hipStream_t stream, int32_t *first_bad_seq);
+
+/* Selects the kernel family for later calls (HMM_KERNEL_*). */
+hmm_status hmm_select_kernel(int32_t kind);
+
+/* Kernel timing for measurement (not needed for computing anything).
+ * While enabled, every launch of a main kernel is bracketed by a pair of HIP
+ * events recorded on the call's stream (skipped while the stream is being
+ * captured into a graph).  hmm_profile_enable(1) clears earlier records;
+ * hmm_profile_read synchronises the recorded events and returns, for one
+ * kernel family, the summed event-to-event milliseconds and the launch count.
+ * Not thread-safe against concurrent calls on other host threads. */
+#define HMM_PROF_FWD_BATCHED 0   /* length-sorted MFMA forward            */
+#define HMM_PROF_ADJ_BATCHED 1   /* checkpointed MFMA backward            */
+#define HMM_PROF_FWD_PLAIN 2     /* plain per-pair forward                */
+hmm_status hmm_profile_enable(int32_t on);
+hmm_status hmm_profile_read(int32_t kernel, double *total_ms, int32_t *launches);
+
+/* Human-readable status name. */
+const char *hmm_status_string(hmm_status status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HMM_MI355X_H */

@@ -1,0 +1,426 @@
+// C ABI of libhmm_mi355x: argument checks, workspace carve-up, kernel choice
+// and launch order.  Enqueues work only; never allocates, synchronises or
+// reads device memory (except hmm_workspace_error, which is documented to).
+#include <atomic>
+#include <climits>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "common.cuh"
+#include "kernels.h"
+
+using namespace hmm;
+
+namespace {
+
+std::atomic<int> g_kernel_kind{HMM_KERNEL_AUTO};
+constexpr int MAX_DEVICES = 64;
+std::atomic<int> g_cu_count[MAX_DEVICES];
+
+constexpr int64_t MAX_PLAN_BINS = 1 << 24;
+
+int device_cu_count() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0) return 256;
+    if (dev < MAX_DEVICES) {
+        int c = g_cu_count[dev].load(std::memory_order_relaxed);
+        if (c > 0) return c;
+    }
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+    if (dev < MAX_DEVICES) g_cu_count[dev].store(n, std::memory_order_relaxed);
+    return n;
+}
+
+// ---- optional kernel timing (hmm_profile_*)
+struct ProfRecord {
+    hipEvent_t start, stop;
+    int kind;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfRecord> g_prof_pool;
+size_t g_prof_used = 0;
+
+// Records the start event of a main-kernel launch; returns the record index or -1.
+int prof_begin(hipStream_t st, int kind) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    if (!g_prof_on) return -1;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return -1;
+    if (g_prof_used == g_prof_pool.size()) {
+        ProfRecord r;
+        if (hipEventCreate(&r.start) != hipSuccess) return -1;
+        if (hipEventCreate(&r.stop) != hipSuccess) {
+            (void)hipEventDestroy(r.start);
+            return -1;
+        }
+        g_prof_pool.push_back(r);
+    }
+    const int idx = (int)g_prof_used++;
+    g_prof_pool[idx].kind = kind;
+    if (hipEventRecord(g_prof_pool[idx].start, st) != hipSuccess) g_prof_pool[idx].kind = -1;
+    return idx;
+}
+
+void prof_end(hipStream_t st, int idx) {
+    if (idx < 0) return;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    if (hipEventRecord(g_prof_pool[idx].stop, st) != hipSuccess) g_prof_pool[idx].kind = -1;
+}
+
+inline size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+inline int pad16(int n) { return ((n + 15) / 16) * 16; }
+
+hmm_status check_shapes(const hmm_bank *b, const hmm_batch *q) {
+    if (!b || !q) return HMM_ERR_NULL;
+    if (b->K < 1 || b->K > 65536 || b->N < 1 || b->N > HMM_MAX_STATES || b->M < 1 || b->M > HMM_MAX_SYMBOLS)
+        return HMM_ERR_SHAPE;
+    if (q->S < 0 || q->S > (1 << 30) || q->max_len < 0 || q->max_len > HMM_MAX_LEN || q->total_symbols < 0)
+        return HMM_ERR_SHAPE;
+    return HMM_OK;
+}
+
+hmm_status check_pointers(const hmm_bank *b, const hmm_batch *q) {
+    if (!b->pi || !b->A || !b->B) return HMM_ERR_NULL;
+    if (q->S > 0 && (!q->offsets || !q->lengths)) return HMM_ERR_NULL;
+    if (q->S > 0 && q->total_symbols > 0 && !q->symbols) return HMM_ERR_NULL;
+    return HMM_OK;
+}
+
+// groups: 1 when every sequence meets every model, else K
+int plan_groups(const hmm_bank *b, const hmm_batch *q, int op) {
+    if (op == HMM_OP_CLASSIFY) return 1;
+    if (op == HMM_OP_GRAD) return b->K;
+    return q->model_of_seq ? b->K : 1;
+}
+
+bool batched_capable(const hmm_bank *b, const hmm_batch *q, int op) {
+    const int NP = pad16(b->N);
+    if (!fwd_mfma_supported(NP)) return false;
+    if (op == HMM_OP_GRAD && !adj_mfma_supported(NP)) return false;
+    const int64_t nbins = (int64_t)plan_groups(b, q, op) * ((int64_t)q->max_len + 1);
+    return nbins <= MAX_PLAN_BINS;
+}
+
+Layout make_layout(const hmm_bank *b, const hmm_batch *q, int op) {
+    Layout L;
+    memset(&L, 0, sizeof(L));
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o = align_up(o + bytes);
+        return at;
+    };
+    const int K = b->K, M = b->M, S = q->S, NP = pad16(b->N);
+    L.err = take(64);
+    if (op == HMM_OP_CLASSIFY) L.ll = take((size_t)S * K * sizeof(float));
+    if (op == HMM_OP_GRAD) L.ll = take((size_t)S * sizeof(float));
+    if (batched_capable(b, q, op)) {
+        const int groups = plan_groups(b, q, op);
+        const size_t nbins = (size_t)groups * ((size_t)q->max_len + 1);
+        L.queue = take((size_t)2 * K * sizeof(int32_t));
+        L.hist = take(nbins * sizeof(int32_t));
+        L.cursor = take(nbins * sizeof(int32_t));
+        L.gstart = take((size_t)(groups + 1) * sizeof(int32_t));
+        L.perm = take((size_t)S * sizeof(int32_t));
+        L.bt = take((size_t)K * M * NP * sizeof(float));
+        if (op == HMM_OP_GRAD) {
+            int nck = 1;
+            while ((int64_t)nck * nck < q->max_len) ++nck;
+            L.nck = nck;
+            L.ckpt = take((size_t)S * nck * NP * sizeof(float));
+            L.ckexp = take((size_t)S * nck * sizeof(int32_t));
+            L.flag = take((size_t)S * sizeof(int32_t));
+            L.seg_slots = adj_mfma_slots(NP, M, K, device_cu_count());
+            L.seg_stride = adj_mfma_seg_stride(NP, q->max_len);
+            L.seg = take((size_t)L.seg_slots * L.seg_stride * sizeof(float));
+        }
+    }
+    L.total = o;
+    return L;
+}
+
+hmm_status check_ws(void *ws, size_t ws_bytes, const Layout &L) {
+    if (!ws) return HMM_ERR_WORKSPACE;
+    if (((uintptr_t)ws & 255) != 0) return HMM_ERR_WORKSPACE;
+    if (ws_bytes < L.total) return HMM_ERR_WORKSPACE;
+    return HMM_OK;
+}
+
+DevPtrs dev_ptrs(const hmm_bank *b, const hmm_batch *q, bool with_models) {
+    DevPtrs d;
+    d.pi = b->pi;
+    d.A = b->A;
+    d.B = b->B;
+    d.symbols = q->symbols;
+    d.offsets = q->offsets;
+    d.lengths = q->lengths;
+    d.model_of_seq = with_models ? q->model_of_seq : nullptr;
+    return d;
+}
+
+// Chooses the family for a call; HMM_ERR_UNSUPPORTED when the batched family
+// is forced for a shape it does not take.
+hmm_status choose(const hmm_bank *b, const hmm_batch *q, int op, bool *batched) {
+    const int kind = g_kernel_kind.load(std::memory_order_relaxed);
+    const bool cap = batched_capable(b, q, op);
+    if (op == HMM_OP_GRAD) {
+        if (!cap) return HMM_ERR_UNSUPPORTED;
+        *batched = true;
+        return HMM_OK;
+    }
+    if (kind == HMM_KERNEL_PLAIN) {
+        *batched = false;
+        return HMM_OK;
+    }
+    if (kind == HMM_KERNEL_BATCHED && !cap) return HMM_ERR_UNSUPPORTED;
+    *batched = cap;
+    return HMM_OK;
+}
+
+hmm_status run_forward(const hmm_bank *b, const hmm_batch *q, int op, float *out, unsigned char *ws, const Layout &L,
+                       hipStream_t st) {
+    const bool all_pairs = (op == HMM_OP_CLASSIFY) || q->model_of_seq == nullptr;
+    bool batched = false;
+    hmm_status rc = choose(b, q, op, &batched);
+    if (rc != HMM_OK) return rc;
+    DevPtrs d = dev_ptrs(b, q, !all_pairs);
+    int32_t *err = (int32_t *)(ws + L.err);
+    const int K = b->K, N = b->N, M = b->M, S = q->S;
+    if (!batched) {
+        launch_fill_i32(err, 1, INT32_MAX, st);
+        const int pr = prof_begin(st, HMM_PROF_FWD_PLAIN);
+        const hipError_t e = launch_fwd_plain(d, K, N, M, S, all_pairs ? 1 : 0, q->max_len, q->total_symbols, out,
+                                              err, st);
+        prof_end(st, pr);
+        return e == hipSuccess ? HMM_OK : HMM_ERR_HIP;
+    }
+    const int NP = pad16(N);
+    const int groups = all_pairs ? 1 : K;
+    const int nbins = groups * (q->max_len + 1);
+    launch_plan(d, K, S, groups, q->max_len, q->total_symbols, nbins, ws, L, st);
+    launch_transpose_b(b->B, (float *)(ws + L.bt), K, N, M, NP, st);
+    if (hipGetLastError() != hipSuccess) return HMM_ERR_HIP;
+    FwdLaunch f;
+    memset(&f, 0, sizeof(f));
+    f.K = K;
+    f.N = N;
+    f.M = M;
+    f.NP = NP;
+    f.S = S;
+    f.all_pairs = all_pairs ? 1 : 0;
+    f.max_len = q->max_len;
+    f.total = q->total_symbols;
+    f.perm = (const int32_t *)(ws + L.perm);
+    f.gstart = (const int32_t *)(ws + L.gstart);
+    f.queue = (int32_t *)(ws + L.queue);
+    f.err = err;
+    f.bt = (const float *)(ws + L.bt);
+    f.ll = out;
+    if (S == 0) return HMM_OK;
+    const int pr = prof_begin(st, HMM_PROF_FWD_BATCHED);
+    const hipError_t e = launch_fwd_mfma(d, f, device_cu_count(), st);
+    prof_end(st, pr);
+    return e == hipSuccess ? HMM_OK : HMM_ERR_HIP;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t hmm_workspace_size(const hmm_bank *bank, const hmm_batch *batch, int op) {
+    if (op < HMM_OP_FORWARD || op > HMM_OP_GRAD) return 0;
+    if (check_shapes(bank, batch) != HMM_OK) return 0;
+    return make_layout(bank, batch, op).total;
+}
+
+hmm_status hmm_forward_loglik(const hmm_bank *bank, const hmm_batch *batch, float *loglik, void *ws,
+                              size_t ws_bytes, hipStream_t stream) {
+    hmm_status rc = check_shapes(bank, batch);
+    if (rc != HMM_OK) return rc;
+    if ((rc = check_pointers(bank, batch)) != HMM_OK) return rc;
+    if (batch->S > 0 && !loglik) return HMM_ERR_NULL;
+    const Layout L = make_layout(bank, batch, HMM_OP_FORWARD);
+    if ((rc = check_ws(ws, ws_bytes, L)) != HMM_OK) return rc;
+    return run_forward(bank, batch, HMM_OP_FORWARD, loglik, (unsigned char *)ws, L, stream);
+}
+
+hmm_status hmm_classify(const hmm_bank *bank, const hmm_batch *batch, int32_t *labels, float *loglik_opt,
+                        void *ws, size_t ws_bytes, hipStream_t stream) {
+    hmm_status rc = check_shapes(bank, batch);
+    if (rc != HMM_OK) return rc;
+    if ((rc = check_pointers(bank, batch)) != HMM_OK) return rc;
+    if (batch->S > 0 && !labels) return HMM_ERR_NULL;
+    const Layout L = make_layout(bank, batch, HMM_OP_CLASSIFY);
+    if ((rc = check_ws(ws, ws_bytes, L)) != HMM_OK) return rc;
+    unsigned char *w = (unsigned char *)ws;
+    float *ll = loglik_opt ? loglik_opt : (float *)(w + L.ll);
+    rc = run_forward(bank, batch, HMM_OP_CLASSIFY, ll, w, L, stream);
+    if (rc != HMM_OK) return rc;
+    launch_argmax(ll, labels, batch->S, bank->K, stream);
+    return hipGetLastError() == hipSuccess ? HMM_OK : HMM_ERR_HIP;
+}
+
+hmm_status hmm_forward_backward_grad(const hmm_bank *bank, const hmm_batch *batch, const float *seq_weight,
+                                     float *loglik, float *cnt_pi, float *cnt_A, float *cnt_B, int32_t phase,
+                                     void *ws, size_t ws_bytes, hipStream_t stream) {
+    hmm_status rc = check_shapes(bank, batch);
+    if (rc != HMM_OK) return rc;
+    if (phase < 0 || phase > 2) return HMM_ERR_ARG;
+    if ((rc = check_pointers(bank, batch)) != HMM_OK) return rc;
+    if (batch->S > 0 && !batch->model_of_seq) return HMM_ERR_NULL;
+    if (phase != 1 && (!cnt_pi || !cnt_A || !cnt_B)) return HMM_ERR_NULL;
+    const Layout L = make_layout(bank, batch, HMM_OP_GRAD);
+    if ((rc = check_ws(ws, ws_bytes, L)) != HMM_OK) return rc;
+    bool batched = false;
+    if ((rc = choose(bank, batch, HMM_OP_GRAD, &batched)) != HMM_OK) return rc;
+    unsigned char *w = (unsigned char *)ws;
+    const int K = bank->K, N = bank->N, M = bank->M, S = batch->S, NP = pad16(N);
+    DevPtrs d = dev_ptrs(bank, batch, true);
+    int32_t *err = (int32_t *)(w + L.err);
+    float *ll = loglik ? loglik : (float *)(w + L.ll);
+    const int cus = device_cu_count();
+    if (phase != 2) {
+        const int nbins = K * (batch->max_len + 1);
+        launch_plan(d, K, S, K, batch->max_len, batch->total_symbols, nbins, w, L, stream);
+        launch_transpose_b(bank->B, (float *)(w + L.bt), K, N, M, NP, stream);
+        if (hipGetLastError() != hipSuccess) return HMM_ERR_HIP;
+        FwdLaunch f;
+        memset(&f, 0, sizeof(f));
+        f.K = K;
+        f.N = N;
+        f.M = M;
+        f.NP = NP;
+        f.S = S;
+        f.all_pairs = 0;
+        f.max_len = batch->max_len;
+        f.total = batch->total_symbols;
+        f.perm = (const int32_t *)(w + L.perm);
+        f.gstart = (const int32_t *)(w + L.gstart);
+        f.queue = (int32_t *)(w + L.queue);
+        f.err = err;
+        f.bt = (const float *)(w + L.bt);
+        f.ll = ll;
+        f.ckpt = (float *)(w + L.ckpt);
+        f.ckexp = (int32_t *)(w + L.ckexp);
+        f.flag = (int32_t *)(w + L.flag);
+        f.nck = L.nck;
+        if (S > 0) {
+            const int pr = prof_begin(stream, HMM_PROF_FWD_BATCHED);
+            const hipError_t e = launch_fwd_mfma(d, f, cus, stream);
+            prof_end(stream, pr);
+            if (e != hipSuccess) return HMM_ERR_HIP;
+        }
+    }
+    if (phase == 1) return HMM_OK;
+    launch_fill_f32(cnt_pi, (size_t)K * N, 0.0f, stream);
+    launch_fill_f32(cnt_A, (size_t)K * N * N, 0.0f, stream);
+    launch_fill_f32(cnt_B, (size_t)K * N * M, 0.0f, stream);
+    int32_t *queue2 = (int32_t *)(w + L.queue) + K;
+    launch_fill_i32(queue2, (size_t)K, 0, stream);
+    if (hipGetLastError() != hipSuccess) return HMM_ERR_HIP;
+    if (S == 0) return HMM_OK;
+    AdjLaunch a;
+    memset(&a, 0, sizeof(a));
+    a.K = K;
+    a.N = N;
+    a.M = M;
+    a.NP = NP;
+    a.S = S;
+    a.max_len = batch->max_len;
+    a.total = batch->total_symbols;
+    a.perm = (const int32_t *)(w + L.perm);
+    a.gstart = (const int32_t *)(w + L.gstart);
+    a.queue = queue2;
+    a.err = err;
+    a.bt = (const float *)(w + L.bt);
+    a.ckpt = (const float *)(w + L.ckpt);
+    a.ckexp = (const int32_t *)(w + L.ckexp);
+    a.flag = (const int32_t *)(w + L.flag);
+    a.nck = L.nck;
+    a.seg = (float *)(w + L.seg);
+    a.seg_stride = L.seg_stride;
+    a.seg_slots = L.seg_slots;
+    a.weight = seq_weight;
+    a.cnt_pi = cnt_pi;
+    a.cnt_A = cnt_A;
+    a.cnt_B = cnt_B;
+    const int pr = prof_begin(stream, HMM_PROF_ADJ_BATCHED);
+    const hipError_t e = launch_adj_mfma(d, a, cus, stream);
+    prof_end(stream, pr);
+    return e == hipSuccess ? HMM_OK : HMM_ERR_HIP;
+}
+
+hmm_status hmm_softmax_rows(const float *logits, float *probs, int64_t rows, int32_t cols, hipStream_t stream) {
+    if (rows < 0 || cols < 1) return HMM_ERR_SHAPE;
+    if (rows > 0 && (!logits || !probs)) return HMM_ERR_NULL;
+    launch_softmax_rows(logits, probs, rows, cols, stream);
+    return hipGetLastError() == hipSuccess ? HMM_OK : HMM_ERR_HIP;
+}
+
+hmm_status hmm_logit_grad(const float *n, const float *probs, float *grad, int64_t rows, int32_t cols,
+                          hipStream_t stream) {
+    if (rows < 0 || cols < 1) return HMM_ERR_SHAPE;
+    if (rows > 0 && (!n || !probs || !grad)) return HMM_ERR_NULL;
+    launch_logit_grad(n, probs, grad, rows, cols, stream);
+    return hipGetLastError() == hipSuccess ? HMM_OK : HMM_ERR_HIP;
+}
+
+hmm_status hmm_workspace_error(const void *ws, hipStream_t stream, int32_t *first_bad_seq) {
+    if (!ws || !first_bad_seq) return HMM_ERR_NULL;
+    if (hipStreamSynchronize(stream) != hipSuccess) return HMM_ERR_HIP;
+    int32_t v = INT32_MAX;
+    if (hipMemcpy(&v, ws, sizeof(v), hipMemcpyDeviceToHost) != hipSuccess) return HMM_ERR_HIP;
+    *first_bad_seq = (v == INT32_MAX) ? -1 : v;
+    return HMM_OK;
+}
+
+hmm_status hmm_select_kernel(int32_t kind) {
+    if (kind < HMM_KERNEL_AUTO || kind > HMM_KERNEL_BATCHED) return HMM_ERR_ARG;
+    g_kernel_kind.store(kind, std::memory_order_relaxed);
+    return HMM_OK;
+}
+
+hmm_status hmm_profile_enable(int32_t on) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_on = on != 0;
+    if (g_prof_on) g_prof_used = 0;
+    return HMM_OK;
+}
+
+hmm_status hmm_profile_read(int32_t kernel, double *total_ms, int32_t *launches) {
+    if (!total_ms || !launches) return HMM_ERR_NULL;
+    if (kernel < HMM_PROF_FWD_BATCHED || kernel > HMM_PROF_FWD_PLAIN) return HMM_ERR_ARG;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    double sum = 0.0;
+    int n = 0;
+    for (size_t i = 0; i < g_prof_used; ++i) {
+        const ProfRecord &r = g_prof_pool[i];
+        if (r.kind != kernel) continue;
+        if (hipEventSynchronize(r.stop) != hipSuccess) return HMM_ERR_HIP;
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, r.start, r.stop) != hipSuccess) return HMM_ERR_HIP;
+        sum += ms;
+        ++n;
+    }
+    *total_ms = sum;
+    *launches = n;
+    return HMM_OK;
+}
+
+const char *hmm_status_string(hmm_status s) {
+    switch (s) {
+        case HMM_OK: return "HMM_OK";
+        case HMM_ERR_NULL: return "HMM_ERR_NULL";
+        case HMM_ERR_SHAPE: return "HMM_ERR_SHAPE";
+        case HMM_ERR_WORKSPACE: return "HMM_ERR_WORKSPACE";
+        case HMM_ERR_UNSUPPORTED: return "HMM_ERR_UNSUPPORTED";
+        case HMM_ERR_HIP: return "HMM_ERR_HIP";
+        case HMM_ERR_ARG: return "HMM_ERR_ARG";
+    }
+    return "HMM_ERR_UNKNOWN";
+}
+
+}  // extern "C"

@@ -1,0 +1,412 @@
+// Backward (adjoint) kernel on FP32 MFMA (gfx950): Baum-Welch E-step counts.
+//
+// The paper's learning mode runs the Baum-Welch function of its HMM stage
+// (Sec. 2.7).  Its E-step is the scaled backward recursion; with the forward
+// pass rescaled by exact powers of two (alphahat_t = alpha_t 2^-E_t,
+// m_T = sum_i alphahat_T(i)) the scaled backward variables are
+//   betahat_T = 1 / m_T,   w_{t+1} = B[:, o_{t+1}] o betahat_{t+1} 2^-e_{t+1},
+//   betahat_t = A w_{t+1},
+// so that gamma_t = alphahat_t o betahat_t sums to one and
+// xi_t(i,j) = alphahat_t(i) A(i,j) w_{t+1}(j).  Each sequence s of weight w_s adds
+//   n_pi += w_s gamma_1,  n_B[:, o_t] += w_s gamma_t,  C += w_s alphahat_t (x) w_{t+1}
+// and n_A = A o C at the end: the gradient of sum_s w_s log P_s w.r.t. ln pi,
+// ln A and ln B.
+//
+// Memory: the forward kernel stored alphahat every L = ceil(sqrt(Tmax)) steps
+// (Tmax the longest sequence of the 16-sequence tile).  Walking the segments
+// last to first, the wave recomputes alphahat for the L steps of a segment
+// with the forward kernel's own step code (bit-identical), parks them in a
+// per-wave buffer in global memory, and runs the backward recursion through
+// the segment.  Memory per sequence grows with sqrt(T).
+//
+// Per step and tile of 16 sequences (layout as in the forward kernel):
+//   betahat_t = A w_{t+1}            16x16x4 MFMAs, A fragments in registers
+//   C += X^T W                       X = w_s alphahat_t, W = w_{t+1}: transposed
+//                                    through a per-wave LDS tile so the 16
+//                                    sequences become the MFMA contraction axis
+//   n_B^T[o_t][i] += w_s gamma_t(i)  LDS float atomics into the workgroup's
+//                                    partial (or global atomics if it does not fit)
+#include <climits>
+
+#include "common.cuh"
+#include "fwd_step.cuh"
+#include "kernels.h"
+
+namespace hmm {
+namespace {
+
+constexpr int ADJ_CH = 16;                  // symbols per staging chunk in the recompute
+constexpr int ADJ_SYM_STRIDE = ADJ_CH + 1;
+
+template <int R>
+struct AdjShape {
+    static constexpr int NP = 16 * R;
+    static constexpr int XS = NP + 4;       // padded row of the transposition tiles
+    static constexpr int tile_floats = 2 * TILE * XS;               // X and W
+    static constexpr int sym_ints = 2 * TILE * ADJ_SYM_STRIDE;
+    static constexpr int per_wave_bytes = tile_floats * 4 + sym_ints * 4;
+};
+
+__host__ __device__ inline int nb_swizzle_mask(int NP) { return (NP & (NP - 1)) == 0 ? NP - 4 : 0; }
+
+template <int R, int WAVES, bool NBLDS>
+__global__ void __launch_bounds__(WAVES * WAVE) k_adj_mfma(DevPtrs d, AdjLaunch a) {
+    using SH = AdjShape<R>;
+    constexpr int NP = SH::NP;
+    constexpr int XS = SH::XS;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int wave = threadIdx.x / WAVE;
+    const int sl = lane & 15, g = lane >> 4;
+    const int K = a.K, N = a.N, M = a.M;
+    const int swz = nb_swizzle_mask(NP);
+    float *nbl = (float *)smem;                                        // [M][NP] when NBLDS
+    unsigned char *wbase = smem + (NBLDS ? (size_t)M * NP * 4 : 0) + (size_t)wave * SH::per_wave_bytes;
+    float *xt = (float *)wbase;                                        // [16][XS]
+    float *wt = xt + TILE * XS;                                        // [16][XS]
+    int32_t *sym = (int32_t *)(wt + TILE * XS);                        // [2][16][ADJ_SYM_STRIDE]
+
+    const int slot = blockIdx.x * WAVES + wave;
+    float *segf = a.seg + (size_t)slot * a.seg_stride;
+    const int Lcap = (int)(a.seg_stride / (WAVE * (4 * R + 2)));
+    float4 *seg_alpha = (float4 *)segf;                                // [Lcap][R][64]
+    int32_t *seg_e = (int32_t *)(segf + (size_t)Lcap * WAVE * 4 * R);  // [Lcap][64]
+    int32_t *seg_o = seg_e + (size_t)Lcap * WAVE;                      // [Lcap][64]
+
+    const int G = gridDim.x;
+    const int k_first = G >= K ? (int)(blockIdx.x % K) : (int)blockIdx.x;
+    const int k_step = G >= K ? K : G;
+    for (int k = k_first; k < K; k += k_step) {
+        const int gbeg = a.gstart[k], gend = a.gstart[k + 1];
+        const int ntiles = (gend - gbeg + TILE - 1) / TILE;
+        const float *btk = a.bt + (size_t)k * M * NP;
+        float *cnt_B = a.cnt_B + (size_t)k * N * M;
+        if (NBLDS) {
+            __syncthreads();
+            for (int i = threadIdx.x; i < M * NP; i += blockDim.x) nbl[i] = 0.0f;
+            __syncthreads();
+        }
+        if (ntiles > 0) {
+            const float *Ak = d.A + (size_t)k * N * N;
+            float af[R][R][4], ab[R][R][4];
+            load_fwd_fragments<R>(af, Ak, N, g, sl);
+            load_bwd_fragments<R>(ab, Ak, N, g, sl);
+            floatx4 C[R][R];
+#pragma unroll
+            for (int ri = 0; ri < R; ++ri)
+#pragma unroll
+                for (int rj = 0; rj < R; ++rj) C[ri][rj] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+
+            for (;;) {
+                int tile = 0;
+                if (lane == 0) tile = atomicAdd(&a.queue[k], 1);
+                tile = __builtin_amdgcn_readfirstlane(tile);
+                if (tile >= ntiles) break;
+
+                const int pos = gbeg + tile * TILE + sl;
+                const bool has = pos < gend;
+                const int seq = has ? a.perm[pos] : 0;
+                int32_t T = 0;
+                int64_t off = 0;
+                bool act = false;
+                if (has) {
+                    T = d.lengths[seq];
+                    off = d.offsets[seq];
+                    const int mk = d.model_of_seq[seq];
+                    const bool bad = seq_bad(T, off, a.max_len, a.total) || mk < 0 || mk >= K;
+                    if (bad) T = 0;
+                    act = !bad && T > 0 && a.flag[pos] == 0;
+                }
+                // the checkpoint grid uses the forward kernel's tile maximum
+                const int Tmax = wave_max_int(T);
+                if (Tmax == 0) continue;
+                int L = 1;
+                while (L * L < Tmax) ++L;
+                const int nseg = (Tmax + L - 1) / L;
+                const float wgt = act ? (a.weight ? a.weight[seq] : 1.0f) : 0.0f;
+                const int st_slot = lane >> 2, st_part = lane & 3;
+                const int32_t st_T = __shfl(T, st_slot, WAVE);
+                const int64_t st_off = __shfl(off, st_slot, WAVE);
+                const int32_t *st_src = d.symbols + st_off;
+                auto stage = [&](int buf, int t0) {
+                    int32_t *dst = sym + buf * TILE * ADJ_SYM_STRIDE + st_slot * ADJ_SYM_STRIDE + st_part * (ADJ_CH / 4);
+#pragma unroll
+                    for (int u = 0; u < ADJ_CH / 4; ++u) {
+                        const int p = t0 + st_part * (ADJ_CH / 4) + u;
+                        int o = p < st_T ? st_src[p] : 0;
+                        dst[u] = ((unsigned)o < (unsigned)M) ? o : 0;
+                    }
+                };
+
+                float wn[R][4];      // w_{t+1}
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) wn[r][v] = 0.0f;
+
+                for (int j = nseg - 1; j >= 0; --j) {
+                    const int t0 = j * L;
+                    const int t1 = min(t0 + L, Tmax);
+                    // ---- recompute alphahat over [t0, t1) from checkpoint j
+                    float acur[R][4];
+                    int e0 = 0;
+                    if (t0 < T) {
+                        const float *src = a.ckpt + ((size_t)pos * a.nck + j) * NP;
+#pragma unroll
+                        for (int r = 0; r < R; ++r) {
+                            float4 q = *(const float4 *)&src[16 * r + 4 * g];
+                            acur[r][0] = q.x;
+                            acur[r][1] = q.y;
+                            acur[r][2] = q.z;
+                            acur[r][3] = q.w;
+                        }
+                        e0 = a.ckexp[(size_t)pos * a.nck + j];
+                    } else {
+#pragma unroll
+                        for (int r = 0; r < R; ++r)
+#pragma unroll
+                            for (int v = 0; v < 4; ++v) acur[r][v] = 0.0f;
+                    }
+                    stage(0, t0);
+                    stage(1, t0 + ADJ_CH);
+                    wave_lds_sync();
+#pragma unroll
+                    for (int r = 0; r < R; ++r)
+                        seg_alpha[(size_t)(0 * R + r) * WAVE + lane] = float4{acur[r][0], acur[r][1], acur[r][2], acur[r][3]};
+                    seg_e[lane] = e0;
+                    seg_o[lane] = sym[sl * ADJ_SYM_STRIDE];
+                    for (int t = t0 + 1; t < t1; ++t) {
+                        const int tl = t - t0;
+                        if ((tl % ADJ_CH) == 0 && tl > 0) {
+                            // chunk tl / ADJ_CH is staged; refill the buffer of the one before
+                            stage(((tl / ADJ_CH) + 1) & 1, t + ADJ_CH);
+                            wave_lds_sync();
+                        }
+                        const int o = sym[((tl / ADJ_CH) & 1) * TILE * ADJ_SYM_STRIDE + sl * ADJ_SYM_STRIDE + (tl % ADJ_CH)];
+                        float4 b[R];
+                        gather_b<R>(&btk[(size_t)o * NP], g, b);
+                        floatx4 u[R];
+                        tile_matvec<R>(af, acur, u);
+                        int e;
+                        emit_and_rescale<R>(u, b, acur, e);
+#pragma unroll
+                        for (int r = 0; r < R; ++r)
+                            seg_alpha[(size_t)(tl * R + r) * WAVE + lane] =
+                                float4{acur[r][0], acur[r][1], acur[r][2], acur[r][3]};
+                        seg_e[(size_t)tl * WAVE + lane] = e;
+                        seg_o[(size_t)tl * WAVE + lane] = o;
+                    }
+                    // ---- backward through the segment
+                    for (int t = t1 - 1; t >= t0; --t) {
+                        const int tl = t - t0;
+                        float al[R][4];
+#pragma unroll
+                        for (int r = 0; r < R; ++r) {
+                            float4 q = seg_alpha[(size_t)(tl * R + r) * WAVE + lane];
+                            al[r][0] = q.x;
+                            al[r][1] = q.y;
+                            al[r][2] = q.z;
+                            al[r][3] = q.w;
+                        }
+                        const int et = seg_e[(size_t)tl * WAVE + lane];
+                        const int ot = seg_o[(size_t)tl * WAVE + lane];
+                        float part = 0.0f;
+#pragma unroll
+                        for (int r = 0; r < R; ++r)
+#pragma unroll
+                            for (int v = 0; v < 4; ++v) part += al[r][v];
+                        const float m = sum_row_groups(part);
+                        const bool live = act && t < T;          // gamma_t exists
+                        const bool trans = act && t + 1 < T;     // xi_t exists
+                        float be[R][4];
+                        if (t + 1 < Tmax) {
+                            floatx4 u[R];
+                            tile_matvec<R>(ab, wn, u);
+#pragma unroll
+                            for (int r = 0; r < R; ++r)
+#pragma unroll
+                                for (int v = 0; v < 4; ++v) be[r][v] = u[r][v];
+                            // C += X^T W with X = w_s alphahat_t, W = w_{t+1}
+#pragma unroll
+                            for (int r = 0; r < R; ++r) {
+                                float4 xv = trans ? float4{wgt * al[r][0], wgt * al[r][1], wgt * al[r][2], wgt * al[r][3]}
+                                                  : float4{0.0f, 0.0f, 0.0f, 0.0f};
+                                float4 wv = trans ? float4{wn[r][0], wn[r][1], wn[r][2], wn[r][3]}
+                                                  : float4{0.0f, 0.0f, 0.0f, 0.0f};
+                                *(float4 *)&xt[sl * XS + 16 * r + 4 * g] = xv;
+                                *(float4 *)&wt[sl * XS + 16 * r + 4 * g] = wv;
+                            }
+                            wave_lds_sync();
+#pragma unroll
+                            for (int q = 0; q < 4; ++q) {
+                                float xa[R], wb[R];
+#pragma unroll
+                                for (int r = 0; r < R; ++r) {
+                                    xa[r] = xt[(4 * q + g) * XS + 16 * r + sl];
+                                    wb[r] = wt[(4 * q + g) * XS + 16 * r + sl];
+                                }
+#pragma unroll
+                                for (int ri = 0; ri < R; ++ri)
+#pragma unroll
+                                    for (int rj = 0; rj < R; ++rj)
+                                        C[ri][rj] = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[ri], wb[rj], C[ri][rj], 0, 0, 0);
+                            }
+                            wave_lds_sync();
+                        } else {
+#pragma unroll
+                            for (int r = 0; r < R; ++r)
+#pragma unroll
+                                for (int v = 0; v < 4; ++v) be[r][v] = 0.0f;
+                        }
+                        if (t == T - 1) {
+                            const float inv = 1.0f / m;
+#pragma unroll
+                            for (int r = 0; r < R; ++r)
+#pragma unroll
+                                for (int v = 0; v < 4; ++v) be[r][v] = inv;
+                        }
+                        // gamma_t -> emission counts (and initial counts at t = 0)
+                        if (live) {
+#pragma unroll
+                            for (int r = 0; r < R; ++r)
+#pragma unroll
+                                for (int v = 0; v < 4; ++v) {
+                                    const int i = 16 * r + 4 * g + v;
+                                    const float gm = wgt * al[r][v] * be[r][v];
+                                    if (i < N) {
+                                        if (NBLDS)
+                                            atomicAdd(&nbl[ot * NP + (i ^ (ot * 4 & swz))], gm);
+                                        else
+                                            atomicAdd(&cnt_B[(size_t)i * M + ot], gm);
+                                        if (t == 0) atomicAdd(&a.cnt_pi[(size_t)k * N + i], gm);
+                                    }
+                                }
+                        }
+                        // w_t = b_t o betahat_t 2^-e_t for the step before
+                        float4 b[R];
+                        gather_b<R>(&btk[(size_t)ot * NP], g, b);
+#pragma unroll
+                        for (int r = 0; r < R; ++r) {
+                            wn[r][0] = ldexp_f(b[r].x * be[r][0], -et);
+                            wn[r][1] = ldexp_f(b[r].y * be[r][1], -et);
+                            wn[r][2] = ldexp_f(b[r].z * be[r][2], -et);
+                            wn[r][3] = ldexp_f(b[r].w * be[r][3], -et);
+                        }
+                    }
+                }
+            }
+            // n_A = A o C for this wave's share of model k
+#pragma unroll
+            for (int ri = 0; ri < R; ++ri)
+#pragma unroll
+                for (int rj = 0; rj < R; ++rj)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int i = 16 * ri + 4 * g + v, jj = 16 * rj + sl;
+                        if (i < N && jj < N) {
+                            const float c = C[ri][rj][v];
+                            if (c != 0.0f) atomicAdd(&a.cnt_A[((size_t)k * N + i) * N + jj], Ak[(size_t)i * N + jj] * c);
+                        }
+                    }
+        }
+        if (NBLDS) {
+            __syncthreads();
+            for (int idx = threadIdx.x; idx < M * NP; idx += blockDim.x) {
+                const int o = idx / NP, ic = idx % NP;
+                const int i = ic ^ (o * 4 & swz);
+                const float v = nbl[idx];
+                if (i < N && v != 0.0f) atomicAdd(&cnt_B[(size_t)i * M + o], v);
+            }
+        }
+    }
+}
+
+template <int R, int WAVES, bool NBLDS>
+size_t adj_lds_bytes(int M) {
+    return (NBLDS ? (size_t)M * 16 * R * 4 : 0) + (size_t)WAVES * AdjShape<R>::per_wave_bytes;
+}
+
+template <int R, int WAVES, bool NBLDS>
+int occupancy_grid(int M, int cu_count, int K, bool set_attr) {
+    auto kern = k_adj_mfma<R, WAVES, NBLDS>;
+    const size_t lds = adj_lds_bytes<R, WAVES, NBLDS>(M);
+    if (set_attr && lds > 64 * 1024)
+        (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, WAVES * WAVE, lds) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    int grid = cu_count * per_cu;
+    if (K > 0 && grid >= K) grid = (grid / K) * K;
+    return grid;
+}
+
+constexpr size_t LDS_LIMIT = 160 * 1024;
+
+// Which variant a shape takes: n_B partial in LDS with 4 or 2 waves, else global atomics.
+template <int R>
+int pick_variant(int M) {
+    if (adj_lds_bytes<R, 4, true>(M) <= LDS_LIMIT) return 0;
+    if (adj_lds_bytes<R, 2, true>(M) <= LDS_LIMIT) return 1;
+    return 2;
+}
+
+template <int R>
+int grid_for(int M, int cu_count, int K, bool set_attr, int *waves) {
+    switch (pick_variant<R>(M)) {
+        case 0: *waves = 4; return occupancy_grid<R, 4, true>(M, cu_count, K, set_attr);
+        case 1: *waves = 2; return occupancy_grid<R, 2, true>(M, cu_count, K, set_attr);
+        default: *waves = 4; return occupancy_grid<R, 4, false>(M, cu_count, K, set_attr);
+    }
+}
+
+template <int R>
+hipError_t launch_r(const DevPtrs &d, const AdjLaunch &a, int cu_count, hipStream_t st) {
+    int waves = 4;
+    const int grid = grid_for<R>(a.M, cu_count, a.K, true, &waves);
+    if (grid * waves > a.seg_slots) return hipErrorInvalidValue;
+    switch (pick_variant<R>(a.M)) {
+        case 0:
+            k_adj_mfma<R, 4, true><<<grid, 4 * WAVE, adj_lds_bytes<R, 4, true>(a.M), st>>>(d, a);
+            break;
+        case 1:
+            k_adj_mfma<R, 2, true><<<grid, 2 * WAVE, adj_lds_bytes<R, 2, true>(a.M), st>>>(d, a);
+            break;
+        default:
+            k_adj_mfma<R, 4, false><<<grid, 4 * WAVE, adj_lds_bytes<R, 4, false>(a.M), st>>>(d, a);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+bool adj_mfma_supported(int NP) { return NP == 16 || NP == 32 || NP == 48 || NP == 64; }
+
+int adj_mfma_slots(int NP, int M, int K, int cu_count) {
+    int waves = 4, grid = 0;
+    switch (NP / 16) {
+        case 1: grid = grid_for<1>(M, cu_count, K, true, &waves); break;
+        case 2: grid = grid_for<2>(M, cu_count, K, true, &waves); break;
+        case 3: grid = grid_for<3>(M, cu_count, K, true, &waves); break;
+        case 4: grid = grid_for<4>(M, cu_count, K, true, &waves); break;
+        default: return 0;
+    }
+    return grid * waves;
+}
+
+int64_t adj_mfma_seg_stride(int NP, int max_len) {
+    int L = 1;
+    while ((int64_t)L * L < max_len) ++L;
+    return (int64_t)L * WAVE * (4 * (NP / 16) + 2);
+}
+
+hipError_t launch_adj_mfma(const DevPtrs &d, const AdjLaunch &a, int cu_count, hipStream_t st) {
+    switch (a.NP / 16) {
+        case 1: return launch_r<1>(d, a, cu_count, st);
+        case 2: return launch_r<2>(d, a, cu_count, st);
+        case 3: return launch_r<3>(d, a, cu_count, st);
+        case 4: return launch_r<4>(d, a, cu_count, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace hmm

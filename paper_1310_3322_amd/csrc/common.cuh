@@ -1,0 +1,64 @@
+// Device helpers shared by the HIP kernels of libhmm_mi355x (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hmm.h"
+
+namespace hmm {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr int WAVE = 64;
+constexpr int TILE = 16;          // sequences per wave tile (the 16 columns of a 16x16 MFMA tile)
+constexpr double LN2 = 0.693147180559945309417232121458176568;
+
+// Host-visible launch parameters shared by the planner and the kernels.
+struct Plan {
+    int32_t K, N, M, NP, S;
+    int32_t groups;        // 1 when every sequence is scored against every model, else K
+    int32_t max_len;
+    int64_t total_symbols;
+    int32_t nbins;         // groups * (max_len + 1)
+};
+
+// Sum over the four 16-lane rows of a wave: lanes l, l^16, l^32, l^48 end
+// with the same (bitwise identical) value.  v_permlane16_swap exchanges odd
+// and even rows, v_permlane32_swap exchanges the two 32-lane halves; adding
+// the pair is commutative, so every lane of a row group gets the same sum.
+__device__ __forceinline__ float sum_row_groups(float x) {
+    auto p = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+    x = __uint_as_float(p[0]) + __uint_as_float(p[1]);
+    auto q = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+    return __uint_as_float(q[0]) + __uint_as_float(q[1]);
+}
+
+__device__ __forceinline__ float wave_sum(float x) {
+    for (int m = 32; m >= 1; m >>= 1) x += __shfl_xor(x, m, WAVE);
+    return x;
+}
+
+__device__ __forceinline__ int wave_max_int(int x) {
+    for (int m = 32; m >= 1; m >>= 1) x = max(x, __shfl_xor(x, m, WAVE));
+    return x;
+}
+
+// Orders LDS traffic between lanes of one wave (no workgroup barrier).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Exponent e with x = m * 2^e, m in [0.5, 1) (0 for x = 0, inf or NaN).
+__device__ __forceinline__ int frexp_exp(float x) { return __builtin_amdgcn_frexp_expf(x); }
+__device__ __forceinline__ float ldexp_f(float x, int e) { return __builtin_amdgcn_ldexpf(x, e); }
+
+// Sequence checks shared by all kernels: returns true when sequence s is
+// malformed (length outside [0, max_len], range outside the symbol array).
+__device__ __forceinline__ bool seq_bad(int32_t T, int64_t off, int32_t max_len, int64_t total) {
+    return T < 0 || T > max_len || off < 0 || off + (int64_t)T > total;
+}
+
+}  // namespace hmm

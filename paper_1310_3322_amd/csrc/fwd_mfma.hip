@@ -1,0 +1,219 @@
+// Batched forward kernel on FP32 MFMA (gfx950): the hot path.
+//
+// Recognition scores every symbol stream against every activity HMM, and the
+// HMMs of the actions are independent (paper Sec. 2.7 and Sec. 3 item 3), so
+// for one model k and a tile of 16 length-sorted sequences the forward step
+//     u[s][j] = sum_i alphahat_{t-1}[s][i] A_k[i][j]
+// is a dense (16 x N) by (N x N) product.  It runs as 16x16x4 FP32 MFMAs in
+// the transposed form U^T = A_k^T alphahat^T: the MFMA A operand is A_k^T (kept
+// in registers for the whole model), the B operand is alphahat^T, and the
+// 16x16 result tile leaves each lane holding one sequence (lane % 16) and four
+// consecutive states of each 16-state block (4 * (lane / 16) + 0..3).  The
+// contraction order over i is free, so the k-step (block r', register v) feeds
+// lane group g the state 16 r' + 4 g + v -- exactly what that lane holds after
+// the previous step: the result registers of step t are the B operand of step
+// t+1, with no data movement between steps.
+//
+// Per step and tile (Sec. 2.7 "Forward", renormalised every step):
+//   alpha~[s][j] = u[s][j] * B_k[j][o_t(s)]      (row o_t of B^T, from LDS or L2)
+//   c_t[s]       = sum_j alpha~[s][j]             (in-lane sum + two row swaps)
+//   alphahat     = alpha~ * 2^-e_t, c_t = m_t 2^e_t, m_t in [0.5, 1)  (exact)
+//   log P        = (sum_{t<T} e_t) ln 2 + ln c_T  (= sum_t ln c_t)
+//
+// Work distribution: each workgroup serves one model at a time; its waves pop
+// 16-sequence tiles of that model's length-sorted list from a per-model
+// queue (longest first), so uneven lengths are balanced inside one launch.
+// With K a multiple of 8 all workgroups of a model land on one XCD.
+#include <climits>
+
+#include "common.cuh"
+#include "fwd_step.cuh"
+#include "kernels.h"
+
+namespace hmm {
+namespace {
+
+constexpr int CH = 32;               // symbols per staging chunk
+constexpr int SYM_STRIDE = CH + 1;   // padded row of the symbol chunk (bank spread)
+constexpr int FWD_WAVES = 4;         // waves per workgroup
+
+template <int R, bool BLDS, bool CKPT>
+__global__ void __launch_bounds__(FWD_WAVES * WAVE) k_fwd_mfma(DevPtrs d, FwdLaunch f) {
+    constexpr int NP = 16 * R;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int wave = threadIdx.x / WAVE;
+    const int sl = lane & 15;        // sequence slot in the tile
+    const int g = lane >> 4;         // row group: states 16r + 4g + 0..3
+    const int K = f.K, N = f.N, M = f.M;
+    float *btl = (float *)smem;      // [M][NP] when BLDS
+    int32_t *sym = (int32_t *)(smem + (BLDS ? (size_t)M * NP * sizeof(float) : 0)) + wave * 2 * TILE * SYM_STRIDE;
+
+    const int G = gridDim.x;
+    const int k_first = G >= K ? (int)(blockIdx.x % K) : (int)blockIdx.x;
+    const int k_step = G >= K ? K : G;
+    for (int k = k_first; k < K; k += k_step) {
+        const int grp = f.all_pairs ? 0 : k;
+        const int gbeg = f.gstart[grp], gend = f.gstart[grp + 1];
+        const int ntiles = (gend - gbeg + TILE - 1) / TILE;
+        const float *btk = f.bt + (size_t)k * M * NP;
+        if (BLDS) {
+            __syncthreads();
+            const int n4 = M * NP / 4;
+            for (int i = threadIdx.x; i < n4; i += blockDim.x)
+                ((float4 *)btl)[i] = ((const float4 *)btk)[i];
+            __syncthreads();
+        }
+        if (ntiles == 0) continue;
+        float af[R][R][4];
+        load_fwd_fragments<R>(af, d.A + (size_t)k * N * N, N, g, sl);
+        const float *pik = d.pi + (size_t)k * N;
+
+        for (;;) {
+            int tile = 0;
+            if (lane == 0) tile = atomicAdd(&f.queue[k], 1);
+            tile = __builtin_amdgcn_readfirstlane(tile);
+            if (tile >= ntiles) break;
+
+            const int pos = gbeg + tile * TILE + sl;
+            const bool has = pos < gend;
+            const int seq = has ? f.perm[pos] : 0;
+            int32_t T = 0;
+            int64_t off = 0;
+            bool bad = false;
+            if (has) {
+                T = d.lengths[seq];
+                off = d.offsets[seq];
+                bad = seq_bad(T, off, f.max_len, f.total);
+                if (!f.all_pairs) {
+                    const int mk = d.model_of_seq[seq];
+                    bad |= (mk < 0 || mk >= K);
+                }
+                if (bad) T = 0;
+            }
+            const int Tmax = wave_max_int(T);
+            // staging lanes: sequence slot lane/4 loads part lane%4 of each chunk
+            const int st_slot = lane >> 2, st_part = lane & 3;
+            const int32_t st_T = __shfl(T, st_slot, WAVE);
+            const int64_t st_off = __shfl(off, st_slot, WAVE);
+            const int32_t *st_src = d.symbols + st_off;
+            auto stage = [&](int buf, int t0) {
+                int32_t *dst = sym + buf * TILE * SYM_STRIDE + st_slot * SYM_STRIDE + st_part * (CH / 4);
+#pragma unroll
+                for (int u = 0; u < CH / 4; ++u) {
+                    const int p = t0 + st_part * (CH / 4) + u;
+                    dst[u] = p < st_T ? st_src[p] : 0;
+                }
+            };
+            int L = 1, ck_base = 0;
+            if (CKPT) {
+                while (L * L < Tmax) ++L;
+                ck_base = pos;
+            }
+
+            float acur[R][4];
+            int E = 0;
+            float ll = 0.0f;
+            bool symbad = false;
+            if (Tmax > 0) {
+                stage(0, 0);
+                stage(1, CH);
+                wave_lds_sync();
+                int o_nx = sym[sl * SYM_STRIDE];
+                symbad |= (0 < T) && (o_nx < 0 || o_nx >= M);
+                o_nx = ((unsigned)o_nx < (unsigned)M) ? o_nx : 0;
+                float4 b_nx[R];
+                gather_b<R>(BLDS ? &btl[o_nx * NP] : &btk[(size_t)o_nx * NP], g, b_nx);
+                for (int t = 0; t < Tmax; ++t) {
+                    float4 bcur[R];
+#pragma unroll
+                    for (int r = 0; r < R; ++r) bcur[r] = b_nx[r];
+                    const int tn = t + 1;
+                    if (tn < Tmax) {
+                        if ((tn % CH) == 0) {
+                            // entering chunk c = tn / CH (staged earlier); refill the
+                            // buffer of chunk c - 1 with chunk c + 1
+                            stage(((tn / CH) + 1) & 1, tn + CH);
+                            wave_lds_sync();
+                        }
+                        int o = sym[((tn / CH) & 1) * TILE * SYM_STRIDE + sl * SYM_STRIDE + (tn % CH)];
+                        symbad |= (tn < T) && (o < 0 || o >= M);
+                        o = ((unsigned)o < (unsigned)M) ? o : 0;
+                        gather_b<R>(BLDS ? &btl[o * NP] : &btk[(size_t)o * NP], g, b_nx);
+                    }
+                    floatx4 u[R];
+                    if (t == 0)
+                        pi_as_u<R>(pik, N, g, u);
+                    else
+                        tile_matvec<R>(af, acur, u);
+                    int e;
+                    const float cs = emit_and_rescale<R>(u, bcur, acur, e);
+                    if (t == T - 1) ll = (float)((double)E * LN2 + log((double)cs));
+                    E += e;
+                    if (CKPT && (t % L) == 0 && t < T) {
+                        const int c = t / L;
+                        float *dst = f.ckpt + ((size_t)ck_base * f.nck + c) * NP;
+#pragma unroll
+                        for (int r = 0; r < R; ++r)
+                            *(float4 *)&dst[16 * r + 4 * g] =
+                                float4{acur[r][0], acur[r][1], acur[r][2], acur[r][3]};
+                        if (g == 0) f.ckexp[(size_t)ck_base * f.nck + c] = e;
+                    }
+                }
+            }
+            if (has && g == 0) {
+                float r = ll;
+                if (bad || symbad) r = NAN;
+                f.ll[f.all_pairs ? (size_t)seq * K + k : (size_t)seq] = r;
+                if (bad || symbad) atomicMin(f.err, seq);
+                // the backward pass skips sequences without a finite likelihood
+                if (CKPT) f.flag[pos] = (r > -INFINITY && r < INFINITY) ? 0 : 1;
+            }
+        }
+    }
+}
+
+template <int R, bool BLDS, bool CKPT>
+hipError_t launch_t(const DevPtrs &d, const FwdLaunch &f, int cu_count, hipStream_t st) {
+    const size_t lds = (BLDS ? (size_t)f.M * 16 * R * sizeof(float) : 0) +
+                       (size_t)FWD_WAVES * 2 * TILE * SYM_STRIDE * sizeof(int32_t);
+    auto kern = k_fwd_mfma<R, BLDS, CKPT>;
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    int per_cu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, FWD_WAVES * WAVE, lds);
+    if (e != hipSuccess) return e;
+    if (per_cu < 1) per_cu = 1;
+    int grid = cu_count * per_cu;
+    if (grid >= f.K) grid = (grid / f.K) * f.K;
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(FWD_WAVES * WAVE), lds, st, d, f);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+bool fwd_mfma_supported(int NP) { return NP == 16 || NP == 32 || NP == 48 || NP == 64; }
+
+hipError_t launch_fwd_mfma(const DevPtrs &d, const FwdLaunch &f, int cu_count, hipStream_t st) {
+    const bool blds = (size_t)f.M * f.NP * sizeof(float) <= 48 * 1024;
+    const bool ck = f.ckpt != nullptr;
+#define HMM_FWD_CASE(R)                                                                  \
+    case R:                                                                              \
+        if (ck) return blds ? launch_t<R, true, true>(d, f, cu_count, st)                \
+                            : launch_t<R, false, true>(d, f, cu_count, st);              \
+        return blds ? launch_t<R, true, false>(d, f, cu_count, st)                       \
+                    : launch_t<R, false, false>(d, f, cu_count, st);
+    switch (f.NP / 16) {
+        HMM_FWD_CASE(1)
+        HMM_FWD_CASE(2)
+        HMM_FWD_CASE(3)
+        HMM_FWD_CASE(4)
+        default:
+            return hipErrorInvalidValue;
+    }
+#undef HMM_FWD_CASE
+}
+
+}  // namespace hmm

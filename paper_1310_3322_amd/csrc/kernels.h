@@ -1,0 +1,90 @@
+// Host-side launchers of the HIP kernels (internal to libhmm_mi355x).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace hmm {
+
+// Workspace carve-up for one call (byte offsets into ws, 256-aligned).
+struct Layout {
+    size_t err;      // int32 first bad sequence (INT32_MAX = none)
+    size_t queue;    // int32 [K] per-model tile queue heads
+    size_t hist;     // int32 [nbins] length histogram
+    size_t cursor;   // int32 [nbins] scatter cursors
+    size_t gstart;   // int32 [groups + 1] start of each group in perm
+    size_t perm;     // int32 [S] sequence ids, grouped by model, longest first
+    size_t bt;       // float [K][M][NP] transposed, zero-padded emission matrix
+    size_t ll;       // float [S][K] log-likelihoods for classify without loglik_opt
+    size_t ckpt;     // float [S][nck][NP] alpha checkpoints (gradient)
+    size_t ckexp;    // int32 [S][nck] exponents of the checkpointed steps
+    size_t flag;     // int32 [S] per sorted position: sequence has no finite likelihood
+    size_t seg;      // float [slots][seg_stride] segment recompute buffers (gradient)
+    size_t total;
+    int32_t nck;         // checkpoints per sequence slot
+    int32_t seg_slots;   // persistent waves of the gradient kernel
+    int64_t seg_stride;  // floats per segment slot
+};
+
+struct DevPtrs {
+    const float *pi, *A, *B;
+    const int32_t *symbols;
+    const int64_t *offsets;
+    const int32_t *lengths;
+    const int32_t *model_of_seq;
+};
+
+// planner.hip
+void launch_plan(const DevPtrs &d, int K, int S, int groups, int max_len, int64_t total, int nbins,
+                 unsigned char *ws, const Layout &L, hipStream_t st);
+void launch_transpose_b(const float *B, float *bt, int K, int N, int M, int NP, hipStream_t st);
+void launch_argmax(const float *ll, int32_t *labels, int S, int K, hipStream_t st);
+void launch_fill_f32(float *p, size_t n, float v, hipStream_t st);
+void launch_fill_i32(int32_t *p, size_t n, int32_t v, hipStream_t st);
+void launch_softmax_rows(const float *z, float *p, int64_t rows, int cols, hipStream_t st);
+void launch_logit_grad(const float *n, const float *p, float *g, int64_t rows, int cols, hipStream_t st);
+
+// fwd_plain.hip: one workgroup per (sequence, model) pair
+hipError_t launch_fwd_plain(const DevPtrs &d, int K, int N, int M, int S, int all_pairs, int max_len,
+                            int64_t total, float *ll, int32_t *err, hipStream_t st);
+
+// fwd_mfma.hip: persistent length-sorted MFMA forward
+struct FwdLaunch {
+    int K, N, M, NP, S, all_pairs, max_len;
+    int64_t total;
+    const int32_t *perm, *gstart;
+    int32_t *queue, *err;
+    const float *bt;
+    float *ll;
+    float *ckpt;      // NULL unless checkpointing for the gradient
+    int32_t *ckexp;
+    int32_t *flag;    // [S] per sorted position: 1 = no finite likelihood (gradient only)
+    int nck;
+};
+bool fwd_mfma_supported(int NP);
+hipError_t launch_fwd_mfma(const DevPtrs &d, const FwdLaunch &f, int cu_count, hipStream_t st);
+
+// adj_mfma.hip: checkpointed backward pass producing expected counts
+struct AdjLaunch {
+    int K, N, M, NP, S, max_len;
+    int64_t total;
+    const int32_t *perm, *gstart;
+    int32_t *queue, *err;
+    const float *bt;
+    const float *ckpt;
+    const int32_t *ckexp;
+    const int32_t *flag;
+    int nck;
+    float *seg;
+    int64_t seg_stride;
+    int seg_slots;
+    const float *weight;
+    float *cnt_pi, *cnt_A, *cnt_B;
+};
+bool adj_mfma_supported(int NP);
+int adj_mfma_slots(int NP, int M, int K, int cu_count);
+int64_t adj_mfma_seg_stride(int NP, int max_len);
+hipError_t launch_adj_mfma(const DevPtrs &d, const AdjLaunch &a, int cu_count, hipStream_t st);
+
+}  // namespace hmm

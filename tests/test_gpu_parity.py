@@ -1,0 +1,359 @@
+"""GPU (HIP) path vs the FP64 oracle, through the C ABI (MI355X only).
+
+Tolerances (stated by the accuracy target of this path):
+  log-likelihood  |l_gpu - l_oracle| / max(|l_oracle|, 1) <= 1e-5, infinities equal
+  gradient        ||g_gpu - g_oracle||_2 / ||g_oracle||_2 <= 1e-4 per tensor and model
+  labels          equal, except where the oracle's top-two gap is within the
+                  log-likelihood tolerance (then the GPU label must be one of the tied)
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import bruteforce
+from oracle import oracle as O
+from paper_1310_3322_amd import hmm, workloads
+
+pytestmark = pytest.mark.gpu
+
+LL_TOL = 1e-5
+GRAD_TOL = 1e-4
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    hmm.load_library()
+    yield
+    hmm.select_kernel(hmm.KERNEL_AUTO)
+
+
+def dev(a, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+def problem(w, own=None):
+    """own: None -> follow the workload; True -> own model; False -> all pairs."""
+    use_own = (not w.all_pairs) if own is None else own
+    return hmm.Problem(dev(w.pi), dev(w.A), dev(w.B), dev(w.symbols), dev(w.offsets), dev(w.lengths),
+                       dev(w.owner) if use_own else None, max_len=w.max_len, total_symbols=w.total_symbols)
+
+
+def rel_err(gpu, ref):
+    gpu = np.asarray(gpu, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    fin = np.isfinite(ref)
+    assert np.array_equal(np.isnan(gpu), np.isnan(ref)), "NaN pattern differs"
+    assert np.array_equal(gpu[np.isinf(ref)], ref[np.isinf(ref)]), "infinities differ"
+    if not fin.any():
+        return 0.0
+    return float(np.max(np.abs(gpu[fin] - ref[fin]) / np.maximum(np.abs(ref[fin]), 1.0)))
+
+
+def oracle_ll(w, own):
+    return O.forward(w.pi, w.A, w.B, w.symbols, w.offsets, w.lengths, w.owner if own else None)
+
+
+KERNELS = {"plain": hmm.KERNEL_PLAIN, "batched": hmm.KERNEL_BATCHED}
+
+
+# --------------------------------------------------------------------------- forward parity
+@pytest.mark.parametrize("kernel", ["plain", "batched"])
+@pytest.mark.parametrize("cfg,scale,own", [("c1", 1.0, True), ("brute", 1.0, True), ("paper", 1.0, False),
+                                           ("c2", 0.25, False), ("c3", 0.004, False), ("c3", 0.004, True),
+                                           ("c4", 0.03, True), ("c4", 0.03, False)])
+def test_forward_parity(kernel, cfg, scale, own):
+    print(f"[case] forward {kernel} {cfg} scale={scale} own={own}", flush=True)
+    w = workloads.make_workload(cfg, scale=scale)
+    p = problem(w, own)
+    hmm.select_kernel(KERNELS[kernel])
+    ll = hmm.forward_loglik(p).cpu().numpy()
+    ref = oracle_ll(w, own)
+    assert rel_err(ll, ref) <= LL_TOL
+
+
+def test_brute_force_through_gpu():
+    w = workloads.make_workload("brute")
+    p = problem(w)
+    ll = hmm.forward_loglik(p).cpu().numpy()[0]
+    P = bruteforce.likelihood(w.pi[0].astype(np.float64).tolist(), w.A[0].astype(np.float64).tolist(),
+                              w.B[0].astype(np.float64).tolist(), w.symbols.tolist())
+    assert abs(ll - math.log(P)) / max(abs(math.log(P)), 1.0) <= LL_TOL
+
+
+@pytest.mark.parametrize("N", [1, 5, 16, 17, 31, 32, 40, 48, 63, 64])
+def test_state_counts_and_padding(N):
+    print(f"[case] padding N={N}", flush=True)
+    rng = np.random.default_rng([7, N])
+    lengths = rng.integers(0, 90, size=45)
+    lengths[:3] = [0, 1, 2]
+    w = workloads.random_lengths_workload(rng, K=3, N=N, M=11, lengths=lengths, all_pairs=True, conc=0.7)
+    ref = oracle_ll(w, False)
+    for kernel in ("plain", "batched"):
+        hmm.select_kernel(KERNELS[kernel])
+        ll = hmm.forward_loglik(problem(w, False)).cpu().numpy()
+        assert rel_err(ll, ref) <= LL_TOL, kernel
+
+
+def test_ragged_edge_lengths():
+    rng = np.random.default_rng(11)
+    # ragged tail, all-equal runs, one very long sequence among short ones, T = 0/1/2
+    lengths = np.concatenate([[0, 1, 2, 3, 1500], np.full(37, 64), rng.integers(1, 40, size=83)])
+    w = workloads.random_lengths_workload(rng, K=5, N=24, M=7, lengths=lengths, all_pairs=True)
+    ref = oracle_ll(w, False)
+    for kernel in ("plain", "batched"):
+        hmm.select_kernel(KERNELS[kernel])
+        ll = hmm.forward_loglik(problem(w, False)).cpu().numpy()
+        assert rel_err(ll, ref) <= LL_TOL, kernel
+        assert np.all(ll[0] == 0.0)
+
+
+def test_m_equals_one_and_k_equals_one():
+    rng = np.random.default_rng(12)
+    w = workloads.random_lengths_workload(rng, K=1, N=9, M=1, lengths=[0, 5, 50, 17], all_pairs=True)
+    ll = hmm.forward_loglik(problem(w, False)).cpu().numpy()
+    assert rel_err(ll, oracle_ll(w, False)) <= LL_TOL
+    # with one symbol every sequence has probability 1
+    np.testing.assert_allclose(ll, 0.0, atol=1e-5)
+
+
+def test_closed_forms_on_gpu():
+    rng = np.random.default_rng(13)
+    N, M, T = 20, 9, 300
+    w = workloads.random_lengths_workload(rng, K=2, N=N, M=M, lengths=[T, T // 2], all_pairs=True)
+    w.B[0] = 1.0 / M                    # uniform emissions: -T ln M
+    w.A[1] = np.eye(N, dtype=np.float32)  # identity transitions
+    for kernel in ("plain", "batched"):
+        hmm.select_kernel(KERNELS[kernel])
+        ll = hmm.forward_loglik(problem(w, False)).cpu().numpy()
+        assert abs(ll[0, 0] + T * math.log(M)) <= LL_TOL * T * math.log(M)
+        assert rel_err(ll, oracle_ll(w, False)) <= LL_TOL
+
+
+def test_impossible_and_invalid_inputs():
+    rng = np.random.default_rng(14)
+    w = workloads.random_lengths_workload(rng, K=2, N=6, M=5, lengths=[10, 10, 10, 10, 10, 10], all_pairs=True)
+    w.B[:, :, 4] = 0.0                       # symbol 4 impossible in both models
+    w.B /= w.B.sum(axis=2, keepdims=True)
+    w.symbols[w.symbols == 4] = 0
+    w.symbols[w.offsets[1] + 3] = 4          # -> -inf
+    w.symbols[w.offsets[2] + 5] = 7          # symbol >= M -> NaN, flagged
+    w.symbols[w.offsets[4] + 0] = -2         # negative symbol -> NaN, flagged
+    lengths = w.lengths.copy()
+    lengths[5] = 10_000                      # beyond max_len and the symbol array -> NaN, flagged
+    for kernel in ("plain", "batched"):
+        hmm.select_kernel(KERNELS[kernel])
+        p = hmm.Problem(dev(w.pi), dev(w.A), dev(w.B), dev(w.symbols), dev(w.offsets), dev(lengths), None,
+                        max_len=10, total_symbols=w.total_symbols)
+        ws = p.workspace(hmm.OP_FORWARD)
+        ll = hmm.forward_loglik(p, ws=ws).cpu().numpy()
+        assert np.all(np.isneginf(ll[1])), kernel
+        assert np.all(np.isnan(ll[2])) and np.all(np.isnan(ll[4])) and np.all(np.isnan(ll[5])), kernel
+        assert np.all(np.isfinite(ll[[0, 3]])), kernel
+        assert hmm.workspace_error(ws) == 2, kernel
+        labels = hmm.classify(p).cpu().numpy()
+        assert labels[2] == -1 and labels[4] == -1 and labels[5] == -1
+        assert labels[1] == 0  # all -inf: smallest index
+
+
+# --------------------------------------------------------------------------- recognition
+def test_classify_c2_labels_full():
+    print("[case] classify c2 full", flush=True)
+    w = workloads.make_workload("c2")
+    p = problem(w, False)
+    hmm.select_kernel(hmm.KERNEL_AUTO)
+    ll = torch.empty((w.S, w.K), dtype=torch.float32, device="cuda")
+    labels = hmm.classify(p, loglik=ll).cpu().numpy()
+    ll = ll.cpu().numpy()
+    ref = oracle_ll(w, False)
+    assert rel_err(ll, ref) <= LL_TOL
+    ref_labels = O.classify(ref.astype(np.float32))
+    srt = np.sort(ref, axis=1)
+    gap = srt[:, -1] - srt[:, -2]
+    tol = 2 * LL_TOL * np.maximum(np.abs(srt[:, -1]), 1.0)
+    clear = gap > tol
+    assert np.array_equal(labels[clear], ref_labels[clear])
+    for s in np.nonzero(~clear)[0]:
+        tied = np.nonzero(ref[s] >= srt[s, -1] - tol[s])[0]
+        assert labels[s] in tied
+    # the recognition rate is that of the oracle (the bank recognises its own sequences)
+    assert np.mean(labels == w.owner) == pytest.approx(np.mean(ref_labels == w.owner), abs=1e-12)
+
+
+def test_full_size_c3_sampled_pairs():
+    """The bench workload at full size, checked on a sample of pairs."""
+    print("[case] c3 full sampled", flush=True)
+    w = workloads.make_workload("c3")
+    p = problem(w, False)
+    hmm.select_kernel(hmm.KERNEL_BATCHED)
+    ll = hmm.forward_loglik(p).cpu().numpy()
+    rng = np.random.default_rng(3)
+    order = np.argsort(-w.lengths, kind="stable")
+    pick = np.unique(np.concatenate([order[:40], order[-40:], rng.choice(w.S, 300, replace=False)]))
+    sub = w.subset(pick)
+    ref = oracle_ll(sub, False)
+    assert rel_err(ll[pick], ref) <= LL_TOL
+    assert np.all(np.isfinite(ll))
+
+
+def test_forward_is_deterministic():
+    w = workloads.make_workload("c2", scale=0.3)
+    p = problem(w, False)
+    hmm.select_kernel(hmm.KERNEL_BATCHED)
+    a = hmm.forward_loglik(p).cpu().numpy()
+    b = hmm.forward_loglik(p).cpu().numpy()
+    assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+
+
+def test_graph_replay_matches_eager():
+    w = workloads.make_workload("c2", scale=0.2)
+    p = problem(w, False)
+    hmm.select_kernel(hmm.KERNEL_AUTO)
+    ws = p.workspace(hmm.OP_CLASSIFY, p.batch_without_models())
+    labels = torch.empty(w.S, dtype=torch.int32, device="cuda")
+    ll = torch.empty((w.S, w.K), dtype=torch.float32, device="cuda")
+    hmm.classify(p, labels=labels, loglik=ll, ws=ws)
+    torch.cuda.synchronize()
+    eager_ll, eager_lab = ll.clone(), labels.clone()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            hmm.classify(p, labels=labels, loglik=ll, ws=ws, stream=s)
+    torch.cuda.current_stream().wait_stream(s)
+    for rep in range(3):
+        ll.fill_(0.0)
+        labels.fill_(-7)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(ll, eager_ll), rep
+        assert torch.equal(labels, eager_lab), rep
+        _ = (ll * 2).sum().item()  # eager work between replays
+
+
+# --------------------------------------------------------------------------- gradient
+def _counts_err(gpu, ref):
+    worst = 0.0
+    for k in range(ref.shape[0]):
+        den = np.linalg.norm(ref[k])
+        if den == 0:
+            assert np.linalg.norm(gpu[k]) == 0
+            continue
+        worst = max(worst, np.linalg.norm(gpu[k] - ref[k]) / den)
+    return worst
+
+
+@pytest.mark.parametrize("cfg,scale", [("c4", 0.02), ("c2", 0.05), ("c1", 1.0), ("paper", 1.0), ("c3", 0.003)])
+def test_counts_parity(cfg, scale):
+    print(f"[case] counts {cfg} scale={scale}", flush=True)
+    w = workloads.make_workload(cfg, scale=scale)
+    p = problem(w, True)
+    rng = np.random.default_rng(5)
+    wts = rng.uniform(0.5, 1.5, size=w.S).astype(np.float32)
+    ll, (npi, nA, nB), _ = hmm.forward_backward_grad(p, seq_weight=dev(wts))
+    rll, rpi, rA, rB = O.counts(w.pi, w.A, w.B, w.symbols, w.offsets, w.lengths, w.owner, weights=wts)
+    assert rel_err(ll.cpu().numpy(), rll) <= LL_TOL
+    assert _counts_err(npi.cpu().numpy(), rpi) <= GRAD_TOL
+    assert _counts_err(nA.cpu().numpy(), rA) <= GRAD_TOL
+    assert _counts_err(nB.cpu().numpy(), rB) <= GRAD_TOL
+
+
+def test_counts_edge_cases():
+    rng = np.random.default_rng(15)
+    lengths = np.array([0, 1, 2, 3, 40, 41, 1, 200, 17, 5], np.int32)
+    w = workloads.random_lengths_workload(rng, K=2, N=19, M=6, lengths=lengths, all_pairs=False)
+    w.B[1, :, 5] = 0.0
+    w.B[1] /= w.B[1].sum(axis=1, keepdims=True)
+    s_dead = 7  # owner 1: make it impossible
+    w.symbols[w.offsets[s_dead] + 10] = 5
+    bad = w.symbols.copy()
+    bad[w.offsets[4] + 2] = 9  # invalid symbol in sequence 4
+    p = hmm.Problem(dev(w.pi), dev(w.A), dev(w.B), dev(bad), dev(w.offsets), dev(w.lengths), dev(w.owner),
+                    max_len=w.max_len, total_symbols=w.total_symbols)
+    ll, (npi, nA, nB), ws = hmm.forward_backward_grad(p)
+    rll, rpi, rA, rB = O.counts(w.pi, w.A, w.B, bad, w.offsets, w.lengths, w.owner)
+    assert rel_err(ll.cpu().numpy(), rll) <= LL_TOL
+    assert np.isneginf(rll[s_dead]) and np.isnan(rll[4])
+    assert _counts_err(npi.cpu().numpy(), rpi) <= GRAD_TOL
+    assert _counts_err(nA.cpu().numpy(), rA) <= GRAD_TOL
+    assert _counts_err(nB.cpu().numpy(), rB) <= GRAD_TOL
+    assert hmm.workspace_error(ws) == 4
+
+
+def test_phase_split_equals_fused():
+    w = workloads.make_workload("c4", scale=0.01)
+    p = problem(w, True)
+    wt = dev(np.linspace(0.2, 2.0, w.S).astype(np.float32))
+    ll0, c0, _ = hmm.forward_backward_grad(p, seq_weight=wt, phase=0)
+    ll1, _, ws = hmm.forward_backward_grad(p, phase=1)
+    _, c2, _ = hmm.forward_backward_grad(p, seq_weight=wt, phase=2, ws=ws)
+    _, c2b, _ = hmm.forward_backward_grad(p, seq_weight=wt, phase=2, ws=ws)  # backward twice from one forward
+    assert torch.equal(ll0, ll1)
+    for a, b, c in zip(c0, c2, c2b):
+        torch.testing.assert_close(a, b, rtol=1e-5, atol=1e-6)
+        torch.testing.assert_close(b, c, rtol=1e-5, atol=1e-6)
+
+
+def test_autograd_logit_gradient_vs_oracle():
+    print("[case] autograd c4 subset", flush=True)
+    w = workloads.make_workload("c4", scale=0.02)
+    lpi, lA, lB = w.logits
+    tpi, tA, tB = (dev(x).requires_grad_(True) for x in (lpi, lA, lB))
+    ll = hmm.loglik_from_logits(tpi, tA, tB, dev(w.symbols), dev(w.offsets), dev(w.lengths), dev(w.owner),
+                                w.max_len)
+    rng = np.random.default_rng(8)
+    go = rng.uniform(0.5, 1.5, size=w.S).astype(np.float32)
+    ll.backward(dev(go))
+    rll, gpi, gA, gB = O.loglik_grad_from_logits(lpi, lA, lB, w.symbols, w.offsets, w.lengths, w.owner, weights=go)
+    assert rel_err(ll.detach().cpu().numpy(), rll) <= LL_TOL
+    for t, ref in ((tpi, gpi), (tA, gA), (tB, gB)):
+        assert _counts_err(t.grad.cpu().numpy(), ref) <= GRAD_TOL
+
+
+def test_gradient_vs_central_differences():
+    """GPU gradient against central differences of the FP64 oracle objective (h = 1e-3)."""
+    w = workloads.make_workload("c4", scale=16 / 8192)
+    lpi, lA, lB = (x.astype(np.float64) for x in w.logits)
+    tpi, tA, tB = (dev(x.astype(np.float32)).requires_grad_(True) for x in (lpi, lA, lB))
+    ll = hmm.loglik_from_logits(tpi, tA, tB, dev(w.symbols), dev(w.offsets), dev(w.lengths), dev(w.owner),
+                                w.max_len)
+    ll.sum().backward()
+    grads = [t.grad.cpu().numpy().astype(np.float64) for t in (tpi, tA, tB)]
+    rng = np.random.default_rng(9)
+    h = 1e-3
+    base = [lpi, lA, lB]
+
+    def f(args):
+        return O.objective_from_logits(*args, w.symbols, w.offsets, w.lengths, w.owner)
+
+    coords = []
+    for which, arr in ((0, lpi), (1, lA), (2, lB)):
+        for _ in range(64):
+            coords.append((which, tuple(int(rng.integers(0, s)) for s in arr.shape)))
+    g_gpu, g_fd = [], []
+    for which, idx in coords:
+        args = [b.copy() for b in base]
+        args[which][idx] += h
+        fp = f(args)
+        args[which][idx] -= 2 * h
+        fm = f(args)
+        g_fd.append((fp - fm) / (2 * h))
+        g_gpu.append(grads[which][idx])
+    g_gpu, g_fd = np.array(g_gpu), np.array(g_fd)
+    assert np.linalg.norm(g_gpu - g_fd) / np.linalg.norm(g_fd) <= GRAD_TOL
+
+
+def test_softmax_and_logit_grad_kernels():
+    rng = np.random.default_rng(10)
+    z = rng.standard_normal((37, 129)).astype(np.float32)
+    n = rng.standard_normal((37, 129)).astype(np.float32)
+    p = hmm.softmax_rows(dev(z)).cpu().numpy()
+    np.testing.assert_allclose(p, O.softmax(z), rtol=2e-6, atol=1e-9)
+    g = hmm.logit_grad(dev(n), dev(p)).cpu().numpy()
+    np.testing.assert_allclose(g, O.logit_grad(n, p), rtol=1e-5, atol=1e-5)
