@@ -33,8 +33,8 @@
 namespace hmm {
 namespace {
 
-constexpr int CH = 32;               // symbols per staging chunk
-constexpr int SYM_STRIDE = CH + 1;   // padded row of the symbol chunk (bank spread)
+constexpr int CH = 32;               // symbols per staging chunk (multiple of 4)
+constexpr int SYM_INTS = CH * TILE;  // one chunk buffer per wave
 constexpr int FWD_WAVES = 4;         // waves per workgroup
 
 template <int R, bool BLDS, bool CKPT>
@@ -42,12 +42,13 @@ __global__ void __launch_bounds__(FWD_WAVES * WAVE) k_fwd_mfma(DevPtrs d, FwdLau
     constexpr int NP = 16 * R;
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x & (WAVE - 1);
-    const int wave = threadIdx.x / WAVE;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     const int sl = lane & 15;        // sequence slot in the tile
     const int g = lane >> 4;         // row group: states 16r + 4g + 0..3
     const int K = f.K, N = f.N, M = f.M;
     float *btl = (float *)smem;      // [M][NP] when BLDS
-    int32_t *sym = (int32_t *)(smem + (BLDS ? (size_t)M * NP * sizeof(float) : 0)) + wave * 2 * TILE * SYM_STRIDE;
+    __shared__ int32_t sym_all[FWD_WAVES * SYM_INTS];   // separate object: never aliases btl
+    int32_t *sym = sym_all + wave * SYM_INTS;
 
     const int G = gridDim.x;
     const int k_first = G >= K ? (int)(blockIdx.x % K) : (int)blockIdx.x;
@@ -91,19 +92,28 @@ __global__ void __launch_bounds__(FWD_WAVES * WAVE) k_fwd_mfma(DevPtrs d, FwdLau
                 }
                 if (bad) T = 0;
             }
-            const int Tmax = wave_max_int(T);
-            // staging lanes: sequence slot lane/4 loads part lane%4 of each chunk
-            const int st_slot = lane >> 2, st_part = lane & 3;
-            const int32_t st_T = __shfl(T, st_slot, WAVE);
-            const int64_t st_off = __shfl(off, st_slot, WAVE);
-            const int32_t *st_src = d.symbols + st_off;
-            auto stage = [&](int buf, int t0) {
-                int32_t *dst = sym + buf * TILE * SYM_STRIDE + st_slot * SYM_STRIDE + st_part * (CH / 4);
+            const int Tmax = __builtin_amdgcn_readfirstlane(wave_max_int(T));
+            // Symbols travel in chunks of CH steps: the next chunk is loaded into
+            // registers (nxt[u] = symbol of sequence sl at step t0 + 4 u + g) while
+            // the current one is read from the wave's LDS buffer, laid out as
+            // sym[u][lane] for the same (u, lane).  Past a sequence's end the
+            // loads repeat its last symbol (a valid address; never used).
+            const int32_t *sbase = T > 0 ? d.symbols + off : d.symbols;
+            const int tlim = T > 0 ? T - 1 : 0;
+            int32_t nxt[CH / 4];
+            auto load_chunk = [&](int t0) {
 #pragma unroll
-                for (int u = 0; u < CH / 4; ++u) {
-                    const int p = t0 + st_part * (CH / 4) + u;
-                    dst[u] = p < st_T ? st_src[p] : 0;
-                }
+                for (int u = 0; u < CH / 4; ++u) nxt[u] = sbase[min(t0 + 4 * u + g, tlim)];
+            };
+            auto store_chunk = [&]() {
+                wave_lds_sync();
+#pragma unroll
+                for (int u = 0; u < CH / 4; ++u) sym[u * WAVE + lane] = nxt[u];
+                wave_lds_sync();
+            };
+            auto read_sym = [&](int t) {
+                const int pp = t % CH;
+                return sym[(pp / 4) * WAVE + 16 * (pp % 4) + sl];
             };
             int L = 1, ck_base = 0;
             if (CKPT) {
@@ -113,33 +123,46 @@ __global__ void __launch_bounds__(FWD_WAVES * WAVE) k_fwd_mfma(DevPtrs d, FwdLau
 
             float acur[R][4];
             int E = 0;
-            float ll = 0.0f;
+            int E_end = 0;        // sum of e_t over t < T - 1 (exponent part of log P)
+            float c_end = 1.0f;   // c_T, the last step's sum (log P = E_end ln 2 + ln c_T)
             bool symbad = false;
             if (Tmax > 0) {
-                stage(0, 0);
-                stage(1, CH);
-                wave_lds_sync();
-                int o_nx = sym[sl * SYM_STRIDE];
-                symbad |= (0 < T) && (o_nx < 0 || o_nx >= M);
-                o_nx = ((unsigned)o_nx < (unsigned)M) ? o_nx : 0;
+                load_chunk(0);
+                store_chunk();
+                load_chunk(CH);
                 float4 b_nx[R];
-                gather_b<R>(BLDS ? &btl[o_nx * NP] : &btk[(size_t)o_nx * NP], g, b_nx);
+                if (!BLDS) {
+                    int o = read_sym(0);
+                    o = ((unsigned)o < (unsigned)M) ? o : 0;
+                    gather_b<R>(&btk[(size_t)o * NP], g, b_nx);
+                }
                 for (int t = 0; t < Tmax; ++t) {
+                    if ((t % CH) == 0 && t > 0) {
+                        // entering chunk t / CH, prefetched a chunk ago
+                        store_chunk();
+                        load_chunk(t + CH);
+                    }
+                    int o = read_sym(t);
+                    symbad |= (t < T) && (o < 0 || o >= M);
+                    o = ((unsigned)o < (unsigned)M) ? o : 0;
                     float4 bcur[R];
+                    if (BLDS) {
+                        gather_b<R>(&btl[o * NP], g, bcur);
+                    } else {
 #pragma unroll
-                    for (int r = 0; r < R; ++r) bcur[r] = b_nx[r];
-                    const int tn = t + 1;
-                    if (tn < Tmax) {
-                        if ((tn % CH) == 0) {
-                            // entering chunk c = tn / CH (staged earlier); refill the
-                            // buffer of chunk c - 1 with chunk c + 1
-                            stage(((tn / CH) + 1) & 1, tn + CH);
-                            wave_lds_sync();
+                        for (int r = 0; r < R; ++r) bcur[r] = b_nx[r];
+                        if (t + 1 < Tmax) {
+                            // the symbol of step t + 1 is in LDS, or (at a chunk
+                            // boundary) still in registers
+                            int on;
+                            if (((t + 1) % CH) == 0) {
+                                on = __shfl(nxt[0], sl, WAVE);
+                            } else {
+                                on = read_sym(t + 1);
+                            }
+                            on = ((unsigned)on < (unsigned)M) ? on : 0;
+                            gather_b<R>(&btk[(size_t)on * NP], g, b_nx);
                         }
-                        int o = sym[((tn / CH) & 1) * TILE * SYM_STRIDE + sl * SYM_STRIDE + (tn % CH)];
-                        symbad |= (tn < T) && (o < 0 || o >= M);
-                        o = ((unsigned)o < (unsigned)M) ? o : 0;
-                        gather_b<R>(BLDS ? &btl[o * NP] : &btk[(size_t)o * NP], g, b_nx);
                     }
                     floatx4 u[R];
                     if (t == 0)
@@ -148,7 +171,10 @@ __global__ void __launch_bounds__(FWD_WAVES * WAVE) k_fwd_mfma(DevPtrs d, FwdLau
                         tile_matvec<R>(af, acur, u);
                     int e;
                     const float cs = emit_and_rescale<R>(u, bcur, acur, e);
-                    if (t == T - 1) ll = (float)((double)E * LN2 + log((double)cs));
+                    if (t == T - 1) {
+                        E_end = E;
+                        c_end = cs;
+                    }
                     E += e;
                     if (CKPT && (t % L) == 0 && t < T) {
                         const int c = t / L;
@@ -162,7 +188,7 @@ __global__ void __launch_bounds__(FWD_WAVES * WAVE) k_fwd_mfma(DevPtrs d, FwdLau
                 }
             }
             if (has && g == 0) {
-                float r = ll;
+                float r = (float)((double)E_end * LN2 + (double)logf(c_end));
                 if (bad || symbad) r = NAN;
                 f.ll[f.all_pairs ? (size_t)seq * K + k : (size_t)seq] = r;
                 if (bad || symbad) atomicMin(f.err, seq);
@@ -175,8 +201,7 @@ __global__ void __launch_bounds__(FWD_WAVES * WAVE) k_fwd_mfma(DevPtrs d, FwdLau
 
 template <int R, bool BLDS, bool CKPT>
 hipError_t launch_t(const DevPtrs &d, const FwdLaunch &f, int cu_count, hipStream_t st) {
-    const size_t lds = (BLDS ? (size_t)f.M * 16 * R * sizeof(float) : 0) +
-                       (size_t)FWD_WAVES * 2 * TILE * SYM_STRIDE * sizeof(int32_t);
+    const size_t lds = BLDS ? (size_t)f.M * 16 * R * sizeof(float) : 0;  // + static symbol buffers
     auto kern = k_fwd_mfma<R, BLDS, CKPT>;
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

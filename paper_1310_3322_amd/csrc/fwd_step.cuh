@@ -1,9 +1,9 @@
 // One step of the batched forward recursion on 16x16x4 FP32 MFMA tiles.
 //
 // Shared by the forward kernel and by the segment recompute of the backward
-// kernel, which must reproduce the forward pass bit for bit.  Explicitly
-// rounded multiplies and adds keep the compiler from contracting them into
-// different fused multiply-adds in the two kernels.
+// kernel, which must reproduce the forward pass bit for bit.  Contraction is
+// off in the emission product so that the compiler cannot fuse multiplies and
+// adds differently in the two kernels.
 //
 // Register layout (one wave, tile of 16 sequences, NP = 16 R padded states):
 // lane l holds sequence slot l % 16 and, for every 16-state block r, the four
@@ -64,16 +64,17 @@ __device__ __forceinline__ void tile_matvec(const float (&f)[R][R][4], const flo
 template <int R>
 __device__ __forceinline__ float emit_and_rescale(const floatx4 (&u)[R], const float4 (&b)[R], float (&out)[R][4],
                                                   int &e) {
+#pragma clang fp contract(off)
     float x[R][4];
     float part = 0.0f;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        x[r][0] = __fmul_rn(u[r][0], b[r].x);
-        x[r][1] = __fmul_rn(u[r][1], b[r].y);
-        x[r][2] = __fmul_rn(u[r][2], b[r].z);
-        x[r][3] = __fmul_rn(u[r][3], b[r].w);
+        x[r][0] = u[r][0] * b[r].x;
+        x[r][1] = u[r][1] * b[r].y;
+        x[r][2] = u[r][2] * b[r].z;
+        x[r][3] = u[r][3] * b[r].w;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) part = __fadd_rn(part, x[r][v]);
+        for (int v = 0; v < 4; ++v) part = part + x[r][v];
     }
     const float cs = sum_row_groups(part);
     e = frexp_exp(cs);
