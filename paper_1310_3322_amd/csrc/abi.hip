@@ -96,10 +96,19 @@ int plan_groups(const hmm_bank *b, const hmm_batch *q, int op) {
     return q->model_of_seq ? b->K : 1;
 }
 
+// States padded for the batched kernels: multiples of 16 up to 64 (one wave
+// per tile), multiples of 32 above (one wave per 16-state block).
+inline int padded_states(int N) { return N <= 64 ? pad16(N) : ((N + 31) / 32) * 32; }
+
+// The gradient's checkpointing forward and its backward must come from the same
+// kernel family (the backward recomputes the forward bit for bit): one wave per
+// tile up to 48 states, one wave per 16-state block from 64 to 128 states.
+inline bool grad_uses_coop(int NP) { return NP >= 64; }
+
 bool batched_capable(const hmm_bank *b, const hmm_batch *q, int op) {
-    const int NP = pad16(b->N);
-    if (!fwd_mfma_supported(NP)) return false;
-    if (op == HMM_OP_GRAD && !adj_mfma_supported(NP)) return false;
+    const int NP = padded_states(b->N);
+    if (!fwd_mfma_supported(NP) && !fwd_coop_supported(NP)) return false;
+    if (op == HMM_OP_GRAD && !(grad_uses_coop(NP) ? adj_coop_supported(NP) : adj_mfma_supported(NP))) return false;
     const int64_t nbins = (int64_t)plan_groups(b, q, op) * ((int64_t)q->max_len + 1);
     return nbins <= MAX_PLAN_BINS;
 }
@@ -113,7 +122,7 @@ Layout make_layout(const hmm_bank *b, const hmm_batch *q, int op) {
         o = align_up(o + bytes);
         return at;
     };
-    const int K = b->K, M = b->M, S = q->S, NP = pad16(b->N);
+    const int K = b->K, M = b->M, S = q->S, NP = padded_states(b->N);
     L.err = take(64);
     if (op == HMM_OP_CLASSIFY) L.ll = take((size_t)S * K * sizeof(float));
     if (op == HMM_OP_GRAD) L.ll = take((size_t)S * sizeof(float));
@@ -133,8 +142,9 @@ Layout make_layout(const hmm_bank *b, const hmm_batch *q, int op) {
             L.ckpt = take((size_t)S * nck * NP * sizeof(float));
             L.ckexp = take((size_t)S * nck * sizeof(int32_t));
             L.flag = take((size_t)S * sizeof(int32_t));
-            L.seg_slots = adj_mfma_slots(NP, M, K, device_cu_count());
-            L.seg_stride = adj_mfma_seg_stride(NP, q->max_len);
+            const bool coop = grad_uses_coop(NP);
+            L.seg_slots = coop ? adj_coop_slots(NP, M, K, device_cu_count()) : adj_mfma_slots(NP, M, K, device_cu_count());
+            L.seg_stride = coop ? adj_coop_seg_stride(NP, q->max_len) : adj_mfma_seg_stride(NP, q->max_len);
             L.seg = take((size_t)L.seg_slots * L.seg_stride * sizeof(float));
         }
     }
@@ -197,7 +207,7 @@ hmm_status run_forward(const hmm_bank *b, const hmm_batch *q, int op, float *out
         prof_end(st, pr);
         return e == hipSuccess ? HMM_OK : HMM_ERR_HIP;
     }
-    const int NP = pad16(N);
+    const int NP = padded_states(N);
     const int groups = all_pairs ? 1 : K;
     const int nbins = groups * (q->max_len + 1);
     launch_plan(d, K, S, groups, q->max_len, q->total_symbols, nbins, ws, L, st);
@@ -220,8 +230,14 @@ hmm_status run_forward(const hmm_bank *b, const hmm_batch *q, int op, float *out
     f.bt = (const float *)(ws + L.bt);
     f.ll = out;
     if (S == 0) return HMM_OK;
+    // One wave per tile while the tiles fill the chip; one wave per 16-state
+    // block (cooperative tile) when the state count needs it or tiles are few.
+    const int cus = device_cu_count();
+    const int64_t tiles = ((int64_t)S + TILE - 1) / TILE + (all_pairs ? 0 : K);
+    const int64_t items = all_pairs ? tiles * K : tiles;
+    const bool coop = !fwd_mfma_supported(NP) || (fwd_coop_supported(NP) && items < (int64_t)8 * cus);
     const int pr = prof_begin(st, HMM_PROF_FWD_BATCHED);
-    const hipError_t e = launch_fwd_mfma(d, f, device_cu_count(), st);
+    const hipError_t e = coop ? launch_fwd_coop(d, f, cus, st) : launch_fwd_mfma(d, f, cus, st);
     prof_end(st, pr);
     return e == hipSuccess ? HMM_OK : HMM_ERR_HIP;
 }
@@ -277,7 +293,7 @@ hmm_status hmm_forward_backward_grad(const hmm_bank *bank, const hmm_batch *batc
     bool batched = false;
     if ((rc = choose(bank, batch, HMM_OP_GRAD, &batched)) != HMM_OK) return rc;
     unsigned char *w = (unsigned char *)ws;
-    const int K = bank->K, N = bank->N, M = bank->M, S = batch->S, NP = pad16(N);
+    const int K = bank->K, N = bank->N, M = bank->M, S = batch->S, NP = padded_states(N);
     DevPtrs d = dev_ptrs(bank, batch, true);
     int32_t *err = (int32_t *)(w + L.err);
     float *ll = loglik ? loglik : (float *)(w + L.ll);
@@ -309,7 +325,7 @@ hmm_status hmm_forward_backward_grad(const hmm_bank *bank, const hmm_batch *batc
         f.nck = L.nck;
         if (S > 0) {
             const int pr = prof_begin(stream, HMM_PROF_FWD_BATCHED);
-            const hipError_t e = launch_fwd_mfma(d, f, cus, stream);
+            const hipError_t e = grad_uses_coop(NP) ? launch_fwd_coop(d, f, cus, stream) : launch_fwd_mfma(d, f, cus, stream);
             prof_end(stream, pr);
             if (e != hipSuccess) return HMM_ERR_HIP;
         }
@@ -348,7 +364,7 @@ hmm_status hmm_forward_backward_grad(const hmm_bank *bank, const hmm_batch *batc
     a.cnt_A = cnt_A;
     a.cnt_B = cnt_B;
     const int pr = prof_begin(stream, HMM_PROF_ADJ_BATCHED);
-    const hipError_t e = launch_adj_mfma(d, a, cus, stream);
+    const hipError_t e = grad_uses_coop(NP) ? launch_adj_coop(d, a, cus, stream) : launch_adj_mfma(d, a, cus, stream);
     prof_end(stream, pr);
     return e == hipSuccess ? HMM_OK : HMM_ERR_HIP;
 }

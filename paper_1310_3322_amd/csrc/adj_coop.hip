@@ -1,0 +1,367 @@
+// Cooperative-tile backward (adjoint) kernel (gfx950): Baum-Welch E-step counts
+// for state counts that need one wave per 16-state block (N = 64 .. 128).
+//
+// Same mathematics as adj_mfma.hip (paper Sec. 2.7 "BalmWelch" E-step; scaled
+// beta recursion of the power-of-two-rescaled forward pass):
+//   betahat_T = 1 / m_T,  w_{t+1} = B[:, o_{t+1}] o betahat_{t+1} 2^-e_{t+1},
+//   betahat_t = A w_{t+1},  gamma_t = alphahat_t o betahat_t,
+//   n_pi += w_s gamma_1,  n_B[:, o_t] += w_s gamma_t,  C += w_s alphahat_t (x) w_{t+1},
+//   n_A = A o C.
+// One workgroup of R waves per tile of 16 length-sorted sequences of one model;
+// wave w owns the 16 states 16 w .. 16 w + 15.  For each sqrt(T) segment, last
+// to first, the workgroup recomputes alphahat from the checkpoint with the
+// cooperative forward step (bit-identical to the checkpointing forward), keeps
+// each lane's own states in a per-workgroup buffer in global memory, then walks
+// the segment backwards: per step one barrier; w_{t+1} of all NP states is
+// exchanged through LDS; wave w forms betahat for its rows (4 R MFMAs with the
+// A_k fragments), adds its rows of C += X^T W (4 R MFMAs, the 16 sequences as
+// the contraction axis, X transposed through a per-wave LDS tile), scatters
+// its rows of gamma into the emission counts, and writes its block of w_t.
+#include <climits>
+
+#include "common.cuh"
+#include "coop_step.cuh"
+#include "kernels.h"
+
+namespace hmm {
+namespace {
+
+constexpr int ACH = 32;  // symbols per staging chunk
+
+template <int R>
+struct AdjCoopShape {
+    static constexpr int NP = 16 * R;
+    static constexpr int XROW = CoopShape<R>::XROW;
+    static constexpr int xch_floats = CoopShape<R>::floats;      // recompute exchange
+    static constexpr int w_floats = 2 * TILE * XROW;             // w exchange, double-buffered
+    static constexpr int at_floats = R * TILE * 17;              // per-wave transposition tiles
+    static constexpr int small_bytes = (xch_floats + w_floats + at_floats) * 4 + 2 * ACH * TILE * 4;
+};
+
+__host__ __device__ inline int nb_swz(int NP) { return (NP & (NP - 1)) == 0 ? NP - 4 : 0; }
+
+template <int R, bool NBLDS>
+__global__ void __launch_bounds__(R * WAVE) k_adj_coop(DevPtrs d, AdjLaunch a) {
+    using SH = AdjCoopShape<R>;
+    constexpr int NP = SH::NP;
+    constexpr int XROW = SH::XROW;
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ __align__(16) float xch[SH::xch_floats];
+    __shared__ __align__(16) float wex[SH::w_floats];
+    __shared__ float atile_all[SH::at_floats];
+    __shared__ int32_t sym[2][ACH * TILE];
+    __shared__ int32_t tile_sh;
+    float *nbl = (float *)smem;  // [M][NP] emission-count partial when NBLDS
+
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+    const int sl = lane & 15, g = lane >> 4;
+    const int K = a.K, N = a.N, M = a.M;
+    const int swz = nb_swz(NP);
+    float *xbuf = xch;
+    float *psum = xch + CoopShape<R>::x_floats;
+    float *atile = atile_all + w * TILE * 17;  // [16 s][17] own alphahat block, transposed reads
+
+    // per-workgroup segment buffer: [Lcap][64 lanes][R waves] float4 alphahat + e + o
+    const int slot = blockIdx.x;
+    float *segf = a.seg + (size_t)slot * a.seg_stride;
+    const int Lcap = (int)(a.seg_stride / ((size_t)R * WAVE * 6));
+    float4 *seg_alpha = (float4 *)segf;
+    int32_t *seg_e = (int32_t *)(segf + (size_t)Lcap * R * WAVE * 4);
+    int32_t *seg_o = seg_e + (size_t)Lcap * R * WAVE;
+    auto sidx = [&](int tl) { return ((size_t)tl * R + w) * WAVE + lane; };
+
+    const int G = gridDim.x;
+    const int k_first = G >= K ? (int)(blockIdx.x % K) : (int)blockIdx.x;
+    const int k_step = G >= K ? K : G;
+    for (int k = k_first; k < K; k += k_step) {
+        const int gbeg = a.gstart[k], gend = a.gstart[k + 1];
+        const int ntiles = (gend - gbeg + TILE - 1) / TILE;
+        const float *btk = a.bt + (size_t)k * M * NP;
+        float *cnt_B = a.cnt_B + (size_t)k * N * M;
+        if (NBLDS) {
+            __syncthreads();
+            for (int i = threadIdx.x; i < M * NP; i += blockDim.x) nbl[i] = 0.0f;
+            __syncthreads();
+        }
+        const float *Ak = d.A + (size_t)k * N * N;
+        if (ntiles > 0) {
+            float af[1][R][4], ab[1][R][4];
+            coop_load_fwd_fragments<R, 1>(af, Ak, N, w, g, sl);
+            coop_load_bwd_fragments<R, 1>(ab, Ak, N, w, g, sl);
+            floatx4 C[R];  // rows 16 w + 4 g + v, columns 16 rj + sl
+#pragma unroll
+            for (int rj = 0; rj < R; ++rj) C[rj] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+
+            for (;;) {
+                if (threadIdx.x == 0) tile_sh = atomicAdd(&a.queue[k], 1);
+                __syncthreads();
+                const int tile = tile_sh;
+                __syncthreads();
+                if (tile >= ntiles) break;
+
+                const int pos = gbeg + tile * TILE + sl;
+                const bool has = pos < gend;
+                const int seq = has ? a.perm[pos] : 0;
+                int32_t T = 0;
+                int64_t off = 0;
+                bool act = false;
+                if (has) {
+                    T = d.lengths[seq];
+                    off = d.offsets[seq];
+                    const int mk = d.model_of_seq[seq];
+                    const bool bad = seq_bad(T, off, a.max_len, a.total) || mk < 0 || mk >= K;
+                    if (bad) T = 0;
+                    act = !bad && T > 0 && a.flag[pos] == 0;
+                }
+                const int Tmax = __builtin_amdgcn_readfirstlane(wave_max_int(T));
+                if (Tmax == 0) continue;
+                int L = 1;
+                while (L * L < Tmax) ++L;
+                const int nseg = (Tmax + L - 1) / L;
+                const float wgt = act ? (a.weight ? a.weight[seq] : 1.0f) : 0.0f;
+                const int32_t *sbase = T > 0 ? d.symbols + off : d.symbols;
+                const int tlim = T > 0 ? T - 1 : 0;
+                float m_last = 1.0f;  // m_T of this lane's sequence (set in the last segment)
+                float wn[4] = {0.0f, 0.0f, 0.0f, 0.0f};  // own block of w_{t+1}
+                // the w exchange buffer of "step Tmax" starts at zero
+                for (int i = threadIdx.x; i < TILE * XROW; i += blockDim.x) wex[(Tmax & 1) * TILE * XROW + i] = 0.0f;
+
+                for (int j = nseg - 1; j >= 0; --j) {
+                    const int t0 = j * L;
+                    const int t1 = min(t0 + L, Tmax);
+                    // ---- symbols of the segment: wave 0 stages them, chunk c in sym[c & 1]
+                    int32_t nxt[ACH / 4];
+                    auto load_chunk = [&](int s0) {
+#pragma unroll
+                        for (int u = 0; u < ACH / 4; ++u) nxt[u] = sbase[min(s0 + 4 * u + g, tlim)];
+                    };
+                    auto store_chunk = [&](int c) {
+#pragma unroll
+                        for (int u = 0; u < ACH / 4; ++u) sym[c & 1][u * WAVE + lane] = nxt[u];
+                    };
+                    auto read_sym = [&](int t) {
+                        const int tl = t - t0, pp = tl % ACH;
+                        int o = sym[(tl / ACH) & 1][(pp / 4) * WAVE + 16 * (pp % 4) + sl];
+                        return ((unsigned)o < (unsigned)M) ? o : 0;
+                    };
+                    __syncthreads();
+                    if (w == 0) {
+                        load_chunk(t0);
+                        store_chunk(0);
+                        load_chunk(t0 + ACH);
+                        store_chunk(1);
+                        load_chunk(t0 + 2 * ACH);
+                    }
+                    // ---- recompute alphahat over [t0, t1) from checkpoint j
+                    float x[1][4];
+                    if (t0 < T) {
+                        const float4 q = *(const float4 *)&a.ckpt[((size_t)pos * a.nck + j) * NP + 16 * w + 4 * g];
+                        x[0][0] = q.x;
+                        x[0][1] = q.y;
+                        x[0][2] = q.z;
+                        x[0][3] = q.w;
+                    } else {
+                        x[0][0] = x[0][1] = x[0][2] = x[0][3] = 0.0f;
+                    }
+                    int e_prev = (t0 < T) ? a.ckexp[(size_t)pos * a.nck + j] : 0;
+                    *(float4 *)&xbuf[(t0 & 1) * TILE * XROW + sl * XROW + 16 * w + 4 * g] =
+                        float4{x[0][0], x[0][1], x[0][2], x[0][3]};
+                    {
+                        // block shares of sum_i alphahat_{t0}(i), in the forward's summation order
+                        float part;
+                        {
+#pragma clang fp contract(off)
+                            part = ((x[0][0] + x[0][1]) + x[0][2]) + x[0][3];
+                        }
+                        part = sum_row_groups(part);
+                        if (g == 0) psum[(t0 & 1) * R * TILE + w * TILE + sl] = part;
+                    }
+                    __syncthreads();
+                    seg_alpha[sidx(0)] = float4{x[0][0], x[0][1], x[0][2], x[0][3]};
+                    seg_e[sidx(0)] = e_prev;
+                    seg_o[sidx(0)] = read_sym(t0);
+                    if (t0 == T - 1) m_last = coop_step_sum<R>(psum + (t0 & 1) * R * TILE, sl);
+                    for (int t = t0 + 1; t <= t1; ++t) {
+                        int e = 0;
+                        if (t > t0 + 1) {
+                            // finish step t - 1: its sum and exponent, store alphahat_{t-1}
+                            const float cs = coop_step_sum<R>(psum + ((t - 1) & 1) * R * TILE, sl);
+                            e = frexp_exp(cs);
+                            const float al[4] = {ldexp_f(x[0][0], -e), ldexp_f(x[0][1], -e), ldexp_f(x[0][2], -e),
+                                                 ldexp_f(x[0][3], -e)};
+                            seg_alpha[sidx(t - 1 - t0)] = float4{al[0], al[1], al[2], al[3]};
+                            seg_e[sidx(t - 1 - t0)] = e;
+                            if (t - 1 == T - 1) m_last = ldexp_f(cs, -e);
+                        }
+                        if (t == t1) break;
+                        if (w == 0 && ((t - t0) % ACH) == 0 && t - t0 >= ACH) {
+                            store_chunk((t - t0) / ACH + 1);
+                            load_chunk(t + 2 * ACH);
+                        }
+                        const int o = read_sym(t);
+                        seg_o[sidx(t - t0)] = o;
+                        const float4 b = *(const float4 *)&btk[(size_t)o * NP + 16 * w + 4 * g];
+                        floatx4 u[1];
+                        // the checkpoint row enters unscaled (exponent 0), later rows by 2^-e
+                        coop_matvec<R, 1>(af, xbuf + ((t - 1) & 1) * TILE * XROW, (t == t0 + 1) ? 0 : e, g, sl, u);
+                        const float part = coop_emit(u[0], b, x[0]);
+                        *(float4 *)&xbuf[(t & 1) * TILE * XROW + sl * XROW + 16 * w + 4 * g] =
+                            float4{x[0][0], x[0][1], x[0][2], x[0][3]};
+                        if (g == 0) psum[(t & 1) * R * TILE + w * TILE + sl] = part;
+                        __syncthreads();
+                    }
+                    // ---- backward through the segment
+                    for (int t = t1 - 1; t >= t0; --t) {
+                        const int tl = t - t0;
+                        const float4 aq = seg_alpha[sidx(tl)];
+                        const float al[4] = {aq.x, aq.y, aq.z, aq.w};
+                        const int et = seg_e[sidx(tl)];
+                        const int ot = seg_o[sidx(tl)];
+                        const bool live = act && t < T;
+                        const bool trans = act && t + 1 < T;
+                        const float *wrow = wex + ((t + 1) & 1) * TILE * XROW;  // w_{t+1}, all states
+                        float be[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+                        if (t + 1 < Tmax) {
+                            floatx4 u[1];
+                            coop_matvec<R, 1>(ab, wrow, 0, g, sl, u);
+#pragma unroll
+                            for (int v = 0; v < 4; ++v) be[v] = u[0][v];
+                            // C[own rows][all] += X^T W: X (own block) through the wave's tile
+#pragma unroll
+                            for (int v = 0; v < 4; ++v) atile[sl * 17 + 4 * g + v] = trans ? wgt * al[v] : 0.0f;
+                            wave_lds_sync();
+#pragma unroll
+                            for (int q = 0; q < 4; ++q) {
+                                const int s = 4 * q + g;
+                                const float xa = atile[s * 17 + sl];
+#pragma unroll
+                                for (int rj = 0; rj < R; ++rj) {
+                                    const float wb = wrow[s * XROW + 16 * rj + sl];
+                                    C[rj] = __builtin_amdgcn_mfma_f32_16x16x4f32(xa, wb, C[rj], 0, 0, 0);
+                                }
+                            }
+                            wave_lds_sync();
+                        }
+                        if (t == T - 1) {
+                            const float inv = 1.0f / m_last;
+#pragma unroll
+                            for (int v = 0; v < 4; ++v) be[v] = inv;
+                        }
+                        if (live) {
+#pragma unroll
+                            for (int v = 0; v < 4; ++v) {
+                                const int i = 16 * w + 4 * g + v;
+                                const float gm = wgt * al[v] * be[v];
+                                if (i < N) {
+                                    if (NBLDS)
+                                        atomicAdd(&nbl[ot * NP + (i ^ (ot * 4 & swz))], gm);
+                                    else
+                                        atomicAdd(&cnt_B[(size_t)i * M + ot], gm);
+                                    if (t == 0) atomicAdd(&a.cnt_pi[(size_t)k * N + i], gm);
+                                }
+                            }
+                        }
+                        // w_t = b_t o betahat_t 2^-e_t; zero where the sequence has ended or
+                        // takes no part (its values may be inf / NaN and w enters the
+                        // contraction over sequences of C)
+                        const float4 b = *(const float4 *)&btk[(size_t)ot * NP + 16 * w + 4 * g];
+                        wn[0] = live ? ldexp_f(b.x * be[0], -et) : 0.0f;
+                        wn[1] = live ? ldexp_f(b.y * be[1], -et) : 0.0f;
+                        wn[2] = live ? ldexp_f(b.z * be[2], -et) : 0.0f;
+                        wn[3] = live ? ldexp_f(b.w * be[3], -et) : 0.0f;
+                        *(float4 *)&wex[(t & 1) * TILE * XROW + sl * XROW + 16 * w + 4 * g] =
+                            float4{wn[0], wn[1], wn[2], wn[3]};
+                        __syncthreads();
+                    }
+                }
+            }
+            // n_A = A o C for this wave's rows of model k
+#pragma unroll
+            for (int rj = 0; rj < R; ++rj)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int i = 16 * w + 4 * g + v, jj = 16 * rj + sl;
+                    if (i < N && jj < N) {
+                        const float c = C[rj][v];
+                        if (c != 0.0f) atomicAdd(&a.cnt_A[((size_t)k * N + i) * N + jj], Ak[(size_t)i * N + jj] * c);
+                    }
+                }
+        }
+        if (NBLDS) {
+            __syncthreads();
+            for (int idx = threadIdx.x; idx < M * NP; idx += blockDim.x) {
+                const int o = idx / NP, ic = idx % NP;
+                const int i = ic ^ (o * 4 & swz);
+                const float v = nbl[idx];
+                if (i < N && v != 0.0f) atomicAdd(&cnt_B[(size_t)i * M + o], v);
+            }
+        }
+    }
+}
+
+constexpr size_t COOP_LDS_LIMIT = 160 * 1024;
+
+template <int R>
+bool use_nb_lds(int M) {
+    return (size_t)M * 16 * R * 4 + AdjCoopShape<R>::small_bytes + 64 <= COOP_LDS_LIMIT;
+}
+
+template <int R, bool NBLDS>
+int grid_t(int M, int cu_count, int K) {
+    auto kern = k_adj_coop<R, NBLDS>;
+    const size_t dyn = NBLDS ? (size_t)M * 16 * R * 4 : 0;
+    if (dyn > 0) (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, R * WAVE, dyn) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    int grid = cu_count * per_cu;
+    if (K > 0 && grid >= K) grid = (grid / K) * K;
+    return grid;
+}
+
+template <int R>
+int grid_r(int M, int cu_count, int K) {
+    return use_nb_lds<R>(M) ? grid_t<R, true>(M, cu_count, K) : grid_t<R, false>(M, cu_count, K);
+}
+
+template <int R>
+hipError_t launch_r(const DevPtrs &d, const AdjLaunch &a, int cu_count, hipStream_t st) {
+    const int grid = grid_r<R>(a.M, cu_count, a.K);
+    if (grid > a.seg_slots) return hipErrorInvalidValue;
+    if (use_nb_lds<R>(a.M))
+        k_adj_coop<R, true><<<grid, R * WAVE, (size_t)a.M * 16 * R * 4, st>>>(d, a);
+    else
+        k_adj_coop<R, false><<<grid, R * WAVE, 0, st>>>(d, a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+bool adj_coop_supported(int NP) { return NP == 64 || NP == 96 || NP == 128; }
+
+int adj_coop_slots(int NP, int M, int K, int cu_count) {
+    switch (NP / 16) {
+        case 4: return grid_r<4>(M, cu_count, K);
+        case 6: return grid_r<6>(M, cu_count, K);
+        case 8: return grid_r<8>(M, cu_count, K);
+        default: return 0;
+    }
+}
+
+int64_t adj_coop_seg_stride(int NP, int max_len) {
+    int L = 1;
+    while ((int64_t)L * L < max_len) ++L;
+    return (int64_t)L * (NP / 16) * WAVE * 6;  // float4 alphahat + e + o per lane and wave
+}
+
+hipError_t launch_adj_coop(const DevPtrs &d, const AdjLaunch &a, int cu_count, hipStream_t st) {
+    switch (a.NP / 16) {
+        case 4: return launch_r<4>(d, a, cu_count, st);
+        case 6: return launch_r<6>(d, a, cu_count, st);
+        case 8: return launch_r<8>(d, a, cu_count, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace hmm

@@ -51,6 +51,14 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Returns v unchanged but opaque to the optimiser, so that address arithmetic
+// derived from it is not hoisted out of the enclosing loop (which would pin one
+// register pair per unrolled load for the whole kernel).
+__device__ __forceinline__ int opaque(int v) {
+    asm volatile("" : "+v"(v));
+    return v;
+}
+
 // Exponent e with x = m * 2^e, m in [0.5, 1) (0 for x = 0, inf or NaN).
 __device__ __forceinline__ int frexp_exp(float x) { return __builtin_amdgcn_frexp_expf(x); }
 __device__ __forceinline__ float ldexp_f(float x, int e) { return __builtin_amdgcn_ldexpf(x, e); }

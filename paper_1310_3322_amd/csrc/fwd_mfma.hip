@@ -61,8 +61,10 @@ __global__ void __launch_bounds__(FWD_WAVES * WAVE) k_fwd_mfma(DevPtrs d, FwdLau
         if (BLDS) {
             __syncthreads();
             const int n4 = M * NP / 4;
-            for (int i = threadIdx.x; i < n4; i += blockDim.x)
-                ((float4 *)btl)[i] = ((const float4 *)btk)[i];
+            for (int i = threadIdx.x; i < n4; i += blockDim.x) {
+                const int o = i / (NP / 4), c = i % (NP / 4);
+                ((float4 *)btl)[o * (NP / 4) + (c ^ (o & chunk_swizzle_mask<R>()))] = ((const float4 *)btk)[i];
+            }
             __syncthreads();
         }
         if (ntiles == 0) continue;
@@ -130,39 +132,33 @@ __global__ void __launch_bounds__(FWD_WAVES * WAVE) k_fwd_mfma(DevPtrs d, FwdLau
                 load_chunk(0);
                 store_chunk();
                 load_chunk(CH);
+                // the symbol and emission row of step t + 1 are fetched during step t
+                int o_nx = read_sym(0);
+                symbad |= (0 < T) && (o_nx < 0 || o_nx >= M);
+                o_nx = ((unsigned)o_nx < (unsigned)M) ? o_nx : 0;
                 float4 b_nx[R];
-                if (!BLDS) {
-                    int o = read_sym(0);
-                    o = ((unsigned)o < (unsigned)M) ? o : 0;
-                    gather_b<R>(&btk[(size_t)o * NP], g, b_nx);
-                }
+                if (BLDS)
+                    gather_b_swz<R>(btl, o_nx, g, b_nx);
+                else
+                    gather_b<R>(&btk[(size_t)o_nx * NP], g, b_nx);
                 for (int t = 0; t < Tmax; ++t) {
-                    if ((t % CH) == 0 && t > 0) {
-                        // entering chunk t / CH, prefetched a chunk ago
-                        store_chunk();
-                        load_chunk(t + CH);
-                    }
-                    int o = read_sym(t);
-                    symbad |= (t < T) && (o < 0 || o >= M);
-                    o = ((unsigned)o < (unsigned)M) ? o : 0;
                     float4 bcur[R];
-                    if (BLDS) {
-                        gather_b<R>(&btl[o * NP], g, bcur);
-                    } else {
 #pragma unroll
-                        for (int r = 0; r < R; ++r) bcur[r] = b_nx[r];
-                        if (t + 1 < Tmax) {
-                            // the symbol of step t + 1 is in LDS, or (at a chunk
-                            // boundary) still in registers
-                            int on;
-                            if (((t + 1) % CH) == 0) {
-                                on = __shfl(nxt[0], sl, WAVE);
-                            } else {
-                                on = read_sym(t + 1);
-                            }
-                            on = ((unsigned)on < (unsigned)M) ? on : 0;
-                            gather_b<R>(&btk[(size_t)on * NP], g, b_nx);
+                    for (int r = 0; r < R; ++r) bcur[r] = b_nx[r];
+                    const int tn = t + 1;
+                    if (tn < Tmax) {
+                        if ((tn % CH) == 0) {
+                            // chunk tn / CH was prefetched a chunk ago
+                            store_chunk();
+                            load_chunk(tn + CH);
                         }
+                        int o = read_sym(tn);
+                        symbad |= (tn < T) && (o < 0 || o >= M);
+                        o = ((unsigned)o < (unsigned)M) ? o : 0;
+                        if (BLDS)
+                            gather_b_swz<R>(btl, o, g, b_nx);
+                        else
+                            gather_b<R>(&btk[(size_t)o * NP], g, b_nx);
                     }
                     floatx4 u[R];
                     if (t == 0)

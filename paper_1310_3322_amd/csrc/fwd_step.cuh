@@ -17,6 +17,7 @@ namespace hmm {
 // A-operand fragments of A_k^T: af[r][rp][v] = A_k[16 rp + 4 g + v][16 r + sl].
 template <int R>
 __device__ __forceinline__ void load_fwd_fragments(float (&af)[R][R][4], const float *Ak, int N, int g, int sl) {
+    const int lane_off = opaque(4 * g * N + sl);
 #pragma unroll
     for (int r = 0; r < R; ++r)
 #pragma unroll
@@ -24,7 +25,7 @@ __device__ __forceinline__ void load_fwd_fragments(float (&af)[R][R][4], const f
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int i = 16 * rp + 4 * g + v, j = 16 * r + sl;
-                af[r][rp][v] = (i < N && j < N) ? Ak[(size_t)i * N + j] : 0.0f;
+                af[r][rp][v] = (i < N && j < N) ? Ak[lane_off + (16 * rp + v) * N + 16 * r] : 0.0f;
             }
 }
 
@@ -32,6 +33,7 @@ __device__ __forceinline__ void load_fwd_fragments(float (&af)[R][R][4], const f
 // (for beta_t = A_k w_{t+1}).
 template <int R>
 __device__ __forceinline__ void load_bwd_fragments(float (&ab)[R][R][4], const float *Ak, int N, int g, int sl) {
+    const int lane_off = opaque(sl * N + 4 * g);
 #pragma unroll
     for (int r = 0; r < R; ++r)
 #pragma unroll
@@ -39,7 +41,7 @@ __device__ __forceinline__ void load_bwd_fragments(float (&ab)[R][R][4], const f
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int i = 16 * r + sl, j = 16 * rp + 4 * g + v;
-                ab[r][rp][v] = (i < N && j < N) ? Ak[(size_t)i * N + j] : 0.0f;
+                ab[r][rp][v] = (i < N && j < N) ? Ak[lane_off + 16 * r * N + 16 * rp + v] : 0.0f;
             }
 }
 
@@ -101,6 +103,23 @@ template <int R>
 __device__ __forceinline__ void gather_b(const float *row, int g, float4 (&b)[R]) {
 #pragma unroll
     for (int r = 0; r < R; ++r) b[r] = *(const float4 *)&row[16 * r + 4 * g];
+}
+
+// LDS copy of B^T: the float4 chunks of row o are XOR-permuted by
+// chunk_swizzle(o) so that the 16 different rows a tile reads in one step fall
+// into different banks.  The mask stays inside an aligned group of chunks, so
+// the permuted index stays inside the row.
+template <int R>
+__host__ __device__ constexpr int chunk_swizzle_mask() {
+    return (R % 2 == 0) ? 7 : 3;   // NP / 4 = 4 R chunks per row
+}
+
+template <int R>
+__device__ __forceinline__ void gather_b_swz(const float *lds_bt, int o, int g, float4 (&b)[R]) {
+    const int m = o & chunk_swizzle_mask<R>();
+    const float4 *row = (const float4 *)lds_bt + o * (4 * R);
+#pragma unroll
+    for (int r = 0; r < R; ++r) b[r] = row[(4 * r + g) ^ m];
 }
 
 }  // namespace hmm

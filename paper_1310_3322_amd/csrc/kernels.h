@@ -65,6 +65,10 @@ struct FwdLaunch {
 bool fwd_mfma_supported(int NP);
 hipError_t launch_fwd_mfma(const DevPtrs &d, const FwdLaunch &f, int cu_count, hipStream_t st);
 
+// fwd_coop.hip: cooperative-tile forward (one wave per 16-state block)
+bool fwd_coop_supported(int NP);
+hipError_t launch_fwd_coop(const DevPtrs &d, const FwdLaunch &f, int cu_count, hipStream_t st);
+
 // adj_mfma.hip: checkpointed backward pass producing expected counts
 struct AdjLaunch {
     int K, N, M, NP, S, max_len;
@@ -83,6 +87,11 @@ struct AdjLaunch {
     float *cnt_pi, *cnt_A, *cnt_B;
 };
 bool adj_mfma_supported(int NP);
+// adj_coop.hip: cooperative-tile backward (one wave per 16-state block)
+bool adj_coop_supported(int NP);
+int adj_coop_slots(int NP, int M, int K, int cu_count);
+int64_t adj_coop_seg_stride(int NP, int max_len);
+hipError_t launch_adj_coop(const DevPtrs &d, const AdjLaunch &a, int cu_count, hipStream_t st);
 int adj_mfma_slots(int NP, int M, int K, int cu_count);
 int64_t adj_mfma_seg_stride(int NP, int max_len);
 hipError_t launch_adj_mfma(const DevPtrs &d, const AdjLaunch &a, int cu_count, hipStream_t st);

@@ -65,7 +65,8 @@ KERNELS = {"plain": hmm.KERNEL_PLAIN, "batched": hmm.KERNEL_BATCHED}
 @pytest.mark.parametrize("kernel", ["plain", "batched"])
 @pytest.mark.parametrize("cfg,scale,own", [("c1", 1.0, True), ("brute", 1.0, True), ("paper", 1.0, False),
                                            ("c2", 0.25, False), ("c3", 0.004, False), ("c3", 0.004, True),
-                                           ("c4", 0.03, True), ("c4", 0.03, False)])
+                                           ("c4", 0.03, True), ("c4", 0.03, False), ("c4", 1.0, True),
+                                           ("c5", 0.003, True)])
 def test_forward_parity(kernel, cfg, scale, own):
     print(f"[case] forward {kernel} {cfg} scale={scale} own={own}", flush=True)
     w = workloads.make_workload(cfg, scale=scale)
@@ -97,6 +98,39 @@ def test_state_counts_and_padding(N):
         hmm.select_kernel(KERNELS[kernel])
         ll = hmm.forward_loglik(problem(w, False)).cpu().numpy()
         assert rel_err(ll, ref) <= LL_TOL, kernel
+
+
+@pytest.mark.parametrize("N", [65, 96, 100, 128, 129, 200, 255, 256])
+def test_large_state_counts_cooperative(N):
+    """N > 64 runs on the cooperative-tile kernel (one wave per 16/32-state block)."""
+    print(f"[case] cooperative N={N}", flush=True)
+    rng = np.random.default_rng([8, N])
+    lengths = rng.integers(0, 120, size=37)
+    lengths[:4] = [0, 1, 2, 33]
+    for all_pairs in (True, False):
+        w = workloads.random_lengths_workload(rng, K=3, N=N, M=13, lengths=lengths, all_pairs=all_pairs, conc=0.3)
+        ref = oracle_ll(w, not all_pairs)
+        for kernel in ("plain", "batched"):
+            hmm.select_kernel(KERNELS[kernel])
+            ll = hmm.forward_loglik(problem(w)).cpu().numpy()
+            assert rel_err(ll, ref) <= LL_TOL, (kernel, all_pairs)
+
+
+def test_c5_subset_and_full_size_sample():
+    """The N=256 bank: a subset against the oracle, and the full batch on sampled sequences."""
+    print("[case] c5", flush=True)
+    w = workloads.make_workload("c5", scale=0.005)
+    hmm.select_kernel(hmm.KERNEL_BATCHED)
+    ll = hmm.forward_loglik(problem(w)).cpu().numpy()
+    assert rel_err(ll, oracle_ll(w, True)) <= LL_TOL
+    wf = workloads.make_workload("c5")
+    llf = hmm.forward_loglik(problem(wf)).cpu().numpy()
+    assert np.all(np.isfinite(llf))
+    order = np.argsort(-wf.lengths, kind="stable")
+    rng = np.random.default_rng(4)
+    pick = np.unique(np.concatenate([order[:16], order[-16:], rng.choice(wf.S, 48, replace=False)]))
+    sub = wf.subset(pick)
+    assert rel_err(llf[pick], oracle_ll(sub, True)) <= LL_TOL
 
 
 def test_ragged_edge_lengths():
@@ -249,7 +283,8 @@ def _counts_err(gpu, ref):
     return worst
 
 
-@pytest.mark.parametrize("cfg,scale", [("c4", 0.02), ("c2", 0.05), ("c1", 1.0), ("paper", 1.0), ("c3", 0.003)])
+@pytest.mark.parametrize("cfg,scale", [("c4", 0.02), ("c2", 0.05), ("c1", 1.0), ("paper", 1.0), ("c3", 0.003),
+                                       ("c4", 0.25)])
 def test_counts_parity(cfg, scale):
     print(f"[case] counts {cfg} scale={scale}", flush=True)
     w = workloads.make_workload(cfg, scale=scale)
@@ -257,6 +292,23 @@ def test_counts_parity(cfg, scale):
     rng = np.random.default_rng(5)
     wts = rng.uniform(0.5, 1.5, size=w.S).astype(np.float32)
     ll, (npi, nA, nB), _ = hmm.forward_backward_grad(p, seq_weight=dev(wts))
+    rll, rpi, rA, rB = O.counts(w.pi, w.A, w.B, w.symbols, w.offsets, w.lengths, w.owner, weights=wts)
+    assert rel_err(ll.cpu().numpy(), rll) <= LL_TOL
+    assert _counts_err(npi.cpu().numpy(), rpi) <= GRAD_TOL
+    assert _counts_err(nA.cpu().numpy(), rA) <= GRAD_TOL
+    assert _counts_err(nB.cpu().numpy(), rB) <= GRAD_TOL
+
+
+@pytest.mark.parametrize("N", [49, 64, 80, 96, 128])
+def test_counts_cooperative_state_counts(N):
+    """Gradient with the cooperative kernels (N = 64 .. 128), ragged lengths incl. T = 1."""
+    print(f"[case] counts cooperative N={N}", flush=True)
+    rng = np.random.default_rng([9, N])
+    lengths = rng.integers(1, 150, size=41)
+    lengths[:3] = [1, 2, 65]
+    w = workloads.random_lengths_workload(rng, K=3, N=N, M=17, lengths=lengths, all_pairs=False, conc=0.5)
+    wts = rng.uniform(0.5, 1.5, size=w.S).astype(np.float32)
+    ll, (npi, nA, nB), _ = hmm.forward_backward_grad(problem(w), seq_weight=dev(wts))
     rll, rpi, rA, rB = O.counts(w.pi, w.A, w.B, w.symbols, w.offsets, w.lengths, w.owner, weights=wts)
     assert rel_err(ll.cpu().numpy(), rll) <= LL_TOL
     assert _counts_err(npi.cpu().numpy(), rpi) <= GRAD_TOL
