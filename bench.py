@@ -15,7 +15,9 @@ time.  Printed as one JSON line, with:
   plain         the plain per-pair kernel on the same workload (batched / plain speedup);
   fwd_bwd       forward + adjoint (expected counts) on the gradient workload
                 (8 models, N=64, M=512, 8192 sequences, T in [100, 1000]),
-                6 algorithmic FLOPs per state-step.
+                6 algorithmic FLOPs per state-step;
+  large_states  the forward of the N=256 bank (16 models, M=1024, 16,384
+                sequences, T in [256, 4096], own model) on the cooperative kernel.
 """
 from __future__ import annotations
 
@@ -114,6 +116,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip the plain and fwd+bwd legs")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run 4 device copies of 512 MiB (reference kernel for HBM counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -206,6 +210,31 @@ def main():
                              "value": u4 / gsec, "unit": "state-steps/s", "ms_per_step": gsec * 1e3,
                              "fwd_kernel_ms": f_ms / max(f_n, 1), "adj_kernel_ms": a_ms / max(a_n, 1),
                              "frac_fp32_peak": 6.0 * u4 / gsec / 1e12 / FP32_PEAK_TFLOPS}
+
+        log("forward of the N=256 bank (16 models, M=1024, 16384 sequences)")
+        w5 = workloads.make_workload("c5")
+        p5 = to_dev(w5, torch, own=True)
+        ws5 = p5.workspace(hmm.OP_FORWARD)
+        ll5 = torch.empty(w5.S, dtype=torch.float32, device="cuda")
+        hmm.profile_enable(True)
+        s5 = time_steps(lambda: hmm.forward_loglik(p5, out=ll5, ws=ws5), 3, 1, torch)
+        k5_ms, k5_n = hmm.profile_read(hmm.PROF_FWD_BATCHED)
+        hmm.profile_enable(False)
+        u5 = w5.units()
+        result["large_states"] = {"workload": "c5: 16 HMMs N=256 M=1024, 16384 sequences, T in [256,4096], own model, "
+                                              "forward (cooperative kernel)",
+                                  "value": u5 / s5, "unit": "state-steps/s", "ms_per_step": s5 * 1e3,
+                                  "kernel_ms": k5_ms / max(k5_n, 1),
+                                  "frac_fp32_peak": 2.0 * u5 / (k5_ms / max(k5_n, 1) / 1e3) / 1e12 / FP32_PEAK_TFLOPS}
+
+    if args.copy_calibration:
+        log("copy calibration: 4 x 512 MiB device-to-device")
+        src = torch.empty(128 << 20, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(4):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        result["copy_calibration_bytes"] = src.numel() * 4
 
     if not args.no_cpu:
         log("CPU oracle baseline on a stratified sample")
