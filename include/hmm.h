@@ -100,10 +100,17 @@ typedef struct {
 #define HMM_OP_CLASSIFY 1
 #define HMM_OP_GRAD 2
 
-/* Kernel family selector (process-wide; affects later calls). */
-#define HMM_KERNEL_AUTO 0     /* batched where supported, else plain               */
-#define HMM_KERNEL_PLAIN 1    /* one workgroup per (sequence, model) pair           */
-#define HMM_KERNEL_BATCHED 2  /* length-sorted persistent MFMA kernels              */
+/* Kernel family selector for the forward pass (process-wide; affects later
+ * calls).  AUTO and BATCHED choose among the batched families by shape; the
+ * last three force one family and make a call return HMM_ERR_UNSUPPORTED when
+ * it does not take the shape.  The gradient always uses the batched family
+ * that matches its backward kernel. */
+#define HMM_KERNEL_AUTO 0     /* batched where supported, else plain                  */
+#define HMM_KERNEL_PLAIN 1    /* one wave per (sequence, model) pair                   */
+#define HMM_KERNEL_BATCHED 2  /* length-sorted persistent MFMA kernels                 */
+#define HMM_KERNEL_TILE16 3   /* one wave per 16-sequence tile (padded N <= 64)        */
+#define HMM_KERNEL_TILE32 4   /* one wave per 32-sequence tile (padded N = 32 or 64)   */
+#define HMM_KERNEL_COOP 5     /* one workgroup per tile, one wave per state block (N >= 49) */
 
 /* Bytes of workspace the call `op` needs for this bank and batch (host only,
  * reads no device memory; pointers in bank/batch may be NULL here).

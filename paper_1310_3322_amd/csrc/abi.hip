@@ -185,7 +185,7 @@ hmm_status choose(const hmm_bank *b, const hmm_batch *q, int op, bool *batched) 
         *batched = false;
         return HMM_OK;
     }
-    if (kind == HMM_KERNEL_BATCHED && !cap) return HMM_ERR_UNSUPPORTED;
+    if (kind >= HMM_KERNEL_BATCHED && !cap) return HMM_ERR_UNSUPPORTED;
     *batched = cap;
     return HMM_OK;
 }
@@ -235,9 +235,26 @@ hmm_status run_forward(const hmm_bank *b, const hmm_batch *q, int op, float *out
     const int cus = device_cu_count();
     const int64_t tiles = ((int64_t)S + TILE - 1) / TILE + (all_pairs ? 0 : K);
     const int64_t items = all_pairs ? tiles * K : tiles;
-    const bool coop = !fwd_mfma_supported(NP) || (fwd_coop_supported(NP) && items < (int64_t)8 * cus);
+    bool coop = !fwd_mfma_supported(NP) || (fwd_coop_supported(NP) && items < (int64_t)8 * cus);
+    // 32-sequence tiles halve the per-state vector work when there are enough of them
+    const int64_t items32 = all_pairs ? (((int64_t)S + 31) / 32) * K : ((int64_t)S + 31) / 32 + K;
+    bool wide = !coop && fwd_mfma32_supported(NP) && items32 >= (int64_t)8 * cus;
+    const int kind = g_kernel_kind.load(std::memory_order_relaxed);
+    if (kind == HMM_KERNEL_TILE16) {
+        if (!fwd_mfma_supported(NP)) return HMM_ERR_UNSUPPORTED;
+        coop = wide = false;
+    } else if (kind == HMM_KERNEL_TILE32) {
+        if (!fwd_mfma32_supported(NP)) return HMM_ERR_UNSUPPORTED;
+        coop = false;
+        wide = true;
+    } else if (kind == HMM_KERNEL_COOP) {
+        if (!fwd_coop_supported(NP)) return HMM_ERR_UNSUPPORTED;
+        coop = true;
+        wide = false;
+    }
     const int pr = prof_begin(st, HMM_PROF_FWD_BATCHED);
-    const hipError_t e = coop ? launch_fwd_coop(d, f, cus, st) : launch_fwd_mfma(d, f, cus, st);
+    const hipError_t e = coop ? launch_fwd_coop(d, f, cus, st)
+                              : (wide ? launch_fwd_mfma32(d, f, cus, st) : launch_fwd_mfma(d, f, cus, st));
     prof_end(st, pr);
     return e == hipSuccess ? HMM_OK : HMM_ERR_HIP;
 }
@@ -394,7 +411,7 @@ hmm_status hmm_workspace_error(const void *ws, hipStream_t stream, int32_t *firs
 }
 
 hmm_status hmm_select_kernel(int32_t kind) {
-    if (kind < HMM_KERNEL_AUTO || kind > HMM_KERNEL_BATCHED) return HMM_ERR_ARG;
+    if (kind < HMM_KERNEL_AUTO || kind > HMM_KERNEL_COOP) return HMM_ERR_ARG;
     g_kernel_kind.store(kind, std::memory_order_relaxed);
     return HMM_OK;
 }

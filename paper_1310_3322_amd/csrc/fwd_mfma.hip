@@ -95,22 +95,31 @@ __global__ void __launch_bounds__(FWD_WAVES * WAVE) k_fwd_mfma(DevPtrs d, FwdLau
                 if (bad) T = 0;
             }
             const int Tmax = __builtin_amdgcn_readfirstlane(wave_max_int(T));
+            // Shortest sequence of the tile: only its last steps can end a sequence.
+            const int Tmin = __builtin_amdgcn_readfirstlane(-wave_max_int(T > 0 ? -T : INT_MIN + 1));
             // Symbols travel in chunks of CH steps: the next chunk is loaded into
             // registers (nxt[u] = symbol of sequence sl at step t0 + 4 u + g) while
             // the current one is read from the wave's LDS buffer, laid out as
             // sym[u][lane] for the same (u, lane).  Past a sequence's end the
-            // loads repeat its last symbol (a valid address; never used).
+            // loads repeat its last symbol (a valid address; never used).  Symbols
+            // are checked and clamped to [0, M) once, when a chunk enters LDS.
             const int32_t *sbase = T > 0 ? d.symbols + off : d.symbols;
             const int tlim = T > 0 ? T - 1 : 0;
             int32_t nxt[CH / 4];
+            bool symbad = false;
             auto load_chunk = [&](int t0) {
 #pragma unroll
                 for (int u = 0; u < CH / 4; ++u) nxt[u] = sbase[min(t0 + 4 * u + g, tlim)];
             };
-            auto store_chunk = [&]() {
+            auto store_chunk = [&](int t0) {
                 wave_lds_sync();
 #pragma unroll
-                for (int u = 0; u < CH / 4; ++u) sym[u * WAVE + lane] = nxt[u];
+                for (int u = 0; u < CH / 4; ++u) {
+                    const int o = nxt[u];
+                    const bool ok = (unsigned)o < (unsigned)M;
+                    symbad |= (t0 + 4 * u + g < T) && !ok;
+                    sym[u * WAVE + lane] = ok ? o : 0;
+                }
                 wave_lds_sync();
             };
             auto read_sym = [&](int t) {
@@ -127,15 +136,12 @@ __global__ void __launch_bounds__(FWD_WAVES * WAVE) k_fwd_mfma(DevPtrs d, FwdLau
             int E = 0;
             int E_end = 0;        // sum of e_t over t < T - 1 (exponent part of log P)
             float c_end = 1.0f;   // c_T, the last step's sum (log P = E_end ln 2 + ln c_T)
-            bool symbad = false;
             if (Tmax > 0) {
                 load_chunk(0);
-                store_chunk();
+                store_chunk(0);
                 load_chunk(CH);
                 // the symbol and emission row of step t + 1 are fetched during step t
-                int o_nx = read_sym(0);
-                symbad |= (0 < T) && (o_nx < 0 || o_nx >= M);
-                o_nx = ((unsigned)o_nx < (unsigned)M) ? o_nx : 0;
+                const int o_nx = read_sym(0);
                 float4 b_nx[R];
                 if (BLDS)
                     gather_b_swz<R>(btl, o_nx, g, b_nx);
@@ -149,12 +155,10 @@ __global__ void __launch_bounds__(FWD_WAVES * WAVE) k_fwd_mfma(DevPtrs d, FwdLau
                     if (tn < Tmax) {
                         if ((tn % CH) == 0) {
                             // chunk tn / CH was prefetched a chunk ago
-                            store_chunk();
+                            store_chunk(tn);
                             load_chunk(tn + CH);
                         }
-                        int o = read_sym(tn);
-                        symbad |= (tn < T) && (o < 0 || o >= M);
-                        o = ((unsigned)o < (unsigned)M) ? o : 0;
+                        const int o = read_sym(tn);
                         if (BLDS)
                             gather_b_swz<R>(btl, o, g, b_nx);
                         else
@@ -167,7 +171,7 @@ __global__ void __launch_bounds__(FWD_WAVES * WAVE) k_fwd_mfma(DevPtrs d, FwdLau
                         tile_matvec<R>(af, acur, u);
                     int e;
                     const float cs = emit_and_rescale<R>(u, bcur, acur, e);
-                    if (t == T - 1) {
+                    if (t + 1 >= Tmin && t == T - 1) {
                         E_end = E;
                         c_end = cs;
                     }
@@ -183,6 +187,12 @@ __global__ void __launch_bounds__(FWD_WAVES * WAVE) k_fwd_mfma(DevPtrs d, FwdLau
                     }
                 }
             }
+            // symbols were checked by the lane that loaded them: combine the four
+            // lanes of each sequence
+            int sb = symbad ? 1 : 0;
+            sb |= __shfl_xor(sb, 16, WAVE);
+            sb |= __shfl_xor(sb, 32, WAVE);
+            symbad = sb != 0;
             if (has && g == 0) {
                 float r = (float)((double)E_end * LN2 + (double)logf(c_end));
                 if (bad || symbad) r = NAN;

@@ -1,0 +1,258 @@
+// Batched forward kernel on 32x32x2 FP32 MFMA (gfx950): tiles of 32 sequences.
+//
+// Same recursion and work distribution as fwd_mfma.hip (paper Sec. 2.7
+// "Forward"; the HMMs of the actions are independent, Sec. 3 item 3), with 32
+// length-sorted sequences of one model per wave.  The 32x32x2 result tile
+// gives each lane one sequence (lane % 32) and sixteen states of each 32-state
+// block r: 32 r + 8 (v / 4) + 4 (lane / 32) + v % 4, v = 0..15.  As in the
+// 16-sequence kernel the k-step (block r', register v) feeds half h = lane / 32
+// exactly the state its lanes hold in register v, so step t's results are step
+// t+1's B operand.  Per step a wave issues 16 R^2 MFMAs of 64 cycles against
+// the same per-sequence epilogue (emission product, one cross-half sum,
+// exponent, rescale), which halves the vector work per MFMA cycle compared with
+// 16-sequence tiles.  Used for recognition and log-likelihoods when tiles are
+// plentiful; the gradient keeps the 16-sequence kernels.
+#include <climits>
+
+#include "common.cuh"
+#include "kernels.h"
+
+namespace hmm {
+namespace {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+constexpr int T32 = 32;              // sequences per tile
+constexpr int CH32 = 16;             // symbols per staging chunk (8 per lane)
+constexpr int SYM32 = CH32 * T32;    // ints per wave buffer
+constexpr int WAVES32 = 4;           // waves per workgroup
+
+// B^T rows in LDS: float4 chunk c of row o at position c ^ (o & mask).
+template <int R>
+__device__ __forceinline__ int swz32(int o) { return o & (R == 1 ? 7 : 15); }
+
+template <int R, bool BLDS>
+__global__ void __launch_bounds__(WAVES32 * WAVE) k_fwd_mfma32(DevPtrs d, FwdLaunch f) {
+    constexpr int NP = 32 * R;
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int32_t sym_all[WAVES32 * SYM32];
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+    const int sl = lane & 31;        // sequence slot
+    const int h = lane >> 5;         // half: states 32 r + 8 q + 4 h + 0..3
+    const int K = f.K, N = f.N, M = f.M;
+    float *btl = (float *)smem;
+    int32_t *sym = sym_all + wave * SYM32;
+
+    const int G = gridDim.x;
+    const int k_first = G >= K ? (int)(blockIdx.x % K) : (int)blockIdx.x;
+    const int k_step = G >= K ? K : G;
+    for (int k = k_first; k < K; k += k_step) {
+        const int grp = f.all_pairs ? 0 : k;
+        const int gbeg = f.gstart[grp], gend = f.gstart[grp + 1];
+        const int ntiles = (gend - gbeg + T32 - 1) / T32;
+        const float *btk = f.bt + (size_t)k * M * NP;
+        if (BLDS) {
+            __syncthreads();
+            const int n4 = M * NP / 4;
+            for (int i = threadIdx.x; i < n4; i += blockDim.x) {
+                const int o = i / (NP / 4), c = i % (NP / 4);
+                ((float4 *)btl)[o * (NP / 4) + (c ^ swz32<R>(o))] = ((const float4 *)btk)[i];
+            }
+            __syncthreads();
+        }
+        if (ntiles == 0) continue;
+        // A operand fragments: af[r][rp][v] = A_k[32 rp + 8 (v/4) + 4 h + v%4][32 r + sl]
+        float af[R][R][16];
+        {
+            const float *Ak = d.A + (size_t)k * N * N;
+            const int lane_off = opaque(4 * h * N + sl);
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int rp = 0; rp < R; ++rp)
+#pragma unroll
+                    for (int v = 0; v < 16; ++v) {
+                        const int i = 32 * rp + 8 * (v / 4) + 4 * h + v % 4, j = 32 * r + sl;
+                        af[r][rp][v] =
+                            (i < N && j < N) ? Ak[lane_off + (32 * rp + 8 * (v / 4) + v % 4) * N + 32 * r] : 0.0f;
+                    }
+        }
+        const float *pik = d.pi + (size_t)k * N;
+
+        for (;;) {
+            int tile = 0;
+            if (lane == 0) tile = atomicAdd(&f.queue[k], 1);
+            tile = __builtin_amdgcn_readfirstlane(tile);
+            if (tile >= ntiles) break;
+
+            const int pos = gbeg + tile * T32 + sl;
+            const bool has = pos < gend;
+            const int seq = has ? f.perm[pos] : 0;
+            int32_t T = 0;
+            int64_t off = 0;
+            bool bad = false;
+            if (has) {
+                T = d.lengths[seq];
+                off = d.offsets[seq];
+                bad = seq_bad(T, off, f.max_len, f.total);
+                if (!f.all_pairs) {
+                    const int mk = d.model_of_seq[seq];
+                    bad |= (mk < 0 || mk >= K);
+                }
+                if (bad) T = 0;
+            }
+            const int Tmax = __builtin_amdgcn_readfirstlane(wave_max_int(T));
+            const int Tmin = __builtin_amdgcn_readfirstlane(-wave_max_int(T > 0 ? -T : INT_MIN + 1));
+            // Symbol chunks: nxt[u] = symbol of sequence sl at step t0 + 2 u + h,
+            // stored as sym[u][lane]; checked and clamped when a chunk enters LDS.
+            const int32_t *sbase = T > 0 ? d.symbols + off : d.symbols;
+            const int tlim = T > 0 ? T - 1 : 0;
+            int32_t nxt[CH32 / 2];
+            bool symbad = false;
+            auto load_chunk = [&](int t0) {
+#pragma unroll
+                for (int u = 0; u < CH32 / 2; ++u) nxt[u] = sbase[min(t0 + 2 * u + h, tlim)];
+            };
+            auto store_chunk = [&](int t0) {
+                wave_lds_sync();
+#pragma unroll
+                for (int u = 0; u < CH32 / 2; ++u) {
+                    const int o = nxt[u];
+                    const bool ok = (unsigned)o < (unsigned)M;
+                    symbad |= (t0 + 2 * u + h < T) && !ok;
+                    sym[u * WAVE + lane] = ok ? o : 0;
+                }
+                wave_lds_sync();
+            };
+            auto read_sym = [&](int t) {
+                const int pp = t % CH32;
+                return sym[(pp / 2) * WAVE + 32 * (pp % 2) + sl];
+            };
+            auto gather = [&](int o, float4 (&b)[R][4]) {
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int c = 8 * r + 2 * q + h;  // float4 chunk of states 32 r + 8 q + 4 h
+                        b[r][q] = BLDS ? ((const float4 *)btl)[o * (NP / 4) + (c ^ swz32<R>(o))]
+                                       : ((const float4 *)btk)[(size_t)o * (NP / 4) + c];
+                    }
+            };
+
+            float acur[R][16];
+            int E = 0, E_end = 0;
+            float c_end = 1.0f;
+            if (Tmax > 0) {
+                load_chunk(0);
+                store_chunk(0);
+                load_chunk(CH32);
+                float4 b_nx[R][4];
+                gather(read_sym(0), b_nx);
+                for (int t = 0; t < Tmax; ++t) {
+                    float4 bcur[R][4];
+#pragma unroll
+                    for (int r = 0; r < R; ++r)
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) bcur[r][q] = b_nx[r][q];
+                    const int tn = t + 1;
+                    if (tn < Tmax) {
+                        if ((tn % CH32) == 0) {
+                            store_chunk(tn);
+                            load_chunk(tn + CH32);
+                        }
+                        gather(read_sym(tn), b_nx);
+                    }
+                    float x[R][16];
+                    float part = 0.0f;
+                    {
+#pragma clang fp contract(off)
+                        if (t == 0) {
+#pragma unroll
+                            for (int r = 0; r < R; ++r)
+#pragma unroll
+                                for (int v = 0; v < 16; ++v) {
+                                    const int i = 32 * r + 8 * (v / 4) + 4 * h + v % 4;
+                                    x[r][v] = (i < N ? pik[i] : 0.0f) * bcur[r][v / 4][v % 4];
+                                }
+                        } else {
+                            floatx16 acc[R];
+#pragma unroll
+                            for (int r = 0; r < R; ++r) acc[r] = floatx16{};
+#pragma unroll
+                            for (int rp = 0; rp < R; ++rp)
+#pragma unroll
+                                for (int v = 0; v < 16; ++v)
+#pragma unroll
+                                    for (int r = 0; r < R; ++r)
+                                        acc[r] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[r][rp][v], acur[rp][v], acc[r],
+                                                                                      0, 0, 0);
+#pragma unroll
+                            for (int r = 0; r < R; ++r)
+#pragma unroll
+                                for (int v = 0; v < 16; ++v) x[r][v] = acc[r][v] * bcur[r][v / 4][v % 4];
+                        }
+#pragma unroll
+                        for (int r = 0; r < R; ++r)
+#pragma unroll
+                            for (int v = 0; v < 16; ++v) part = part + x[r][v];
+                    }
+                    auto q = __builtin_amdgcn_permlane32_swap(__float_as_uint(part), __float_as_uint(part), false, false);
+                    const float cs = __uint_as_float(q[0]) + __uint_as_float(q[1]);
+                    const int e = frexp_exp(cs);
+#pragma unroll
+                    for (int r = 0; r < R; ++r)
+#pragma unroll
+                        for (int v = 0; v < 16; ++v) acur[r][v] = ldexp_f(x[r][v], -e);
+                    if (t + 1 >= Tmin && t == T - 1) {
+                        E_end = E;
+                        c_end = cs;
+                    }
+                    E += e;
+                }
+            }
+            int sb = symbad ? 1 : 0;
+            sb |= __shfl_xor(sb, 32, WAVE);
+            if (has && h == 0) {
+                float r = (float)((double)E_end * LN2 + (double)logf(c_end));
+                if (bad || sb) r = NAN;
+                f.ll[f.all_pairs ? (size_t)seq * K + k : (size_t)seq] = r;
+                if (bad || sb) atomicMin(f.err, seq);
+            }
+        }
+    }
+}
+
+template <int R, bool BLDS>
+hipError_t launch_t(const DevPtrs &d, const FwdLaunch &f, int cu_count, hipStream_t st) {
+    const size_t lds = BLDS ? (size_t)f.M * 32 * R * sizeof(float) : 0;
+    auto kern = k_fwd_mfma32<R, BLDS>;
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    int per_cu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, WAVES32 * WAVE, lds);
+    if (e != hipSuccess) return e;
+    if (per_cu < 1) per_cu = 1;
+    int grid = cu_count * per_cu;
+    if (grid >= f.K) grid = (grid / f.K) * f.K;
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(WAVES32 * WAVE), lds, st, d, f);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+bool fwd_mfma32_supported(int NP) { return NP == 32 || NP == 64; }
+
+hipError_t launch_fwd_mfma32(const DevPtrs &d, const FwdLaunch &f, int cu_count, hipStream_t st) {
+    if (f.ckpt != nullptr) return hipErrorInvalidValue;
+    const bool blds = (size_t)f.M * f.NP * sizeof(float) <= 48 * 1024;
+    switch (f.NP) {
+        case 32: return blds ? launch_t<1, true>(d, f, cu_count, st) : launch_t<1, false>(d, f, cu_count, st);
+        case 64: return blds ? launch_t<2, true>(d, f, cu_count, st) : launch_t<2, false>(d, f, cu_count, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace hmm

@@ -65,6 +65,10 @@ struct FwdLaunch {
 bool fwd_mfma_supported(int NP);
 hipError_t launch_fwd_mfma(const DevPtrs &d, const FwdLaunch &f, int cu_count, hipStream_t st);
 
+// fwd_mfma32.hip: persistent length-sorted forward on 32x32x2 MFMA, 32-sequence tiles
+bool fwd_mfma32_supported(int NP);
+hipError_t launch_fwd_mfma32(const DevPtrs &d, const FwdLaunch &f, int cu_count, hipStream_t st);
+
 // fwd_coop.hip: cooperative-tile forward (one wave per 16-state block)
 bool fwd_coop_supported(int NP);
 hipError_t launch_fwd_coop(const DevPtrs &d, const FwdLaunch &f, int cu_count, hipStream_t st);

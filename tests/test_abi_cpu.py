@@ -105,8 +105,9 @@ def test_host_side_errors_enqueue_nothing(lib):
 
 
 def test_kernel_selector(lib):
-    assert lib.hmm_select_kernel(5) == -6
-    for k in (1, 2, 0):
+    assert lib.hmm_select_kernel(6) == -6
+    assert lib.hmm_select_kernel(-1) == -6
+    for k in (1, 2, 3, 4, 5, 0):
         assert lib.hmm_select_kernel(k) == 0
 
 

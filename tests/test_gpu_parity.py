@@ -77,6 +77,27 @@ def test_forward_parity(kernel, cfg, scale, own):
     assert rel_err(ll, ref) <= LL_TOL
 
 
+@pytest.mark.parametrize("N", [17, 32, 40, 64])
+def test_every_batched_family(N):
+    """Each forced forward family against the oracle, all pairs and own model."""
+    print(f"[case] families N={N}", flush=True)
+    rng = np.random.default_rng([10, N])
+    lengths = rng.integers(0, 70, size=75)
+    lengths[:4] = [0, 1, 2, 69]
+    for all_pairs in (True, False):
+        w = workloads.random_lengths_workload(rng, K=5, N=N, M=9, lengths=lengths, all_pairs=all_pairs, conc=0.6)
+        ref = oracle_ll(w, not all_pairs)
+        for kind in (hmm.KERNEL_TILE16, hmm.KERNEL_TILE32, hmm.KERNEL_COOP):
+            hmm.select_kernel(kind)
+            try:
+                ll = hmm.forward_loglik(problem(w)).cpu().numpy()
+            except hmm.HMMError as e:
+                assert e.status == -4  # the family does not take this N
+                continue
+            assert rel_err(ll, ref) <= LL_TOL, (kind, all_pairs)
+    hmm.select_kernel(hmm.KERNEL_AUTO)
+
+
 def test_brute_force_through_gpu():
     w = workloads.make_workload("brute")
     p = problem(w)
