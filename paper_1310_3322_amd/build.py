@@ -19,9 +19,12 @@ OBJDIR = os.path.join(ROOT, "_build", "hip")
 SOURCES = ["planner.hip", "fwd_plain.hip", "fwd_mfma.hip", "fwd_mfma32.hip", "fwd_coop.hip", "adj_mfma.hip", "adj_coop.hip", "abi.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-# Packed FP32 VALU instructions are disabled for all device code.
+# Packed FP32 VALU instructions are disabled for all device code.  MFMA
+# accumulators are allocated in ordinary VGPRs (not AGPRs), which saves the
+# copies between the two files in the per-step epilogues.
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
-         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-I", INCLUDE]
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-mllvm", "-amdgpu-mfma-vgpr-form", "-I", INCLUDE]
 
 
 def _compile(src: str) -> str:

@@ -176,6 +176,10 @@ __global__ void __launch_bounds__(WAVES32 * WAVE) k_fwd_mfma32(DevPtrs d, FwdLau
                                     x[r][v] = (i < N ? pik[i] : 0.0f) * bcur[r][v / 4][v % 4];
                                 }
                         } else {
+                            // Raised wave priority while the MFMA chain issues, so that a
+                            // wave entering its chain is not held behind another wave's
+                            // epilogue arithmetic.
+                            __builtin_amdgcn_s_setprio(1);
                             floatx16 acc[R];
 #pragma unroll
                             for (int r = 0; r < R; ++r) acc[r] = floatx16{};
@@ -187,6 +191,7 @@ __global__ void __launch_bounds__(WAVES32 * WAVE) k_fwd_mfma32(DevPtrs d, FwdLau
                                     for (int r = 0; r < R; ++r)
                                         acc[r] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[r][rp][v], acur[rp][v], acc[r],
                                                                                       0, 0, 0);
+                            __builtin_amdgcn_s_setprio(0);
 #pragma unroll
                             for (int r = 0; r < R; ++r)
 #pragma unroll
