@@ -146,6 +146,7 @@ Layout make_layout(const hmm_bank *b, const hmm_batch *q, int op) {
             L.seg_slots = coop ? adj_coop_slots(NP, M, K, device_cu_count()) : adj_mfma_slots(NP, M, K, device_cu_count());
             L.seg_stride = coop ? adj_coop_seg_stride(NP, q->max_len) : adj_mfma_seg_stride(NP, q->max_len);
             L.seg = take((size_t)L.seg_slots * L.seg_stride * sizeof(float));
+            if (coop) L.nbt = take((size_t)K * M * NP * sizeof(float));
         }
     }
     L.total = o;
@@ -348,13 +349,21 @@ hmm_status hmm_forward_backward_grad(const hmm_bank *bank, const hmm_batch *batc
         }
     }
     if (phase == 1) return HMM_OK;
+    const bool coop = grad_uses_coop(NP);
+    float *nbt = coop ? (float *)(w + L.nbt) : nullptr;
     launch_fill_f32(cnt_pi, (size_t)K * N, 0.0f, stream);
     launch_fill_f32(cnt_A, (size_t)K * N * N, 0.0f, stream);
-    launch_fill_f32(cnt_B, (size_t)K * N * M, 0.0f, stream);
+    if (coop)
+        launch_fill_f32(nbt, (size_t)K * M * NP, 0.0f, stream);
+    else
+        launch_fill_f32(cnt_B, (size_t)K * N * M, 0.0f, stream);
     int32_t *queue2 = (int32_t *)(w + L.queue) + K;
     launch_fill_i32(queue2, (size_t)K, 0, stream);
     if (hipGetLastError() != hipSuccess) return HMM_ERR_HIP;
-    if (S == 0) return HMM_OK;
+    if (S == 0) {
+        if (coop) launch_counts_transpose(nbt, cnt_B, K, N, M, NP, stream);
+        return hipGetLastError() == hipSuccess ? HMM_OK : HMM_ERR_HIP;
+    }
     AdjLaunch a;
     memset(&a, 0, sizeof(a));
     a.K = K;
@@ -380,10 +389,13 @@ hmm_status hmm_forward_backward_grad(const hmm_bank *bank, const hmm_batch *batc
     a.cnt_pi = cnt_pi;
     a.cnt_A = cnt_A;
     a.cnt_B = cnt_B;
+    a.nbt = nbt;
     const int pr = prof_begin(stream, HMM_PROF_ADJ_BATCHED);
-    const hipError_t e = grad_uses_coop(NP) ? launch_adj_coop(d, a, cus, stream) : launch_adj_mfma(d, a, cus, stream);
+    const hipError_t e = coop ? launch_adj_coop(d, a, cus, stream) : launch_adj_mfma(d, a, cus, stream);
     prof_end(stream, pr);
-    return e == hipSuccess ? HMM_OK : HMM_ERR_HIP;
+    if (e != hipSuccess) return HMM_ERR_HIP;
+    if (coop) launch_counts_transpose(nbt, cnt_B, K, N, M, NP, stream);
+    return hipGetLastError() == hipSuccess ? HMM_OK : HMM_ERR_HIP;
 }
 
 hmm_status hmm_softmax_rows(const float *logits, float *probs, int64_t rows, int32_t cols, hipStream_t stream) {

@@ -78,7 +78,7 @@ __global__ void __launch_bounds__(R * WAVE) k_adj_coop(DevPtrs d, AdjLaunch a) {
         const int gbeg = a.gstart[k], gend = a.gstart[k + 1];
         const int ntiles = (gend - gbeg + TILE - 1) / TILE;
         const float *btk = a.bt + (size_t)k * M * NP;
-        float *cnt_B = a.cnt_B + (size_t)k * N * M;
+        float *nbt = a.nbt + (size_t)k * M * NP;  // [M][NP] symbol-major counts of model k
         if (NBLDS) {
             __syncthreads();
             for (int i = threadIdx.x; i < M * NP; i += blockDim.x) nbl[i] = 0.0f;
@@ -257,7 +257,7 @@ __global__ void __launch_bounds__(R * WAVE) k_adj_coop(DevPtrs d, AdjLaunch a) {
                                     if (NBLDS)
                                         atomicAdd(&nbl[ot * NP + (i ^ (ot * 4 & swz))], gm);
                                     else
-                                        atomicAdd(&cnt_B[(size_t)i * M + ot], gm);
+                                        atomicAdd(&nbt[(size_t)ot * NP + i], gm);
                                     if (t == 0) atomicAdd(&a.cnt_pi[(size_t)k * N + i], gm);
                                 }
                             }
@@ -294,7 +294,7 @@ __global__ void __launch_bounds__(R * WAVE) k_adj_coop(DevPtrs d, AdjLaunch a) {
                 const int o = idx / NP, ic = idx % NP;
                 const int i = ic ^ (o * 4 & swz);
                 const float v = nbl[idx];
-                if (i < N && v != 0.0f) atomicAdd(&cnt_B[(size_t)i * M + o], v);
+                if (i < N && v != 0.0f) atomicAdd(&nbt[(size_t)o * NP + i], v);
             }
         }
     }

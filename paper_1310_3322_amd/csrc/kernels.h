@@ -21,6 +21,7 @@ struct Layout {
     size_t ckexp;    // int32 [S][nck] exponents of the checkpointed steps
     size_t flag;     // int32 [S] per sorted position: sequence has no finite likelihood
     size_t seg;      // float [slots][seg_stride] segment recompute buffers (gradient)
+    size_t nbt;      // float [K][M][NP] symbol-major emission counts (cooperative gradient)
     size_t total;
     int32_t nck;         // checkpoints per sequence slot
     int32_t seg_slots;   // persistent waves of the gradient kernel
@@ -40,6 +41,7 @@ void launch_plan(const DevPtrs &d, int K, int S, int groups, int max_len, int64_
                  unsigned char *ws, const Layout &L, hipStream_t st);
 void launch_transpose_b(const float *B, float *bt, int K, int N, int M, int NP, hipStream_t st);
 void launch_argmax(const float *ll, int32_t *labels, int S, int K, hipStream_t st);
+void launch_counts_transpose(const float *nbt, float *cnt_B, int K, int N, int M, int NP, hipStream_t st);
 void launch_fill_f32(float *p, size_t n, float v, hipStream_t st);
 void launch_fill_i32(int32_t *p, size_t n, int32_t v, hipStream_t st);
 void launch_softmax_rows(const float *z, float *p, int64_t rows, int cols, hipStream_t st);
@@ -89,6 +91,7 @@ struct AdjLaunch {
     int seg_slots;
     const float *weight;
     float *cnt_pi, *cnt_A, *cnt_B;
+    float *nbt;  // [K][M][NP] zeroed symbol-major emission counts (cooperative kernel)
 };
 bool adj_mfma_supported(int NP);
 // adj_coop.hip: cooperative-tile backward (one wave per 16-state block)

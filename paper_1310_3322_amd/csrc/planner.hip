@@ -108,6 +108,26 @@ __global__ void k_transpose_b(const float *B, float *bt, int N, int M, int NP) {
     }
 }
 
+// cnt_B[k][i][o] = nbt[k][o][i] for i < N: the emission counts accumulated
+// symbol-major (one contiguous NP-float row per symbol) back in the caller's
+// [K][N][M] layout.
+__global__ void k_counts_transpose(const float *nbt, float *cnt_B, int N, int M, int NP) {
+    __shared__ float tile[32][33];
+    const int k = blockIdx.z;
+    const int i0 = blockIdx.x * 32, o0 = blockIdx.y * 32;
+    const float *src = nbt + (size_t)k * M * NP;
+    float *dst = cnt_B + (size_t)k * N * M;
+    for (int r = threadIdx.y; r < 32; r += 8) {
+        const int o = o0 + r, i = i0 + threadIdx.x;
+        tile[r][threadIdx.x] = (o < M && i < N) ? src[(size_t)o * NP + i] : 0.0f;
+    }
+    __syncthreads();
+    for (int r = threadIdx.y; r < 32; r += 8) {
+        const int i = i0 + r, o = o0 + threadIdx.x;
+        if (i < N && o < M) dst[(size_t)i * M + o] = tile[threadIdx.x][r];
+    }
+}
+
 // label[s] = smallest k attaining the maximum of ll[s][:], NaN skipped, -1 if all NaN.
 __global__ void k_argmax(const float *ll, int32_t *labels, int S, int K) {
     int s = blockIdx.x * blockDim.x + threadIdx.x;
@@ -196,6 +216,11 @@ void launch_plan(const DevPtrs &d, int K, int S, int groups, int max_len, int64_
 void launch_transpose_b(const float *B, float *bt, int K, int N, int M, int NP, hipStream_t st) {
     dim3 grid((M + 31) / 32, (NP + 31) / 32, K);
     hipLaunchKernelGGL(k_transpose_b, grid, dim3(32, 8), 0, st, B, bt, N, M, NP);
+}
+
+void launch_counts_transpose(const float *nbt, float *cnt_B, int K, int N, int M, int NP, hipStream_t st) {
+    dim3 grid((N + 31) / 32, (M + 31) / 32, K);
+    hipLaunchKernelGGL(k_counts_transpose, grid, dim3(32, 8), 0, st, nbt, cnt_B, N, M, NP);
 }
 
 void launch_argmax(const float *ll, int32_t *labels, int S, int K, hipStream_t st) {
