@@ -69,3 +69,21 @@ def expected_counts(pi, A, B, o):
     n_A = [[x / P for x in row] for row in n_A]
     n_B = [[x / P for x in row] for row in n_B]
     return P, n_pi, n_A, n_B
+
+
+def best_paths(pi, A, B, o):
+    """(max_Q P(Q, O), every state path attaining it) by enumerating all N^T paths.
+
+    This is the quantity the Viterbi function of the paper's HMM stage decodes: the most
+    likely hidden state path for an observed symbol string."""
+    N = len(pi)
+    T = len(o)
+    best = None
+    arg = []
+    for q in itertools.product(range(N), repeat=T):
+        p = joint(pi, A, B, q, o)
+        if best is None or p > best:
+            best, arg = p, [q]
+        elif p == best:
+            arg.append(q)
+    return best, arg

@@ -276,6 +276,114 @@ int oracle_counts(int K, int N, int M, const double *pi, const double *A, const 
     return 0;
 }
 
+/*
+ * Most likely state path (the "Viterbi" function of Sec. 2.7), in the log
+ * domain, each sequence with its own model:
+ *   delta_1(i) = ln pi[i] + ln B[i][o_1]
+ *   delta_t(j) = max_i (delta_{t-1}(i) + ln A[i][j]) + ln B[j][o_t]        t >= 2
+ *   psi_t(j)   = the smallest i attaining that maximum
+ *   score      = max_j delta_T(j);  q_T = the smallest j attaining it;  q_{t-1} = psi_t(q_t)
+ * with ln 0 = -inf ("attaining" compares exactly, so when every candidate is
+ * -inf the smallest index is taken).  T = 0 gives score 0 and an empty path;
+ * an invalid symbol or length gives score NaN and a path of -1.
+ * margin[s] (may be NULL) receives the smallest gap, over the final choice and
+ * every backtracking choice on the returned path, between the chosen
+ * candidate and the best other candidate (+inf when N = 1 or T = 0): when it is
+ * large compared with the rounding of an implementation, that implementation
+ * must return the same path.
+ */
+int oracle_viterbi(int K, int N, int M, const double *pi, const double *A, const double *B, int S,
+                   const int32_t *symbols, const int64_t *offsets, const int32_t *lengths,
+                   const int32_t *model_of_seq, double *score, int32_t *path, double *margin, int nthreads) {
+    if (K <= 0 || N <= 0 || M <= 0 || S < 0 || !model_of_seq) return -1;
+    for (int s = 0; s < S; ++s)
+        if (model_of_seq[s] < 0 || model_of_seq[s] >= K) return -1;
+    int32_t Tmax = 0;
+    for (int s = 0; s < S; ++s)
+        if (lengths[s] > Tmax) Tmax = lengths[s];
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+#pragma omp parallel
+    {
+        size_t Tc = Tmax > 0 ? (size_t)Tmax : 1;
+        double *delta = (double *)malloc(sizeof(double) * Tc * N);
+        int32_t *psi = (int32_t *)malloc(sizeof(int32_t) * Tc * N);
+#pragma omp for schedule(dynamic, 1)
+        for (int s = 0; s < S; ++s) {
+            const int k = model_of_seq[s];
+            const double *pk = pi + (size_t)k * N;
+            const double *Ak = A + (size_t)k * N * N;
+            const double *Bk = B + (size_t)k * N * M;
+            const int32_t *o = symbols + offsets[s];
+            const int32_t T = lengths[s];
+            int32_t *q = path + offsets[s];
+            if (!seq_is_valid(M, o, T)) {
+                score[s] = NAN;
+                for (int32_t t = 0; t < T; ++t) q[t] = -1;
+                if (margin) margin[s] = NAN;
+                continue;
+            }
+            if (T == 0) {
+                score[s] = 0.0;
+                if (margin) margin[s] = INFINITY;
+                continue;
+            }
+            for (int i = 0; i < N; ++i) delta[i] = log(pk[i]) + log(Bk[(size_t)i * M + o[0]]);
+            for (int t = 1; t < T; ++t) {
+                const double *dp = delta + (size_t)(t - 1) * N;
+                double *dt = delta + (size_t)t * N;
+                for (int j = 0; j < N; ++j) {
+                    double best = -INFINITY;
+                    int arg = 0;
+                    for (int i = 0; i < N; ++i) {
+                        const double cand = dp[i] + log(Ak[(size_t)i * N + j]);
+                        if (cand > best) {
+                            best = cand;
+                            arg = i;
+                        }
+                    }
+                    dt[j] = best + log(Bk[(size_t)j * M + o[t]]);
+                    psi[(size_t)t * N + j] = arg;
+                }
+            }
+            const double *dl = delta + (size_t)(T - 1) * N;
+            double best = -INFINITY;
+            int arg = 0;
+            for (int j = 0; j < N; ++j)
+                if (dl[j] > best) {
+                    best = dl[j];
+                    arg = j;
+                }
+            score[s] = best;
+            q[T - 1] = arg;
+            for (int32_t t = T - 1; t > 0; --t) q[t - 1] = psi[(size_t)t * N + q[t]];
+            if (margin) {
+                /* gap between the chosen candidate and the best other one, at each choice */
+                double gap = INFINITY;
+                for (int j = 0; j < N; ++j)
+                    if (j != q[T - 1] && best - dl[j] < gap) gap = best - dl[j];
+                for (int32_t t = T - 1; t > 0; --t) {
+                    const double *dp = delta + (size_t)(t - 1) * N;
+                    const int j = q[t], c = q[t - 1];
+                    const double chosen = dp[c] + log(Ak[(size_t)c * N + j]);
+                    for (int i = 0; i < N; ++i) {
+                        if (i == c) continue;
+                        const double g = chosen - (dp[i] + log(Ak[(size_t)i * N + j]));
+                        if (g < gap) gap = g;
+                    }
+                }
+                margin[s] = gap;
+            }
+        }
+        free(delta);
+        free(psi);
+    }
+    return 0;
+}
+
 int oracle_max_threads(void) {
 #ifdef _OPENMP
     return omp_get_max_threads();

@@ -51,6 +51,9 @@ def _bind(lib):
     lib.oracle_counts.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp, _dp, _dp,
                                   ctypes.c_int, _i32p, _i64p, _i32p, _i32p, _dp, _dp,
                                   _dp, _dp, _dp, ctypes.c_int]
+    lib.oracle_viterbi.restype = ctypes.c_int
+    lib.oracle_viterbi.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp, _dp, _dp, ctypes.c_int,
+                                   _i32p, _i64p, _i32p, _i32p, _dp, _i32p, _dp, ctypes.c_int]
     lib.oracle_max_threads.restype = ctypes.c_int
     lib.oracle_max_threads.argtypes = []
     return lib
@@ -155,6 +158,31 @@ def counts(pi, A, B, symbols, offsets, lengths, model_of_seq, weights=None, nthr
     if rc != 0:
         raise ValueError("oracle_counts: bad arguments")
     return ll, npi, nA, nB
+
+
+def viterbi(pi, A, B, symbols, offsets, lengths, model_of_seq, nthreads: int = 0, lib=None):
+    """(score[S], path[sum T] int32, margin[S]) in FP64; each sequence decoded with its own model.
+
+    score = max over state paths of ln P(O, Q); path holds the decoded state of step t of
+    sequence s at offsets[s] + t (smallest-index rule on ties); margin is the smallest gap
+    between a choice on that path and its best alternative."""
+    pi, A, B = _f64(pi), _f64(A), _f64(B)
+    K, N = pi.shape
+    M = B.shape[2]
+    sym = np.ascontiguousarray(symbols, dtype=np.int32)
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    lens = np.ascontiguousarray(lengths, dtype=np.int32)
+    mos = np.ascontiguousarray(model_of_seq, dtype=np.int32)
+    S = lens.shape[0]
+    score = np.empty(S)
+    margin = np.empty(S)
+    path = np.full(sym.shape[0], -2, dtype=np.int32)
+    rc = (lib or _load()).oracle_viterbi(K, N, M, _ptr(pi, _dp), _ptr(A, _dp), _ptr(B, _dp), S, _ptr(sym, _i32p),
+                                         _ptr(off, _i64p), _ptr(lens, _i32p), _ptr(mos, _i32p), _ptr(score, _dp),
+                                         _ptr(path, _i32p), _ptr(margin, _dp), int(nthreads))
+    if rc != 0:
+        raise ValueError("oracle_viterbi: bad arguments")
+    return score, path, margin
 
 
 def softmax(logits) -> np.ndarray:

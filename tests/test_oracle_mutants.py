@@ -39,6 +39,14 @@ MUTANTS = {
     "zero_prob_not_inf": ("if (c == 0.0) return -INFINITY;", "if (c == 0.0) return 0.0;"),
     "argmax_last_tie": ("if (best < 0 || v > bv) {\n                best = k;\n                bv = v;\n            }\n        }\n        labels[s] = best;\n    }\n}\n\n/* Same",
                         "if (best < 0 || v >= bv) {\n                best = k;\n                bv = v;\n            }\n        }\n        labels[s] = best;\n    }\n}\n\n/* Same"),
+    "viterbi_transpose_A": ("const double cand = dp[i] + log(Ak[(size_t)i * N + j]);",
+                            "const double cand = dp[i] + log(Ak[(size_t)j * N + i]);"),
+    "viterbi_drop_first_emission": ("delta[i] = log(pk[i]) + log(Bk[(size_t)i * M + o[0]]);",
+                                    "delta[i] = log(pk[i]);"),
+    "viterbi_emission_time_shift": ("dt[j] = best + log(Bk[(size_t)j * M + o[t]]);",
+                                    "dt[j] = best + log(Bk[(size_t)j * M + o[t - 1]]);"),
+    "viterbi_step_tie_last": ("if (cand > best) {", "if (cand >= best) {"),
+    "viterbi_final_tie_last": ("if (dl[j] > best) {", "if (dl[j] >= best) {"),
 }
 
 
@@ -121,7 +129,27 @@ def pin_classify(lib):
     return labels.tolist() == [1, 1]
 
 
-PINS = [pin_bruteforce, pin_trace_invariant, pin_axiom, pin_impossible, pin_classify]
+def pin_viterbi(lib):
+    rng = _rng(4)
+    for N, M, T in [(3, 4, 6), (2, 3, 5), (3, 3, 1)]:
+        pi = workloads.dirichlet_rows(rng, (1,), N, 0.7)
+        A = workloads.dirichlet_rows(rng, (1, N), N, 0.7)
+        B = workloads.dirichlet_rows(rng, (1, N), M, 0.7)
+        o = rng.integers(0, M, size=T).astype(np.int32)
+        best, args = bruteforce.best_paths(pi[0].tolist(), A[0].tolist(), B[0].tolist(), o.tolist())
+        sc, path, _ = O.viterbi(pi, A, B, o, np.zeros(1, np.int64), np.array([T], np.int32), np.zeros(1, np.int32),
+                                lib=lib)
+        if not abs(sc[0] - math.log(best)) <= 1e-12 * max(1.0, abs(sc[0])) or tuple(path.tolist()) not in args:
+            return False
+    # every path ties under a uniform model: the smallest-index rule gives all zeros
+    N, M, T = 3, 2, 4
+    u = lambda *shape: np.full(shape, 1.0 / shape[-1])
+    _, path, _ = O.viterbi(u(1, N), u(1, N, N), u(1, N, M), np.array([0, 1, 1, 0], np.int32), np.zeros(1, np.int64),
+                           np.array([T], np.int32), np.zeros(1, np.int32), lib=lib)
+    return path.tolist() == [0] * T
+
+
+PINS = [pin_bruteforce, pin_trace_invariant, pin_axiom, pin_impossible, pin_classify, pin_viterbi]
 
 
 def test_real_oracle_passes_every_predicate():
