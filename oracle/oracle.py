@@ -219,3 +219,29 @@ def objective_from_logits(lpi, lA, lB, symbols, offsets, lengths, model_of_seq, 
     ll = forward(pi, A, B, symbols, offsets, lengths, model_of_seq, nthreads)
     w = np.ones_like(ll) if weights is None else _f64(weights)
     return float(np.sum(w * ll))
+
+
+def reestimate(n_rows, old_rows) -> np.ndarray:
+    """Baum-Welch M-step for one parameter array: each row of expected counts divided by
+    its sum (the maximum-likelihood row given the counts); a row whose counts sum to zero
+    (a state never visited, a model without sequences) keeps its old values."""
+    n = _f64(n_rows)
+    old = _f64(old_rows)
+    tot = n.sum(axis=-1, keepdims=True)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        new = n / tot
+    return np.where(tot > 0, new, old)
+
+
+def baum_welch(pi, A, B, symbols, offsets, lengths, model_of_seq, iters: int, nthreads: int = 0):
+    """EM for the bank (each sequence trains its own model): `iters` rounds of E-step
+    (expected counts of the current parameters) and M-step (reestimate).  Returns the
+    parameters after every round and the total log-likelihood before every round, FP64."""
+    pi, A, B = _f64(pi), _f64(A), _f64(B)
+    hist, lls = [], []
+    for _ in range(iters):
+        ll, npi, nA, nB = counts(pi, A, B, symbols, offsets, lengths, model_of_seq, nthreads=nthreads)
+        lls.append(float(np.sum(ll)))
+        pi, A, B = reestimate(npi, pi), reestimate(nA, A), reestimate(nB, B)
+        hist.append((pi, A, B))
+    return hist, lls
