@@ -16,8 +16,14 @@ time.  Printed as one JSON line, with:
   fwd_bwd       forward + adjoint (expected counts) on the gradient workload
                 (8 models, N=64, M=512, 8192 sequences, T in [100, 1000]),
                 6 algorithmic FLOPs per state-step;
-  large_states  the forward of the N=256 bank (16 models, M=1024, 16,384
-                sequences, T in [256, 4096], own model) on the cooperative kernel.
+  large_states  the N=256 bank (16 models, M=1024, 16,384 sequences, T in
+                [256, 4096], own model): forward, and forward + adjoint, on the
+                cooperative kernels;
+  latency       the small workloads, whose time is the serial chain of steps
+                (c1: one sequence of 64 steps; c2: 4096 sequences x 12 models,
+                T up to 400, with labels): microseconds per call, eager and as a
+                replayed HIP graph;
+  graph         the recognition step captured once as a HIP graph and replayed.
 """
 from __future__ import annotations
 
@@ -90,6 +96,50 @@ def time_steps(fn, steps, warmup, torch):
         fn()
     torch.cuda.synchronize()
     return (time.perf_counter() - t0) / max(steps, 1)
+
+
+def graph_ms(fn, reps, torch):
+    """Mean milliseconds of `reps` replays of fn captured as one HIP graph (after 3 warm-up replays)."""
+    fn()
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        fn()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        fn()
+    for _ in range(3):
+        g.replay()
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(reps):
+        g.replay()
+    t1.record()
+    torch.cuda.synchronize()
+    return t0.elapsed_time(t1) / reps
+
+
+def cpu_oracle_counts(w, target_s: float = 5.0):
+    """FP64 oracle forward + backward (expected counts) on every stride-th sequence in length order."""
+    from oracle import oracle as O
+    order = np.argsort(-w.lengths, kind="stable")
+    probe = w.subset(order[::256])
+    t0 = time.perf_counter()
+    O.counts(probe.pi, probe.A, probe.B, probe.symbols, probe.offsets, probe.lengths, probe.owner)
+    dt = max(time.perf_counter() - t0, 1e-3)
+    stride = int(np.clip(np.ceil(w.units() / (probe.units() / dt * target_s)), 1, 256))
+    sample = w.subset(order[::stride])
+    t0 = time.perf_counter()
+    O.counts(sample.pi, sample.A, sample.B, sample.symbols, sample.offsets, sample.lengths, sample.owner)
+    dt = time.perf_counter() - t0
+    return {"value": sample.units() / dt, "unit": "state-steps/s", "cores": O.max_threads(), "kind": "oracle",
+            "sample": f"every {stride}th sequence in length order ({sample.S} of {w.S}), own model, "
+                      f"{sample.units():.3e} state-steps in {dt:.1f} s, FP64 forward + backward counts"}
 
 
 def cpu_baseline(w, target_s: float = 15.0):
@@ -214,8 +264,12 @@ def main():
                              "value": u4 / gsec, "unit": "state-steps/s", "ms_per_step": gsec * 1e3,
                              "fwd_kernel_ms": f_ms / max(f_n, 1), "adj_kernel_ms": a_ms / max(a_n, 1),
                              "frac_fp32_peak": 6.0 * u4 / gsec / 1e12 / FP32_PEAK_TFLOPS}
+        if not args.no_cpu:
+            log("CPU oracle forward + backward on a c4 sample")
+            result["fwd_bwd"]["cpu_oracle"] = cpu_oracle_counts(w4)
+        del p4, ws4, cnt
 
-        log("forward of the N=256 bank (16 models, M=1024, 16384 sequences)")
+        log("the N=256 bank (16 models, M=1024, 16384 sequences): forward, then forward + adjoint")
         w5 = workloads.make_workload("c5")
         p5 = to_dev(w5, torch, own=True)
         ws5 = p5.workspace(hmm.OP_FORWARD)
@@ -224,12 +278,60 @@ def main():
         s5 = time_steps(lambda: hmm.forward_loglik(p5, out=ll5, ws=ws5), 3, 1, torch)
         k5_ms, k5_n = hmm.profile_read(hmm.PROF_FWD_BATCHED)
         hmm.profile_enable(False)
+        del ws5
         u5 = w5.units()
-        result["large_states"] = {"workload": "c5: 16 HMMs N=256 M=1024, 16384 sequences, T in [256,4096], own model, "
-                                              "forward (cooperative kernel)",
-                                  "value": u5 / s5, "unit": "state-steps/s", "ms_per_step": s5 * 1e3,
-                                  "kernel_ms": k5_ms / max(k5_n, 1),
-                                  "frac_fp32_peak": 2.0 * u5 / (k5_ms / max(k5_n, 1) / 1e3) / 1e12 / FP32_PEAK_TFLOPS}
+        large = {"workload": "c5: 16 HMMs N=256 M=1024 (A = Dirichlet(0.1) + band of 8), 16384 sequences, "
+                             "T in [256,4096], own model, cooperative kernels",
+                 "value": u5 / s5, "unit": "state-steps/s", "ms_per_step": s5 * 1e3,
+                 "kernel_ms": k5_ms / max(k5_n, 1),
+                 "frac_fp32_peak": 2.0 * u5 / (k5_ms / max(k5_n, 1) / 1e3) / 1e12 / FP32_PEAK_TFLOPS}
+        ws5g = p5.workspace(hmm.OP_GRAD)
+        cnt5 = (torch.empty((w5.K, w5.N), device="cuda"), torch.empty((w5.K, w5.N, w5.N), device="cuda"),
+                torch.empty((w5.K, w5.N, w5.M), device="cuda"))
+        g5 = lambda: hmm.forward_backward_grad(p5, phase=0, loglik=ll5, counts=cnt5, ws=ws5g)
+        g5()
+        torch.cuda.synchronize()
+        hmm.profile_enable(True)
+        gs5 = time_steps(g5, 2, 0, torch)
+        f5_ms, f5_n = hmm.profile_read(hmm.PROF_FWD_BATCHED)
+        a5_ms, a5_n = hmm.profile_read(hmm.PROF_ADJ_BATCHED)
+        hmm.profile_enable(False)
+        large["fwd_bwd"] = {"value": u5 / gs5, "unit": "state-steps/s", "ms_per_step": gs5 * 1e3,
+                            "fwd_kernel_ms": f5_ms / max(f5_n, 1), "adj_kernel_ms": a5_ms / max(a5_n, 1),
+                            "frac_fp32_peak": 6.0 * u5 / gs5 / 1e12 / FP32_PEAK_TFLOPS}
+        result["large_states"] = large
+        del p5, ws5g, cnt5
+
+        log("latency-bound workloads c1 and c2")
+        lat = {}
+        w1 = workloads.make_workload("c1")
+        p1 = to_dev(w1, torch, own=True)
+        ws1 = p1.workspace(hmm.OP_FORWARD)
+        ll1 = torch.empty(w1.S, dtype=torch.float32, device="cuda")
+        f1 = lambda: hmm.forward_loglik(p1, out=ll1, ws=ws1)
+        e1 = time_steps(f1, 50, 5, torch)
+        lat["c1"] = {"workload": "c1: 1 HMM N=8 M=16, one sequence T=64, forward",
+                     "us_per_call": e1 * 1e6, "us_per_call_graph": graph_ms(f1, 50, torch) * 1e3,
+                     "ns_per_step_graph": None}
+        lat["c1"]["ns_per_step_graph"] = lat["c1"]["us_per_call_graph"] * 1e3 / int(w1.lengths.max())
+        w2 = workloads.make_workload("c2")
+        p2 = to_dev(w2, torch, own=False)
+        b2 = p2.batch_without_models()
+        ws2 = p2.workspace(hmm.OP_CLASSIFY, b2)
+        lab2 = torch.empty(w2.S, dtype=torch.int32, device="cuda")
+        ll2 = torch.empty((w2.S, w2.K), dtype=torch.float32, device="cuda")
+        f2 = lambda: hmm.classify(p2, labels=lab2, loglik=ll2, ws=ws2)
+        e2 = time_steps(f2, 20, 3, torch)
+        g2 = graph_ms(f2, 20, torch)
+        lat["c2"] = {"workload": "c2: 12 HMMs N=16 M=64, 4096 sequences, T in [50,400], all pairs + labels",
+                     "us_per_call": e2 * 1e6, "us_per_call_graph": g2 * 1e3,
+                     "ns_per_step_graph": g2 * 1e6 / int(w2.lengths.max()),
+                     "state_steps_per_s_graph": w2.units() / (g2 / 1e3)}
+        result["latency"] = lat
+
+    if not args.no_extra:
+        result["graph"] = {"ms_per_step": graph_ms(step, 10, torch),
+                           "note": "the same recognition step captured once as a HIP graph, mean of 10 replays"}
 
     if args.copy_calibration:
         log("copy calibration: 4 x 512 MiB device-to-device")

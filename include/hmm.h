@@ -99,6 +99,7 @@ typedef struct {
 #define HMM_OP_FORWARD 0
 #define HMM_OP_CLASSIFY 1
 #define HMM_OP_GRAD 2
+#define HMM_OP_VITERBI 3
 
 /* Kernel family selector for the forward pass (process-wide; affects later
  * calls).  AUTO and BATCHED choose among the batched families by shape; the
@@ -150,6 +151,22 @@ hmm_status hmm_forward_backward_grad(const hmm_bank *bank, const hmm_batch *batc
                                      float *cnt_A, float *cnt_B, int32_t phase, void *ws,
                                      size_t ws_bytes, hipStream_t stream);
 
+/* Viterbi decoding (Sec. 2.7 "Viterbi"): the most likely state path of each
+ * sequence under its own model (batch->model_of_seq is required), in the log
+ * domain:
+ *   score[s] = max over state paths Q of ln P(O_s, Q | lambda_{m(s)})   [S], FP32
+ *   path[offsets[s] + t] = q_{t+1} of that path, t = 0 .. T_s - 1      [total_symbols], int32
+ * (the same layout as the symbols).  Ties are broken towards the smallest
+ * state index, both for the last state and for every back-pointer.
+ * T = 0 gives score 0; an impossible observation gives score -inf (and the
+ * path the tie rule produces); an invalid symbol or model index gives score
+ * NaN, path entries -1 and the error word in ws.  Supports N <= 64
+ * (HMM_ERR_UNSUPPORTED above).  The workspace (op HMM_OP_VITERBI) holds one
+ * byte of back-pointer per state and symbol: about total_symbols * 64 bytes
+ * at most. */
+hmm_status hmm_viterbi(const hmm_bank *bank, const hmm_batch *batch, float *score, int32_t *path,
+                       void *ws, size_t ws_bytes, hipStream_t stream);
+
 /* Row-wise softmax of FP32 logits: probs[r][c] = exp(z[r][c]) / sum_c' exp(z[r][c']).
  * The parameterisation of the gradient entry point's logits. */
 hmm_status hmm_softmax_rows(const float *logits, float *probs, int64_t rows, int32_t cols,
@@ -159,6 +176,16 @@ hmm_status hmm_softmax_rows(const float *logits, float *probs, int64_t rows, int
  * (row-wise softmax):  grad[r][c] = n[r][c] - p[r][c] * sum_c' n[r][c']. */
 hmm_status hmm_logit_grad(const float *n, const float *probs, float *grad, int64_t rows,
                           int32_t cols, hipStream_t stream);
+
+/* Baum-Welch M-step (Sec. 2.7 "BalmWelch") for one parameter array of `rows`
+ * rows of `cols` entries (pi: K rows of N; A: K*N rows of N; B: K*N rows of M):
+ *   out[r][c] = n[r][c] / sum_c' n[r][c']   when that sum is > 0,
+ *   out[r][c] = old[r][c]                   otherwise (a state or model without counts),
+ * where n holds the expected counts of hmm_forward_backward_grad with unit
+ * weights.  out may alias old (not n).  One EM iteration is one gradient call
+ * followed by this call for pi, A and B. */
+hmm_status hmm_reestimate_rows(const float *n, const float *old, float *out, int64_t rows, int32_t cols,
+                               hipStream_t stream);
 
 /* Synchronises `stream`, then reads the workspace error word: *first_bad_seq
  * is the smallest sequence index the last call flagged, or -1 if none. */
@@ -177,6 +204,7 @@ hmm_status hmm_select_kernel(int32_t kind);
 #define HMM_PROF_FWD_BATCHED 0   /* length-sorted MFMA forward            */
 #define HMM_PROF_ADJ_BATCHED 1   /* checkpointed MFMA backward            */
 #define HMM_PROF_FWD_PLAIN 2     /* plain per-pair forward                */
+#define HMM_PROF_VITERBI 3       /* max-plus decoding (without traceback)  */
 hmm_status hmm_profile_enable(int32_t on);
 hmm_status hmm_profile_read(int32_t kernel, double *total_ms, int32_t *launches);
 

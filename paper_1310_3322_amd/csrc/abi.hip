@@ -92,7 +92,7 @@ hmm_status check_pointers(const hmm_bank *b, const hmm_batch *q) {
 // groups: 1 when every sequence meets every model, else K
 int plan_groups(const hmm_bank *b, const hmm_batch *q, int op) {
     if (op == HMM_OP_CLASSIFY) return 1;
-    if (op == HMM_OP_GRAD) return b->K;
+    if (op == HMM_OP_GRAD || op == HMM_OP_VITERBI) return b->K;
     return q->model_of_seq ? b->K : 1;
 }
 
@@ -102,10 +102,18 @@ inline int padded_states(int N) { return N <= 64 ? pad16(N) : ((N + 31) / 32) * 
 
 // The gradient's checkpointing forward and its backward must come from the same
 // kernel family (the backward recomputes the forward bit for bit): one wave per
-// tile up to 48 states, one wave per 16-state block from 64 to 128 states.
+// tile up to 48 states, cooperative tiles (one wave per one or two 16-state
+// blocks) from 64 to 256 states.
 inline bool grad_uses_coop(int NP) { return NP >= 64; }
 
+// States padded for the decoder: its lane groups divide a wave.
+inline int viterbi_states(int N) { return N <= 16 ? 16 : N <= 32 ? 32 : N <= 64 ? 64 : 0; }
+
 bool batched_capable(const hmm_bank *b, const hmm_batch *q, int op) {
+    if (op == HMM_OP_VITERBI) {
+        const int64_t nbins = (int64_t)b->K * ((int64_t)q->max_len + 1);
+        return viterbi_states(b->N) > 0 && nbins <= MAX_PLAN_BINS;
+    }
     const int NP = padded_states(b->N);
     if (!fwd_mfma_supported(NP) && !fwd_coop_supported(NP)) return false;
     if (op == HMM_OP_GRAD && !(grad_uses_coop(NP) ? adj_coop_supported(NP) : adj_mfma_supported(NP))) return false;
@@ -122,7 +130,8 @@ Layout make_layout(const hmm_bank *b, const hmm_batch *q, int op) {
         o = align_up(o + bytes);
         return at;
     };
-    const int K = b->K, M = b->M, S = q->S, NP = padded_states(b->N);
+    const int K = b->K, M = b->M, S = q->S;
+    const int NP = op == HMM_OP_VITERBI ? viterbi_states(b->N) : padded_states(b->N);
     L.err = take(64);
     if (op == HMM_OP_CLASSIFY) L.ll = take((size_t)S * K * sizeof(float));
     if (op == HMM_OP_GRAD) L.ll = take((size_t)S * sizeof(float));
@@ -135,6 +144,7 @@ Layout make_layout(const hmm_bank *b, const hmm_batch *q, int op) {
         L.gstart = take((size_t)(groups + 1) * sizeof(int32_t));
         L.perm = take((size_t)S * sizeof(int32_t));
         L.bt = take((size_t)K * M * NP * sizeof(float));
+        if (op == HMM_OP_VITERBI) L.bp = take((size_t)q->total_symbols * NP);
         if (op == HMM_OP_GRAD) {
             int nck = 1;
             while ((int64_t)nck * nck < q->max_len) ++nck;
@@ -147,6 +157,7 @@ Layout make_layout(const hmm_bank *b, const hmm_batch *q, int op) {
             L.seg_stride = coop ? adj_coop_seg_stride(NP, q->max_len) : adj_mfma_seg_stride(NP, q->max_len);
             L.seg = take((size_t)L.seg_slots * L.seg_stride * sizeof(float));
             if (coop) L.nbt = take((size_t)K * M * NP * sizeof(float));
+            if (coop && adj_coop_streams(NP)) L.frag = take((size_t)K * 2 * NP * NP * sizeof(float));
         }
     }
     L.total = o;
@@ -265,7 +276,7 @@ hmm_status run_forward(const hmm_bank *b, const hmm_batch *q, int op, float *out
 extern "C" {
 
 size_t hmm_workspace_size(const hmm_bank *bank, const hmm_batch *batch, int op) {
-    if (op < HMM_OP_FORWARD || op > HMM_OP_GRAD) return 0;
+    if (op < HMM_OP_FORWARD || op > HMM_OP_VITERBI) return 0;
     if (check_shapes(bank, batch) != HMM_OK) return 0;
     return make_layout(bank, batch, op).total;
 }
@@ -390,11 +401,64 @@ hmm_status hmm_forward_backward_grad(const hmm_bank *bank, const hmm_batch *batc
     a.cnt_A = cnt_A;
     a.cnt_B = cnt_B;
     a.nbt = nbt;
+    if (coop && adj_coop_streams(NP)) {
+        float *frag = (float *)(w + L.frag);
+        launch_coop_frags(bank->A, frag, K, N, NP, stream);
+        a.frag = frag;
+    }
     const int pr = prof_begin(stream, HMM_PROF_ADJ_BATCHED);
     const hipError_t e = coop ? launch_adj_coop(d, a, cus, stream) : launch_adj_mfma(d, a, cus, stream);
     prof_end(stream, pr);
     if (e != hipSuccess) return HMM_ERR_HIP;
     if (coop) launch_counts_transpose(nbt, cnt_B, K, N, M, NP, stream);
+    return hipGetLastError() == hipSuccess ? HMM_OK : HMM_ERR_HIP;
+}
+
+hmm_status hmm_viterbi(const hmm_bank *bank, const hmm_batch *batch, float *score, int32_t *path, void *ws,
+                       size_t ws_bytes, hipStream_t stream) {
+    hmm_status rc = check_shapes(bank, batch);
+    if (rc != HMM_OK) return rc;
+    if ((rc = check_pointers(bank, batch)) != HMM_OK) return rc;
+    if (batch->S > 0 && (!batch->model_of_seq || !score)) return HMM_ERR_NULL;
+    if (batch->total_symbols > 0 && !path) return HMM_ERR_NULL;
+    const Layout L = make_layout(bank, batch, HMM_OP_VITERBI);
+    if ((rc = check_ws(ws, ws_bytes, L)) != HMM_OK) return rc;
+    if (!batched_capable(bank, batch, HMM_OP_VITERBI)) return HMM_ERR_UNSUPPORTED;
+    unsigned char *w = (unsigned char *)ws;
+    const int K = bank->K, N = bank->N, M = bank->M, S = batch->S, NP = viterbi_states(N);
+    DevPtrs d = dev_ptrs(bank, batch, true);
+    const int nbins = K * (batch->max_len + 1);
+    launch_plan(d, K, S, K, batch->max_len, batch->total_symbols, nbins, w, L, stream);
+    launch_log_transpose_b(bank->B, (float *)(w + L.bt), K, N, M, NP, stream);
+    if (hipGetLastError() != hipSuccess) return HMM_ERR_HIP;
+    VitLaunch v;
+    memset(&v, 0, sizeof(v));
+    v.K = K;
+    v.N = N;
+    v.M = M;
+    v.NP = NP;
+    v.S = S;
+    v.max_len = batch->max_len;
+    v.total = batch->total_symbols;
+    v.perm = (const int32_t *)(w + L.perm);
+    v.gstart = (const int32_t *)(w + L.gstart);
+    v.queue = (int32_t *)(w + L.queue);
+    v.err = (int32_t *)(w + L.err);
+    v.lnbt = (const float *)(w + L.bt);
+    v.bp = (uint8_t *)(w + L.bp);
+    v.score = score;
+    v.path = path;
+    const int pr = prof_begin(stream, HMM_PROF_VITERBI);
+    const hipError_t e = launch_viterbi(d, v, device_cu_count(), stream);
+    prof_end(stream, pr);
+    return e == hipSuccess ? HMM_OK : HMM_ERR_HIP;
+}
+
+hmm_status hmm_reestimate_rows(const float *n, const float *old, float *out, int64_t rows, int32_t cols,
+                               hipStream_t stream) {
+    if (rows < 0 || cols < 1) return HMM_ERR_SHAPE;
+    if (rows > 0 && (!n || !old || !out)) return HMM_ERR_NULL;
+    launch_reestimate_rows(n, old, out, rows, cols, stream);
     return hipGetLastError() == hipSuccess ? HMM_OK : HMM_ERR_HIP;
 }
 
@@ -437,7 +501,7 @@ hmm_status hmm_profile_enable(int32_t on) {
 
 hmm_status hmm_profile_read(int32_t kernel, double *total_ms, int32_t *launches) {
     if (!total_ms || !launches) return HMM_ERR_NULL;
-    if (kernel < HMM_PROF_FWD_BATCHED || kernel > HMM_PROF_FWD_PLAIN) return HMM_ERR_ARG;
+    if (kernel < HMM_PROF_FWD_BATCHED || kernel > HMM_PROF_VITERBI) return HMM_ERR_ARG;
     std::lock_guard<std::mutex> lk(g_prof_mu);
     double sum = 0.0;
     int n = 0;

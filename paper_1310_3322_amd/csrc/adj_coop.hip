@@ -1,5 +1,5 @@
 // Cooperative-tile backward (adjoint) kernel (gfx950): Baum-Welch E-step counts
-// for state counts that need one wave per 16-state block (N = 64 .. 128).
+// for state counts that need several waves per tile (N = 64 .. 256).
 //
 // Same mathematics as adj_mfma.hip (paper Sec. 2.7 "BalmWelch" E-step; scaled
 // beta recursion of the power-of-two-rescaled forward pass):
@@ -7,16 +7,27 @@
 //   betahat_t = A w_{t+1},  gamma_t = alphahat_t o betahat_t,
 //   n_pi += w_s gamma_1,  n_B[:, o_t] += w_s gamma_t,  C += w_s alphahat_t (x) w_{t+1},
 //   n_A = A o C.
-// One workgroup of R waves per tile of 16 length-sorted sequences of one model;
-// wave w owns the 16 states 16 w .. 16 w + 15.  For each sqrt(T) segment, last
-// to first, the workgroup recomputes alphahat from the checkpoint with the
-// cooperative forward step (bit-identical to the checkpointing forward), keeps
-// each lane's own states in a per-workgroup buffer in global memory, then walks
-// the segment backwards: per step one barrier; w_{t+1} of all NP states is
-// exchanged through LDS; wave w forms betahat for its rows (4 R MFMAs with the
-// A_k fragments), adds its rows of C += X^T W (4 R MFMAs, the 16 sequences as
-// the contraction axis, X transposed through a per-wave LDS tile), scatters
-// its rows of gamma into the emission counts, and writes its block of w_t.
+// One workgroup of R / BO waves per tile of 16 length-sorted sequences of one
+// model; wave w owns the BO 16-state blocks BO w .. BO w + BO - 1 (the
+// partition of the checkpointing forward, fwd_coop.hip).  For each sqrt(T)
+// segment, last to first, the workgroup recomputes alphahat from the
+// checkpoint with the cooperative forward step (bit-identical to the
+// checkpointing forward), keeps each lane's own states in a per-workgroup
+// buffer in global memory, then walks the segment backwards: per step one
+// barrier; w_{t+1} of all NP states is exchanged through LDS; wave w forms
+// betahat for its rows (4 R BO MFMAs), adds its rows of C += X^T W (4 R BO
+// MFMAs, the 16 sequences as the contraction axis, X transposed through a
+// per-wave LDS tile), scatters its rows of gamma into the emission counts, and
+// writes its blocks of w_t.
+//
+// Register budget.  A lane holds its rows of C (4 R BO floats) for the whole
+// tile.  Up to N = 128 (BO = 1) the MFMA fragments of A_k^T (recompute) and of
+// A_k (beta) stay in registers too; above that the three sets (3 N^2 floats per
+// tile) exceed the register file of a CU, so the fragments are streamed from a
+// pre-arranged copy in the workspace ([K][2][waves][R][64][BO] float4; 2 NP^2
+// floats per model, resident in the XCD's L2) a few blocks ahead of use.
+// Emission counts go to an LDS partial [M][NP] when it fits, else straight to
+// the symbol-major global buffer (one contiguous NP-float row per symbol).
 #include <climits>
 
 #include "common.cuh"
@@ -26,24 +37,66 @@
 namespace hmm {
 namespace {
 
-constexpr int ACH = 32;  // symbols per staging chunk
+constexpr int ACH = 32;      // symbols per staging chunk
+constexpr int STREAM_D = 2;  // blocks of streamed fragments in flight
 
-template <int R>
+// Blocks per wave: as in the forward (one up to 8 blocks, two above).
+constexpr int adj_bo(int R) { return R > 8 ? 2 : 1; }
+
+template <int R, int BO>
 struct AdjCoopShape {
     static constexpr int NP = 16 * R;
+    static constexpr int NW = R / BO;                        // waves per workgroup
     static constexpr int XROW = CoopShape<R>::XROW;
-    static constexpr int xch_floats = CoopShape<R>::floats;      // recompute exchange
-    static constexpr int w_floats = 2 * TILE * XROW;             // w exchange, double-buffered
-    static constexpr int at_floats = R * TILE * 17;              // per-wave transposition tiles
+    static constexpr int xch_floats = CoopShape<R>::floats;  // recompute exchange
+    static constexpr int w_floats = 2 * TILE * XROW;         // w exchange, double-buffered
+    static constexpr int at_floats = NW * BO * TILE * 17;    // per-wave transposition tiles
     static constexpr int small_bytes = (xch_floats + w_floats + at_floats) * 4 + 2 * ACH * TILE * 4;
 };
 
 __host__ __device__ inline int nb_swz(int NP) { return (NP & (NP - 1)) == 0 ? NP - 4 : 0; }
 
-template <int R, bool NBLDS>
-__global__ void __launch_bounds__(R * WAVE) k_adj_coop(DevPtrs d, AdjLaunch a) {
-    using SH = AdjCoopShape<R>;
+// The two fragment sets of a wave: resident in registers, or streamed.
+template <int R, int BO, bool STREAM>
+struct AdjFrags;
+
+template <int R, int BO>
+struct AdjFrags<R, BO, false> {
+    float af[BO][R][4], ab[BO][R][4];
+    __device__ __forceinline__ void load(const float *Ak, int N, int r0, int g, int sl, const float4 *, int) {
+        coop_load_fwd_fragments<R, BO>(af, Ak, N, r0, g, sl);
+        coop_load_bwd_fragments<R, BO>(ab, Ak, N, r0, g, sl);
+    }
+    __device__ __forceinline__ void fwd(const float *x, int e, int g, int sl, floatx4 (&u)[BO]) const {
+        coop_matvec<R, BO>(af, x, e, g, sl, u);
+    }
+    __device__ __forceinline__ void bwd(const float *x, int g, int sl, floatx4 (&u)[BO]) const {
+        coop_matvec<R, BO>(ab, x, 0, g, sl, u);
+    }
+};
+
+template <int R, int BO>
+struct AdjFrags<R, BO, true> {
+    const float4 *faf, *fab;
+    // frag_k: model k's two sets; lane_w: offset of this wave's and lane's first float4
+    __device__ __forceinline__ void load(const float *, int, int, int, int, const float4 *frag_k, int lane_w) {
+        constexpr size_t set = (size_t)R * R * WAVE;  // float4 per set (NW waves x R blocks x 64 lanes x BO)
+        faf = frag_k + lane_w;
+        fab = frag_k + set + lane_w;
+    }
+    __device__ __forceinline__ void fwd(const float *x, int e, int g, int sl, floatx4 (&u)[BO]) const {
+        coop_matvec_stream<R, BO, STREAM_D>(faf, x, e, g, sl, u);
+    }
+    __device__ __forceinline__ void bwd(const float *x, int g, int sl, floatx4 (&u)[BO]) const {
+        coop_matvec_stream<R, BO, STREAM_D>(fab, x, 0, g, sl, u);
+    }
+};
+
+template <int R, int BO, bool NBLDS, bool STREAM>
+__global__ void __launch_bounds__(R / BO * WAVE) k_adj_coop(DevPtrs d, AdjLaunch a) {
+    using SH = AdjCoopShape<R, BO>;
     constexpr int NP = SH::NP;
+    constexpr int NW = SH::NW;
     constexpr int XROW = SH::XROW;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ __align__(16) float xch[SH::xch_floats];
@@ -55,21 +108,23 @@ __global__ void __launch_bounds__(R * WAVE) k_adj_coop(DevPtrs d, AdjLaunch a) {
 
     const int lane = threadIdx.x & (WAVE - 1);
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+    const int r0 = BO * w;  // first owned 16-state block
     const int sl = lane & 15, g = lane >> 4;
     const int K = a.K, N = a.N, M = a.M;
     const int swz = nb_swz(NP);
     float *xbuf = xch;
     float *psum = xch + CoopShape<R>::x_floats;
-    float *atile = atile_all + w * TILE * 17;  // [16 s][17] own alphahat block, transposed reads
+    float *atile = atile_all + w * BO * TILE * 17;  // [BO][16 s][17] own alphahat blocks, transposed reads
 
-    // per-workgroup segment buffer: [Lcap][64 lanes][R waves] float4 alphahat + e + o
+    // per-workgroup segment buffer: alphahat [Lcap][NW][BO][64] float4, then e and o [Lcap][NW][64]
     const int slot = blockIdx.x;
     float *segf = a.seg + (size_t)slot * a.seg_stride;
-    const int Lcap = (int)(a.seg_stride / ((size_t)R * WAVE * 6));
+    const int Lcap = (int)(a.seg_stride / ((size_t)NW * WAVE * (4 * BO + 2)));
     float4 *seg_alpha = (float4 *)segf;
-    int32_t *seg_e = (int32_t *)(segf + (size_t)Lcap * R * WAVE * 4);
-    int32_t *seg_o = seg_e + (size_t)Lcap * R * WAVE;
-    auto sidx = [&](int tl) { return ((size_t)tl * R + w) * WAVE + lane; };
+    int32_t *seg_e = (int32_t *)(segf + (size_t)Lcap * NW * WAVE * 4 * BO);
+    int32_t *seg_o = seg_e + (size_t)Lcap * NW * WAVE;
+    auto aidx = [&](int tl, int b) { return (((size_t)tl * NW + w) * BO + b) * WAVE + lane; };
+    auto sidx = [&](int tl) { return ((size_t)tl * NW + w) * WAVE + lane; };
 
     const int G = gridDim.x;
     const int k_first = G >= K ? (int)(blockIdx.x % K) : (int)blockIdx.x;
@@ -86,12 +141,14 @@ __global__ void __launch_bounds__(R * WAVE) k_adj_coop(DevPtrs d, AdjLaunch a) {
         }
         const float *Ak = d.A + (size_t)k * N * N;
         if (ntiles > 0) {
-            float af[1][R][4], ab[1][R][4];
-            coop_load_fwd_fragments<R, 1>(af, Ak, N, w, g, sl);
-            coop_load_bwd_fragments<R, 1>(ab, Ak, N, w, g, sl);
-            floatx4 C[R];  // rows 16 w + 4 g + v, columns 16 rj + sl
+            AdjFrags<R, BO, STREAM> fr;
+            fr.load(Ak, N, r0, g, sl, STREAM ? (const float4 *)a.frag + (size_t)k * 2 * R * R * WAVE : nullptr,
+                    (w * R * WAVE + lane) * BO);
+            floatx4 C[BO][R];  // rows 16 (r0 + b) + 4 g + v, columns 16 rj + sl
 #pragma unroll
-            for (int rj = 0; rj < R; ++rj) C[rj] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+            for (int b = 0; b < BO; ++b)
+#pragma unroll
+                for (int rj = 0; rj < R; ++rj) C[b][rj] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
 
             for (;;) {
                 if (threadIdx.x == 0) tile_sh = atomicAdd(&a.queue[k], 1);
@@ -123,7 +180,6 @@ __global__ void __launch_bounds__(R * WAVE) k_adj_coop(DevPtrs d, AdjLaunch a) {
                 const int32_t *sbase = T > 0 ? d.symbols + off : d.symbols;
                 const int tlim = T > 0 ? T - 1 : 0;
                 float m_last = 1.0f;  // m_T of this lane's sequence (set in the last segment)
-                float wn[4] = {0.0f, 0.0f, 0.0f, 0.0f};  // own block of w_{t+1}
                 // the w exchange buffer of "step Tmax" starts at zero
                 for (int i = threadIdx.x; i < TILE * XROW; i += blockDim.x) wex[(Tmax & 1) * TILE * XROW + i] = 0.0f;
 
@@ -154,31 +210,37 @@ __global__ void __launch_bounds__(R * WAVE) k_adj_coop(DevPtrs d, AdjLaunch a) {
                         load_chunk(t0 + 2 * ACH);
                     }
                     // ---- recompute alphahat over [t0, t1) from checkpoint j
-                    float x[1][4];
-                    if (t0 < T) {
-                        const float4 q = *(const float4 *)&a.ckpt[((size_t)pos * a.nck + j) * NP + 16 * w + 4 * g];
-                        x[0][0] = q.x;
-                        x[0][1] = q.y;
-                        x[0][2] = q.z;
-                        x[0][3] = q.w;
-                    } else {
-                        x[0][0] = x[0][1] = x[0][2] = x[0][3] = 0.0f;
+                    float x[BO][4];
+#pragma unroll
+                    for (int b = 0; b < BO; ++b) {
+                        if (t0 < T) {
+                            const float4 q =
+                                *(const float4 *)&a.ckpt[((size_t)pos * a.nck + j) * NP + 16 * (r0 + b) + 4 * g];
+                            x[b][0] = q.x;
+                            x[b][1] = q.y;
+                            x[b][2] = q.z;
+                            x[b][3] = q.w;
+                        } else {
+                            x[b][0] = x[b][1] = x[b][2] = x[b][3] = 0.0f;
+                        }
                     }
                     int e_prev = (t0 < T) ? a.ckexp[(size_t)pos * a.nck + j] : 0;
-                    *(float4 *)&xbuf[(t0 & 1) * TILE * XROW + sl * XROW + 16 * w + 4 * g] =
-                        float4{x[0][0], x[0][1], x[0][2], x[0][3]};
-                    {
+#pragma unroll
+                    for (int b = 0; b < BO; ++b) {
+                        *(float4 *)&xbuf[(t0 & 1) * TILE * XROW + sl * XROW + 16 * (r0 + b) + 4 * g] =
+                            float4{x[b][0], x[b][1], x[b][2], x[b][3]};
                         // block shares of sum_i alphahat_{t0}(i), in the forward's summation order
                         float part;
                         {
 #pragma clang fp contract(off)
-                            part = ((x[0][0] + x[0][1]) + x[0][2]) + x[0][3];
+                            part = ((x[b][0] + x[b][1]) + x[b][2]) + x[b][3];
                         }
                         part = sum_row_groups(part);
-                        if (g == 0) psum[(t0 & 1) * R * TILE + w * TILE + sl] = part;
+                        if (g == 0) psum[(t0 & 1) * R * TILE + (r0 + b) * TILE + sl] = part;
                     }
                     __syncthreads();
-                    seg_alpha[sidx(0)] = float4{x[0][0], x[0][1], x[0][2], x[0][3]};
+#pragma unroll
+                    for (int b = 0; b < BO; ++b) seg_alpha[aidx(0, b)] = float4{x[b][0], x[b][1], x[b][2], x[b][3]};
                     seg_e[sidx(0)] = e_prev;
                     seg_o[sidx(0)] = read_sym(t0);
                     if (t0 == T - 1) m_last = coop_step_sum<R>(psum + (t0 & 1) * R * TILE, sl);
@@ -188,9 +250,10 @@ __global__ void __launch_bounds__(R * WAVE) k_adj_coop(DevPtrs d, AdjLaunch a) {
                             // finish step t - 1: its sum and exponent, store alphahat_{t-1}
                             const float cs = coop_step_sum<R>(psum + ((t - 1) & 1) * R * TILE, sl);
                             e = frexp_exp(cs);
-                            const float al[4] = {ldexp_f(x[0][0], -e), ldexp_f(x[0][1], -e), ldexp_f(x[0][2], -e),
-                                                 ldexp_f(x[0][3], -e)};
-                            seg_alpha[sidx(t - 1 - t0)] = float4{al[0], al[1], al[2], al[3]};
+#pragma unroll
+                            for (int b = 0; b < BO; ++b)
+                                seg_alpha[aidx(t - 1 - t0, b)] = float4{ldexp_f(x[b][0], -e), ldexp_f(x[b][1], -e),
+                                                                        ldexp_f(x[b][2], -e), ldexp_f(x[b][3], -e)};
                             seg_e[sidx(t - 1 - t0)] = e;
                             if (t - 1 == T - 1) m_last = ldexp_f(cs, -e);
                         }
@@ -201,92 +264,122 @@ __global__ void __launch_bounds__(R * WAVE) k_adj_coop(DevPtrs d, AdjLaunch a) {
                         }
                         const int o = read_sym(t);
                         seg_o[sidx(t - t0)] = o;
-                        const float4 b = *(const float4 *)&btk[(size_t)o * NP + 16 * w + 4 * g];
-                        floatx4 u[1];
+                        floatx4 u[BO];
                         // the checkpoint row enters unscaled (exponent 0), later rows by 2^-e
-                        coop_matvec<R, 1>(af, xbuf + ((t - 1) & 1) * TILE * XROW, (t == t0 + 1) ? 0 : e, g, sl, u);
-                        const float part = coop_emit(u[0], b, x[0]);
-                        *(float4 *)&xbuf[(t & 1) * TILE * XROW + sl * XROW + 16 * w + 4 * g] =
-                            float4{x[0][0], x[0][1], x[0][2], x[0][3]};
-                        if (g == 0) psum[(t & 1) * R * TILE + w * TILE + sl] = part;
+                        fr.fwd(xbuf + ((t - 1) & 1) * TILE * XROW, (t == t0 + 1) ? 0 : e, g, sl, u);
+#pragma unroll
+                        for (int b = 0; b < BO; ++b) {
+                            const float4 bb = *(const float4 *)&btk[(size_t)o * NP + 16 * (r0 + b) + 4 * g];
+                            const float part = coop_emit(u[b], bb, x[b]);
+                            *(float4 *)&xbuf[(t & 1) * TILE * XROW + sl * XROW + 16 * (r0 + b) + 4 * g] =
+                                float4{x[b][0], x[b][1], x[b][2], x[b][3]};
+                            if (g == 0) psum[(t & 1) * R * TILE + (r0 + b) * TILE + sl] = part;
+                        }
                         __syncthreads();
                     }
                     // ---- backward through the segment
                     for (int t = t1 - 1; t >= t0; --t) {
                         const int tl = t - t0;
-                        const float4 aq = seg_alpha[sidx(tl)];
-                        const float al[4] = {aq.x, aq.y, aq.z, aq.w};
+                        float al[BO][4];
+#pragma unroll
+                        for (int b = 0; b < BO; ++b) {
+                            const float4 aq = seg_alpha[aidx(tl, b)];
+                            al[b][0] = aq.x;
+                            al[b][1] = aq.y;
+                            al[b][2] = aq.z;
+                            al[b][3] = aq.w;
+                        }
                         const int et = seg_e[sidx(tl)];
                         const int ot = seg_o[sidx(tl)];
                         const bool live = act && t < T;
                         const bool trans = act && t + 1 < T;
                         const float *wrow = wex + ((t + 1) & 1) * TILE * XROW;  // w_{t+1}, all states
-                        float be[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+                        float be[BO][4] = {};
                         if (t + 1 < Tmax) {
-                            floatx4 u[1];
-                            coop_matvec<R, 1>(ab, wrow, 0, g, sl, u);
+                            floatx4 u[BO];
+                            fr.bwd(wrow, g, sl, u);
 #pragma unroll
-                            for (int v = 0; v < 4; ++v) be[v] = u[0][v];
-                            // C[own rows][all] += X^T W: X (own block) through the wave's tile
+                            for (int b = 0; b < BO; ++b)
 #pragma unroll
-                            for (int v = 0; v < 4; ++v) atile[sl * 17 + 4 * g + v] = trans ? wgt * al[v] : 0.0f;
+                                for (int v = 0; v < 4; ++v) be[b][v] = u[b][v];
+                            // C[own rows][all] += X^T W: X (own blocks) through the wave's tiles
+#pragma unroll
+                            for (int b = 0; b < BO; ++b)
+#pragma unroll
+                                for (int v = 0; v < 4; ++v)
+                                    atile[(b * TILE + sl) * 17 + 4 * g + v] = trans ? wgt * al[b][v] : 0.0f;
                             wave_lds_sync();
 #pragma unroll
                             for (int q = 0; q < 4; ++q) {
                                 const int s = 4 * q + g;
-                                const float xa = atile[s * 17 + sl];
+                                float xa[BO];
+#pragma unroll
+                                for (int b = 0; b < BO; ++b) xa[b] = atile[(b * TILE + s) * 17 + sl];
 #pragma unroll
                                 for (int rj = 0; rj < R; ++rj) {
                                     const float wb = wrow[s * XROW + 16 * rj + sl];
-                                    C[rj] = __builtin_amdgcn_mfma_f32_16x16x4f32(xa, wb, C[rj], 0, 0, 0);
+#pragma unroll
+                                    for (int b = 0; b < BO; ++b)
+                                        C[b][rj] = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[b], wb, C[b][rj], 0, 0, 0);
                                 }
+                                if (STREAM) __builtin_amdgcn_sched_barrier(0);
                             }
                             wave_lds_sync();
                         }
                         if (t == T - 1) {
                             const float inv = 1.0f / m_last;
 #pragma unroll
-                            for (int v = 0; v < 4; ++v) be[v] = inv;
+                            for (int b = 0; b < BO; ++b)
+#pragma unroll
+                                for (int v = 0; v < 4; ++v) be[b][v] = inv;
                         }
                         if (live) {
 #pragma unroll
-                            for (int v = 0; v < 4; ++v) {
-                                const int i = 16 * w + 4 * g + v;
-                                const float gm = wgt * al[v] * be[v];
-                                if (i < N) {
-                                    if (NBLDS)
-                                        atomicAdd(&nbl[ot * NP + (i ^ (ot * 4 & swz))], gm);
-                                    else
-                                        atomicAdd(&nbt[(size_t)ot * NP + i], gm);
-                                    if (t == 0) atomicAdd(&a.cnt_pi[(size_t)k * N + i], gm);
+                            for (int b = 0; b < BO; ++b)
+#pragma unroll
+                                for (int v = 0; v < 4; ++v) {
+                                    const int i = 16 * (r0 + b) + 4 * g + v;
+                                    const float gm = wgt * al[b][v] * be[b][v];
+                                    if (i < N) {
+                                        if (NBLDS)
+                                            atomicAdd(&nbl[ot * NP + (i ^ (ot * 4 & swz))], gm);
+                                        else
+                                            atomicAdd(&nbt[(size_t)ot * NP + i], gm);
+                                        if (t == 0) atomicAdd(&a.cnt_pi[(size_t)k * N + i], gm);
+                                    }
                                 }
-                            }
                         }
                         // w_t = b_t o betahat_t 2^-e_t; zero where the sequence has ended or
                         // takes no part (its values may be inf / NaN and w enters the
                         // contraction over sequences of C)
-                        const float4 b = *(const float4 *)&btk[(size_t)ot * NP + 16 * w + 4 * g];
-                        wn[0] = live ? ldexp_f(b.x * be[0], -et) : 0.0f;
-                        wn[1] = live ? ldexp_f(b.y * be[1], -et) : 0.0f;
-                        wn[2] = live ? ldexp_f(b.z * be[2], -et) : 0.0f;
-                        wn[3] = live ? ldexp_f(b.w * be[3], -et) : 0.0f;
-                        *(float4 *)&wex[(t & 1) * TILE * XROW + sl * XROW + 16 * w + 4 * g] =
-                            float4{wn[0], wn[1], wn[2], wn[3]};
+#pragma unroll
+                        for (int b = 0; b < BO; ++b) {
+                            const float4 bb = *(const float4 *)&btk[(size_t)ot * NP + 16 * (r0 + b) + 4 * g];
+                            const float wn0 = live ? ldexp_f(bb.x * be[b][0], -et) : 0.0f;
+                            const float wn1 = live ? ldexp_f(bb.y * be[b][1], -et) : 0.0f;
+                            const float wn2 = live ? ldexp_f(bb.z * be[b][2], -et) : 0.0f;
+                            const float wn3 = live ? ldexp_f(bb.w * be[b][3], -et) : 0.0f;
+                            *(float4 *)&wex[(t & 1) * TILE * XROW + sl * XROW + 16 * (r0 + b) + 4 * g] =
+                                float4{wn0, wn1, wn2, wn3};
+                        }
                         __syncthreads();
                     }
                 }
             }
             // n_A = A o C for this wave's rows of model k
 #pragma unroll
-            for (int rj = 0; rj < R; ++rj)
+            for (int b = 0; b < BO; ++b)
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int i = 16 * w + 4 * g + v, jj = 16 * rj + sl;
-                    if (i < N && jj < N) {
-                        const float c = C[rj][v];
-                        if (c != 0.0f) atomicAdd(&a.cnt_A[((size_t)k * N + i) * N + jj], Ak[(size_t)i * N + jj] * c);
+                for (int rj = 0; rj < R; ++rj)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int i = 16 * (r0 + b) + 4 * g + v, jj = 16 * rj + sl;
+                        if (i < N && jj < N) {
+                            const float c = C[b][rj][v];
+                            if (c != 0.0f)
+                                atomicAdd(&a.cnt_A[((size_t)k * N + i) * N + jj], Ak[(size_t)i * N + jj] * c);
+                        }
                     }
-                }
         }
         if (NBLDS) {
             __syncthreads();
@@ -304,16 +397,18 @@ constexpr size_t COOP_LDS_LIMIT = 160 * 1024;
 
 template <int R>
 bool use_nb_lds(int M) {
-    return (size_t)M * 16 * R * 4 + AdjCoopShape<R>::small_bytes + 64 <= COOP_LDS_LIMIT;
+    constexpr int BO = adj_bo(R);
+    return (size_t)M * 16 * R * 4 + AdjCoopShape<R, BO>::small_bytes + 64 <= COOP_LDS_LIMIT;
 }
 
 template <int R, bool NBLDS>
 int grid_t(int M, int cu_count, int K) {
-    auto kern = k_adj_coop<R, NBLDS>;
+    constexpr int BO = adj_bo(R);
+    auto kern = k_adj_coop<R, BO, NBLDS, (BO > 1)>;
     const size_t dyn = NBLDS ? (size_t)M * 16 * R * 4 : 0;
     if (dyn > 0) (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, R * WAVE, dyn) != hipSuccess || per_cu < 1)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, R / BO * WAVE, dyn) != hipSuccess || per_cu < 1)
         per_cu = 1;
     int grid = cu_count * per_cu;
     if (K > 0 && grid >= K) grid = (grid / K) * K;
@@ -327,24 +422,60 @@ int grid_r(int M, int cu_count, int K) {
 
 template <int R>
 hipError_t launch_r(const DevPtrs &d, const AdjLaunch &a, int cu_count, hipStream_t st) {
-    const int grid = grid_r<R>(a.M, cu_count, a.K);
+    constexpr int BO = adj_bo(R);
+    constexpr bool STREAM = BO > 1;
+    if (STREAM && a.frag == nullptr) return hipErrorInvalidValue;
+    const int grid = persistent_grid(grid_r<R>(a.M, cu_count, a.K), tile_bound(a.S, a.K, false, TILE), 1, a.K);
     if (grid > a.seg_slots) return hipErrorInvalidValue;
     if (use_nb_lds<R>(a.M))
-        k_adj_coop<R, true><<<grid, R * WAVE, (size_t)a.M * 16 * R * 4, st>>>(d, a);
+        k_adj_coop<R, BO, true, STREAM><<<grid, R / BO * WAVE, (size_t)a.M * 16 * R * 4, st>>>(d, a);
     else
-        k_adj_coop<R, false><<<grid, R * WAVE, 0, st>>>(d, a);
+        k_adj_coop<R, BO, false, STREAM><<<grid, R / BO * WAVE, 0, st>>>(d, a);
     return hipGetLastError();
+}
+
+// Streamed fragments of model k: set 0 (A_k^T, recompute) and set 1 (A_k,
+// beta), float4 index (((set * NW + w) * R + rp) * 64 + lane) * BO + b with
+// components v = 0..3:
+//   set 0: A_k[16 rp + 4 g + v][16 (BO w + b) + sl],  set 1: A_k[16 (BO w + b) + sl][16 rp + 4 g + v]
+// (g = lane / 16, sl = lane % 16; zero outside N x N).
+__global__ void k_coop_frags(const float *A, float4 *frag, int N, int R, int BO) {
+    const int k = blockIdx.y;
+    const size_t per_model = (size_t)2 * R * R * WAVE;  // float4
+    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= per_model) return;
+    const int NW = R / BO;
+    const int b = (int)(idx % BO);
+    const int lane = (int)((idx / BO) % WAVE);
+    const int rp = (int)((idx / ((size_t)BO * WAVE)) % R);
+    const int w = (int)((idx / ((size_t)BO * WAVE * R)) % NW);
+    const int set = (int)(idx / ((size_t)BO * WAVE * R * NW));
+    const int g = lane >> 4, sl = lane & 15;
+    const float *Ak = A + (size_t)k * N * N;
+    float v4[4];
+    for (int v = 0; v < 4; ++v) {
+        const int i = set == 0 ? 16 * rp + 4 * g + v : 16 * (BO * w + b) + sl;
+        const int j = set == 0 ? 16 * (BO * w + b) + sl : 16 * rp + 4 * g + v;
+        v4[v] = (i < N && j < N) ? Ak[(size_t)i * N + j] : 0.0f;
+    }
+    frag[(size_t)k * per_model + idx] = float4{v4[0], v4[1], v4[2], v4[3]};
 }
 
 }  // namespace
 
-bool adj_coop_supported(int NP) { return NP == 64 || NP == 96 || NP == 128; }
+bool adj_coop_supported(int NP) { return NP >= 64 && NP <= 256 && NP % 32 == 0; }
+
+bool adj_coop_streams(int NP) { return adj_bo(NP / 16) > 1; }
 
 int adj_coop_slots(int NP, int M, int K, int cu_count) {
     switch (NP / 16) {
         case 4: return grid_r<4>(M, cu_count, K);
         case 6: return grid_r<6>(M, cu_count, K);
         case 8: return grid_r<8>(M, cu_count, K);
+        case 10: return grid_r<10>(M, cu_count, K);
+        case 12: return grid_r<12>(M, cu_count, K);
+        case 14: return grid_r<14>(M, cu_count, K);
+        case 16: return grid_r<16>(M, cu_count, K);
         default: return 0;
     }
 }
@@ -352,7 +483,16 @@ int adj_coop_slots(int NP, int M, int K, int cu_count) {
 int64_t adj_coop_seg_stride(int NP, int max_len) {
     int L = 1;
     while ((int64_t)L * L < max_len) ++L;
-    return (int64_t)L * (NP / 16) * WAVE * 6;  // float4 alphahat + e + o per lane and wave
+    const int R = NP / 16, BO = adj_bo(R);
+    // float4 alphahat per owned block + e + o, per lane and wave
+    return (int64_t)L * (R / BO) * WAVE * (4 * BO + 2);
+}
+
+void launch_coop_frags(const float *A, float *frag, int K, int N, int NP, hipStream_t st) {
+    const int R = NP / 16, BO = adj_bo(R);
+    const size_t per_model = (size_t)2 * R * R * WAVE;
+    dim3 grid((unsigned)((per_model + 255) / 256), (unsigned)K);
+    hipLaunchKernelGGL(k_coop_frags, grid, dim3(256), 0, st, A, (float4 *)frag, N, R, BO);
 }
 
 hipError_t launch_adj_coop(const DevPtrs &d, const AdjLaunch &a, int cu_count, hipStream_t st) {
@@ -360,6 +500,10 @@ hipError_t launch_adj_coop(const DevPtrs &d, const AdjLaunch &a, int cu_count, h
         case 4: return launch_r<4>(d, a, cu_count, st);
         case 6: return launch_r<6>(d, a, cu_count, st);
         case 8: return launch_r<8>(d, a, cu_count, st);
+        case 10: return launch_r<10>(d, a, cu_count, st);
+        case 12: return launch_r<12>(d, a, cu_count, st);
+        case 14: return launch_r<14>(d, a, cu_count, st);
+        case 16: return launch_r<16>(d, a, cu_count, st);
         default: return hipErrorInvalidValue;
     }
 }

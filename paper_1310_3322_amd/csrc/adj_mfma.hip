@@ -98,9 +98,7 @@ __global__ void __launch_bounds__(WAVES * WAVE) k_adj_mfma(DevPtrs d, AdjLaunch 
                 for (int rj = 0; rj < R; ++rj) C[ri][rj] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
 
             for (;;) {
-                int tile = 0;
-                if (lane == 0) tile = atomicAdd(&a.queue[k], 1);
-                tile = __builtin_amdgcn_readfirstlane(tile);
+                const int tile = wave_pop(&a.queue[k]);
                 if (tile >= ntiles) break;
 
                 const int pos = gbeg + tile * TILE + sl;
@@ -362,7 +360,8 @@ int grid_for(int M, int cu_count, int K, bool set_attr, int *waves) {
 template <int R>
 hipError_t launch_r(const DevPtrs &d, const AdjLaunch &a, int cu_count, hipStream_t st) {
     int waves = 4;
-    const int grid = grid_for<R>(a.M, cu_count, a.K, true, &waves);
+    const int full = grid_for<R>(a.M, cu_count, a.K, true, &waves);
+    const int grid = persistent_grid(full, tile_bound(a.S, a.K, false, TILE), waves, a.K);
     if (grid * waves > a.seg_slots) return hipErrorInvalidValue;
     switch (pick_variant<R>(a.M)) {
         case 0:

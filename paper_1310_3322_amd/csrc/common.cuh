@@ -51,6 +51,20 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Next item of a per-wave work queue: the old value of *head, the same in every
+// lane, after adding 1.  Every lane takes part in the atomic (lane 0 adds 1, the
+// others 0) and the result is read from the first lane, so the pop is not under
+// a lane-dependent branch.  A pop written as `if (lane == 0) x = atomicAdd(..);
+// x = readfirstlane(x)` may be merged by the compiler with a later branch on the
+// same lane predicate (for example an output written by lane 0), rotating the
+// loop so that the other lanes re-enter it without lane 0 and never leave.
+// Call with every lane of the wave active.
+__device__ __forceinline__ int wave_pop(int32_t *head) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int v = atomicAdd(head, lane == 0 ? 1 : 0);
+    return __builtin_amdgcn_readfirstlane(v);
+}
+
 // Returns v unchanged but opaque to the optimiser, so that address arithmetic
 // derived from it is not hoisted out of the enclosing loop (which would pin one
 // register pair per unrolled load for the whole kernel).

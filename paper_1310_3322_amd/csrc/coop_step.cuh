@@ -101,6 +101,49 @@ __device__ __forceinline__ void coop_matvec(const float (&f)[BO][R][4], const fl
     }
 }
 
+// Fragments streamed from memory instead of registers, for state counts whose
+// fragments and count accumulators do not fit the register file together.
+// fr points at this lane's fragments of block rp = 0 of the wave, laid out
+// [R rp][64 lanes][BO] float4 (v = 0..3 in the float4); the fragments of block
+// rp + D are loaded while the MFMAs of block rp issue (each load's offset is
+// opaque, so that its address is formed next to it rather than hoisted out of
+// the step loop as one register pair per block).  Same chains and order as
+// coop_matvec, so the results are bit-identical to it.
+template <int R, int BO, int D>
+__device__ __forceinline__ void coop_matvec_stream(const float4 *fr, const float *xrow_base, int e, int g, int sl,
+                                                   floatx4 (&u)[BO]) {
+#pragma unroll
+    for (int b = 0; b < BO; ++b) u[b] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+    const float *row = xrow_base + sl * CoopShape<R>::XROW + 4 * g;
+    float4 ring[D][BO];
+#pragma unroll
+    for (int dd = 0; dd < D; ++dd)
+#pragma unroll
+        for (int b = 0; b < BO; ++b) ring[dd][b] = fr[opaque(dd * WAVE * BO + b)];
+    float4 qn = *(const float4 *)&row[0];
+#pragma unroll
+    for (int rp = 0; rp < R; ++rp) {
+        const float4 q = qn;
+        if (rp + 1 < R) qn = *(const float4 *)&row[16 * (rp + 1)];
+        float4 f[BO];
+#pragma unroll
+        for (int b = 0; b < BO; ++b) f[b] = ring[rp % D][b];
+        if (rp + D < R) {
+#pragma unroll
+            for (int b = 0; b < BO; ++b) ring[rp % D][b] = fr[opaque((rp + D) * WAVE * BO + b)];
+        }
+        const float in[4] = {ldexp_f(q.x, -e), ldexp_f(q.y, -e), ldexp_f(q.z, -e), ldexp_f(q.w, -e)};
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+#pragma unroll
+            for (int b = 0; b < BO; ++b) {
+                const float a = v == 0 ? f[b].x : v == 1 ? f[b].y : v == 2 ? f[b].z : f[b].w;
+                u[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, in[v], u[b], 0, 0, 0);
+            }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
 // alpha~ block = u o b, its share of the per-sequence sum (identical in the 4
 // lanes of a sequence).
 __device__ __forceinline__ float coop_emit(const floatx4 &u, const float4 &b, float (&x)[4]) {

@@ -81,9 +81,7 @@ __global__ void __launch_bounds__(WAVES32 * WAVE) k_fwd_mfma32(DevPtrs d, FwdLau
         const float *pik = d.pi + (size_t)k * N;
 
         for (;;) {
-            int tile = 0;
-            if (lane == 0) tile = atomicAdd(&f.queue[k], 1);
-            tile = __builtin_amdgcn_readfirstlane(tile);
+            const int tile = wave_pop(&f.queue[k]);
             if (tile >= ntiles) break;
 
             const int pos = gbeg + tile * T32 + sl;
@@ -240,8 +238,7 @@ hipError_t launch_t(const DevPtrs &d, const FwdLaunch &f, int cu_count, hipStrea
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, WAVES32 * WAVE, lds);
     if (e != hipSuccess) return e;
     if (per_cu < 1) per_cu = 1;
-    int grid = cu_count * per_cu;
-    if (grid >= f.K) grid = (grid / f.K) * f.K;
+    const int grid = persistent_grid(cu_count * per_cu, tile_bound(f.S, f.K, f.all_pairs, T32), WAVES32, f.K);
     hipLaunchKernelGGL(kern, dim3(grid), dim3(WAVES32 * WAVE), lds, st, d, f);
     return hipGetLastError();
 }

@@ -22,11 +22,35 @@ struct Layout {
     size_t flag;     // int32 [S] per sorted position: sequence has no finite likelihood
     size_t seg;      // float [slots][seg_stride] segment recompute buffers (gradient)
     size_t nbt;      // float [K][M][NP] symbol-major emission counts (cooperative gradient)
+    size_t frag;     // float4 [K][2][NP^2 / 4] streamed MFMA fragments (cooperative gradient, NP > 128)
+    size_t bp;       // uint8 [total][NP] Viterbi back-pointers (bt then holds ln B transposed)
     size_t total;
     int32_t nck;         // checkpoints per sequence slot
     int32_t seg_slots;   // persistent waves of the gradient kernel
     int64_t seg_stride;  // floats per segment slot
 };
+
+// Persistent launches: the occupancy-limited grid, reduced when a host-side
+// bound on the work items (tiles) is far smaller, so that a small batch does
+// not send every resident wave to the same queue counters (same-address
+// atomics serialise in L2); then rounded down to a multiple of K when it is at
+// least K, so that every model gets the same number of workgroups.
+inline int persistent_grid(int occ_grid, int64_t items_bound, int items_per_wg, int K) {
+    int grid = occ_grid;
+    const int64_t need = (items_bound + items_per_wg - 1) / items_per_wg;
+    if (need * 2 < grid) {
+        const int64_t floor_k = K < occ_grid ? K : occ_grid;
+        grid = (int)(need > floor_k ? need : floor_k);
+    }
+    if (K > 0 && grid >= K) grid = grid / K * K;
+    return grid > 0 ? grid : 1;
+}
+
+// Upper bound on the tiles of `tile` sequences the planner can form.
+inline int64_t tile_bound(int S, int K, bool all_pairs, int tile) {
+    const int64_t t = ((int64_t)S + tile - 1) / tile;
+    return all_pairs ? t * K : t + K;
+}
 
 struct DevPtrs {
     const float *pi, *A, *B;
@@ -46,6 +70,7 @@ void launch_fill_f32(float *p, size_t n, float v, hipStream_t st);
 void launch_fill_i32(int32_t *p, size_t n, int32_t v, hipStream_t st);
 void launch_softmax_rows(const float *z, float *p, int64_t rows, int cols, hipStream_t st);
 void launch_logit_grad(const float *n, const float *p, float *g, int64_t rows, int cols, hipStream_t st);
+void launch_reestimate_rows(const float *n, const float *old, float *out, int64_t rows, int cols, hipStream_t st);
 
 // fwd_plain.hip: one workgroup per (sequence, model) pair
 hipError_t launch_fwd_plain(const DevPtrs &d, int K, int N, int M, int S, int all_pairs, int max_len,
@@ -91,16 +116,34 @@ struct AdjLaunch {
     int seg_slots;
     const float *weight;
     float *cnt_pi, *cnt_A, *cnt_B;
-    float *nbt;  // [K][M][NP] zeroed symbol-major emission counts (cooperative kernel)
+    float *nbt;         // [K][M][NP] zeroed symbol-major emission counts (cooperative kernel)
+    const float *frag;  // pre-arranged fragments when the cooperative kernel streams them
 };
 bool adj_mfma_supported(int NP);
 // adj_coop.hip: cooperative-tile backward (one wave per 16-state block)
 bool adj_coop_supported(int NP);
+bool adj_coop_streams(int NP);  // fragments streamed from the workspace (launch_coop_frags first)
+void launch_coop_frags(const float *A, float *frag, int K, int N, int NP, hipStream_t st);
 int adj_coop_slots(int NP, int M, int K, int cu_count);
 int64_t adj_coop_seg_stride(int NP, int max_len);
 hipError_t launch_adj_coop(const DevPtrs &d, const AdjLaunch &a, int cu_count, hipStream_t st);
 int adj_mfma_slots(int NP, int M, int K, int cu_count);
 int64_t adj_mfma_seg_stride(int NP, int max_len);
 hipError_t launch_adj_mfma(const DevPtrs &d, const AdjLaunch &a, int cu_count, hipStream_t st);
+
+// viterbi.hip: max-plus decoding of each sequence with its own model, and its traceback
+struct VitLaunch {
+    int K, N, M, NP, S, max_len;
+    int64_t total;
+    const int32_t *perm, *gstart;
+    int32_t *queue, *err;
+    const float *lnbt;  // [K][M][NP] ln B transposed, -inf beyond N
+    uint8_t *bp;        // [total][NP] back-pointers
+    float *score;       // [S]
+    int32_t *path;      // [total]
+};
+bool viterbi_supported(int NP);
+void launch_log_transpose_b(const float *B, float *lnbt, int K, int N, int M, int NP, hipStream_t st);
+hipError_t launch_viterbi(const DevPtrs &d, const VitLaunch &v, int cu_count, hipStream_t st);
 
 }  // namespace hmm

@@ -108,6 +108,25 @@ __global__ void k_transpose_b(const float *B, float *bt, int N, int M, int NP) {
     }
 }
 
+// lnbt[k][o][i] = ln B[k][i][o] for i < N, -inf for N <= i < NP (the emission
+// table of the log-domain decoder).
+__global__ void k_log_transpose_b(const float *B, float *lnbt, int N, int M, int NP) {
+    __shared__ float tile[32][33];
+    const int k = blockIdx.z;
+    const int o0 = blockIdx.x * 32, i0 = blockIdx.y * 32;
+    const float *Bk = B + (size_t)k * N * M;
+    float *dst = lnbt + (size_t)k * M * NP;
+    for (int r = threadIdx.y; r < 32; r += 8) {
+        const int i = i0 + r, o = o0 + threadIdx.x;
+        tile[r][threadIdx.x] = (i < N && o < M) ? logf(Bk[(size_t)i * M + o]) : -INFINITY;
+    }
+    __syncthreads();
+    for (int r = threadIdx.y; r < 32; r += 8) {
+        const int o = o0 + r, i = i0 + threadIdx.x;
+        if (o < M && i < NP) dst[(size_t)o * NP + i] = tile[threadIdx.x][r];
+    }
+}
+
 // cnt_B[k][i][o] = nbt[k][o][i] for i < N: the emission counts accumulated
 // symbol-major (one contiguous NP-float row per symbol) back in the caller's
 // [K][N][M] layout.
@@ -188,6 +207,25 @@ __global__ void k_logit_grad(const float *n, const float *p, float *g, int64_t r
     for (int c = lane; c < cols; c += WAVE) gr[c] = nr[c] - pr[c] * s;
 }
 
+// Baum-Welch M-step for one parameter array: row r of the expected counts
+// divided by its sum; a row whose counts sum to zero keeps its old values.
+__global__ void k_reestimate_rows(const float *n, const float *old, float *out, int64_t rows, int cols) {
+    int64_t r = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+    int lane = threadIdx.x % WAVE;
+    if (r >= rows) return;
+    const float *nr = n + r * cols;
+    const float *orow = old + r * cols;
+    float *dst = out + r * cols;
+    float s = 0.0f;
+    for (int c = lane; c < cols; c += WAVE) s += nr[c];
+    s = wave_sum(s);
+    if (s > 0.0f) {
+        for (int c = lane; c < cols; c += WAVE) dst[c] = nr[c] / s;
+    } else {
+        for (int c = lane; c < cols; c += WAVE) dst[c] = orow[c];
+    }
+}
+
 inline int blocks_for(int64_t n, int bs) { return (int)((n + bs - 1) / bs); }
 
 }  // namespace
@@ -218,6 +256,11 @@ void launch_transpose_b(const float *B, float *bt, int K, int N, int M, int NP, 
     hipLaunchKernelGGL(k_transpose_b, grid, dim3(32, 8), 0, st, B, bt, N, M, NP);
 }
 
+void launch_log_transpose_b(const float *B, float *lnbt, int K, int N, int M, int NP, hipStream_t st) {
+    dim3 grid((M + 31) / 32, (NP + 31) / 32, K);
+    hipLaunchKernelGGL(k_log_transpose_b, grid, dim3(32, 8), 0, st, B, lnbt, N, M, NP);
+}
+
 void launch_counts_transpose(const float *nbt, float *cnt_B, int K, int N, int M, int NP, hipStream_t st) {
     dim3 grid((N + 31) / 32, (M + 31) / 32, K);
     hipLaunchKernelGGL(k_counts_transpose, grid, dim3(32, 8), 0, st, nbt, cnt_B, N, M, NP);
@@ -243,6 +286,11 @@ void launch_fill_i32(int32_t *p, size_t n, int32_t v, hipStream_t st) {
 
 void launch_softmax_rows(const float *z, float *p, int64_t rows, int cols, hipStream_t st) {
     if (rows > 0) hipLaunchKernelGGL(k_softmax_rows, dim3(blocks_for(rows, 4)), dim3(256), 0, st, z, p, rows, cols);
+}
+
+void launch_reestimate_rows(const float *n, const float *old, float *out, int64_t rows, int cols, hipStream_t st) {
+    if (rows > 0)
+        hipLaunchKernelGGL(k_reestimate_rows, dim3(blocks_for(rows, 4)), dim3(256), 0, st, n, old, out, rows, cols);
 }
 
 void launch_logit_grad(const float *n, const float *p, float *g, int64_t rows, int cols, hipStream_t st) {

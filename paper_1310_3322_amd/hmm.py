@@ -20,12 +20,12 @@ LIB_PATH = os.path.join(_PKG, "libhmm_mi355x.so")
 HMM_OK = 0
 STATUS = {0: "HMM_OK", -1: "HMM_ERR_NULL", -2: "HMM_ERR_SHAPE", -3: "HMM_ERR_WORKSPACE",
           -4: "HMM_ERR_UNSUPPORTED", -5: "HMM_ERR_HIP", -6: "HMM_ERR_ARG"}
-OP_FORWARD, OP_CLASSIFY, OP_GRAD = 0, 1, 2
+OP_FORWARD, OP_CLASSIFY, OP_GRAD, OP_VITERBI = 0, 1, 2, 3
 KERNEL_AUTO, KERNEL_PLAIN, KERNEL_BATCHED, KERNEL_TILE16, KERNEL_TILE32, KERNEL_COOP = 0, 1, 2, 3, 4, 5
 EXPORTS = ("hmm_workspace_size", "hmm_forward_loglik", "hmm_classify", "hmm_forward_backward_grad",
-           "hmm_softmax_rows", "hmm_logit_grad", "hmm_workspace_error", "hmm_select_kernel",
+           "hmm_viterbi", "hmm_reestimate_rows", "hmm_softmax_rows", "hmm_logit_grad", "hmm_workspace_error", "hmm_select_kernel",
            "hmm_profile_enable", "hmm_profile_read", "hmm_status_string")
-PROF_FWD_BATCHED, PROF_ADJ_BATCHED, PROF_FWD_PLAIN = 0, 1, 2
+PROF_FWD_BATCHED, PROF_ADJ_BATCHED, PROF_FWD_PLAIN, PROF_VITERBI = 0, 1, 2, 3
 
 
 class HMMError(RuntimeError):
@@ -67,6 +67,10 @@ def load_library(path: str = LIB_PATH):
     lib.hmm_classify.argtypes = [BP, QP, P, P, P, ctypes.c_size_t, P]
     lib.hmm_forward_backward_grad.restype = st
     lib.hmm_forward_backward_grad.argtypes = [BP, QP, P, P, P, P, P, ctypes.c_int32, P, ctypes.c_size_t, P]
+    lib.hmm_viterbi.restype = st
+    lib.hmm_viterbi.argtypes = [BP, QP, P, P, P, ctypes.c_size_t, P]
+    lib.hmm_reestimate_rows.restype = st
+    lib.hmm_reestimate_rows.argtypes = [P, P, P, ctypes.c_int64, ctypes.c_int32, P]
     lib.hmm_softmax_rows.restype = st
     lib.hmm_softmax_rows.argtypes = [P, P, ctypes.c_int64, ctypes.c_int32, P]
     lib.hmm_logit_grad.restype = st
@@ -235,6 +239,67 @@ def forward_backward_grad(p: Problem, seq_weight: Optional[torch.Tensor] = None,
         _ptr(c[2]), int(phase), _ptr(ws), ws.numel(), _stream(stream))
     _check("hmm_forward_backward_grad", rc)
     return loglik, counts, ws
+
+
+def viterbi(p: Problem, score: Optional[torch.Tensor] = None, path: Optional[torch.Tensor] = None,
+            ws: Optional[torch.Tensor] = None, stream=None):
+    """Most likely state path of each sequence under its own model.
+
+    Returns (score [S] = max_Q ln P(O, Q), path [total_symbols] int32 in the layout of the symbols)."""
+    if p.model_of_seq is None:
+        raise ValueError("Viterbi decoding needs model_of_seq")
+    dev = p.pi.device
+    if score is None:
+        score = torch.empty(p.S, dtype=torch.float32, device=dev)
+    if path is None:
+        path = torch.empty(p.total_symbols, dtype=torch.int32, device=dev)
+    _dev(score, torch.float32, "score")
+    _dev(path, torch.int32, "path")
+    if score.shape[0] != p.S or path.shape[0] != p.total_symbols:
+        raise ValueError("score must be [S] and path [total_symbols]")
+    if ws is None:
+        ws = p.workspace(OP_VITERBI)
+    rc = load_library().hmm_viterbi(ctypes.byref(p.bank), ctypes.byref(p.batch), _ptr(score), _ptr(path), _ptr(ws),
+                                    ws.numel(), _stream(stream))
+    _check("hmm_viterbi", rc)
+    return score, path
+
+
+def reestimate_rows(n: torch.Tensor, old: torch.Tensor, out: Optional[torch.Tensor] = None,
+                    stream=None) -> torch.Tensor:
+    """Baum-Welch M-step for one parameter array (rows over the last axis)."""
+    _dev(n, torch.float32, "n")
+    _dev(old, torch.float32, "old")
+    if tuple(n.shape) != tuple(old.shape):
+        raise ValueError("n and old must have the same shape")
+    if out is None:
+        out = torch.empty_like(old)
+    _dev(out, torch.float32, "out")
+    cols = n.shape[-1]
+    rows = n.numel() // cols if cols else 0
+    rc = load_library().hmm_reestimate_rows(_ptr(n), _ptr(old), _ptr(out), rows, cols, _stream(stream))
+    _check("hmm_reestimate_rows", rc)
+    return out
+
+
+def baum_welch(p: Problem, iters: int, stream=None):
+    """EM on the bank (each sequence trains its own model): `iters` rounds of E-step
+    (expected counts, hmm_forward_backward_grad with unit weights) and M-step
+    (hmm_reestimate_rows), updating p.pi, p.A, p.B in place.  Returns the
+    log-likelihoods of the sequences before each round, a device tensor [iters][S]."""
+    if p.model_of_seq is None:
+        raise ValueError("Baum-Welch needs model_of_seq")
+    dev = p.pi.device
+    ws = p.workspace(OP_GRAD)
+    counts = (torch.empty((p.K, p.N), dtype=torch.float32, device=dev),
+              torch.empty((p.K, p.N, p.N), dtype=torch.float32, device=dev),
+              torch.empty((p.K, p.N, p.M), dtype=torch.float32, device=dev))
+    lls = torch.empty((iters, p.S), dtype=torch.float32, device=dev)
+    for it in range(iters):
+        forward_backward_grad(p, phase=0, loglik=lls[it], counts=counts, ws=ws, stream=stream)
+        for n, par in zip(counts, (p.pi, p.A, p.B)):
+            reestimate_rows(n, par, out=par, stream=stream)
+    return lls
 
 
 def softmax_rows(logits: torch.Tensor, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:

@@ -43,7 +43,7 @@ def _batch(S=100, max_len=50, total=5000, models=False):
 def test_workspace_size_rules(lib):
     b = _bank()
     q = _batch()
-    for op in (0, 1, 2):
+    for op in (0, 1, 2, 3):
         assert lib.hmm_workspace_size(ctypes.byref(b), ctypes.byref(q), op) > 0
     assert lib.hmm_workspace_size(ctypes.byref(b), ctypes.byref(q), 7) == 0
     bad = hmm.Bank(0, 16, 32, 0x1000, 0x2000, 0x3000)
@@ -93,11 +93,25 @@ def test_host_side_errors_enqueue_nothing(lib):
                                          1 << 40, None) == -1
     assert lib.hmm_forward_backward_grad(ctypes.byref(b), ctypes.byref(qm), None, out, out, out, out, 3, ws_al,
                                          1 << 40, None) == -6
-    # gradient beyond the batched state range is reported, not attempted
-    big = hmm.Bank(2, 200, 32, 0x1000, 0x2000, 0x3000)
-    need = lib.hmm_workspace_size(ctypes.byref(big), ctypes.byref(qm), 2)
-    assert lib.hmm_forward_backward_grad(ctypes.byref(big), ctypes.byref(qm), None, out, out, out, out, 0, ws_al,
+    # a gradient whose length-sorting plan would exceed its bin limit (models x (max_len + 1))
+    # is reported, not attempted
+    big = hmm.Bank(64, 16, 32, 0x1000, 0x2000, 0x3000)
+    ql = hmm.Batch(100, 0x4000, 0x5000, 0x6000, 0x7000, 1 << 20, 5000)
+    need = lib.hmm_workspace_size(ctypes.byref(big), ctypes.byref(ql), 2)
+    assert lib.hmm_forward_backward_grad(ctypes.byref(big), ctypes.byref(ql), None, out, out, out, out, 0, ws_al,
                                          need, None) == -4
+    # Viterbi: model_of_seq, score and path required; more than 64 states reported, not attempted
+    assert lib.hmm_viterbi(ctypes.byref(b), ctypes.byref(q), out, out, ws_al, 1 << 40, None) == -1
+    assert lib.hmm_viterbi(ctypes.byref(b), ctypes.byref(qm), None, out, ws_al, 1 << 40, None) == -1
+    assert lib.hmm_viterbi(ctypes.byref(b), ctypes.byref(qm), out, None, ws_al, 1 << 40, None) == -1
+    need = lib.hmm_workspace_size(ctypes.byref(b), ctypes.byref(qm), 3)
+    assert need >= 5000 * 16  # one back-pointer byte per padded state and symbol
+    assert lib.hmm_viterbi(ctypes.byref(b), ctypes.byref(qm), out, out, ws_al, need - 1, None) == -3
+    wide = hmm.Bank(4, 65, 32, 0x1000, 0x2000, 0x3000)
+    need = lib.hmm_workspace_size(ctypes.byref(wide), ctypes.byref(qm), 3)
+    assert lib.hmm_viterbi(ctypes.byref(wide), ctypes.byref(qm), out, out, ws_al, need, None) == -4
+    assert lib.hmm_reestimate_rows(out, out, out, -1, 4, None) == -2
+    assert lib.hmm_reestimate_rows(None, out, out, 3, 4, None) == -1
     # softmax / logit-grad shape checks
     assert lib.hmm_softmax_rows(out, out, -1, 4, None) == -2
     assert lib.hmm_logit_grad(out, out, out, 4, 0, None) == -2

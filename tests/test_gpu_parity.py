@@ -320,16 +320,33 @@ def test_counts_parity(cfg, scale):
     assert _counts_err(nB.cpu().numpy(), rB) <= GRAD_TOL
 
 
-@pytest.mark.parametrize("N", [49, 64, 80, 96, 128])
-def test_counts_cooperative_state_counts(N):
-    """Gradient with the cooperative kernels (N = 64 .. 128), ragged lengths incl. T = 1."""
-    print(f"[case] counts cooperative N={N}", flush=True)
-    rng = np.random.default_rng([9, N])
+@pytest.mark.parametrize("N,M", [(49, 17), (64, 17), (80, 17), (96, 17), (128, 17), (128, 700), (129, 17),
+                                 (160, 17), (200, 40), (255, 300), (256, 17), (256, 1024)])
+def test_counts_cooperative_state_counts(N, M):
+    """Gradient with the cooperative kernels (N = 64 .. 256), ragged lengths incl. T = 1;
+    M large enough that the emission counts go straight to global memory in some cases,
+    and N > 128 (fragments streamed from the workspace)."""
+    print(f"[case] counts cooperative N={N} M={M}", flush=True)
+    rng = np.random.default_rng([9, N, M])
     lengths = rng.integers(1, 150, size=41)
     lengths[:3] = [1, 2, 65]
-    w = workloads.random_lengths_workload(rng, K=3, N=N, M=17, lengths=lengths, all_pairs=False, conc=0.5)
+    w = workloads.random_lengths_workload(rng, K=3, N=N, M=M, lengths=lengths, all_pairs=False, conc=0.5)
     wts = rng.uniform(0.5, 1.5, size=w.S).astype(np.float32)
     ll, (npi, nA, nB), _ = hmm.forward_backward_grad(problem(w), seq_weight=dev(wts))
+    rll, rpi, rA, rB = O.counts(w.pi, w.A, w.B, w.symbols, w.offsets, w.lengths, w.owner, weights=wts)
+    assert rel_err(ll.cpu().numpy(), rll) <= LL_TOL
+    assert _counts_err(npi.cpu().numpy(), rpi) <= GRAD_TOL
+    assert _counts_err(nA.cpu().numpy(), rA) <= GRAD_TOL
+    assert _counts_err(nB.cpu().numpy(), rB) <= GRAD_TOL
+
+
+def test_counts_c5_subset():
+    """The N=256 bank's gradient (long sequences: several checkpoint segments) against the oracle."""
+    print("[case] counts c5 subset", flush=True)
+    w = workloads.make_workload("c5", scale=0.001)
+    rng = np.random.default_rng(6)
+    wts = rng.uniform(0.5, 1.5, size=w.S).astype(np.float32)
+    ll, (npi, nA, nB), _ = hmm.forward_backward_grad(problem(w, True), seq_weight=dev(wts))
     rll, rpi, rA, rB = O.counts(w.pi, w.A, w.B, w.symbols, w.offsets, w.lengths, w.owner, weights=wts)
     assert rel_err(ll.cpu().numpy(), rll) <= LL_TOL
     assert _counts_err(npi.cpu().numpy(), rpi) <= GRAD_TOL
