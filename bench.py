@@ -23,7 +23,11 @@ time.  Printed as one JSON line, with:
                 (c1: one sequence of 64 steps; c2: 4096 sequences x 12 models,
                 T up to 400, with labels): microseconds per call, eager and as a
                 replayed HIP graph;
-  graph         the recognition step captured once as a HIP graph and replayed.
+  graph         the recognition step captured once as a HIP graph and replayed;
+  viterbi       Viterbi decoding of the c3 sequences, each with its owner model
+                (max-plus on the vector ALUs: 2 operations per state-step against
+                the FP32 vector issue rate without packing, 39.3 Tops/s);
+  em            one Baum-Welch iteration on c4 (forward + adjoint + M-step).
 """
 from __future__ import annotations
 
@@ -41,6 +45,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "HMM state-steps/s (N²·ΣT·models) fwd and fwd+bwd, batched vs plain, FP32"
 FP32_PEAK_TFLOPS = 157.3
+# vector ALU issue rate for single (unpacked) FP32 operations: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+VALU_PEAK_TOPS = 39.3
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 # The recognition workload (N=32, 8192 tiles of 32 sequences) runs on the
@@ -328,6 +334,38 @@ def main():
                      "ns_per_step_graph": g2 * 1e6 / int(w2.lengths.max()),
                      "state_steps_per_s_graph": w2.units() / (g2 / 1e3)}
         result["latency"] = lat
+
+        log("Viterbi decoding of the c3 sequences with their owner models")
+        p3o = to_dev(w, torch, own=True)
+        wsv = p3o.workspace(hmm.OP_VITERBI)
+        scv = torch.empty(w.S, dtype=torch.float32, device="cuda")
+        pav = torch.empty(w.total_symbols, dtype=torch.int32, device="cuda")
+        fv = lambda: hmm.viterbi(p3o, score=scv, path=pav, ws=wsv)
+        fv()
+        torch.cuda.synchronize()
+        hmm.profile_enable(True)
+        sv = time_steps(fv, 5, 0, torch)
+        kv_ms, kv_n = hmm.profile_read(hmm.PROF_VITERBI)
+        hmm.profile_enable(False)
+        uv = float(w.N) ** 2 * float(w.lengths.sum())
+        kv_s = kv_ms / max(kv_n, 1) / 1e3
+        result["viterbi"] = {"workload": "c3 bank, 65536 sequences each decoded with its owner model, "
+                                         "score + path (N=32)",
+                             "value": uv / sv, "unit": "state-steps/s", "ms_per_step": sv * 1e3,
+                             "decode_kernel_ms": kv_s * 1e3,
+                             "roofline": {"bound": "alu", "achieved": round(2.0 * uv / kv_s / 1e12, 3),
+                                          "peak": VALU_PEAK_TOPS, "unit": "Tops/s",
+                                          "frac": round(2.0 * uv / kv_s / 1e12 / VALU_PEAK_TOPS, 4)}}
+        del p3o, wsv, scv, pav
+
+        log("one Baum-Welch iteration on c4")
+        p4e = to_dev(w4, torch, own=True)
+        hmm.baum_welch(p4e, 1)
+        torch.cuda.synchronize()
+        se = time_steps(lambda: hmm.baum_welch(p4e, 1), 5, 0, torch)
+        result["em"] = {"workload": "c4: one EM iteration (forward + adjoint + M-step), parameters updated in place",
+                        "value": w4.units() / se, "unit": "state-steps/s", "ms_per_iteration": se * 1e3}
+        del p4e
 
     if not args.no_extra:
         result["graph"] = {"ms_per_step": graph_ms(step, 10, torch),

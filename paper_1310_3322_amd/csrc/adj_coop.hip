@@ -54,7 +54,11 @@ struct AdjCoopShape {
     static constexpr int small_bytes = (xch_floats + w_floats + at_floats) * 4 + 2 * ACH * TILE * 4;
 };
 
-__host__ __device__ inline int nb_swz(int NP) { return (NP & (NP - 1)) == 0 ? NP - 4 : 0; }
+// LDS partial of the emission counts: state i of symbol o at o * NP + (i ^ (4 o & 12)).
+// The XOR rotates the 4-state groups inside each 16-state block (spreading banks
+// across symbols) and never moves a state out of its block, so the wave that owns
+// a block owns all of that block's addresses.
+__host__ __device__ inline int nb_swz(int) { return 12; }
 
 // The two fragment sets of a wave: resident in registers, or streamed.
 template <int R, int BO, bool STREAM>
@@ -95,6 +99,8 @@ struct AdjFrags<R, BO, true> {
 template <int R, int BO, bool NBLDS, bool STREAM>
 __global__ void __launch_bounds__(R / BO * WAVE) k_adj_coop(DevPtrs d, AdjLaunch a) {
     using SH = AdjCoopShape<R, BO>;
+    // emission counts into the LDS partial one step late, overlapped with the next step's MFMAs
+    constexpr bool DEFER = NBLDS && !STREAM;
     constexpr int NP = SH::NP;
     constexpr int NW = SH::NW;
     constexpr int XROW = SH::XROW;
@@ -180,6 +186,42 @@ __global__ void __launch_bounds__(R / BO * WAVE) k_adj_coop(DevPtrs d, AdjLaunch
                 const int32_t *sbase = T > 0 ? d.symbols + off : d.symbols;
                 const int tlim = T > 0 ? T - 1 : 0;
                 float m_last = 1.0f;  // m_T of this lane's sequence (set in the last segment)
+                // gamma_1 of this lane's states, added to n_pi after the tile (a global atomic
+                // inside the step would make every step wait for all outstanding loads)
+                float gpi[BO][4] = {};
+                // Emission counts of the previous backward step, added to the LDS partial
+                // during the next step.  A lane adds its 4 consecutive states of one symbol
+                // with a plain 16-byte read-add-write when no other sequence of the tile
+                // has that symbol at that step (the lanes of a wave then touch disjoint
+                // addresses, and other waves own other state blocks); a lane whose symbol
+                // repeats in an earlier slot adds with atomics instead, issued after the
+                // plain writes (in order within the wave).
+                float4 pend_gm[BO];
+                int pend_ix[BO] = {};
+                bool pend_on = false, pend_dup = false;
+                auto flush_pending = [&]() {
+                    if (pend_on && !pend_dup) {
+#pragma unroll
+                        for (int b = 0; b < BO; ++b) {
+                            float4 q = *(const float4 *)&nbl[pend_ix[b]];
+                            q.x += pend_gm[b].x;
+                            q.y += pend_gm[b].y;
+                            q.z += pend_gm[b].z;
+                            q.w += pend_gm[b].w;
+                            *(float4 *)&nbl[pend_ix[b]] = q;
+                        }
+                    }
+                    if (pend_on && pend_dup) {
+#pragma unroll
+                        for (int b = 0; b < BO; ++b) {
+                            atomicAdd(&nbl[pend_ix[b]], pend_gm[b].x);
+                            atomicAdd(&nbl[pend_ix[b] + 1], pend_gm[b].y);
+                            atomicAdd(&nbl[pend_ix[b] + 2], pend_gm[b].z);
+                            atomicAdd(&nbl[pend_ix[b] + 3], pend_gm[b].w);
+                        }
+                    }
+                    pend_on = false;
+                };
                 // the w exchange buffer of "step Tmax" starts at zero
                 for (int i = threadIdx.x; i < TILE * XROW; i += blockDim.x) wex[(Tmax & 1) * TILE * XROW + i] = 0.0f;
 
@@ -264,33 +306,54 @@ __global__ void __launch_bounds__(R / BO * WAVE) k_adj_coop(DevPtrs d, AdjLaunch
                         }
                         const int o = read_sym(t);
                         seg_o[sidx(t - t0)] = o;
+                        // the emission row is requested before the matvec, which hides its latency
+                        float4 bb[BO];
+#pragma unroll
+                        for (int b = 0; b < BO; ++b) bb[b] = *(const float4 *)&btk[(size_t)o * NP + 16 * (r0 + b) + 4 * g];
                         floatx4 u[BO];
                         // the checkpoint row enters unscaled (exponent 0), later rows by 2^-e
                         fr.fwd(xbuf + ((t - 1) & 1) * TILE * XROW, (t == t0 + 1) ? 0 : e, g, sl, u);
 #pragma unroll
                         for (int b = 0; b < BO; ++b) {
-                            const float4 bb = *(const float4 *)&btk[(size_t)o * NP + 16 * (r0 + b) + 4 * g];
-                            const float part = coop_emit(u[b], bb, x[b]);
+                            const float part = coop_emit(u[b], bb[b], x[b]);
                             *(float4 *)&xbuf[(t & 1) * TILE * XROW + sl * XROW + 16 * (r0 + b) + 4 * g] =
                                 float4{x[b][0], x[b][1], x[b][2], x[b][3]};
                             if (g == 0) psum[(t & 1) * R * TILE + (r0 + b) * TILE + sl] = part;
                         }
                         __syncthreads();
                     }
-                    // ---- backward through the segment
+                    // ---- backward through the segment; the segment entries of step t - 1
+                    // are requested during step t, and the emission row of step t at its start
+                    float4 aq_n[BO];
+                    int et_n = 0, ot_n = 0;
+#pragma unroll
+                    for (int b = 0; b < BO; ++b) aq_n[b] = seg_alpha[aidx(t1 - 1 - t0, b)];
+                    et_n = seg_e[sidx(t1 - 1 - t0)];
+                    ot_n = seg_o[sidx(t1 - 1 - t0)];
                     for (int t = t1 - 1; t >= t0; --t) {
                         const int tl = t - t0;
                         float al[BO][4];
 #pragma unroll
                         for (int b = 0; b < BO; ++b) {
-                            const float4 aq = seg_alpha[aidx(tl, b)];
-                            al[b][0] = aq.x;
-                            al[b][1] = aq.y;
-                            al[b][2] = aq.z;
-                            al[b][3] = aq.w;
+                            al[b][0] = aq_n[b].x;
+                            al[b][1] = aq_n[b].y;
+                            al[b][2] = aq_n[b].z;
+                            al[b][3] = aq_n[b].w;
                         }
-                        const int et = seg_e[sidx(tl)];
-                        const int ot = seg_o[sidx(tl)];
+                        const int et = et_n;
+                        const int ot = ot_n;
+                        float4 bb[BO];
+#pragma unroll
+                        for (int b = 0; b < BO; ++b) bb[b] = *(const float4 *)&btk[(size_t)ot * NP + 16 * (r0 + b) + 4 * g];
+                        {
+                            // unconditional (index clamped at the segment start), so that the
+                            // wait for the emission row above can leave these loads in flight
+                            const int tp = tl > 0 ? tl - 1 : 0;
+#pragma unroll
+                            for (int b = 0; b < BO; ++b) aq_n[b] = seg_alpha[aidx(tp, b)];
+                            et_n = seg_e[sidx(tp)];
+                            ot_n = seg_o[sidx(tp)];
+                        }
                         const bool live = act && t < T;
                         const bool trans = act && t + 1 < T;
                         const float *wrow = wex + ((t + 1) & 1) * TILE * XROW;  // w_{t+1}, all states
@@ -309,22 +372,49 @@ __global__ void __launch_bounds__(R / BO * WAVE) k_adj_coop(DevPtrs d, AdjLaunch
                                 for (int v = 0; v < 4; ++v)
                                     atile[(b * TILE + sl) * 17 + 4 * g + v] = trans ? wgt * al[b][v] : 0.0f;
                             wave_lds_sync();
+                            if (DEFER) {
+                                // all operands of the C update first; the deferred emission
+                                // counts then run in the LDS while the MFMAs issue
+                                float xa[4][BO], wb[4][R];
 #pragma unroll
-                            for (int q = 0; q < 4; ++q) {
-                                const int s = 4 * q + g;
-                                float xa[BO];
+                                for (int q = 0; q < 4; ++q) {
+                                    const int s = 4 * q + g;
 #pragma unroll
-                                for (int b = 0; b < BO; ++b) xa[b] = atile[(b * TILE + s) * 17 + sl];
+                                    for (int b = 0; b < BO; ++b) xa[q][b] = atile[(b * TILE + s) * 17 + sl];
 #pragma unroll
-                                for (int rj = 0; rj < R; ++rj) {
-                                    const float wb = wrow[s * XROW + 16 * rj + sl];
-#pragma unroll
-                                    for (int b = 0; b < BO; ++b)
-                                        C[b][rj] = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[b], wb, C[b][rj], 0, 0, 0);
+                                    for (int rj = 0; rj < R; ++rj) wb[q][rj] = wrow[s * XROW + 16 * rj + sl];
                                 }
-                                if (STREAM) __builtin_amdgcn_sched_barrier(0);
+                                flush_pending();
+                                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                                for (int q = 0; q < 4; ++q)
+#pragma unroll
+                                    for (int rj = 0; rj < R; ++rj)
+#pragma unroll
+                                        for (int b = 0; b < BO; ++b)
+                                            C[b][rj] = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[q][b], wb[q][rj], C[b][rj],
+                                                                                          0, 0, 0);
+                            } else {
+#pragma unroll
+                                for (int q = 0; q < 4; ++q) {
+                                    const int s = 4 * q + g;
+                                    float xa[BO];
+#pragma unroll
+                                    for (int b = 0; b < BO; ++b) xa[b] = atile[(b * TILE + s) * 17 + sl];
+#pragma unroll
+                                    for (int rj = 0; rj < R; ++rj) {
+                                        const float wb = wrow[s * XROW + 16 * rj + sl];
+#pragma unroll
+                                        for (int b = 0; b < BO; ++b)
+                                            C[b][rj] =
+                                                __builtin_amdgcn_mfma_f32_16x16x4f32(xa[b], wb, C[b][rj], 0, 0, 0);
+                                    }
+                                    if (STREAM) __builtin_amdgcn_sched_barrier(0);
+                                }
                             }
                             wave_lds_sync();
+                        } else if (DEFER) {
+                            flush_pending();
                         }
                         if (t == T - 1) {
                             const float inv = 1.0f / m_last;
@@ -333,7 +423,28 @@ __global__ void __launch_bounds__(R / BO * WAVE) k_adj_coop(DevPtrs d, AdjLaunch
 #pragma unroll
                                 for (int v = 0; v < 4; ++v) be[b][v] = inv;
                         }
-                        if (live) {
+                        if (DEFER) {
+                            // this step's emission counts wait in registers for the next step;
+                            // first slot of the tile with the same symbol at this step
+                            int first = sl;
+#pragma unroll
+                            for (int j = 15; j >= 0; --j)
+                                if (__builtin_amdgcn_readlane(ot, j) == ot) first = j;
+#pragma unroll
+                            for (int b = 0; b < BO; ++b) {
+                                float gm[4];
+#pragma unroll
+                                for (int v = 0; v < 4; ++v) {
+                                    const int i = 16 * (r0 + b) + 4 * g + v;
+                                    gm[v] = (i < N) ? wgt * al[b][v] * be[b][v] : 0.0f;
+                                    if (live && t == 0) gpi[b][v] = gm[v];
+                                }
+                                pend_gm[b] = float4{gm[0], gm[1], gm[2], gm[3]};
+                                pend_ix[b] = ot * NP + ((16 * (r0 + b) + 4 * g) ^ (ot * 4 & swz));
+                            }
+                            pend_on = live;
+                            pend_dup = first != sl;
+                        } else if (live) {
 #pragma unroll
                             for (int b = 0; b < BO; ++b)
 #pragma unroll
@@ -345,8 +456,8 @@ __global__ void __launch_bounds__(R / BO * WAVE) k_adj_coop(DevPtrs d, AdjLaunch
                                             atomicAdd(&nbl[ot * NP + (i ^ (ot * 4 & swz))], gm);
                                         else
                                             atomicAdd(&nbt[(size_t)ot * NP + i], gm);
-                                        if (t == 0) atomicAdd(&a.cnt_pi[(size_t)k * N + i], gm);
                                     }
+                                    if (t == 0) gpi[b][v] = gm;
                                 }
                         }
                         // w_t = b_t o betahat_t 2^-e_t; zero where the sequence has ended or
@@ -354,17 +465,24 @@ __global__ void __launch_bounds__(R / BO * WAVE) k_adj_coop(DevPtrs d, AdjLaunch
                         // contraction over sequences of C)
 #pragma unroll
                         for (int b = 0; b < BO; ++b) {
-                            const float4 bb = *(const float4 *)&btk[(size_t)ot * NP + 16 * (r0 + b) + 4 * g];
-                            const float wn0 = live ? ldexp_f(bb.x * be[b][0], -et) : 0.0f;
-                            const float wn1 = live ? ldexp_f(bb.y * be[b][1], -et) : 0.0f;
-                            const float wn2 = live ? ldexp_f(bb.z * be[b][2], -et) : 0.0f;
-                            const float wn3 = live ? ldexp_f(bb.w * be[b][3], -et) : 0.0f;
+                            const float wn0 = live ? ldexp_f(bb[b].x * be[b][0], -et) : 0.0f;
+                            const float wn1 = live ? ldexp_f(bb[b].y * be[b][1], -et) : 0.0f;
+                            const float wn2 = live ? ldexp_f(bb[b].z * be[b][2], -et) : 0.0f;
+                            const float wn3 = live ? ldexp_f(bb[b].w * be[b][3], -et) : 0.0f;
                             *(float4 *)&wex[(t & 1) * TILE * XROW + sl * XROW + 16 * (r0 + b) + 4 * g] =
                                 float4{wn0, wn1, wn2, wn3};
                         }
                         __syncthreads();
                     }
                 }
+                if (DEFER) flush_pending();
+#pragma unroll
+                for (int b = 0; b < BO; ++b)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int i = 16 * (r0 + b) + 4 * g + v;
+                        if (i < N && gpi[b][v] != 0.0f) atomicAdd(&a.cnt_pi[(size_t)k * N + i], gpi[b][v]);
+                    }
             }
             // n_A = A o C for this wave's rows of model k
 #pragma unroll
