@@ -309,6 +309,7 @@ def main():
         del p5, ws5g, cnt5
 
         log("latency-bound workloads c1 and c2")
+        hmm.select_kernel(hmm.KERNEL_AUTO)
         lat = {}
         w1 = workloads.make_workload("c1")
         p1 = to_dev(w1, torch, own=True)
@@ -316,10 +317,25 @@ def main():
         ll1 = torch.empty(w1.S, dtype=torch.float32, device="cuda")
         f1 = lambda: hmm.forward_loglik(p1, out=ll1, ws=ws1)
         e1 = time_steps(f1, 50, 5, torch)
-        lat["c1"] = {"workload": "c1: 1 HMM N=8 M=16, one sequence T=64, forward",
+        lat["c1"] = {"workload": "c1: 1 HMM N=8 M=16, one sequence T=64, forward (automatic choice: "
+                                 "time-parallel product tree)",
                      "us_per_call": e1 * 1e6, "us_per_call_graph": graph_ms(f1, 50, torch) * 1e3,
                      "ns_per_step_graph": None}
         lat["c1"]["ns_per_step_graph"] = lat["c1"]["us_per_call_graph"] * 1e3 / int(w1.lengths.max())
+        hmm.select_kernel(hmm.KERNEL_TILE16)
+        lat["c1"]["us_per_call_tiles"] = time_steps(f1, 50, 5, torch) * 1e6
+        hmm.select_kernel(hmm.KERNEL_AUTO)
+        w1l = workloads.random_lengths_workload(np.random.default_rng(7), K=1, N=8, M=16,
+                                                lengths=np.array([4096]), all_pairs=False)
+        p1l = to_dev(w1l, torch, own=True)
+        ws1l = p1l.workspace(hmm.OP_FORWARD)
+        ll1l = torch.empty(1, dtype=torch.float32, device="cuda")
+        f1l = lambda: hmm.forward_loglik(p1l, out=ll1l, ws=ws1l)
+        lat["one_long"] = {"workload": "one sequence T=4096, N=8 M=16 (c1 bank shape), forward",
+                           "us_per_call_scan": time_steps(f1l, 20, 3, torch) * 1e6}
+        hmm.select_kernel(hmm.KERNEL_TILE16)
+        lat["one_long"]["us_per_call_tiles"] = time_steps(f1l, 20, 3, torch) * 1e6
+        hmm.select_kernel(hmm.KERNEL_AUTO)
         w2 = workloads.make_workload("c2")
         p2 = to_dev(w2, torch, own=False)
         b2 = p2.batch_without_models()

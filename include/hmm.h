@@ -112,6 +112,8 @@ typedef struct {
 #define HMM_KERNEL_TILE16 3   /* one wave per 16-sequence tile (padded N <= 64)        */
 #define HMM_KERNEL_TILE32 4   /* one wave per 32-sequence tile (padded N = 32 or 64)   */
 #define HMM_KERNEL_COOP 5     /* one workgroup per tile, one wave per state block (N >= 49) */
+#define HMM_KERNEL_SCAN 6     /* time-parallel product tree of step matrices, one workgroup
+                                 per pair (N <= 16); AUTO takes it for few pairs          */
 
 /* Bytes of workspace the call `op` needs for this bank and batch (host only,
  * reads no device memory; pointers in bank/batch may be NULL here).

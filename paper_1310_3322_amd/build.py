@@ -16,7 +16,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libhmm_mi355x.so")
 OBJDIR = os.path.join(ROOT, "_build", "hip")
 
-SOURCES = ["planner.hip", "fwd_plain.hip", "fwd_mfma.hip", "fwd_mfma32.hip", "fwd_coop.hip", "adj_mfma.hip", "adj_coop.hip", "viterbi.hip", "abi.hip"]
+SOURCES = ["planner.hip", "fwd_plain.hip", "fwd_mfma.hip", "fwd_mfma32.hip", "fwd_coop.hip", "fwd_scan.hip", "adj_mfma.hip", "adj_coop.hip", "viterbi.hip", "abi.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # Packed FP32 VALU instructions are disabled for all device code.  MFMA

@@ -121,6 +121,25 @@ bool batched_capable(const hmm_bank *b, const hmm_batch *q, int op) {
     return nbins <= MAX_PLAN_BINS;
 }
 
+// The time-parallel forward: forced, or chosen for few pairs with long
+// sequences, where tiles would leave most of the chip idle while one sequence
+// advances step by step.  HMM_ERR_UNSUPPORTED when forced on a shape it does
+// not take.
+hmm_status scan_choice(const hmm_bank *b, const hmm_batch *q, int op, bool *scan) {
+    *scan = false;
+    if (op != HMM_OP_FORWARD && op != HMM_OP_CLASSIFY) return HMM_OK;
+    const bool all_pairs = (op == HMM_OP_CLASSIFY) || q->model_of_seq == nullptr;
+    const int64_t pairs = all_pairs ? (int64_t)q->S * b->K : (int64_t)q->S;
+    const int kind = g_kernel_kind.load(std::memory_order_relaxed);
+    if (kind == HMM_KERNEL_SCAN) {
+        if (!fwd_scan_supported(b->N) || pairs > 65535) return HMM_ERR_UNSUPPORTED;
+        *scan = true;
+    } else if (kind == HMM_KERNEL_AUTO) {
+        *scan = fwd_scan_supported(b->N) && pairs * 4 <= device_cu_count() && q->max_len >= 32;
+    }
+    return HMM_OK;
+}
+
 Layout make_layout(const hmm_bank *b, const hmm_batch *q, int op) {
     Layout L;
     memset(&L, 0, sizeof(L));
@@ -159,6 +178,14 @@ Layout make_layout(const hmm_bank *b, const hmm_batch *q, int op) {
             if (coop) L.nbt = take((size_t)K * M * NP * sizeof(float));
             if (coop && adj_coop_streams(NP)) L.frag = take((size_t)K * 2 * NP * NP * sizeof(float));
         }
+    }
+    bool scan = false;
+    if (scan_choice(b, q, op, &scan) == HMM_OK && scan) {
+        const bool all_pairs = (op == HMM_OP_CLASSIFY) || q->model_of_seq == nullptr;
+        const int64_t pairs = all_pairs ? (int64_t)S * K : (int64_t)S;
+        L.scan_nch = scan_chunks(q->max_len);
+        const size_t slots = (size_t)pairs * (size_t)L.scan_nch;
+        L.scan = take(slots * (256 * sizeof(float) + 2 * sizeof(int32_t)));
     }
     L.total = o;
     return L;
@@ -220,6 +247,37 @@ hmm_status run_forward(const hmm_bank *b, const hmm_batch *q, int op, float *out
         return e == hipSuccess ? HMM_OK : HMM_ERR_HIP;
     }
     const int NP = padded_states(N);
+    const int cus = device_cu_count();
+    {
+        bool scan = false;
+        rc = scan_choice(b, q, op, &scan);
+        if (rc != HMM_OK) return rc;
+        if (scan) {
+            launch_fill_i32(err, 1, INT32_MAX, st);
+            FwdLaunch f;
+            memset(&f, 0, sizeof(f));
+            f.K = K;
+            f.N = N;
+            f.M = M;
+            f.NP = 16;
+            f.S = S;
+            f.all_pairs = all_pairs ? 1 : 0;
+            f.max_len = q->max_len;
+            f.total = q->total_symbols;
+            f.err = err;
+            f.ll = out;
+            const int64_t pairs = all_pairs ? (int64_t)S * K : (int64_t)S;
+            ScanWs sw;
+            sw.nch = L.scan_nch;
+            sw.prod = (float *)(ws + L.scan);
+            sw.pexp = (int32_t *)(sw.prod + (size_t)pairs * sw.nch * 256);
+            sw.pbad = sw.pexp + (size_t)pairs * sw.nch;
+            const int pr = prof_begin(st, HMM_PROF_FWD_BATCHED);
+            const hipError_t e = launch_fwd_scan(d, f, sw, st);
+            prof_end(st, pr);
+            return e == hipSuccess ? HMM_OK : HMM_ERR_HIP;
+        }
+    }
     const int groups = all_pairs ? 1 : K;
     const int nbins = groups * (q->max_len + 1);
     launch_plan(d, K, S, groups, q->max_len, q->total_symbols, nbins, ws, L, st);
@@ -244,7 +302,6 @@ hmm_status run_forward(const hmm_bank *b, const hmm_batch *q, int op, float *out
     if (S == 0) return HMM_OK;
     // One wave per tile while the tiles fill the chip; one wave per 16-state
     // block (cooperative tile) when the state count needs it or tiles are few.
-    const int cus = device_cu_count();
     const int64_t tiles = ((int64_t)S + TILE - 1) / TILE + (all_pairs ? 0 : K);
     const int64_t items = all_pairs ? tiles * K : tiles;
     bool coop = !fwd_mfma_supported(NP) || (fwd_coop_supported(NP) && items < (int64_t)8 * cus);
@@ -487,7 +544,7 @@ hmm_status hmm_workspace_error(const void *ws, hipStream_t stream, int32_t *firs
 }
 
 hmm_status hmm_select_kernel(int32_t kind) {
-    if (kind < HMM_KERNEL_AUTO || kind > HMM_KERNEL_COOP) return HMM_ERR_ARG;
+    if (kind < HMM_KERNEL_AUTO || kind > HMM_KERNEL_SCAN) return HMM_ERR_ARG;
     g_kernel_kind.store(kind, std::memory_order_relaxed);
     return HMM_OK;
 }

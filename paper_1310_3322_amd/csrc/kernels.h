@@ -24,6 +24,8 @@ struct Layout {
     size_t nbt;      // float [K][M][NP] symbol-major emission counts (cooperative gradient)
     size_t frag;     // float4 [K][2][NP^2 / 4] streamed MFMA fragments (cooperative gradient, NP > 128)
     size_t bp;       // uint8 [total][NP] Viterbi back-pointers (bt then holds ln B transposed)
+    size_t scan;     // time-parallel forward: chunk products, exponents, flags (ScanWs)
+    int32_t scan_nch;    // chunks per pair of the time-parallel forward (0: not used)
     size_t total;
     int32_t nck;         // checkpoints per sequence slot
     int32_t seg_slots;   // persistent waves of the gradient kernel
@@ -95,6 +97,20 @@ hipError_t launch_fwd_mfma(const DevPtrs &d, const FwdLaunch &f, int cu_count, h
 // fwd_mfma32.hip: persistent length-sorted forward on 32x32x2 MFMA, 32-sequence tiles
 bool fwd_mfma32_supported(int NP);
 hipError_t launch_fwd_mfma32(const DevPtrs &d, const FwdLaunch &f, int cu_count, hipStream_t st);
+
+// fwd_scan.hip: time-parallel forward (product tree of step matrices), N <= 16.  Pass 1
+// reduces every chunk of SCAN_CHUNK steps of every pair; pass 2 reduces the chunk
+// products of each pair.
+constexpr int SCAN_CHUNK = 64;
+struct ScanWs {
+    float *prod;     // [pairs][nch][16][16] chunk products
+    int32_t *pexp;   // [pairs][nch] their power-of-two exponents
+    int32_t *pbad;   // [pairs][nch] 1 if the chunk holds a symbol outside [0, M)
+    int nch;         // chunks per pair (from max_len)
+};
+bool fwd_scan_supported(int N);
+int scan_chunks(int max_len);
+hipError_t launch_fwd_scan(const DevPtrs &d, const FwdLaunch &f, const ScanWs &w, hipStream_t st);
 
 // fwd_coop.hip: cooperative-tile forward (one wave per 16-state block)
 bool fwd_coop_supported(int NP);

@@ -21,7 +21,7 @@ HMM_OK = 0
 STATUS = {0: "HMM_OK", -1: "HMM_ERR_NULL", -2: "HMM_ERR_SHAPE", -3: "HMM_ERR_WORKSPACE",
           -4: "HMM_ERR_UNSUPPORTED", -5: "HMM_ERR_HIP", -6: "HMM_ERR_ARG"}
 OP_FORWARD, OP_CLASSIFY, OP_GRAD, OP_VITERBI = 0, 1, 2, 3
-KERNEL_AUTO, KERNEL_PLAIN, KERNEL_BATCHED, KERNEL_TILE16, KERNEL_TILE32, KERNEL_COOP = 0, 1, 2, 3, 4, 5
+KERNEL_AUTO, KERNEL_PLAIN, KERNEL_BATCHED, KERNEL_TILE16, KERNEL_TILE32, KERNEL_COOP, KERNEL_SCAN = 0, 1, 2, 3, 4, 5, 6
 EXPORTS = ("hmm_workspace_size", "hmm_forward_loglik", "hmm_classify", "hmm_forward_backward_grad",
            "hmm_viterbi", "hmm_reestimate_rows", "hmm_softmax_rows", "hmm_logit_grad", "hmm_workspace_error", "hmm_select_kernel",
            "hmm_profile_enable", "hmm_profile_read", "hmm_status_string")

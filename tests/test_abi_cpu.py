@@ -50,12 +50,15 @@ def test_workspace_size_rules(lib):
     assert lib.hmm_workspace_size(ctypes.byref(bad), ctypes.byref(q), 0) == 0
     bad = hmm.Bank(4, 300, 32, 0x1000, 0x2000, 0x3000)
     assert lib.hmm_workspace_size(ctypes.byref(bad), ctypes.byref(q), 0) == 0
-    # monotone in S and max_len
+    # monotone in S and max_len (past the few-pairs range where the time-parallel forward is chosen)
     prev = 0
-    for S in (0, 1, 100, 10000):
+    for S in (100, 1000, 10000):
         n = lib.hmm_workspace_size(ctypes.byref(b), ctypes.byref(_batch(S=S)), 1)
         assert n >= prev
         prev = n
+    # few pairs: the time-parallel forward reserves one 16x16 product per chunk of 64 steps and pair
+    few = lib.hmm_workspace_size(ctypes.byref(b), ctypes.byref(_batch(S=2, max_len=1000)), 0)
+    assert few >= 2 * 16 * 1024
     prev = 0
     for ml in (0, 10, 1000):
         n = lib.hmm_workspace_size(ctypes.byref(b), ctypes.byref(_batch(max_len=ml, models=True)), 2)
@@ -119,9 +122,9 @@ def test_host_side_errors_enqueue_nothing(lib):
 
 
 def test_kernel_selector(lib):
-    assert lib.hmm_select_kernel(6) == -6
+    assert lib.hmm_select_kernel(7) == -6
     assert lib.hmm_select_kernel(-1) == -6
-    for k in (1, 2, 3, 4, 5, 0):
+    for k in (1, 2, 3, 4, 5, 6, 0):
         assert lib.hmm_select_kernel(k) == 0
 
 

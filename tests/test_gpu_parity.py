@@ -447,3 +447,48 @@ def test_softmax_and_logit_grad_kernels():
     np.testing.assert_allclose(p, O.softmax(z), rtol=2e-6, atol=1e-9)
     g = hmm.logit_grad(dev(n), dev(p)).cpu().numpy()
     np.testing.assert_allclose(g, O.logit_grad(n, p), rtol=1e-5, atol=1e-5)
+
+
+# --------------------------------------------------------------------------- time-parallel forward
+@pytest.mark.parametrize("N", [1, 5, 8, 16])
+def test_scan_forward_parity(N):
+    """The product-tree forward (forced) against the oracle: chunk boundaries (64 steps),
+    T = 0 / 1 / 2, a long sequence, all pairs and own model."""
+    print(f"[case] scan N={N}", flush=True)
+    rng = np.random.default_rng([12, N])
+    lengths = np.array([0, 1, 2, 3, 63, 64, 65, 66, 127, 128, 129, 500, 3000, 17], np.int32)
+    for all_pairs in (True, False):
+        w = workloads.random_lengths_workload(rng, K=3, N=N, M=9, lengths=lengths, all_pairs=all_pairs, conc=0.5)
+        ref = oracle_ll(w, not all_pairs)
+        hmm.select_kernel(hmm.KERNEL_SCAN)
+        ll = hmm.forward_loglik(problem(w)).cpu().numpy()
+        hmm.select_kernel(hmm.KERNEL_AUTO)
+        assert rel_err(ll, ref) <= LL_TOL, all_pairs
+
+
+def test_scan_forward_special_inputs_and_auto_choice():
+    rng = np.random.default_rng(13)
+    lengths = np.array([70, 5, 140, 0], np.int32)
+    w = workloads.random_lengths_workload(rng, K=2, N=6, M=5, lengths=lengths, all_pairs=False)
+    w.B[1, :, 4] = 0.0
+    w.B[1] /= w.B[1].sum(axis=1, keepdims=True)
+    sym = w.symbols.copy()
+    sym[w.offsets[1] + 2] = 4                      # impossible under model 1 (sequence 1 is owned by model 1)
+    sym[w.offsets[2] + 100] = 77                   # invalid symbol
+    p = hmm.Problem(dev(w.pi), dev(w.A), dev(w.B), dev(sym), dev(w.offsets), dev(w.lengths), dev(w.owner),
+                    max_len=w.max_len, total_symbols=w.total_symbols)
+    ref = O.forward(w.pi, w.A, w.B, sym, w.offsets, w.lengths, w.owner)
+    for kind in (hmm.KERNEL_SCAN, hmm.KERNEL_AUTO):   # AUTO takes the scan for these few pairs
+        hmm.select_kernel(kind)
+        ws = p.workspace(hmm.OP_FORWARD)
+        ll = hmm.forward_loglik(p, ws=ws).cpu().numpy()
+        assert rel_err(ll, ref) <= LL_TOL
+        assert np.isneginf(ll[1]) and np.isnan(ll[2]) and ll[3] == 0.0
+        assert hmm.workspace_error(ws) == 2
+    hmm.select_kernel(hmm.KERNEL_AUTO)
+    # N > 16 cannot be forced onto the scan
+    w2 = workloads.random_lengths_workload(rng, K=1, N=17, M=5, lengths=np.array([40]), all_pairs=False)
+    hmm.select_kernel(hmm.KERNEL_SCAN)
+    with pytest.raises(hmm.HMMError):
+        hmm.forward_loglik(problem(w2))
+    hmm.select_kernel(hmm.KERNEL_AUTO)
