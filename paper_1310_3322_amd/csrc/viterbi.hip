@@ -164,27 +164,63 @@ __global__ void __launch_bounds__(VWAVES * WAVE) k_viterbi(DevPtrs d, VitLaunch 
     }
 }
 
-// Follows the back-pointers of one sequence per thread from q_T (left in path
-// by the decoding kernel) down to q_1; sequences with an invalid symbol or
-// model get -1 everywhere (their range is written only when it is valid).
+// Traceback: follows the back-pointers from q_T (left in path by the decoding
+// kernel) down to q_1, one wave per sequence, sequences taken in the planner's
+// length-sorted order so that a round of waves has similar lengths; sequences
+// with an invalid symbol or model get -1 everywhere (their range is written
+// only when it is valid).  The back-pointer rows of 64 steps are copied to the
+// wave's LDS buffer at once (lane l brings the row of step t_hi - l, NP bytes),
+// with the next 64 rows in flight; the chase then reads one byte per step at a
+// wave-uniform LDS address, and lane l keeps q_{t_hi - l - 1} for one coalesced
+// store per chunk.
 template <int NP>
-__global__ void k_viterbi_trace(DevPtrs d, VitLaunch v) {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= v.S) return;
+__global__ void __launch_bounds__(VWAVES * WAVE) k_viterbi_trace_wave(DevPtrs d, VitLaunch v) {
+    constexpr int DW = NP / 4;
+    __shared__ uint32_t rowbuf[VWAVES][2][WAVE * DW];
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int wave = threadIdx.x / WAVE;
+    const int64_t pos = (int64_t)blockIdx.x * VWAVES + wave;
+    if (pos >= v.S) return;
+    const int s = v.perm[pos];
     const int32_t T = d.lengths[s];
     const int64_t off = d.offsets[s];
     if (seq_bad(T, off, v.max_len, v.total) || T == 0) return;
     int32_t *q = v.path + off;
     const float sc = v.score[s];
     if (sc != sc) {
-        for (int32_t t = 0; t < T; ++t) q[t] = -1;
+        for (int32_t t = lane; t < T; t += WAVE) q[t] = -1;
         return;
     }
-    const uint8_t *bp = v.bp + off * NP;
-    int cur = q[T - 1];
-    for (int32_t t = T - 1; t > 0; --t) {
-        cur = bp[(size_t)t * NP + cur];
-        q[t - 1] = cur;
+    const uint32_t *bp = (const uint32_t *)(v.bp + off * NP);
+    uint32_t nxt[DW];
+    auto load_rows = [&](int t_hi) {
+        const int t = t_hi - lane;
+#pragma unroll
+        for (int u = 0; u < DW; ++u) nxt[u] = t >= 1 ? bp[(size_t)t * DW + u] : 0u;
+    };
+    auto store_rows = [&](int b) {
+#pragma unroll
+        for (int u = 0; u < DW; ++u) rowbuf[wave][b][lane * DW + u] = nxt[u];
+    };
+    int cur = __builtin_amdgcn_readfirstlane(q[T - 1]);
+    int t_hi = T - 1;
+    int buf = 0;
+    load_rows(t_hi);
+    store_rows(0);
+    while (t_hi >= 1) {
+        const int n = min(WAVE, t_hi);  // steps t_hi .. t_hi - n + 1 in this chunk
+        if (t_hi - n >= 1) load_rows(t_hi - n);
+        wave_lds_sync();
+        const uint8_t *rb = (const uint8_t *)rowbuf[wave][buf];
+        int mine = 0;  // q_{t_hi - lane - 1}, the state this lane decodes
+        for (int l = 0; l < n; ++l) {
+            cur = __builtin_amdgcn_readfirstlane((int)rb[l * NP + cur]);
+            if (lane == l) mine = cur;
+        }
+        if (lane < n) q[t_hi - lane - 1] = mine;
+        t_hi -= n;
+        buf ^= 1;
+        if (t_hi >= 1) store_rows(buf);
     }
 }
 
@@ -198,8 +234,7 @@ hipError_t launch_t(const DevPtrs &d, const VitLaunch &v, int cu_count, hipStrea
     const int grid = persistent_grid(cu_count * per_cu, tile_bound(v.S, v.K, false, WAVE / NP), VWAVES, v.K);
     hipLaunchKernelGGL(kern, dim3(grid), dim3(VWAVES * WAVE), 0, st, d, v);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    const int tb = 256;
-    hipLaunchKernelGGL(k_viterbi_trace<NP>, dim3((v.S + tb - 1) / tb), dim3(tb), 0, st, d, v);
+    hipLaunchKernelGGL(k_viterbi_trace_wave<NP>, dim3((v.S + VWAVES - 1) / VWAVES), dim3(VWAVES * WAVE), 0, st, d, v);
     return hipGetLastError();
 }
 
