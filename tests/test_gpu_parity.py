@@ -492,3 +492,61 @@ def test_scan_forward_special_inputs_and_auto_choice():
     with pytest.raises(hmm.HMMError):
         hmm.forward_loglik(problem(w2))
     hmm.select_kernel(hmm.KERNEL_AUTO)
+
+
+def _graph_replays(fn, outs, exact):
+    """Captures fn (which writes outs on the given stream) once, replays it three times with
+    eager work in between, and compares every replay with an eager run."""
+    fn(torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    ref = [o.clone() for o in outs]
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            fn(s)
+    torch.cuda.current_stream().wait_stream(s)
+    for rep in range(3):
+        for o in outs:
+            o.fill_(-3)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for o, r in zip(outs, ref):
+            if exact:
+                assert torch.equal(o, r), rep
+            else:
+                den = r.double().norm().item()
+                assert (o.double() - r.double()).norm().item() <= 1e-5 * max(den, 1e-30), rep
+        _ = (outs[0].float() * 2).sum().item()  # eager work between replays
+
+
+def test_graph_replay_gradient_viterbi_scan():
+    """The gradient (counts), Viterbi decoding and the time-parallel forward also capture and
+    replay (no allocation, no host synchronisation, no memset nodes inside the calls)."""
+    hmm.select_kernel(hmm.KERNEL_AUTO)
+    w = workloads.make_workload("c4", scale=0.02)
+    p = problem(w, True)
+    ws = p.workspace(hmm.OP_GRAD)
+    ll = torch.empty(w.S, device="cuda")
+    cnt = (torch.empty((w.K, w.N), device="cuda"), torch.empty((w.K, w.N, w.N), device="cuda"),
+           torch.empty((w.K, w.N, w.M), device="cuda"))
+    _graph_replays(lambda st: hmm.forward_backward_grad(p, phase=0, loglik=ll, counts=cnt, ws=ws, stream=st),
+                   [ll, *cnt], exact=False)
+    w2 = workloads.make_workload("c2", scale=0.05)
+    w2.all_pairs = False
+    p2 = problem(w2, True)
+    ws2 = p2.workspace(hmm.OP_VITERBI)
+    sc = torch.empty(w2.S, device="cuda")
+    pa = torch.empty(w2.total_symbols, dtype=torch.int32, device="cuda")
+    _graph_replays(lambda st: hmm.viterbi(p2, score=sc, path=pa, ws=ws2, stream=st), [sc, pa], exact=True)
+    rng = np.random.default_rng(21)
+    w3 = workloads.random_lengths_workload(rng, K=2, N=8, M=7, lengths=np.array([300, 64, 1, 0, 129]),
+                                           all_pairs=False)
+    p3 = problem(w3, True)
+    hmm.select_kernel(hmm.KERNEL_SCAN)
+    ws3 = p3.workspace(hmm.OP_FORWARD)
+    l3 = torch.empty(w3.S, device="cuda")
+    _graph_replays(lambda st: hmm.forward_loglik(p3, out=l3, ws=ws3, stream=st), [l3], exact=True)
+    hmm.select_kernel(hmm.KERNEL_AUTO)
