@@ -111,6 +111,8 @@ __global__ void __launch_bounds__(R / BO * WAVE) k_adj_coop(DevPtrs d, AdjLaunch
     __shared__ int32_t sym[2][ACH * TILE];
     __shared__ int32_t tile_sh;
     float *nbl = (float *)smem;  // [M][NP] emission-count partial when NBLDS
+    // [NW][M] bytes after the partial: per-wave table that finds repeated symbols in a step
+    volatile uint8_t *duptab = (volatile uint8_t *)(smem + (size_t)a.M * NP * 4);
 
     const int lane = threadIdx.x & (WAVE - 1);
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
@@ -424,12 +426,12 @@ __global__ void __launch_bounds__(R / BO * WAVE) k_adj_coop(DevPtrs d, AdjLaunch
                                 for (int v = 0; v < 4; ++v) be[b][v] = inv;
                         }
                         if (DEFER) {
-                            // this step's emission counts wait in registers for the next step;
-                            // first slot of the tile with the same symbol at this step
-                            int first = sl;
-#pragma unroll
-                            for (int j = 15; j >= 0; --j)
-                                if (__builtin_amdgcn_readlane(ot, j) == ot) first = j;
+                            // this step's emission counts wait in registers for the next step.
+                            // Repeated symbols: every slot writes its index at its symbol's entry
+                            // of the wave's table and reads the entry back; exactly one slot per
+                            // symbol finds its own index (volatile: the read is not folded)
+                            duptab[w * M + ot] = (uint8_t)sl;
+                            const int first = duptab[w * M + ot];
 #pragma unroll
                             for (int b = 0; b < BO; ++b) {
                                 float gm[4];
@@ -513,17 +515,24 @@ __global__ void __launch_bounds__(R / BO * WAVE) k_adj_coop(DevPtrs d, AdjLaunch
 
 constexpr size_t COOP_LDS_LIMIT = 160 * 1024;
 
+// Dynamic LDS of the partial variant: the [M][NP] partial, then the [waves][M] byte table.
+template <int R>
+size_t nb_lds_bytes(int M) {
+    constexpr int BO = adj_bo(R);
+    return ((size_t)M * 16 * R * 4 + (size_t)(R / BO) * M + 15) / 16 * 16;
+}
+
 template <int R>
 bool use_nb_lds(int M) {
     constexpr int BO = adj_bo(R);
-    return (size_t)M * 16 * R * 4 + AdjCoopShape<R, BO>::small_bytes + 64 <= COOP_LDS_LIMIT;
+    return nb_lds_bytes<R>(M) + AdjCoopShape<R, BO>::small_bytes + 64 <= COOP_LDS_LIMIT;
 }
 
 template <int R, bool NBLDS>
 int grid_t(int M, int cu_count, int K) {
     constexpr int BO = adj_bo(R);
     auto kern = k_adj_coop<R, BO, NBLDS, (BO > 1)>;
-    const size_t dyn = NBLDS ? (size_t)M * 16 * R * 4 : 0;
+    const size_t dyn = NBLDS ? nb_lds_bytes<R>(M) : 0;
     if (dyn > 0) (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, R / BO * WAVE, dyn) != hipSuccess || per_cu < 1)
@@ -546,7 +555,7 @@ hipError_t launch_r(const DevPtrs &d, const AdjLaunch &a, int cu_count, hipStrea
     const int grid = persistent_grid(grid_r<R>(a.M, cu_count, a.K), tile_bound(a.S, a.K, false, TILE), 1, a.K);
     if (grid > a.seg_slots) return hipErrorInvalidValue;
     if (use_nb_lds<R>(a.M))
-        k_adj_coop<R, BO, true, STREAM><<<grid, R / BO * WAVE, (size_t)a.M * 16 * R * 4, st>>>(d, a);
+        k_adj_coop<R, BO, true, STREAM><<<grid, R / BO * WAVE, nb_lds_bytes<R>(a.M), st>>>(d, a);
     else
         k_adj_coop<R, BO, false, STREAM><<<grid, R / BO * WAVE, 0, st>>>(d, a);
     return hipGetLastError();
