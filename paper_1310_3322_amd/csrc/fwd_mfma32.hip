@@ -31,8 +31,11 @@ constexpr int WAVES32 = 4;           // waves per workgroup
 template <int R>
 __device__ __forceinline__ int swz32(int o) { return o & (R == 1 ? 7 : 15); }
 
+// With one 32-state block (R = 1) the step fits 128 VGPRs, which allows four
+// waves per SIMD; R = 2 needs about twice that.
 template <int R, bool BLDS>
-__global__ void __launch_bounds__(WAVES32 * WAVE) k_fwd_mfma32(DevPtrs d, FwdLaunch f) {
+__global__ void __launch_bounds__(WAVES32 * WAVE) __attribute__((amdgpu_waves_per_eu(R == 1 ? 4 : 1, 8)))
+k_fwd_mfma32(DevPtrs d, FwdLaunch f) {
     constexpr int NP = 32 * R;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int32_t sym_all[WAVES32 * SYM32];
@@ -145,24 +148,20 @@ __global__ void __launch_bounds__(WAVES32 * WAVE) k_fwd_mfma32(DevPtrs d, FwdLau
                 load_chunk(0);
                 store_chunk(0);
                 load_chunk(CH32);
-                float4 b_nx[R][4];
-                gather(read_sym(0), b_nx);
-                for (int t = 0; t < Tmax; ++t) {
-                    float4 bcur[R][4];
-#pragma unroll
-                    for (int r = 0; r < R; ++r)
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) bcur[r][q] = b_nx[r][q];
+                // one step: bcur holds the emission row of step t, bnext receives the
+                // one of step t + 1 (the loop below alternates the two buffers, so no
+                // copy is needed between steps)
+                auto step = [&](int t, const float4 (&bcur)[R][4], float4 (&bnext)[R][4]) {
                     const int tn = t + 1;
                     if (tn < Tmax) {
                         if ((tn % CH32) == 0) {
                             store_chunk(tn);
                             load_chunk(tn + CH32);
                         }
-                        gather(read_sym(tn), b_nx);
+                        gather(read_sym(tn), bnext);
                     }
                     float x[R][16];
-                    float part = 0.0f;
+                    float part;
                     {
 #pragma clang fp contract(off)
                         if (t == 0) {
@@ -195,10 +194,11 @@ __global__ void __launch_bounds__(WAVES32 * WAVE) k_fwd_mfma32(DevPtrs d, FwdLau
 #pragma unroll
                                 for (int v = 0; v < 16; ++v) x[r][v] = acc[r][v] * bcur[r][v / 4][v % 4];
                         }
+                        part = x[0][0];
 #pragma unroll
                         for (int r = 0; r < R; ++r)
 #pragma unroll
-                            for (int v = 0; v < 16; ++v) part = part + x[r][v];
+                            for (int v = (r == 0 ? 1 : 0); v < 16; ++v) part = part + x[r][v];
                     }
                     auto q = __builtin_amdgcn_permlane32_swap(__float_as_uint(part), __float_as_uint(part), false, false);
                     const float cs = __uint_as_float(q[0]) + __uint_as_float(q[1]);
@@ -212,6 +212,12 @@ __global__ void __launch_bounds__(WAVES32 * WAVE) k_fwd_mfma32(DevPtrs d, FwdLau
                         c_end = cs;
                     }
                     E += e;
+                };
+                float4 bA[R][4], bB[R][4];
+                gather(read_sym(0), bA);
+                for (int t = 0; t < Tmax; t += 2) {
+                    step(t, bA, bB);
+                    if (t + 1 < Tmax) step(t + 1, bB, bA);
                 }
             }
             int sb = symbad ? 1 : 0;
