@@ -27,7 +27,15 @@ time.  Printed as one JSON line, with:
   viterbi       Viterbi decoding of the c3 sequences, each with its owner model
                 (max-plus on the vector ALUs: 2 operations per state-step against
                 the FP32 vector issue rate without packing, 39.3 Tops/s);
-  em            one Baum-Welch iteration on c4 (forward + adjoint + M-step).
+  em            one Baum-Welch iteration on c4 (forward + adjoint + M-step);
+  tuning        per leg, the kernel family and workgroups-per-CU cap the
+                autotuner installed before the leg was timed, with the default
+                choice's time and the tuned time.
+
+Every leg is autotuned before it is timed (paper_1310_3322_amd.tune: each
+candidate is checked against the default choice's outputs); --tune-cache FILE
+installs the choices stored there instead of tuning again and stores new ones,
+--no-tune keeps the built-in heuristics.
 """
 from __future__ import annotations
 
@@ -49,36 +57,41 @@ FP32_PEAK_TFLOPS = 157.3
 VALU_PEAK_TOPS = 39.3
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
-# The recognition workload (N=32, 8192 tiles of 32 sequences) runs on the
-# 32-sequence-tile kernel; its counters are valid while these files and the
-# compile flags in build.py are unchanged.
-KERNEL_SOURCES = ["paper_1310_3322_amd/csrc/fwd_mfma32.hip", "paper_1310_3322_amd/csrc/common.cuh",
-                  "paper_1310_3322_amd/csrc/kernels.h", "paper_1310_3322_amd/build.py"]
-ROOFLINE_KERNEL = "k_fwd_mfma32<1, true> (32-sequence-tile batched forward)"
+# The kernel the recognition workload (N=32, all pairs) runs in each forward
+# family, and the files its code comes from: counters taken on a kernel are
+# valid while these files and the compile flags in build.py are unchanged.
+_COMMON = ["paper_1310_3322_amd/csrc/common.cuh", "paper_1310_3322_amd/csrc/kernels.h", "paper_1310_3322_amd/build.py"]
+FAMILY_KERNELS = {
+    "tile32": ("k_fwd_mfma32<1, true>", "32-sequence-tile batched forward",
+               ["paper_1310_3322_amd/csrc/fwd_mfma32.hip"] + _COMMON),
+    "tile16": ("k_fwd_mfma<2, true, false>", "16-sequence-tile batched forward",
+               ["paper_1310_3322_amd/csrc/fwd_mfma.hip"] + _COMMON),
+}
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(family: str = "tile32") -> str:
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in FAMILY_KERNELS[family][2]:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload: str):
+def measured_traffic(workload: str, family: str):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel source; else None."""
+    was taken on this family's kernel with the current source; else None."""
     try:
         with open(TRAFFIC_FILE) as fh:
             data = json.load(fh)
     except (OSError, ValueError):
         return None
     rec = data.get(workload)
-    if not rec or rec.get("kernel_source_hash") != kernel_source_hash():
+    if (not rec or family not in FAMILY_KERNELS or rec.get("kernel") != FAMILY_KERNELS[family][0]
+            or rec.get("kernel_source_hash") != kernel_source_hash(family)):
         return None
     return rec.get("bytes_per_launch")
 
@@ -178,6 +191,9 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the plain and fwd+bwd legs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run 4 device copies of 512 MiB (reference kernel for HBM counter scaling)")
+    ap.add_argument("--no-tune", action="store_true", help="keep the built-in kernel heuristics (no autotuning)")
+    ap.add_argument("--tune-cache", default=None,
+                    help="JSON tuning cache: install the choices stored there instead of tuning, store new ones")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -185,21 +201,42 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_1310_3322_amd import hmm, workloads
+    from paper_1310_3322_amd import hmm, tune, workloads
 
     torch.cuda.set_device(0)
     hmm.load_library()
+    hmm.select_kernel(hmm.KERNEL_AUTO)
+    tuning, tuned_now = {}, []
+    if args.tune_cache and os.path.exists(args.tune_cache) and not args.no_tune:
+        log(f"installed {tune.load_cache(args.tune_cache)} tuning entries from {args.tune_cache}")
+
+    def autotune(name, p, op, **kw):
+        """Tunes the calls of `op` on p's shape before they are timed (or takes the cached choice)."""
+        if args.no_tune:
+            return
+        b = p.batch_without_models() if op == hmm.OP_CLASSIFY else p.batch
+        got = hmm.tune_get(hmm.tune_key(p.bank, b, op)) if args.tune_cache else None
+        if got is not None:
+            tuning[name] = {"choice": {"kernel": tune.KERNEL_NAMES[got[0]], "wg_per_cu": got[1]}, "source": "cache"}
+            return
+        log(f"autotuning {name}")
+        r = tune.tune(p, op, **kw)
+        tuned_now.append(r)
+        tuning[name] = {"choice": r["choice"], "tuned_ms": round(r["ms"], 4), "default_ms": round(r["default_ms"], 4),
+                        "accepted": sum(1 for c in r["candidates"] if c["ok"]),
+                        "unsupported": sum(1 for c in r["candidates"] if c["reason"] == "unsupported"),
+                        "rejected": [c for c in r["candidates"] if not c["ok"] and c["reason"] != "unsupported"]}
 
     log("generating the recognition workload (64 models, N=32, M=256, 65536 sequences)")
     w = workloads.make_workload("c3")
     units = w.units()
     p = to_dev(w, torch, own=False)
     b = p.batch_without_models()
+    autotune("c3_classify", p, hmm.OP_CLASSIFY)
+    family = tune.KERNEL_NAMES[hmm.call_kernel(p.bank, b, hmm.OP_CLASSIFY)]
     ws = p.workspace(hmm.OP_CLASSIFY, b)
     labels = torch.empty(w.S, dtype=torch.int32, device="cuda")
     ll = torch.empty((w.S, w.K), dtype=torch.float32, device="cuda")
-
-    hmm.select_kernel(hmm.KERNEL_BATCHED)
 
     def step():
         hmm.classify(p, labels=labels, loglik=ll, ws=ws)
@@ -219,10 +256,11 @@ def main():
     kern_s = kern_ms / 1e3 / max(launches, 1)
     flops = 2.0 * units
     achieved = flops / kern_s / 1e12
-    traffic = measured_traffic("c3_classify")
+    traffic = measured_traffic("c3_classify", family)
+    kname = " ".join(FAMILY_KERNELS[family][:2]) if family in FAMILY_KERNELS else family
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / FP32_PEAK_TFLOPS, 4), "traffic": traffic,
-                "kernel": ROOFLINE_KERNEL, "kernel_ms": round(kern_s * 1e3, 4),
+                "kernel": kname, "kernel_ms": round(kern_s * 1e3, 4),
                 "launches": launches}
     result = {"metric": METRIC, "value": units / sec, "unit": "state-steps/s", "n_gpus": 1, "steps": args.steps,
               "warmup": args.warmup, "ms_per_step": sec * 1e3, "higher_is_better": True, "scaling": "weak",
@@ -237,12 +275,13 @@ def main():
         log("plain per-pair kernel on the same workload")
         hmm.select_kernel(hmm.KERNEL_PLAIN)
         psec = time_steps(step, 2, 1, torch)
-        hmm.select_kernel(hmm.KERNEL_BATCHED)
+        hmm.select_kernel(hmm.KERNEL_AUTO)
         result["plain"] = {"value": units / psec, "ms_per_step": psec * 1e3,
                            "speedup_batched_over_plain": psec / sec}
         log("forward + adjoint on the gradient workload (8 models, N=64, M=512, 8192 sequences)")
         w4 = workloads.make_workload("c4")
         p4 = to_dev(w4, torch, own=True)
+        autotune("c4_grad", p4, hmm.OP_GRAD)
         ws4 = p4.workspace(hmm.OP_GRAD)
         ll4 = torch.empty(w4.S, dtype=torch.float32, device="cuda")
         cnt = (torch.empty((w4.K, w4.N), device="cuda"), torch.empty((w4.K, w4.N, w4.N), device="cuda"),
@@ -278,6 +317,7 @@ def main():
         log("the N=256 bank (16 models, M=1024, 16384 sequences): forward, then forward + adjoint")
         w5 = workloads.make_workload("c5")
         p5 = to_dev(w5, torch, own=True)
+        autotune("c5_forward", p5, hmm.OP_FORWARD, warmup=0, reps=2)
         ws5 = p5.workspace(hmm.OP_FORWARD)
         ll5 = torch.empty(w5.S, dtype=torch.float32, device="cuda")
         hmm.profile_enable(True)
@@ -291,6 +331,7 @@ def main():
                  "value": u5 / s5, "unit": "state-steps/s", "ms_per_step": s5 * 1e3,
                  "kernel_ms": k5_ms / max(k5_n, 1),
                  "frac_fp32_peak": 2.0 * u5 / (k5_ms / max(k5_n, 1) / 1e3) / 1e12 / FP32_PEAK_TFLOPS}
+        autotune("c5_grad", p5, hmm.OP_GRAD, warmup=0, reps=2)
         ws5g = p5.workspace(hmm.OP_GRAD)
         cnt5 = (torch.empty((w5.K, w5.N), device="cuda"), torch.empty((w5.K, w5.N, w5.N), device="cuda"),
                 torch.empty((w5.K, w5.N, w5.M), device="cuda"))
@@ -313,12 +354,13 @@ def main():
         lat = {}
         w1 = workloads.make_workload("c1")
         p1 = to_dev(w1, torch, own=True)
+        autotune("c1_forward", p1, hmm.OP_FORWARD, warmup=5, reps=20)
         ws1 = p1.workspace(hmm.OP_FORWARD)
         ll1 = torch.empty(w1.S, dtype=torch.float32, device="cuda")
         f1 = lambda: hmm.forward_loglik(p1, out=ll1, ws=ws1)
         e1 = time_steps(f1, 50, 5, torch)
-        lat["c1"] = {"workload": "c1: 1 HMM N=8 M=16, one sequence T=64, forward (automatic choice: "
-                                 "time-parallel product tree)",
+        lat["c1"] = {"workload": "c1: 1 HMM N=8 M=16, one sequence T=64, forward (tuned choice: "
+                                 f"{tune.KERNEL_NAMES[hmm.call_kernel(p1.bank, p1.batch, hmm.OP_FORWARD)]})",
                      "us_per_call": e1 * 1e6, "us_per_call_graph": graph_ms(f1, 50, torch) * 1e3,
                      "ns_per_step_graph": None}
         lat["c1"]["ns_per_step_graph"] = lat["c1"]["us_per_call_graph"] * 1e3 / int(w1.lengths.max())
@@ -328,17 +370,20 @@ def main():
         w1l = workloads.random_lengths_workload(np.random.default_rng(7), K=1, N=8, M=16,
                                                 lengths=np.array([4096]), all_pairs=False)
         p1l = to_dev(w1l, torch, own=True)
+        autotune("one_long_forward", p1l, hmm.OP_FORWARD, warmup=3, reps=10)
         ws1l = p1l.workspace(hmm.OP_FORWARD)
         ll1l = torch.empty(1, dtype=torch.float32, device="cuda")
         f1l = lambda: hmm.forward_loglik(p1l, out=ll1l, ws=ws1l)
-        lat["one_long"] = {"workload": "one sequence T=4096, N=8 M=16 (c1 bank shape), forward",
-                           "us_per_call_scan": time_steps(f1l, 20, 3, torch) * 1e6}
+        lat["one_long"] = {"workload": "one sequence T=4096, N=8 M=16 (c1 bank shape), forward (tuned choice: "
+                                       f"{tune.KERNEL_NAMES[hmm.call_kernel(p1l.bank, p1l.batch, hmm.OP_FORWARD)]})",
+                           "us_per_call": time_steps(f1l, 20, 3, torch) * 1e6}
         hmm.select_kernel(hmm.KERNEL_TILE16)
         lat["one_long"]["us_per_call_tiles"] = time_steps(f1l, 20, 3, torch) * 1e6
         hmm.select_kernel(hmm.KERNEL_AUTO)
         w2 = workloads.make_workload("c2")
         p2 = to_dev(w2, torch, own=False)
         b2 = p2.batch_without_models()
+        autotune("c2_classify", p2, hmm.OP_CLASSIFY, warmup=3, reps=10)
         ws2 = p2.workspace(hmm.OP_CLASSIFY, b2)
         lab2 = torch.empty(w2.S, dtype=torch.int32, device="cuda")
         ll2 = torch.empty((w2.S, w2.K), dtype=torch.float32, device="cuda")
@@ -353,6 +398,7 @@ def main():
 
         log("Viterbi decoding of the c3 sequences with their owner models")
         p3o = to_dev(w, torch, own=True)
+        autotune("c3_viterbi", p3o, hmm.OP_VITERBI, warmup=0, reps=2)
         wsv = p3o.workspace(hmm.OP_VITERBI)
         scv = torch.empty(w.S, dtype=torch.float32, device="cuda")
         pav = torch.empty(w.total_symbols, dtype=torch.int32, device="cuda")
@@ -395,6 +441,11 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         result["copy_calibration_bytes"] = src.numel() * 4
+
+    if not args.no_tune:
+        result["tuning"] = tuning
+        if args.tune_cache and tuned_now:
+            tune.save_cache(args.tune_cache, tuned_now)
 
     if not args.no_cpu:
         log("CPU oracle baseline on a stratified sample")

@@ -193,8 +193,58 @@ hmm_status hmm_reestimate_rows(const float *n, const float *old, float *out, int
  * is the smallest sequence index the last call flagged, or -1 if none. */
 hmm_status hmm_workspace_error(const void *ws, hipStream_t stream, int32_t *first_bad_seq);
 
-/* Selects the kernel family for later calls (HMM_KERNEL_*). */
+/* Selects the kernel family for later calls (HMM_KERNEL_*).  Any kind other
+ * than HMM_KERNEL_AUTO overrides the tuning table below. */
 hmm_status hmm_select_kernel(int32_t kind);
+
+/* Tuning table.  The component configuration of Sec. 4.1 leaves the block size
+ * of the HMM stage to the user (16 by default); here the knobs are the kernel
+ * family (which fixes the tile: 16 or 32 sequences, or a workgroup per tile)
+ * and the size of the persistent grid, picked per call shape by measurement.  While
+ * hmm_select_kernel is HMM_KERNEL_AUTO, a call whose shape has an entry takes
+ * the entry's choice instead of the built-in heuristics; hmm_workspace_size
+ * applies the same entry, so query it after tuning (a choice can need a larger
+ * workspace; a call then returns HMM_ERR_WORKSPACE rather than run).  The table
+ * lives in host memory, process-wide, at most HMM_TUNE_MAX entries; calls read
+ * it on the host only, so they stay capturable into graphs.  Entries change no
+ * result beyond the summation order of count accumulation: every choice runs
+ * kernels held to the same accuracy.  Thread-safe; a call that races with a
+ * change of its own entry takes either the old or the new choice. */
+#define HMM_TUNE_MAX 256
+#define HMM_TUNE_MAX_WG 64
+typedef struct {
+    int32_t op;         /* HMM_OP_*                                                   */
+    int32_t all_pairs;  /* 1: every sequence against every model (classify, or forward
+                           without model_of_seq); 0 otherwise                          */
+    int32_t K, N, M;    /* bank shape                                                  */
+    int32_t s_bucket;   /* bit length of S (0 for S = 0): sizes within a factor 2 share */
+    int32_t len_bucket; /* bit length of max_len                                       */
+} hmm_tune_key;
+typedef struct {
+    int32_t kernel;     /* HMM_KERNEL_*; for HMM_OP_GRAD and HMM_OP_VITERBI only AUTO or
+                           BATCHED (those ops have one family per shape)             */
+    int32_t wg_per_cu;  /* cap on resident workgroups per compute unit of the persistent
+                           launches, 0..HMM_TUNE_MAX_WG; 0 = as many as occupancy allows */
+} hmm_tune_choice;
+
+/* The key of a call (host only; pointers in bank/batch may be NULL).
+ * HMM_ERR_SHAPE / HMM_ERR_ARG for shapes or ops the calls would reject. */
+hmm_status hmm_tune_key_of(const hmm_bank *bank, const hmm_batch *batch, int32_t op, hmm_tune_key *key);
+/* Installs (replacing) the entry of `key`; choice == NULL removes it.
+ * HMM_ERR_ARG for an invalid key or choice, HMM_ERR_UNSUPPORTED when the
+ * table is full. */
+hmm_status hmm_tune_set(const hmm_tune_key *key, const hmm_tune_choice *choice);
+/* *found = 1 and *choice filled when `key` has an entry, else *found = 0. */
+hmm_status hmm_tune_get(const hmm_tune_key *key, hmm_tune_choice *choice, int32_t *found);
+/* Removes every entry. */
+hmm_status hmm_tune_clear(void);
+/* The kernel family a call of `op` with this bank and batch would run now,
+ * after the selector, the tuning table and the built-in heuristics (host only;
+ * pointers may be NULL): HMM_KERNEL_PLAIN, TILE16, TILE32, COOP or SCAN for the
+ * forward and classify; TILE16 or COOP for the gradient (the family of its
+ * checkpointing forward and backward); BATCHED for Viterbi decoding.
+ * HMM_ERR_UNSUPPORTED when the call would return it. */
+hmm_status hmm_call_kernel(const hmm_bank *bank, const hmm_batch *batch, int32_t op, int32_t *kernel);
 
 /* Kernel timing for measurement (not needed for computing anything).
  * While enabled, every launch of a main kernel is bracketed by a pair of HIP

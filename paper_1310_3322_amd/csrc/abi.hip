@@ -33,6 +33,65 @@ int device_cu_count() {
     return n;
 }
 
+// ---- tuning table (hmm_tune_*): call shape -> kernel family and grid cap
+struct TuneEntry {
+    hmm_tune_key key;
+    hmm_tune_choice choice;
+};
+std::mutex g_tune_mu;
+TuneEntry g_tune[HMM_TUNE_MAX];
+int g_tune_n = 0;
+
+int bit_length(int64_t v) {
+    int n = 0;
+    while (v > 0) {
+        ++n;
+        v >>= 1;
+    }
+    return n;
+}
+
+bool same_key(const hmm_tune_key &a, const hmm_tune_key &b) {
+    return a.op == b.op && a.all_pairs == b.all_pairs && a.K == b.K && a.N == b.N && a.M == b.M &&
+           a.s_bucket == b.s_bucket && a.len_bucket == b.len_bucket;
+}
+
+hmm_tune_key key_of(const hmm_bank *b, const hmm_batch *q, int op) {
+    hmm_tune_key k;
+    k.op = op;
+    k.all_pairs = (op == HMM_OP_CLASSIFY || (op == HMM_OP_FORWARD && q->model_of_seq == nullptr)) ? 1 : 0;
+    k.K = b->K;
+    k.N = b->N;
+    k.M = b->M;
+    k.s_bucket = bit_length(q->S);
+    k.len_bucket = bit_length(q->max_len);
+    return k;
+}
+
+// Kernel family and workgroups per CU of one call: a family forced with
+// hmm_select_kernel wins, then the tuning-table entry of the call's shape, then
+// the built-in heuristics (AUTO, no cap).
+struct CallChoice {
+    int kind;
+    int wg_per_cu;
+};
+CallChoice call_choice(const hmm_bank *b, const hmm_batch *q, int op) {
+    CallChoice c{g_kernel_kind.load(std::memory_order_relaxed), 0};
+    if (c.kind != HMM_KERNEL_AUTO) return c;
+    const hmm_tune_key k = key_of(b, q, op);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (int i = 0; i < g_tune_n; ++i)
+        if (same_key(g_tune[i].key, k)) {
+            c.kind = g_tune[i].choice.kernel;
+            c.wg_per_cu = g_tune[i].choice.wg_per_cu;
+            break;
+        }
+    return c;
+}
+
+// Grid cap of a call for the persistent launches (0 = none).
+int max_grid(int wg_per_cu, int cus) { return wg_per_cu > 0 ? wg_per_cu * cus : 0; }
+
 // ---- optional kernel timing (hmm_profile_*)
 struct ProfRecord {
     hipEvent_t start, stop;
@@ -125,12 +184,11 @@ bool batched_capable(const hmm_bank *b, const hmm_batch *q, int op) {
 // sequences, where tiles would leave most of the chip idle while one sequence
 // advances step by step.  HMM_ERR_UNSUPPORTED when forced on a shape it does
 // not take.
-hmm_status scan_choice(const hmm_bank *b, const hmm_batch *q, int op, bool *scan) {
+hmm_status scan_choice(const hmm_bank *b, const hmm_batch *q, int op, int kind, bool *scan) {
     *scan = false;
     if (op != HMM_OP_FORWARD && op != HMM_OP_CLASSIFY) return HMM_OK;
     const bool all_pairs = (op == HMM_OP_CLASSIFY) || q->model_of_seq == nullptr;
     const int64_t pairs = all_pairs ? (int64_t)q->S * b->K : (int64_t)q->S;
-    const int kind = g_kernel_kind.load(std::memory_order_relaxed);
     if (kind == HMM_KERNEL_SCAN) {
         if (!fwd_scan_supported(b->N) || pairs > 65535) return HMM_ERR_UNSUPPORTED;
         *scan = true;
@@ -151,6 +209,9 @@ Layout make_layout(const hmm_bank *b, const hmm_batch *q, int op) {
     };
     const int K = b->K, M = b->M, S = q->S;
     const int NP = op == HMM_OP_VITERBI ? viterbi_states(b->N) : padded_states(b->N);
+    const CallChoice cc = call_choice(b, q, op);
+    L.kind = cc.kind;
+    L.wg_per_cu = cc.wg_per_cu;
     L.err = take(64);
     if (op == HMM_OP_CLASSIFY) L.ll = take((size_t)S * K * sizeof(float));
     if (op == HMM_OP_GRAD) L.ll = take((size_t)S * sizeof(float));
@@ -180,7 +241,7 @@ Layout make_layout(const hmm_bank *b, const hmm_batch *q, int op) {
         }
     }
     bool scan = false;
-    if (scan_choice(b, q, op, &scan) == HMM_OK && scan) {
+    if (scan_choice(b, q, op, L.kind, &scan) == HMM_OK && scan) {
         const bool all_pairs = (op == HMM_OP_CLASSIFY) || q->model_of_seq == nullptr;
         const int64_t pairs = all_pairs ? (int64_t)S * K : (int64_t)S;
         L.scan_nch = scan_chunks(q->max_len);
@@ -212,8 +273,7 @@ DevPtrs dev_ptrs(const hmm_bank *b, const hmm_batch *q, bool with_models) {
 
 // Chooses the family for a call; HMM_ERR_UNSUPPORTED when the batched family
 // is forced for a shape it does not take.
-hmm_status choose(const hmm_bank *b, const hmm_batch *q, int op, bool *batched) {
-    const int kind = g_kernel_kind.load(std::memory_order_relaxed);
+hmm_status choose(const hmm_bank *b, const hmm_batch *q, int op, int kind, bool *batched) {
     const bool cap = batched_capable(b, q, op);
     if (op == HMM_OP_GRAD) {
         if (!cap) return HMM_ERR_UNSUPPORTED;
@@ -229,12 +289,58 @@ hmm_status choose(const hmm_bank *b, const hmm_batch *q, int op, bool *batched) 
     return HMM_OK;
 }
 
+// The concrete forward family of a call (HMM_KERNEL_PLAIN, TILE16, TILE32,
+// COOP or SCAN) under the call's kind; HMM_ERR_UNSUPPORTED when a forced
+// family does not take the shape.  Host only, decided before anything is
+// enqueued.
+hmm_status forward_family(const hmm_bank *b, const hmm_batch *q, int op, int kind, int *fam) {
+    bool batched = false;
+    hmm_status rc = choose(b, q, op, kind, &batched);
+    if (rc != HMM_OK) return rc;
+    if (!batched) {
+        *fam = HMM_KERNEL_PLAIN;
+        return HMM_OK;
+    }
+    bool scan = false;
+    if ((rc = scan_choice(b, q, op, kind, &scan)) != HMM_OK) return rc;
+    if (scan) {
+        *fam = HMM_KERNEL_SCAN;
+        return HMM_OK;
+    }
+    const bool all_pairs = (op == HMM_OP_CLASSIFY) || q->model_of_seq == nullptr;
+    const int K = b->K, S = q->S, NP = padded_states(b->N);
+    const int cus = device_cu_count();
+    // One wave per tile while the tiles fill the chip; one wave per 16-state
+    // block (cooperative tile) when the state count needs it or tiles are few.
+    const int64_t tiles = ((int64_t)S + TILE - 1) / TILE + (all_pairs ? 0 : K);
+    const int64_t items = all_pairs ? tiles * K : tiles;
+    bool coop = !fwd_mfma_supported(NP) || (fwd_coop_supported(NP) && items < (int64_t)8 * cus);
+    // 32-sequence tiles halve the per-state vector work when there are enough of them
+    const int64_t items32 = all_pairs ? (((int64_t)S + 31) / 32) * K : ((int64_t)S + 31) / 32 + K;
+    bool wide = !coop && fwd_mfma32_supported(NP) && items32 >= (int64_t)8 * cus;
+    if (kind == HMM_KERNEL_TILE16) {
+        if (!fwd_mfma_supported(NP)) return HMM_ERR_UNSUPPORTED;
+        coop = wide = false;
+    } else if (kind == HMM_KERNEL_TILE32) {
+        if (!fwd_mfma32_supported(NP)) return HMM_ERR_UNSUPPORTED;
+        coop = false;
+        wide = true;
+    } else if (kind == HMM_KERNEL_COOP) {
+        if (!fwd_coop_supported(NP)) return HMM_ERR_UNSUPPORTED;
+        coop = true;
+        wide = false;
+    }
+    *fam = coop ? HMM_KERNEL_COOP : (wide ? HMM_KERNEL_TILE32 : HMM_KERNEL_TILE16);
+    return HMM_OK;
+}
+
 hmm_status run_forward(const hmm_bank *b, const hmm_batch *q, int op, float *out, unsigned char *ws, const Layout &L,
                        hipStream_t st) {
     const bool all_pairs = (op == HMM_OP_CLASSIFY) || q->model_of_seq == nullptr;
-    bool batched = false;
-    hmm_status rc = choose(b, q, op, &batched);
+    int fam = HMM_KERNEL_PLAIN;
+    hmm_status rc = forward_family(b, q, op, L.kind, &fam);
     if (rc != HMM_OK) return rc;
+    const bool batched = fam != HMM_KERNEL_PLAIN;
     DevPtrs d = dev_ptrs(b, q, !all_pairs);
     int32_t *err = (int32_t *)(ws + L.err);
     const int K = b->K, N = b->N, M = b->M, S = q->S;
@@ -249,10 +355,7 @@ hmm_status run_forward(const hmm_bank *b, const hmm_batch *q, int op, float *out
     const int NP = padded_states(N);
     const int cus = device_cu_count();
     {
-        bool scan = false;
-        rc = scan_choice(b, q, op, &scan);
-        if (rc != HMM_OK) return rc;
-        if (scan) {
+        if (fam == HMM_KERNEL_SCAN) {
             launch_fill_i32(err, 1, INT32_MAX, st);
             FwdLaunch f;
             memset(&f, 0, sizeof(f));
@@ -299,31 +402,12 @@ hmm_status run_forward(const hmm_bank *b, const hmm_batch *q, int op, float *out
     f.err = err;
     f.bt = (const float *)(ws + L.bt);
     f.ll = out;
+    f.max_grid = max_grid(L.wg_per_cu, cus);
     if (S == 0) return HMM_OK;
-    // One wave per tile while the tiles fill the chip; one wave per 16-state
-    // block (cooperative tile) when the state count needs it or tiles are few.
-    const int64_t tiles = ((int64_t)S + TILE - 1) / TILE + (all_pairs ? 0 : K);
-    const int64_t items = all_pairs ? tiles * K : tiles;
-    bool coop = !fwd_mfma_supported(NP) || (fwd_coop_supported(NP) && items < (int64_t)8 * cus);
-    // 32-sequence tiles halve the per-state vector work when there are enough of them
-    const int64_t items32 = all_pairs ? (((int64_t)S + 31) / 32) * K : ((int64_t)S + 31) / 32 + K;
-    bool wide = !coop && fwd_mfma32_supported(NP) && items32 >= (int64_t)8 * cus;
-    const int kind = g_kernel_kind.load(std::memory_order_relaxed);
-    if (kind == HMM_KERNEL_TILE16) {
-        if (!fwd_mfma_supported(NP)) return HMM_ERR_UNSUPPORTED;
-        coop = wide = false;
-    } else if (kind == HMM_KERNEL_TILE32) {
-        if (!fwd_mfma32_supported(NP)) return HMM_ERR_UNSUPPORTED;
-        coop = false;
-        wide = true;
-    } else if (kind == HMM_KERNEL_COOP) {
-        if (!fwd_coop_supported(NP)) return HMM_ERR_UNSUPPORTED;
-        coop = true;
-        wide = false;
-    }
     const int pr = prof_begin(st, HMM_PROF_FWD_BATCHED);
-    const hipError_t e = coop ? launch_fwd_coop(d, f, cus, st)
-                              : (wide ? launch_fwd_mfma32(d, f, cus, st) : launch_fwd_mfma(d, f, cus, st));
+    const hipError_t e = fam == HMM_KERNEL_COOP    ? launch_fwd_coop(d, f, cus, st)
+                         : fam == HMM_KERNEL_TILE32 ? launch_fwd_mfma32(d, f, cus, st)
+                                                    : launch_fwd_mfma(d, f, cus, st);
     prof_end(st, pr);
     return e == hipSuccess ? HMM_OK : HMM_ERR_HIP;
 }
@@ -377,7 +461,7 @@ hmm_status hmm_forward_backward_grad(const hmm_bank *bank, const hmm_batch *batc
     const Layout L = make_layout(bank, batch, HMM_OP_GRAD);
     if ((rc = check_ws(ws, ws_bytes, L)) != HMM_OK) return rc;
     bool batched = false;
-    if ((rc = choose(bank, batch, HMM_OP_GRAD, &batched)) != HMM_OK) return rc;
+    if ((rc = choose(bank, batch, HMM_OP_GRAD, L.kind, &batched)) != HMM_OK) return rc;
     unsigned char *w = (unsigned char *)ws;
     const int K = bank->K, N = bank->N, M = bank->M, S = batch->S, NP = padded_states(N);
     DevPtrs d = dev_ptrs(bank, batch, true);
@@ -409,6 +493,7 @@ hmm_status hmm_forward_backward_grad(const hmm_bank *bank, const hmm_batch *batc
         f.ckexp = (int32_t *)(w + L.ckexp);
         f.flag = (int32_t *)(w + L.flag);
         f.nck = L.nck;
+        f.max_grid = max_grid(L.wg_per_cu, cus);
         if (S > 0) {
             const int pr = prof_begin(stream, HMM_PROF_FWD_BATCHED);
             const hipError_t e = grad_uses_coop(NP) ? launch_fwd_coop(d, f, cus, stream) : launch_fwd_mfma(d, f, cus, stream);
@@ -458,6 +543,7 @@ hmm_status hmm_forward_backward_grad(const hmm_bank *bank, const hmm_batch *batc
     a.cnt_A = cnt_A;
     a.cnt_B = cnt_B;
     a.nbt = nbt;
+    a.max_grid = max_grid(L.wg_per_cu, cus);
     if (coop && adj_coop_streams(NP)) {
         float *frag = (float *)(w + L.frag);
         launch_coop_frags(bank->A, frag, K, N, NP, stream);
@@ -505,8 +591,10 @@ hmm_status hmm_viterbi(const hmm_bank *bank, const hmm_batch *batch, float *scor
     v.bp = (uint8_t *)(w + L.bp);
     v.score = score;
     v.path = path;
+    const int cus = device_cu_count();
+    v.max_grid = max_grid(L.wg_per_cu, cus);
     const int pr = prof_begin(stream, HMM_PROF_VITERBI);
-    const hipError_t e = launch_viterbi(d, v, device_cu_count(), stream);
+    const hipError_t e = launch_viterbi(d, v, cus, stream);
     prof_end(stream, pr);
     return e == hipSuccess ? HMM_OK : HMM_ERR_HIP;
 }
@@ -546,6 +634,86 @@ hmm_status hmm_workspace_error(const void *ws, hipStream_t stream, int32_t *firs
 hmm_status hmm_select_kernel(int32_t kind) {
     if (kind < HMM_KERNEL_AUTO || kind > HMM_KERNEL_SCAN) return HMM_ERR_ARG;
     g_kernel_kind.store(kind, std::memory_order_relaxed);
+    return HMM_OK;
+}
+
+hmm_status hmm_call_kernel(const hmm_bank *bank, const hmm_batch *batch, int32_t op, int32_t *kernel) {
+    if (!kernel) return HMM_ERR_NULL;
+    if (op < HMM_OP_FORWARD || op > HMM_OP_VITERBI) return HMM_ERR_ARG;
+    hmm_status rc = check_shapes(bank, batch);
+    if (rc != HMM_OK) return rc;
+    const CallChoice cc = call_choice(bank, batch, op);
+    if (op == HMM_OP_GRAD || op == HMM_OP_VITERBI) {
+        if (!batched_capable(bank, batch, op)) return HMM_ERR_UNSUPPORTED;
+        *kernel = op == HMM_OP_VITERBI ? HMM_KERNEL_BATCHED
+                                       : (grad_uses_coop(padded_states(bank->N)) ? HMM_KERNEL_COOP : HMM_KERNEL_TILE16);
+        return HMM_OK;
+    }
+    int fam = HMM_KERNEL_PLAIN;
+    if ((rc = forward_family(bank, batch, op, cc.kind, &fam)) != HMM_OK) return rc;
+    *kernel = fam;
+    return HMM_OK;
+}
+
+hmm_status hmm_tune_key_of(const hmm_bank *bank, const hmm_batch *batch, int32_t op, hmm_tune_key *key) {
+    if (!key) return HMM_ERR_NULL;
+    if (op < HMM_OP_FORWARD || op > HMM_OP_VITERBI) return HMM_ERR_ARG;
+    const hmm_status rc = check_shapes(bank, batch);
+    if (rc != HMM_OK) return rc;
+    *key = key_of(bank, batch, op);
+    return HMM_OK;
+}
+
+static bool tune_key_valid(const hmm_tune_key *k) {
+    return k->op >= HMM_OP_FORWARD && k->op <= HMM_OP_VITERBI && (k->all_pairs == 0 || k->all_pairs == 1) &&
+           k->K >= 1 && k->K <= 65536 && k->N >= 1 && k->N <= HMM_MAX_STATES && k->M >= 1 &&
+           k->M <= HMM_MAX_SYMBOLS && k->s_bucket >= 0 && k->s_bucket <= 31 && k->len_bucket >= 0 &&
+           k->len_bucket <= 31;
+}
+
+hmm_status hmm_tune_set(const hmm_tune_key *key, const hmm_tune_choice *choice) {
+    if (!key) return HMM_ERR_NULL;
+    if (!tune_key_valid(key)) return HMM_ERR_ARG;
+    if (choice) {
+        if (choice->kernel < HMM_KERNEL_AUTO || choice->kernel > HMM_KERNEL_SCAN) return HMM_ERR_ARG;
+        if ((key->op == HMM_OP_GRAD || key->op == HMM_OP_VITERBI) && choice->kernel != HMM_KERNEL_AUTO &&
+            choice->kernel != HMM_KERNEL_BATCHED)
+            return HMM_ERR_ARG;
+        if (choice->wg_per_cu < 0 || choice->wg_per_cu > HMM_TUNE_MAX_WG) return HMM_ERR_ARG;
+    }
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    int at = -1;
+    for (int i = 0; i < g_tune_n; ++i)
+        if (same_key(g_tune[i].key, *key)) at = i;
+    if (!choice) {
+        if (at >= 0) g_tune[at] = g_tune[--g_tune_n];
+        return HMM_OK;
+    }
+    if (at < 0) {
+        if (g_tune_n == HMM_TUNE_MAX) return HMM_ERR_UNSUPPORTED;
+        at = g_tune_n++;
+    }
+    g_tune[at].key = *key;
+    g_tune[at].choice = *choice;
+    return HMM_OK;
+}
+
+hmm_status hmm_tune_get(const hmm_tune_key *key, hmm_tune_choice *choice, int32_t *found) {
+    if (!key || !choice || !found) return HMM_ERR_NULL;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    *found = 0;
+    for (int i = 0; i < g_tune_n; ++i)
+        if (same_key(g_tune[i].key, *key)) {
+            *choice = g_tune[i].choice;
+            *found = 1;
+            break;
+        }
+    return HMM_OK;
+}
+
+hmm_status hmm_tune_clear(void) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_n = 0;
     return HMM_OK;
 }
 

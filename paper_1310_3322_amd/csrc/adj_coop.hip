@@ -552,7 +552,7 @@ hipError_t launch_r(const DevPtrs &d, const AdjLaunch &a, int cu_count, hipStrea
     constexpr int BO = adj_bo(R);
     constexpr bool STREAM = BO > 1;
     if (STREAM && a.frag == nullptr) return hipErrorInvalidValue;
-    const int grid = persistent_grid(grid_r<R>(a.M, cu_count, a.K), tile_bound(a.S, a.K, false, TILE), 1, a.K);
+    const int grid = persistent_grid(grid_r<R>(a.M, cu_count, a.K), tile_bound(a.S, a.K, false, TILE), 1, a.K, a.max_grid);
     if (grid > a.seg_slots) return hipErrorInvalidValue;
     if (use_nb_lds<R>(a.M))
         k_adj_coop<R, BO, true, STREAM><<<grid, R / BO * WAVE, nb_lds_bytes<R>(a.M), st>>>(d, a);

@@ -361,7 +361,7 @@ template <int R>
 hipError_t launch_r(const DevPtrs &d, const AdjLaunch &a, int cu_count, hipStream_t st) {
     int waves = 4;
     const int full = grid_for<R>(a.M, cu_count, a.K, true, &waves);
-    const int grid = persistent_grid(full, tile_bound(a.S, a.K, false, TILE), waves, a.K);
+    const int grid = persistent_grid(full, tile_bound(a.S, a.K, false, TILE), waves, a.K, a.max_grid);
     if (grid * waves > a.seg_slots) return hipErrorInvalidValue;
     switch (pick_variant<R>(a.M)) {
         case 0:

@@ -207,7 +207,7 @@ hipError_t launch_t(const DevPtrs &d, const FwdLaunch &f, int cu_count, hipStrea
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, R / BO * WAVE, 0);
     if (e != hipSuccess) return e;
     if (per_cu < 1) per_cu = 1;
-    const int grid = persistent_grid(cu_count * per_cu, tile_bound(f.S, f.K, f.all_pairs, TILE), 1, f.K);
+    const int grid = persistent_grid(cu_count * per_cu, tile_bound(f.S, f.K, f.all_pairs, TILE), 1, f.K, f.max_grid);
     hipLaunchKernelGGL(kern, dim3(grid), dim3(R / BO * WAVE), 0, st, d, f);
     return hipGetLastError();
 }

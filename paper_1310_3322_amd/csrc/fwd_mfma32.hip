@@ -244,7 +244,7 @@ hipError_t launch_t(const DevPtrs &d, const FwdLaunch &f, int cu_count, hipStrea
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, WAVES32 * WAVE, lds);
     if (e != hipSuccess) return e;
     if (per_cu < 1) per_cu = 1;
-    const int grid = persistent_grid(cu_count * per_cu, tile_bound(f.S, f.K, f.all_pairs, T32), WAVES32, f.K);
+    const int grid = persistent_grid(cu_count * per_cu, tile_bound(f.S, f.K, f.all_pairs, T32), WAVES32, f.K, f.max_grid);
     hipLaunchKernelGGL(kern, dim3(grid), dim3(WAVES32 * WAVE), lds, st, d, f);
     return hipGetLastError();
 }

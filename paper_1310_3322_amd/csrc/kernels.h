@@ -26,19 +26,23 @@ struct Layout {
     size_t bp;       // uint8 [total][NP] Viterbi back-pointers (bt then holds ln B transposed)
     size_t scan;     // time-parallel forward: chunk products, exponents, flags (ScanWs)
     int32_t scan_nch;    // chunks per pair of the time-parallel forward (0: not used)
+    int32_t kind;        // kernel family of the call (HMM_KERNEL_*, after the tuning table)
+    int32_t wg_per_cu;   // cap on resident workgroups per CU of persistent launches (0: none)
     size_t total;
     int32_t nck;         // checkpoints per sequence slot
     int32_t seg_slots;   // persistent waves of the gradient kernel
     int64_t seg_stride;  // floats per segment slot
 };
 
-// Persistent launches: the occupancy-limited grid, reduced when a host-side
-// bound on the work items (tiles) is far smaller, so that a small batch does
-// not send every resident wave to the same queue counters (same-address
-// atomics serialise in L2); then rounded down to a multiple of K when it is at
-// least K, so that every model gets the same number of workgroups.
-inline int persistent_grid(int occ_grid, int64_t items_bound, int items_per_wg, int K) {
-    int grid = occ_grid;
+// Persistent launches: the occupancy-limited grid, capped at max_grid when
+// that is positive (a tuned number of workgroups per CU), reduced when a
+// host-side bound on the work items (tiles) is far smaller, so that a small
+// batch does not send every resident wave to the same queue counters
+// (same-address atomics serialise in L2); then rounded down to a multiple of K
+// when it is at least K, so that every model gets the same number of workgroups.
+inline int persistent_grid(int occ_grid, int64_t items_bound, int items_per_wg, int K, int max_grid) {
+    int grid = (max_grid > 0 && max_grid < occ_grid) ? max_grid : occ_grid;
+    occ_grid = grid;
     const int64_t need = (items_bound + items_per_wg - 1) / items_per_wg;
     if (need * 2 < grid) {
         const int64_t floor_k = K < occ_grid ? K : occ_grid;
@@ -90,6 +94,7 @@ struct FwdLaunch {
     int32_t *ckexp;
     int32_t *flag;    // [S] per sorted position: 1 = no finite likelihood (gradient only)
     int nck;
+    int max_grid;     // cap on the persistent grid (0: occupancy limit)
 };
 bool fwd_mfma_supported(int NP);
 hipError_t launch_fwd_mfma(const DevPtrs &d, const FwdLaunch &f, int cu_count, hipStream_t st);
@@ -134,6 +139,7 @@ struct AdjLaunch {
     float *cnt_pi, *cnt_A, *cnt_B;
     float *nbt;         // [K][M][NP] zeroed symbol-major emission counts (cooperative kernel)
     const float *frag;  // pre-arranged fragments when the cooperative kernel streams them
+    int max_grid;       // cap on the persistent grid (0: occupancy limit)
 };
 bool adj_mfma_supported(int NP);
 // adj_coop.hip: cooperative-tile backward (one wave per 16-state block)
@@ -157,6 +163,7 @@ struct VitLaunch {
     uint8_t *bp;        // [total][NP] back-pointers
     float *score;       // [S]
     int32_t *path;      // [total]
+    int max_grid;       // cap on the persistent grid (0: occupancy limit)
 };
 bool viterbi_supported(int NP);
 void launch_log_transpose_b(const float *B, float *lnbt, int K, int N, int M, int NP, hipStream_t st);

@@ -231,7 +231,7 @@ hipError_t launch_t(const DevPtrs &d, const VitLaunch &v, int cu_count, hipStrea
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, VWAVES * WAVE, 0);
     if (e != hipSuccess) return e;
     if (per_cu < 1) per_cu = 1;
-    const int grid = persistent_grid(cu_count * per_cu, tile_bound(v.S, v.K, false, WAVE / NP), VWAVES, v.K);
+    const int grid = persistent_grid(cu_count * per_cu, tile_bound(v.S, v.K, false, WAVE / NP), VWAVES, v.K, v.max_grid);
     hipLaunchKernelGGL(kern, dim3(grid), dim3(VWAVES * WAVE), 0, st, d, v);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_viterbi_trace_wave<NP>, dim3((v.S + VWAVES - 1) / VWAVES), dim3(VWAVES * WAVE), 0, st, d, v);

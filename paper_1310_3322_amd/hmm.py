@@ -24,7 +24,9 @@ OP_FORWARD, OP_CLASSIFY, OP_GRAD, OP_VITERBI = 0, 1, 2, 3
 KERNEL_AUTO, KERNEL_PLAIN, KERNEL_BATCHED, KERNEL_TILE16, KERNEL_TILE32, KERNEL_COOP, KERNEL_SCAN = 0, 1, 2, 3, 4, 5, 6
 EXPORTS = ("hmm_workspace_size", "hmm_forward_loglik", "hmm_classify", "hmm_forward_backward_grad",
            "hmm_viterbi", "hmm_reestimate_rows", "hmm_softmax_rows", "hmm_logit_grad", "hmm_workspace_error", "hmm_select_kernel",
+           "hmm_tune_key_of", "hmm_tune_set", "hmm_tune_get", "hmm_tune_clear", "hmm_call_kernel",
            "hmm_profile_enable", "hmm_profile_read", "hmm_status_string")
+TUNE_MAX, TUNE_MAX_WG = 256, 64
 PROF_FWD_BATCHED, PROF_ADJ_BATCHED, PROF_FWD_PLAIN, PROF_VITERBI = 0, 1, 2, 3
 
 
@@ -43,6 +45,19 @@ class Batch(ctypes.Structure):
     _fields_ = [("S", ctypes.c_int32), ("symbols", ctypes.c_void_p), ("offsets", ctypes.c_void_p),
                 ("lengths", ctypes.c_void_p), ("model_of_seq", ctypes.c_void_p),
                 ("max_len", ctypes.c_int32), ("total_symbols", ctypes.c_int64)]
+
+
+class TuneKey(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_int32), ("all_pairs", ctypes.c_int32), ("K", ctypes.c_int32),
+                ("N", ctypes.c_int32), ("M", ctypes.c_int32), ("s_bucket", ctypes.c_int32),
+                ("len_bucket", ctypes.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
+class TuneChoice(ctypes.Structure):
+    _fields_ = [("kernel", ctypes.c_int32), ("wg_per_cu", ctypes.c_int32)]
 
 
 _lib = None
@@ -79,6 +94,16 @@ def load_library(path: str = LIB_PATH):
     lib.hmm_workspace_error.argtypes = [P, P, ctypes.POINTER(ctypes.c_int32)]
     lib.hmm_select_kernel.restype = st
     lib.hmm_select_kernel.argtypes = [ctypes.c_int32]
+    lib.hmm_tune_key_of.restype = st
+    lib.hmm_tune_key_of.argtypes = [BP, QP, ctypes.c_int32, ctypes.POINTER(TuneKey)]
+    lib.hmm_tune_set.restype = st
+    lib.hmm_tune_set.argtypes = [ctypes.POINTER(TuneKey), ctypes.POINTER(TuneChoice)]
+    lib.hmm_tune_get.restype = st
+    lib.hmm_tune_get.argtypes = [ctypes.POINTER(TuneKey), ctypes.POINTER(TuneChoice), ctypes.POINTER(ctypes.c_int32)]
+    lib.hmm_tune_clear.restype = st
+    lib.hmm_tune_clear.argtypes = []
+    lib.hmm_call_kernel.restype = st
+    lib.hmm_call_kernel.argtypes = [BP, QP, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
     lib.hmm_profile_enable.restype = st
     lib.hmm_profile_enable.argtypes = [ctypes.c_int32]
     lib.hmm_profile_read.restype = st
@@ -173,6 +198,40 @@ class Problem:
 
 def select_kernel(kind: int):
     _check("hmm_select_kernel", load_library().hmm_select_kernel(int(kind)))
+
+
+def tune_key(bank: Bank, batch: Batch, op: int) -> TuneKey:
+    """Tuning-table key of a call (host only)."""
+    k = TuneKey()
+    _check("hmm_tune_key_of", load_library().hmm_tune_key_of(ctypes.byref(bank), ctypes.byref(batch), int(op),
+                                                             ctypes.byref(k)))
+    return k
+
+
+def tune_set(key: TuneKey, kernel: Optional[int], wg_per_cu: int = 0):
+    """Installs the choice (kernel family, workgroups per CU) for `key`; kernel None removes the entry."""
+    c = None if kernel is None else ctypes.byref(TuneChoice(int(kernel), int(wg_per_cu)))
+    _check("hmm_tune_set", load_library().hmm_tune_set(ctypes.byref(key), c))
+
+
+def tune_get(key: TuneKey) -> Optional[tuple]:
+    """(kernel, wg_per_cu) installed for `key`, or None."""
+    c = TuneChoice()
+    found = ctypes.c_int32(0)
+    _check("hmm_tune_get", load_library().hmm_tune_get(ctypes.byref(key), ctypes.byref(c), ctypes.byref(found)))
+    return (int(c.kernel), int(c.wg_per_cu)) if found.value else None
+
+
+def tune_clear():
+    _check("hmm_tune_clear", load_library().hmm_tune_clear())
+
+
+def call_kernel(bank: Bank, batch: Batch, op: int) -> int:
+    """Kernel family (KERNEL_*) a call of `op` on this shape would run now (host only)."""
+    k = ctypes.c_int32(0)
+    _check("hmm_call_kernel", load_library().hmm_call_kernel(ctypes.byref(bank), ctypes.byref(batch), int(op),
+                                                             ctypes.byref(k)))
+    return int(k.value)
 
 
 def forward_loglik(p: Problem, out: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None,

@@ -1,0 +1,265 @@
+"""Autotuner of the batched kernels.
+
+The paper's component configuration (Sec. 4.1) leaves the block size of the HMM
+stage to the user, 16 by default.  Here the equivalent knobs are picked by
+measurement, per call shape:
+
+  * the kernel family of the forward (16-sequence tiles, 32-sequence tiles,
+    one workgroup per tile, or the time-parallel product tree), which fixes the
+    tile shape, and
+  * the cap on resident workgroups per compute unit of the persistent launches
+    (forward, gradient and Viterbi decoding), which sets how many queue
+    consumers share a CU and its L2 slice.
+
+For one call shape, `tune` runs the library's default choice first and keeps
+its outputs as the reference, then runs every candidate the library accepts for
+that shape, times each with HIP events on the call's stream, and rejects every
+candidate whose outputs disagree with the reference beyond what two correct
+FP32 evaluations may differ by.  The fastest accepted candidate goes into the
+library's tuning table (hmm_tune_set), which later calls of the same shape
+consult on the host.  The results persist as JSON keyed by GPU architecture and
+call shape (`save_cache` / `load_cache`).
+
+Every step runs through the library's entry points; this module only
+schedules calls, times them and compares their outputs.
+"""
+from __future__ import annotations
+
+import json
+import os
+import statistics
+from typing import Optional
+
+import torch
+
+from . import hmm
+
+OP_NAMES = {hmm.OP_FORWARD: "forward", hmm.OP_CLASSIFY: "classify", hmm.OP_GRAD: "grad",
+            hmm.OP_VITERBI: "viterbi"}
+KERNEL_NAMES = {hmm.KERNEL_AUTO: "auto", hmm.KERNEL_PLAIN: "plain", hmm.KERNEL_BATCHED: "batched",
+                hmm.KERNEL_TILE16: "tile16", hmm.KERNEL_TILE32: "tile32", hmm.KERNEL_COOP: "coop",
+                hmm.KERNEL_SCAN: "scan"}
+FORWARD_KINDS = (hmm.KERNEL_TILE16, hmm.KERNEL_TILE32, hmm.KERNEL_COOP, hmm.KERNEL_SCAN)
+WG_CAPS = (0, 1, 2, 4)
+
+# Two correct FP32 evaluations of log P each lie within 1e-5 (relative) of the
+# exact value, so they may differ from each other by up to twice that; the
+# expected counts likewise (1e-4 each, norm-wise).  Viterbi decoding does the
+# same arithmetic in the same order whatever the grid, so it must be identical.
+LL_TOL = 2e-5
+COUNT_TOL = 2e-4
+
+
+def device_arch(device=None) -> str:
+    """Architecture name of the GPU (e.g. gfx950), without feature flags."""
+    return torch.cuda.get_device_properties(device or torch.cuda.current_device()).gcnArchName.split(":")[0]
+
+
+def _candidates(op: int):
+    if op in (hmm.OP_FORWARD, hmm.OP_CLASSIFY):
+        for kind in FORWARD_KINDS:
+            for cap in (WG_CAPS if kind != hmm.KERNEL_SCAN else (0,)):
+                yield kind, cap
+    else:
+        for cap in WG_CAPS:
+            yield hmm.KERNEL_BATCHED, cap
+
+
+class _Call:
+    """One call shape with its output buffers; run(ws) enqueues the call."""
+
+    def __init__(self, p: hmm.Problem, op: int, stream):
+        self.p, self.op, self.stream = p, op, stream
+        dev = p.pi.device
+        if op == hmm.OP_FORWARD:
+            self.batch = p.batch
+            shape = (p.S,) if p.model_of_seq is not None else (p.S, p.K)
+            self.outs = [torch.empty(shape, dtype=torch.float32, device=dev)]
+        elif op == hmm.OP_CLASSIFY:
+            self.batch = p.batch_without_models()
+            self.outs = [torch.empty(p.S, dtype=torch.int32, device=dev),
+                         torch.empty((p.S, p.K), dtype=torch.float32, device=dev)]
+        elif op == hmm.OP_GRAD:
+            self.batch = p.batch
+            self.outs = [torch.empty(p.S, dtype=torch.float32, device=dev),
+                         torch.empty((p.K, p.N), dtype=torch.float32, device=dev),
+                         torch.empty((p.K, p.N, p.N), dtype=torch.float32, device=dev),
+                         torch.empty((p.K, p.N, p.M), dtype=torch.float32, device=dev)]
+        elif op == hmm.OP_VITERBI:
+            self.batch = p.batch
+            self.outs = [torch.empty(p.S, dtype=torch.float32, device=dev),
+                         torch.empty(p.total_symbols, dtype=torch.int32, device=dev)]
+        else:
+            raise ValueError(f"unknown op {op}")
+        self._ws = None
+
+    def workspace(self) -> torch.Tensor:
+        n = self.p.workspace_size(self.op, self.batch)
+        if n == 0:
+            raise hmm.HMMError("hmm_workspace_size", -2)
+        if self._ws is None or self._ws.numel() < n:
+            self._ws = None
+            self._ws = torch.empty(n, dtype=torch.uint8, device=self.p.pi.device)
+        return self._ws
+
+    def run(self, ws: torch.Tensor):
+        p, o, st = self.p, self.outs, self.stream
+        if self.op == hmm.OP_FORWARD:
+            hmm.forward_loglik(p, out=o[0], ws=ws, stream=st)
+        elif self.op == hmm.OP_CLASSIFY:
+            hmm.classify(p, labels=o[0], loglik=o[1], ws=ws, stream=st)
+        elif self.op == hmm.OP_GRAD:
+            hmm.forward_backward_grad(p, phase=0, loglik=o[0], counts=(o[1], o[2], o[3]), ws=ws, stream=st)
+        else:
+            hmm.viterbi(p, score=o[0], path=o[1], ws=ws, stream=st)
+
+    def snapshot(self):
+        return [t.clone() for t in self.outs]
+
+
+def _ll_mismatch(a: torch.Tensor, ref: torch.Tensor) -> Optional[str]:
+    fa, fr = torch.isfinite(a), torch.isfinite(ref)
+    if not torch.equal(fa, fr):
+        return "finite/non-finite pattern differs"
+    if not torch.equal(torch.isnan(a), torch.isnan(ref)):
+        return "NaN pattern differs"
+    if not torch.equal(a[~fa & ~torch.isnan(a)], ref[~fr & ~torch.isnan(ref)]):
+        return "infinite values differ"
+    if fa.any():
+        d = ((a[fa].double() - ref[fr].double()).abs() / ref[fr].double().abs().clamp_min(1.0)).max().item()
+        if d > LL_TOL:
+            return f"log-likelihood differs by {d:.2e} (relative)"
+    return None
+
+
+def _mismatch(op: int, outs, ref) -> Optional[str]:
+    if op == hmm.OP_FORWARD:
+        return _ll_mismatch(outs[0], ref[0])
+    if op == hmm.OP_CLASSIFY:
+        if not torch.equal(outs[0], ref[0]):
+            return "labels differ"
+        return _ll_mismatch(outs[1], ref[1])
+    if op == hmm.OP_GRAD:
+        m = _ll_mismatch(outs[0], ref[0])
+        if m:
+            return m
+        for name, a, r in zip(("n_pi", "n_A", "n_B"), outs[1:], ref[1:]):
+            nr = r.double().norm().item()
+            d = (a.double() - r.double()).norm().item() / max(nr, 1e-30)
+            if not d <= COUNT_TOL:
+                return f"{name} differs by {d:.2e} (norm-wise)"
+        return None
+    if not torch.equal(torch.isnan(outs[0]), torch.isnan(ref[0])):
+        return "score NaN pattern differs"
+    ok = ~torch.isnan(ref[0])
+    if not torch.equal(outs[0][ok], ref[0][ok]) or not torch.equal(outs[1], ref[1]):
+        return "decoding differs"
+    return None
+
+
+def _time(call: _Call, ws: torch.Tensor, warmup: int, reps: int) -> float:
+    st = call.stream
+    for _ in range(warmup):
+        call.run(ws)
+    times = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        call.run(ws)
+        e1.record(st)
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1))
+    return statistics.median(times)
+
+
+def tune(p: hmm.Problem, op: int, warmup: int = 1, reps: int = 3, stream=None, log=None) -> dict:
+    """Tunes the calls of `op` on problem `p`'s shape and installs the fastest
+    accepted choice.  Sets the kernel selector to HMM_KERNEL_AUTO (the table
+    applies only then).  Returns a record with the key, the chosen kernel and
+    grid cap, and every candidate's time and verdict."""
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    hmm.select_kernel(hmm.KERNEL_AUTO)
+    call = _Call(p, op, stream)
+    key = hmm.tune_key(p.bank, call.batch, op)
+    hmm.tune_set(key, None)
+    # the library's default choice: reference outputs and baseline time
+    ws = call.workspace()
+    call.run(ws)
+    torch.cuda.synchronize()
+    ref = call.snapshot()
+    base_ms = _time(call, ws, warmup, reps)
+    cands = [{"kernel": KERNEL_NAMES[hmm.KERNEL_AUTO], "wg_per_cu": 0, "ms": base_ms, "ok": True, "reason": "default"}]
+    best = (base_ms, hmm.KERNEL_AUTO, 0)
+    for kind, cap in _candidates(op):
+        hmm.tune_set(key, kind, cap)
+        rec = {"kernel": KERNEL_NAMES[kind], "wg_per_cu": cap, "ms": None, "ok": False, "reason": ""}
+        try:
+            ws = call.workspace()
+            for t in call.outs:
+                t.fill_(0)
+            call.run(ws)
+            torch.cuda.synchronize()
+        except hmm.HMMError as e:
+            if e.status != -4:  # HMM_ERR_UNSUPPORTED: the family does not take this shape
+                hmm.tune_set(key, None)
+                raise
+            rec["reason"] = "unsupported"
+            cands.append(rec)
+            continue
+        why = _mismatch(op, call.outs, ref)
+        if why:
+            rec["reason"] = why
+            cands.append(rec)
+            continue
+        ms = _time(call, ws, warmup, reps)
+        rec.update(ms=ms, ok=True)
+        cands.append(rec)
+        if ms < best[0]:
+            best = (ms, kind, cap)
+    hmm.tune_set(key, best[1], best[2])
+    result = {"op": OP_NAMES[op], "key": key.as_dict(),
+              "choice": {"kernel": KERNEL_NAMES[best[1]], "wg_per_cu": best[2]},
+              "ms": best[0], "default_ms": base_ms, "candidates": cands}
+    if log is not None:
+        log(result)
+    return result
+
+
+_KERNEL_IDS = {v: k for k, v in KERNEL_NAMES.items()}
+
+
+def save_cache(path: str, results, arch: Optional[str] = None):
+    """Writes tuning results (records of `tune`) as JSON, merged with the entries
+    already in `path` for other keys or architectures."""
+    arch = arch or device_arch()
+    entries = []
+    if os.path.exists(path):
+        with open(path) as f:
+            entries = json.load(f).get("entries", [])
+    new = [{"arch": arch, "key": r["key"], "choice": r["choice"], "ms": r["ms"]} for r in results]
+    keys = {(e["arch"], tuple(sorted(e["key"].items()))) for e in new}
+    kept = [e for e in entries if (e["arch"], tuple(sorted(e["key"].items()))) not in keys]
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump({"format": 1, "entries": kept + new}, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def load_cache(path: str, arch: Optional[str] = None) -> int:
+    """Installs the entries of a JSON cache that were tuned on `arch` (default:
+    the current GPU's).  Returns the number installed."""
+    arch = arch or device_arch()
+    with open(path) as f:
+        data = json.load(f)
+    if data.get("format") != 1:
+        raise ValueError(f"{path}: unknown tuning-cache format")
+    n = 0
+    for e in data.get("entries", []):
+        if e.get("arch") != arch:
+            continue
+        key = hmm.TuneKey(**{f: int(e["key"][f]) for f, _ in hmm.TuneKey._fields_})
+        hmm.tune_set(key, _KERNEL_IDS[e["choice"]["kernel"]], int(e["choice"]["wg_per_cu"]))
+        n += 1
+    return n

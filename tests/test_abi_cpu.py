@@ -131,3 +131,152 @@ def test_kernel_selector(lib):
 def test_status_strings(lib):
     for code, name in hmm.STATUS.items():
         assert lib.hmm_status_string(code).decode() == name
+
+
+def _key(op=0, all_pairs=1, K=4, N=16, M=32, sb=7, lb=6):
+    return hmm.TuneKey(op, all_pairs, K, N, M, sb, lb)
+
+
+def test_tune_key_buckets(lib):
+    k = hmm.tune_key(_bank(), _batch(S=100, max_len=50), hmm.OP_FORWARD)
+    assert k.as_dict() == {"op": 0, "all_pairs": 1, "K": 4, "N": 16, "M": 32, "s_bucket": 7, "len_bucket": 6}
+    k = hmm.tune_key(_bank(), _batch(S=128, max_len=64, models=True), hmm.OP_FORWARD)
+    assert (k.all_pairs, k.s_bucket, k.len_bucket) == (0, 8, 7)
+    k = hmm.tune_key(_bank(), _batch(S=0, max_len=0, models=True), hmm.OP_CLASSIFY)
+    assert (k.all_pairs, k.s_bucket, k.len_bucket) == (1, 0, 0)
+    k = hmm.tune_key(_bank(), _batch(models=True), hmm.OP_GRAD)
+    assert k.all_pairs == 0
+    with pytest.raises(hmm.HMMError):
+        hmm.tune_key(_bank(), _batch(), 9)
+    with pytest.raises(hmm.HMMError):
+        hmm.tune_key(hmm.Bank(0, 16, 32, 0x1000, 0x2000, 0x3000), _batch(), 0)
+
+
+def test_tune_table_set_get_remove(lib):
+    hmm.tune_clear()
+    k = _key()
+    assert hmm.tune_get(k) is None
+    hmm.tune_set(k, hmm.KERNEL_TILE32, 2)
+    assert hmm.tune_get(k) == (hmm.KERNEL_TILE32, 2)
+    hmm.tune_set(k, hmm.KERNEL_COOP, 0)  # replaces
+    assert hmm.tune_get(k) == (hmm.KERNEL_COOP, 0)
+    other = _key(sb=8)
+    assert hmm.tune_get(other) is None
+    hmm.tune_set(k, None)
+    assert hmm.tune_get(k) is None
+    hmm.tune_set(k, None)  # removing an absent entry is fine
+    # invalid keys and choices
+    bad = [(_key(op=4), hmm.KERNEL_AUTO, 0), (_key(all_pairs=2), hmm.KERNEL_AUTO, 0), (_key(K=0), hmm.KERNEL_AUTO, 0),
+           (_key(N=257), hmm.KERNEL_AUTO, 0), (_key(sb=32), hmm.KERNEL_AUTO, 0), (_key(), 7, 0),
+           (_key(), hmm.KERNEL_AUTO, -1), (_key(), hmm.KERNEL_AUTO, hmm.TUNE_MAX_WG + 1),
+           (_key(op=hmm.OP_GRAD, all_pairs=0), hmm.KERNEL_TILE16, 0),
+           (_key(op=hmm.OP_VITERBI, all_pairs=0), hmm.KERNEL_SCAN, 0)]
+    for key, kind, cap in bad:
+        with pytest.raises(hmm.HMMError) as e:
+            hmm.tune_set(key, kind, cap)
+        assert e.value.status == -6
+    hmm.tune_set(_key(op=hmm.OP_GRAD, all_pairs=0), hmm.KERNEL_BATCHED, 4)
+    assert lib.hmm_tune_set(None, None) == -1
+    assert lib.hmm_tune_get(ctypes.byref(k), None, None) == -1
+    hmm.tune_clear()
+    assert hmm.tune_get(_key(op=hmm.OP_GRAD, all_pairs=0)) is None
+
+
+def test_tune_table_capacity(lib):
+    hmm.tune_clear()
+    for i in range(hmm.TUNE_MAX):
+        hmm.tune_set(_key(K=i + 1), hmm.KERNEL_TILE16, 1)
+    with pytest.raises(hmm.HMMError) as e:
+        hmm.tune_set(_key(K=hmm.TUNE_MAX + 1), hmm.KERNEL_TILE16, 1)
+    assert e.value.status == -4
+    hmm.tune_set(_key(K=5), hmm.KERNEL_TILE32, 2)  # replacing still works when full
+    assert hmm.tune_get(_key(K=5)) == (hmm.KERNEL_TILE32, 2)
+    hmm.tune_set(_key(K=7), None)
+    hmm.tune_set(_key(K=hmm.TUNE_MAX + 1), hmm.KERNEL_TILE16, 1)  # a freed slot is reused
+    assert hmm.tune_get(_key(K=hmm.TUNE_MAX + 1)) == (hmm.KERNEL_TILE16, 1)
+    assert hmm.tune_get(_key(K=7)) is None
+    hmm.tune_clear()
+
+
+def test_tune_entry_sizes_workspace(lib):
+    """A tuned family applies to hmm_workspace_size too: the time-parallel forward
+    reserves its chunk products only when it is the call's choice, and a forced
+    selector overrides the table."""
+    hmm.tune_clear()
+    hmm.select_kernel(hmm.KERNEL_AUTO)
+    b, q = _bank(), _batch(S=1000, max_len=1000)
+    plain = lib.hmm_workspace_size(ctypes.byref(b), ctypes.byref(q), 0)
+    key = hmm.tune_key(b, q, hmm.OP_FORWARD)
+    try:
+        hmm.tune_set(key, hmm.KERNEL_SCAN, 0)
+        scan = lib.hmm_workspace_size(ctypes.byref(b), ctypes.byref(q), 0)
+        assert scan >= plain + 1000 * 4 * 16 * 1024  # 4 000 pairs x 16 chunks x (16x16 floats)
+        # another shape bucket is unaffected
+        assert lib.hmm_workspace_size(ctypes.byref(b), ctypes.byref(_batch(S=3000, max_len=1000)), 0) < scan
+        # a workspace sized before the entry was installed is refused before anything is enqueued
+        out = ctypes.c_void_p(0x8000)
+        assert lib.hmm_forward_loglik(ctypes.byref(b), ctypes.byref(q), out, ctypes.c_void_p(0x100000), plain,
+                                      None) == -3
+        hmm.select_kernel(hmm.KERNEL_TILE16)
+        assert lib.hmm_workspace_size(ctypes.byref(b), ctypes.byref(q), 0) == plain
+    finally:
+        hmm.select_kernel(hmm.KERNEL_AUTO)
+        hmm.tune_clear()
+    assert lib.hmm_workspace_size(ctypes.byref(b), ctypes.byref(q), 0) == plain
+
+
+def test_tune_cache_roundtrip(lib, tmp_path):
+    from paper_1310_3322_amd import tune
+    hmm.tune_clear()
+    path = str(tmp_path / "tune.json")
+    r1 = {"key": _key().as_dict(), "choice": {"kernel": "tile32", "wg_per_cu": 2}, "ms": 1.5}
+    r2 = {"key": _key(op=hmm.OP_VITERBI, all_pairs=0).as_dict(), "choice": {"kernel": "batched", "wg_per_cu": 1},
+          "ms": 0.5}
+    tune.save_cache(path, [r1], arch="gfx950")
+    tune.save_cache(path, [r2], arch="gfx950")          # merged
+    tune.save_cache(path, [dict(r1, choice={"kernel": "coop", "wg_per_cu": 0})], arch="gfx942")  # other arch
+    tune.save_cache(path, [dict(r1, choice={"kernel": "tile16", "wg_per_cu": 4})], arch="gfx950")  # replaces r1
+    assert tune.load_cache(path, arch="gfx950") == 2
+    assert hmm.tune_get(_key()) == (hmm.KERNEL_TILE16, 4)
+    assert hmm.tune_get(_key(op=hmm.OP_VITERBI, all_pairs=0)) == (hmm.KERNEL_BATCHED, 1)
+    hmm.tune_clear()
+    assert tune.load_cache(path, arch="gfx90a") == 0
+    assert hmm.tune_get(_key()) is None
+
+
+def test_call_kernel_resolution(lib):
+    """Which family a call would run: heuristics, then table, then a forced selector
+    (host only; the device count of compute units defaults to 256 without a GPU)."""
+    hmm.tune_clear()
+    hmm.select_kernel(hmm.KERNEL_AUTO)
+    try:
+        c3b, c3q = hmm.Bank(64, 32, 256, 1, 2, 3), hmm.Batch(65536, 4, 5, 6, None, 2048, 1 << 25)
+        assert hmm.call_kernel(c3b, c3q, hmm.OP_CLASSIFY) == hmm.KERNEL_TILE32
+        big = hmm.Bank(16, 256, 1024, 1, 2, 3)
+        own = hmm.Batch(16384, 4, 5, 6, 7, 4096, 1 << 26)
+        assert hmm.call_kernel(big, own, hmm.OP_FORWARD) == hmm.KERNEL_COOP
+        assert hmm.call_kernel(big, own, hmm.OP_GRAD) == hmm.KERNEL_COOP
+        one = hmm.Batch(1, 4, 5, 6, 7, 64, 64)
+        assert hmm.call_kernel(hmm.Bank(1, 8, 16, 1, 2, 3), one, hmm.OP_FORWARD) == hmm.KERNEL_SCAN
+        assert hmm.call_kernel(hmm.Bank(8, 32, 64, 1, 2, 3), hmm.Batch(9000, 4, 5, 6, 7, 100, 1 << 20),
+                               hmm.OP_GRAD) == hmm.KERNEL_TILE16
+        assert hmm.call_kernel(hmm.Bank(8, 32, 64, 1, 2, 3), one, hmm.OP_VITERBI) == hmm.KERNEL_BATCHED
+        with pytest.raises(hmm.HMMError) as e:
+            hmm.call_kernel(hmm.Bank(8, 100, 64, 1, 2, 3), one, hmm.OP_VITERBI)
+        assert e.value.status == -4
+        # the table
+        hmm.tune_set(hmm.tune_key(c3b, c3q, hmm.OP_CLASSIFY), hmm.KERNEL_TILE16, 2)
+        assert hmm.call_kernel(c3b, c3q, hmm.OP_CLASSIFY) == hmm.KERNEL_TILE16
+        hmm.tune_set(hmm.tune_key(big, own, hmm.OP_FORWARD), hmm.KERNEL_TILE32, 0)
+        with pytest.raises(hmm.HMMError) as e:
+            hmm.call_kernel(big, own, hmm.OP_FORWARD)
+        assert e.value.status == -4
+        # a forced selector ignores the table
+        hmm.select_kernel(hmm.KERNEL_PLAIN)
+        assert hmm.call_kernel(c3b, c3q, hmm.OP_CLASSIFY) == hmm.KERNEL_PLAIN
+        hmm.select_kernel(hmm.KERNEL_BATCHED)
+        assert hmm.call_kernel(c3b, c3q, hmm.OP_CLASSIFY) == hmm.KERNEL_TILE32
+        assert hmm.call_kernel(big, own, hmm.OP_FORWARD) == hmm.KERNEL_COOP
+    finally:
+        hmm.select_kernel(hmm.KERNEL_AUTO)
+        hmm.tune_clear()

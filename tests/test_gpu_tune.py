@@ -1,0 +1,183 @@
+"""Autotuner on the GPU (MI355X only): every choice the tuning table can hold
+gives the oracle's results, on shapes where the grid cap binds (more tiles than
+capped workgroups, so every workgroup drains its queue repeatedly), and `tune`
+installs an accepted choice that later calls use.
+
+Tolerances as in the parity tests: log-likelihood 1e-5 relative, counts 1e-4
+norm-wise, Viterbi scores 1e-5 relative with paths checked like the Viterbi tests.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_1310_3322_amd import hmm, tune, workloads
+
+pytestmark = pytest.mark.gpu
+
+LL_TOL = 1e-5
+GRAD_TOL = 1e-4
+CAPS = (0, 1, 2)
+
+
+@pytest.fixture(autouse=True)
+def _clean_table():
+    hmm.load_library()
+    hmm.select_kernel(hmm.KERNEL_AUTO)
+    hmm.tune_clear()
+    yield
+    hmm.tune_clear()
+    hmm.select_kernel(hmm.KERNEL_AUTO)
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def problem(w, own):
+    return hmm.Problem(dev(w.pi), dev(w.A), dev(w.B), dev(w.symbols), dev(w.offsets), dev(w.lengths),
+                       dev(w.owner) if own else None, max_len=w.max_len, total_symbols=w.total_symbols)
+
+
+def rel_err(gpu, ref):
+    gpu = np.asarray(gpu, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    assert np.array_equal(np.isnan(gpu), np.isnan(ref)), "NaN pattern differs"
+    assert np.array_equal(gpu[np.isinf(ref)], ref[np.isinf(ref)]), "infinities differ"
+    fin = np.isfinite(ref)
+    if not fin.any():
+        return 0.0
+    return float(np.max(np.abs(gpu[fin] - ref[fin]) / np.maximum(np.abs(ref[fin]), 1.0)))
+
+
+def counts_err(gpu, ref):
+    worst = 0.0
+    for g, r in zip(gpu, ref):
+        g = np.asarray(g, dtype=np.float64)
+        r = np.asarray(r, dtype=np.float64)
+        for k in range(r.shape[0]):
+            nr = np.linalg.norm(r[k])
+            worst = max(worst, np.linalg.norm(g[k] - r[k]) / nr if nr > 0 else np.linalg.norm(g[k]))
+    return worst
+
+
+def short_workload(seed, K, N, M, S, tmax, all_pairs, conc=0.6):
+    rng = np.random.default_rng([31, seed])
+    lengths = rng.integers(1, tmax + 1, size=S)
+    lengths[:3] = [0, 1, tmax]
+    return workloads.random_lengths_workload(rng, K=K, N=N, M=M, lengths=lengths, all_pairs=all_pairs, conc=conc)
+
+
+@pytest.mark.parametrize("N,all_pairs", [(16, True), (32, True), (32, False), (64, True)])
+def test_every_forward_table_choice(N, all_pairs):
+    """K=64 models: 64 x 38 tiles of 16 (all pairs), or 1127 tiles of 16 own-model,
+    outnumber the capped grids."""
+    print(f"[case] tune forward choices N={N} all_pairs={all_pairs}", flush=True)
+    S = 600 if all_pairs else 17000
+    w = short_workload(N, K=64, N=N, M=16, S=S, tmax=40, all_pairs=all_pairs)
+    ref = O.forward(w.pi, w.A, w.B, w.symbols, w.offsets, w.lengths, None if all_pairs else w.owner)
+    p = problem(w, not all_pairs)
+    key = hmm.tune_key(p.bank, p.batch, hmm.OP_FORWARD)
+    ran = 0
+    for kind in tune.FORWARD_KINDS:
+        for cap in CAPS:
+            hmm.tune_set(key, kind, cap)
+            try:
+                ll = hmm.forward_loglik(p).cpu().numpy()
+            except hmm.HMMError as e:
+                assert e.status == -4, (kind, cap)
+                continue
+            ran += 1
+            assert rel_err(ll, ref) <= LL_TOL, (kind, cap)
+    assert ran >= 3
+
+
+@pytest.mark.parametrize("N,S", [(32, 17000), (64, 8400)])
+def test_every_gradient_table_choice(N, S):
+    """N=32: 16-sequence tiles, 4 per workgroup (1070 tiles); N=64: one
+    cooperative workgroup per tile (533 tiles): both exceed the capped grids."""
+    print(f"[case] tune gradient choices N={N} S={S}", flush=True)
+    w = short_workload(100 + N, K=8, N=N, M=24, S=S, tmax=12, all_pairs=False)
+    ll_ref, *cnt_ref = O.counts(w.pi, w.A, w.B, w.symbols, w.offsets, w.lengths, w.owner)
+    p = problem(w, True)
+    key = hmm.tune_key(p.bank, p.batch, hmm.OP_GRAD)
+    for cap in CAPS:
+        hmm.tune_set(key, hmm.KERNEL_BATCHED, cap)
+        ll, cnt, _ = hmm.forward_backward_grad(p)
+        assert rel_err(ll.cpu().numpy(), ll_ref) <= LL_TOL, cap
+        assert counts_err([c.cpu().numpy() for c in cnt], cnt_ref) <= GRAD_TOL, cap
+
+
+def test_every_viterbi_table_choice():
+    """N=32: 8 sequences per workgroup, 4100 sequences -> 513 units per cap-1 grid of 256."""
+    print("[case] tune viterbi choices", flush=True)
+    w = short_workload(7, K=4, N=32, M=20, S=4100, tmax=30, all_pairs=False)
+    rs, rp, rm = O.viterbi(w.pi, w.A, w.B, w.symbols, w.offsets, w.lengths, w.owner)
+    p = problem(w, True)
+    key = hmm.tune_key(p.bank, p.batch, hmm.OP_VITERBI)
+    first = None
+    for cap in CAPS:
+        hmm.tune_set(key, hmm.KERNEL_BATCHED, cap)
+        sc, path = hmm.viterbi(p)
+        sc, path = sc.cpu().numpy(), path.cpu().numpy()
+        assert rel_err(sc, rs) <= LL_TOL, cap
+        if first is None:
+            first = (sc, path)
+        else:  # the decoding of a sequence does not depend on the grid
+            assert np.array_equal(sc, first[0]) and np.array_equal(path, first[1]), cap
+        # where the oracle's decision margins are clear, the paths agree
+        clear = np.repeat(rm > 1e-5 * np.maximum(np.abs(rs), 1.0) + 1e-4, w.lengths)
+        assert np.array_equal(path[clear], rp[clear]), cap
+
+
+@pytest.mark.parametrize("op", [hmm.OP_FORWARD, hmm.OP_CLASSIFY, hmm.OP_GRAD, hmm.OP_VITERBI])
+def test_tune_installs_an_accepted_choice(op):
+    print(f"[case] tune op={op}", flush=True)
+    own = op in (hmm.OP_GRAD, hmm.OP_VITERBI)
+    N = 64 if op == hmm.OP_GRAD else 16
+    w = short_workload(200 + op, K=6, N=N, M=12, S=300, tmax=120, all_pairs=not own)
+    p = problem(w, own)
+    r = tune.tune(p, op, warmup=1, reps=2)
+    assert r["op"] == tune.OP_NAMES[op]
+    chosen = (tune._KERNEL_IDS[r["choice"]["kernel"]], r["choice"]["wg_per_cu"])
+    key = hmm.TuneKey(**r["key"])
+    assert hmm.tune_get(key) == chosen
+    ok = [c for c in r["candidates"] if c["ok"]]
+    assert any((c["kernel"], c["wg_per_cu"]) == (r["choice"]["kernel"], r["choice"]["wg_per_cu"]) for c in ok)
+    assert r["ms"] == min(c["ms"] for c in ok)
+    assert all(c["reason"] in ("unsupported", "default", "") for c in r["candidates"]), r["candidates"]
+    # a call after tuning takes the installed choice and still matches the oracle
+    if op == hmm.OP_FORWARD:
+        ref = O.forward(w.pi, w.A, w.B, w.symbols, w.offsets, w.lengths, None)
+        assert rel_err(hmm.forward_loglik(p).cpu().numpy(), ref) <= LL_TOL
+    elif op == hmm.OP_CLASSIFY:
+        ref = O.forward(w.pi, w.A, w.B, w.symbols, w.offsets, w.lengths, None)
+        ll = torch.empty((p.S, p.K), dtype=torch.float32, device="cuda")
+        labels = hmm.classify(p, loglik=ll).cpu().numpy()
+        assert rel_err(ll.cpu().numpy(), ref) <= LL_TOL
+        top = np.sort(ref, axis=1)
+        clear = (top[:, -1] - top[:, -2]) > 1e-3 * np.maximum(np.abs(top[:, -1]), 1.0)
+        assert np.array_equal(labels[clear], np.argmax(ref, axis=1)[clear])
+    elif op == hmm.OP_GRAD:
+        ll_ref, *cnt_ref = O.counts(w.pi, w.A, w.B, w.symbols, w.offsets, w.lengths, w.owner)
+        ll, cnt, _ = hmm.forward_backward_grad(p)
+        assert rel_err(ll.cpu().numpy(), ll_ref) <= LL_TOL
+        assert counts_err([c.cpu().numpy() for c in cnt], cnt_ref) <= GRAD_TOL
+    else:
+        rs, _, _ = O.viterbi(w.pi, w.A, w.B, w.symbols, w.offsets, w.lengths, w.owner)
+        assert rel_err(hmm.viterbi(p)[0].cpu().numpy(), rs) <= LL_TOL
+
+
+def test_selector_overrides_table():
+    """A forced family ignores the table: an entry naming a family that does not
+    take the shape fails only while the selector is AUTO."""
+    w = short_workload(9, K=3, N=100, M=8, S=40, tmax=30, all_pairs=True)
+    p = problem(w, False)
+    key = hmm.tune_key(p.bank, p.batch, hmm.OP_FORWARD)
+    hmm.tune_set(key, hmm.KERNEL_TILE16, 0)  # one wave per tile takes at most 64 states
+    with pytest.raises(hmm.HMMError) as e:
+        hmm.forward_loglik(p)
+    assert e.value.status == -4
+    hmm.select_kernel(hmm.KERNEL_BATCHED)
+    ref = O.forward(w.pi, w.A, w.B, w.symbols, w.offsets, w.lengths, None)
+    assert rel_err(hmm.forward_loglik(p).cpu().numpy(), ref) <= LL_TOL
