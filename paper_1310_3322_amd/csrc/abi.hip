@@ -234,7 +234,7 @@ Layout make_layout(const hmm_bank *b, const hmm_batch *q, int op) {
             L.flag = take((size_t)S * sizeof(int32_t));
             const bool coop = grad_uses_coop(NP);
             L.seg_slots = coop ? adj_coop_slots(NP, M, K, device_cu_count()) : adj_mfma_slots(NP, M, K, device_cu_count());
-            L.seg_stride = coop ? adj_coop_seg_stride(NP, q->max_len) : adj_mfma_seg_stride(NP, q->max_len);
+            L.seg_stride = coop ? adj_coop_seg_stride(NP, M, q->max_len) : adj_mfma_seg_stride(NP, q->max_len);
             L.seg = take((size_t)L.seg_slots * L.seg_stride * sizeof(float));
             if (coop) L.nbt = take((size_t)K * M * NP * sizeof(float));
             if (coop && adj_coop_streams(NP)) L.frag = take((size_t)K * 2 * NP * NP * sizeof(float));

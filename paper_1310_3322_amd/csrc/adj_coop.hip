@@ -322,7 +322,7 @@ __global__ void __launch_bounds__(R / BO * WAVE) k_adj_coop(DevPtrs d, AdjLaunch
                                 float4{x[b][0], x[b][1], x[b][2], x[b][3]};
                             if (g == 0) psum[(t & 1) * R * TILE + (r0 + b) * TILE + sl] = part;
                         }
-                        __syncthreads();
+                        lds_barrier();  // LDS exchange only; segment entries are the wave's own
                     }
                     // ---- backward through the segment; the segment entries of step t - 1
                     // are requested during step t, and the emission row of step t at its start
@@ -474,7 +474,7 @@ __global__ void __launch_bounds__(R / BO * WAVE) k_adj_coop(DevPtrs d, AdjLaunch
                             *(float4 *)&wex[(t & 1) * TILE * XROW + sl * XROW + 16 * (r0 + b) + 4 * g] =
                                 float4{wn0, wn1, wn2, wn3};
                         }
-                        __syncthreads();
+                        lds_barrier();
                     }
                 }
                 if (DEFER) flush_pending();
@@ -513,6 +513,361 @@ __global__ void __launch_bounds__(R / BO * WAVE) k_adj_coop(DevPtrs d, AdjLaunch
     }
 }
 
+// Pipelined variant for 64 states with the LDS partial (one 16-state block
+// per wave): 2 R waves per tile, in two groups that advance in lockstep,
+// one barrier per step for all of them.  The backward group (waves 0 .. R-1)
+// walks segment j backwards: betahat, the emission counts and w_t, as in
+// k_adj_coop.  The recompute group (waves R .. 2R-1, wave R + w owning block w)
+// meanwhile recomputes segment j - 1 from its checkpoint into the other half of
+// the segment buffer and, for each backward step t of segment j, adds its rows
+// of C += X^T W from alphahat_t (its own entries of the previous phase) and
+// w_{t+1} (the exchange row the backward group reads in the same step).  A
+// tile thus takes nseg + 1 phases of at most L steps instead of 2 nseg, and the
+// two groups' matrix-core chains share each SIMD.  Every quantity is formed by
+// the same operations in the same order as in k_adj_coop.
+template <int R>
+__global__ void __launch_bounds__(2 * R * WAVE) k_adj_pipe(DevPtrs d, AdjLaunch a) {
+    using SH = AdjCoopShape<R, 1>;
+    constexpr int NP = SH::NP;
+    constexpr int XROW = SH::XROW;
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ __align__(16) float xch[SH::xch_floats];
+    __shared__ __align__(16) float wex[SH::w_floats];
+    __shared__ float atile_all[SH::at_floats];
+    __shared__ int32_t sym[2][ACH * TILE];
+    __shared__ float mlast[TILE];  // m_T of each sequence of the tile
+    __shared__ int32_t tile_sh;
+    float *nbl = (float *)smem;  // [M][NP] emission-count partial
+    // [R][M] bytes after the partial: per-wave table that finds repeated symbols in a step
+    volatile uint8_t *duptab = (volatile uint8_t *)(smem + (size_t)a.M * NP * 4);
+
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+    const bool rec = wid >= R;          // recompute group (wave-uniform)
+    const int w = rec ? wid - R : wid;  // owned 16-state block
+    const int sl = lane & 15, g = lane >> 4;
+    const int K = a.K, N = a.N, M = a.M;
+    const int swz = nb_swz(NP);
+    float *xbuf = xch;
+    float *psum = xch + CoopShape<R>::x_floats;
+    float *atile = atile_all + w * TILE * 17;  // [16 s][17] own alphahat block, transposed reads (recompute group)
+
+    // segment buffer: two halves (segment parity), each alphahat [Lcap][R][64]
+    // float4, then e and o [Lcap][R][64] int32
+    float *segf = a.seg + (size_t)blockIdx.x * a.seg_stride;
+    const int64_t half = a.seg_stride / 2;
+    const int Lcap = (int)(half / ((int64_t)R * WAVE * 6));
+    auto seg_alpha = [&](int j) { return (float4 *)(segf + (j & 1) * half); };
+    auto seg_e = [&](int j) { return (int32_t *)(segf + (j & 1) * half + (int64_t)Lcap * R * WAVE * 4); };
+    auto seg_o = [&](int j) { return (int32_t *)(segf + (j & 1) * half + (int64_t)Lcap * R * WAVE * 5); };
+    auto sidx = [&](int tl) { return ((size_t)tl * R + w) * WAVE + lane; };
+
+    const int G = gridDim.x;
+    const int k_first = G >= K ? (int)(blockIdx.x % K) : (int)blockIdx.x;
+    const int k_step = G >= K ? K : G;
+    for (int k = k_first; k < K; k += k_step) {
+        const int gbeg = a.gstart[k], gend = a.gstart[k + 1];
+        const int ntiles = (gend - gbeg + TILE - 1) / TILE;
+        const float *btk = a.bt + (size_t)k * M * NP;
+        float *nbt = a.nbt + (size_t)k * M * NP;
+        __syncthreads();
+        for (int i = threadIdx.x; i < M * NP; i += blockDim.x) nbl[i] = 0.0f;
+        __syncthreads();
+        const float *Ak = d.A + (size_t)k * N * N;
+        if (ntiles > 0) {
+            AdjFrags<R, 1, false> fr;
+            fr.load(Ak, N, w, g, sl, nullptr, 0);
+            floatx4 C[R];  // recompute group: rows 16 w + 4 g + v, columns 16 rj + sl
+#pragma unroll
+            for (int rj = 0; rj < R; ++rj) C[rj] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+
+            for (;;) {
+                if (threadIdx.x == 0) tile_sh = atomicAdd(&a.queue[k], 1);
+                __syncthreads();
+                const int tile = tile_sh;
+                __syncthreads();
+                if (tile >= ntiles) break;
+
+                const int pos = gbeg + tile * TILE + sl;
+                const bool has = pos < gend;
+                const int seq = has ? a.perm[pos] : 0;
+                int32_t T = 0;
+                int64_t off = 0;
+                bool act = false;
+                if (has) {
+                    T = d.lengths[seq];
+                    off = d.offsets[seq];
+                    const int mk = d.model_of_seq[seq];
+                    const bool bad = seq_bad(T, off, a.max_len, a.total) || mk < 0 || mk >= K;
+                    if (bad) T = 0;
+                    act = !bad && T > 0 && a.flag[pos] == 0;
+                }
+                const int Tmax = __builtin_amdgcn_readfirstlane(wave_max_int(T));
+                if (Tmax == 0) continue;
+                int L = 1;
+                while (L * L < Tmax) ++L;
+                const int nseg = (Tmax + L - 1) / L;
+                const float wgt = act ? (a.weight ? a.weight[seq] : 1.0f) : 0.0f;
+                const int32_t *sbase = T > 0 ? d.symbols + off : d.symbols;
+                const int tlim = T > 0 ? T - 1 : 0;
+                // backward group: gamma_1 (added after the tile) and the deferred emission counts
+                float gpi[4] = {};
+                float4 pend_gm = {0.0f, 0.0f, 0.0f, 0.0f};
+                int pend_ix = 0;
+                bool pend_on = false, pend_dup = false;
+                auto flush_pending = [&]() {
+                    if (pend_on && !pend_dup) {
+                        float4 q = *(const float4 *)&nbl[pend_ix];
+                        q.x += pend_gm.x;
+                        q.y += pend_gm.y;
+                        q.z += pend_gm.z;
+                        q.w += pend_gm.w;
+                        *(float4 *)&nbl[pend_ix] = q;
+                    }
+                    if (pend_on && pend_dup) {
+                        atomicAdd(&nbl[pend_ix], pend_gm.x);
+                        atomicAdd(&nbl[pend_ix + 1], pend_gm.y);
+                        atomicAdd(&nbl[pend_ix + 2], pend_gm.z);
+                        atomicAdd(&nbl[pend_ix + 3], pend_gm.w);
+                    }
+                    pend_on = false;
+                };
+                for (int i = threadIdx.x; i < TILE * XROW; i += blockDim.x) wex[(Tmax & 1) * TILE * XROW + i] = 0.0f;
+                if (threadIdx.x < TILE) mlast[threadIdx.x] = 1.0f;
+
+                // recompute group state: symbols staged by its first wave, chunk c in sym[c & 1]
+                int32_t nxt[ACH / 4];
+                float x[4] = {};
+                int e = 0, e_prev = 0;
+                int t0B = 0;
+                auto load_chunk = [&](int s0) {
+#pragma unroll
+                    for (int u = 0; u < ACH / 4; ++u) nxt[u] = sbase[min(s0 + 4 * u + g, tlim)];
+                };
+                auto store_chunk = [&](int c) {
+#pragma unroll
+                    for (int u = 0; u < ACH / 4; ++u) sym[c & 1][u * WAVE + lane] = nxt[u];
+                };
+                auto read_sym = [&](int t) {
+                    const int tl = t - t0B, pp = tl % ACH;
+                    int o = sym[(tl / ACH) & 1][(pp / 4) * WAVE + 16 * (pp % 4) + sl];
+                    return ((unsigned)o < (unsigned)M) ? o : 0;
+                };
+                // entry 0 of a recomputed segment: the checkpoint itself
+                auto store_entry0 = [&](int jB) {
+                    seg_alpha(jB)[sidx(0)] = float4{x[0], x[1], x[2], x[3]};
+                    seg_e(jB)[sidx(0)] = e_prev;
+                    seg_o(jB)[sidx(0)] = read_sym(t0B);
+                    if (t0B == T - 1 && w == 0 && g == 0) mlast[sl] = coop_step_sum<R>(psum + (t0B & 1) * R * TILE, sl);
+                };
+                // step tf's sum and exponent; alphahat_tf into the segment buffer
+                auto finish = [&](int jB, int tf) {
+                    const float cs = coop_step_sum<R>(psum + (tf & 1) * R * TILE, sl);
+                    e = frexp_exp(cs);
+                    seg_alpha(jB)[sidx(tf - t0B)] =
+                        float4{ldexp_f(x[0], -e), ldexp_f(x[1], -e), ldexp_f(x[2], -e), ldexp_f(x[3], -e)};
+                    seg_e(jB)[sidx(tf - t0B)] = e;
+                    if (tf == T - 1 && w == 0 && g == 0) mlast[sl] = ldexp_f(cs, -e);
+                };
+
+                for (int p = 0; p <= nseg; ++p) {
+                    const int jA = nseg - p;  // segment of the backward group (p >= 1)
+                    const int jB = jA - 1;    // segment of the recompute group (>= 0)
+                    const int t0A = jA * L;
+                    const int LA = p >= 1 ? min(t0A + L, Tmax) - t0A : 0;
+                    t0B = jB * L;
+                    const int LB = jB >= 0 ? min(t0B + L, Tmax) - t0B : 0;
+                    const int nint = max(LA, LB);
+                    // the previous phase's segment entries and m_T values are visible after this
+                    __syncthreads();
+                    float4 aq_n = {0.0f, 0.0f, 0.0f, 0.0f};
+                    int et_n = 0, ot_n = 0;
+                    if (LA > 0) {
+                        aq_n = seg_alpha(jA)[sidx(LA - 1)];
+                        if (!rec) {
+                            et_n = seg_e(jA)[sidx(LA - 1)];
+                            ot_n = seg_o(jA)[sidx(LA - 1)];
+                        }
+                    }
+                    for (int it = 0; it < nint; ++it) {
+                        const int t = t0A + LA - 1 - it;  // backward step of both groups (it < LA)
+                        if (!rec) {
+                            if (it < LA) {
+                                const int tl = t - t0A;
+                                const float al[4] = {aq_n.x, aq_n.y, aq_n.z, aq_n.w};
+                                const int et = et_n, ot = ot_n;
+                                const float4 bb = *(const float4 *)&btk[(size_t)ot * NP + 16 * w + 4 * g];
+                                {
+                                    const int tp = tl > 0 ? tl - 1 : 0;
+                                    aq_n = seg_alpha(jA)[sidx(tp)];
+                                    et_n = seg_e(jA)[sidx(tp)];
+                                    ot_n = seg_o(jA)[sidx(tp)];
+                                }
+                                const bool live = act && t < T;
+                                float be[4] = {};
+                                flush_pending();
+                                if (t + 1 < Tmax) {
+                                    floatx4 u[1];
+                                    fr.bwd(wex + ((t + 1) & 1) * TILE * XROW, g, sl, u);
+#pragma unroll
+                                    for (int v = 0; v < 4; ++v) be[v] = u[0][v];
+                                }
+                                if (t == T - 1) {
+                                    const float inv = 1.0f / mlast[sl];
+#pragma unroll
+                                    for (int v = 0; v < 4; ++v) be[v] = inv;
+                                }
+                                // this step's emission counts wait in registers for the next step
+                                // (repeated symbols in the wave's 16 slots take atomics, as in k_adj_coop)
+                                duptab[w * M + ot] = (uint8_t)sl;
+                                const int first = duptab[w * M + ot];
+                                float gm[4];
+#pragma unroll
+                                for (int v = 0; v < 4; ++v) {
+                                    const int i = 16 * w + 4 * g + v;
+                                    gm[v] = (i < N) ? wgt * al[v] * be[v] : 0.0f;
+                                    if (live && t == 0) gpi[v] = gm[v];
+                                }
+                                pend_gm = float4{gm[0], gm[1], gm[2], gm[3]};
+                                pend_ix = ot * NP + ((16 * w + 4 * g) ^ (ot * 4 & swz));
+                                pend_on = live;
+                                pend_dup = first != sl;
+                                // w_t = b_t o betahat_t 2^-e_t; zero where the sequence has ended or takes no part
+                                const float wn0 = live ? ldexp_f(bb.x * be[0], -et) : 0.0f;
+                                const float wn1 = live ? ldexp_f(bb.y * be[1], -et) : 0.0f;
+                                const float wn2 = live ? ldexp_f(bb.z * be[2], -et) : 0.0f;
+                                const float wn3 = live ? ldexp_f(bb.w * be[3], -et) : 0.0f;
+                                *(float4 *)&wex[(t & 1) * TILE * XROW + sl * XROW + 16 * w + 4 * g] =
+                                    float4{wn0, wn1, wn2, wn3};
+                            }
+                        } else {
+                            if (it < LB) {
+                                if (it == 0) {
+                                    // the segment's first symbols (read from the next step on, after the barrier)
+                                    if (w == 0) {
+                                        load_chunk(t0B);
+                                        store_chunk(0);
+                                        load_chunk(t0B + ACH);
+                                        store_chunk(1);
+                                        load_chunk(t0B + 2 * ACH);
+                                    }
+                                    // alphahat at the checkpoint of segment jB
+                                    if (t0B < T) {
+                                        const float4 q =
+                                            *(const float4 *)&a.ckpt[((size_t)pos * a.nck + jB) * NP + 16 * w + 4 * g];
+                                        x[0] = q.x;
+                                        x[1] = q.y;
+                                        x[2] = q.z;
+                                        x[3] = q.w;
+                                    } else {
+                                        x[0] = x[1] = x[2] = x[3] = 0.0f;
+                                    }
+                                    e_prev = (t0B < T) ? a.ckexp[(size_t)pos * a.nck + jB] : 0;
+                                    *(float4 *)&xbuf[(t0B & 1) * TILE * XROW + sl * XROW + 16 * w + 4 * g] =
+                                        float4{x[0], x[1], x[2], x[3]};
+                                    float part;
+                                    {
+#pragma clang fp contract(off)
+                                        part = ((x[0] + x[1]) + x[2]) + x[3];
+                                    }
+                                    part = sum_row_groups(part);
+                                    if (g == 0) psum[(t0B & 1) * R * TILE + w * TILE + sl] = part;
+                                } else {
+                                    const int tr = t0B + it;  // recomputed step
+                                    if (it == 1)
+                                        store_entry0(jB);
+                                    else
+                                        finish(jB, tr - 1);
+                                    if (w == 0 && (it % ACH) == 0 && it >= ACH) {
+                                        store_chunk(it / ACH + 1);
+                                        load_chunk(tr + 2 * ACH);
+                                    }
+                                    const int o = read_sym(tr);
+                                    seg_o(jB)[sidx(it)] = o;
+                                    const float4 bb = *(const float4 *)&btk[(size_t)o * NP + 16 * w + 4 * g];
+                                    floatx4 u[1];
+                                    // the checkpoint row enters unscaled (exponent 0), later rows by 2^-e
+                                    fr.fwd(xbuf + ((tr - 1) & 1) * TILE * XROW, it == 1 ? 0 : e, g, sl, u);
+                                    const float part = coop_emit(u[0], bb, x);
+                                    *(float4 *)&xbuf[(tr & 1) * TILE * XROW + sl * XROW + 16 * w + 4 * g] =
+                                        float4{x[0], x[1], x[2], x[3]};
+                                    if (g == 0) psum[(tr & 1) * R * TILE + w * TILE + sl] = part;
+                                }
+                            }
+                            if (it < LA && t + 1 < Tmax) {
+                                // C[own rows][all] += X^T W for backward step t
+                                const int tl = t - t0A;
+                                const float al[4] = {aq_n.x, aq_n.y, aq_n.z, aq_n.w};
+                                aq_n = seg_alpha(jA)[sidx(tl > 0 ? tl - 1 : 0)];
+                                const bool trans = act && t + 1 < T;
+                                const float *wrow = wex + ((t + 1) & 1) * TILE * XROW;
+#pragma unroll
+                                for (int v = 0; v < 4; ++v) atile[sl * 17 + 4 * g + v] = trans ? wgt * al[v] : 0.0f;
+                                wave_lds_sync();
+                                float xa[4], wb[4][R];
+#pragma unroll
+                                for (int q = 0; q < 4; ++q) {
+                                    const int s = 4 * q + g;
+                                    xa[q] = atile[s * 17 + sl];
+#pragma unroll
+                                    for (int rj = 0; rj < R; ++rj) wb[q][rj] = wrow[s * XROW + 16 * rj + sl];
+                                }
+#pragma unroll
+                                for (int q = 0; q < 4; ++q)
+#pragma unroll
+                                    for (int rj = 0; rj < R; ++rj)
+                                        C[rj] = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[q], wb[q][rj], C[rj], 0, 0, 0);
+                                wave_lds_sync();
+                            } else if (it < LA) {
+                                const int tl = t - t0A;
+                                aq_n = seg_alpha(jA)[sidx(tl > 0 ? tl - 1 : 0)];
+                            }
+                        }
+                        // the steps exchange data through LDS only; global traffic crosses
+                        // between the groups at phase boundaries (full barrier above)
+                        lds_barrier();
+                    }
+                    // last recomputed step of segment jB (its sum is in psum since the last barrier)
+                    if (rec && LB > 0) {
+                        if (LB == 1)
+                            store_entry0(jB);
+                        else
+                            finish(jB, t0B + LB - 1);
+                    }
+                }
+                if (!rec) {
+                    flush_pending();
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int i = 16 * w + 4 * g + v;
+                        if (i < N && gpi[v] != 0.0f) atomicAdd(&a.cnt_pi[(size_t)k * N + i], gpi[v]);
+                    }
+                }
+            }
+            if (rec) {
+                // n_A = A o C for this wave's rows of model k
+#pragma unroll
+                for (int rj = 0; rj < R; ++rj)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int i = 16 * w + 4 * g + v, jj = 16 * rj + sl;
+                        if (i < N && jj < N) {
+                            const float c = C[rj][v];
+                            if (c != 0.0f) atomicAdd(&a.cnt_A[((size_t)k * N + i) * N + jj], Ak[(size_t)i * N + jj] * c);
+                        }
+                    }
+            }
+        }
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < M * NP; idx += blockDim.x) {
+            const int o = idx / NP, ic = idx % NP;
+            const int i = ic ^ (o * 4 & swz);
+            const float v = nbl[idx];
+            if (i < N && v != 0.0f) atomicAdd(&nbt[(size_t)o * NP + i], v);
+        }
+    }
+}
+
 constexpr size_t COOP_LDS_LIMIT = 160 * 1024;
 
 // Dynamic LDS of the partial variant: the [M][NP] partial, then the [waves][M] byte table.
@@ -526,6 +881,35 @@ template <int R>
 bool use_nb_lds(int M) {
     constexpr int BO = adj_bo(R);
     return nb_lds_bytes<R>(M) + AdjCoopShape<R, BO>::small_bytes + 64 <= COOP_LDS_LIMIT;
+}
+
+// The pipelined kernel serves 64-state tiles whose LDS partial fits next to
+// its buffers.  (With 6 or 8 blocks its 12 or 16 waves leave fewer than 170
+// registers per wave, and the step spills.)
+template <int R>
+bool use_pipe(int M) {
+    if constexpr (R != 4) {
+        return false;
+    } else {
+        return nb_lds_bytes<R>(M) + AdjCoopShape<R, 1>::small_bytes + TILE * 4 + 64 <= COOP_LDS_LIMIT;
+    }
+}
+
+template <int R>
+int grid_pipe(int M, int cu_count, int K) {
+    if constexpr (R != 4) {
+        return 0;
+    } else {
+        auto kern = k_adj_pipe<R>;
+        const size_t dyn = nb_lds_bytes<R>(M);
+        (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 2 * R * WAVE, dyn) != hipSuccess || per_cu < 1)
+            per_cu = 1;
+        int grid = cu_count * per_cu;
+        if (K > 0 && grid >= K) grid = (grid / K) * K;
+        return grid;
+    }
 }
 
 template <int R, bool NBLDS>
@@ -544,6 +928,7 @@ int grid_t(int M, int cu_count, int K) {
 
 template <int R>
 int grid_r(int M, int cu_count, int K) {
+    if (use_pipe<R>(M)) return grid_pipe<R>(M, cu_count, K);
     return use_nb_lds<R>(M) ? grid_t<R, true>(M, cu_count, K) : grid_t<R, false>(M, cu_count, K);
 }
 
@@ -554,6 +939,12 @@ hipError_t launch_r(const DevPtrs &d, const AdjLaunch &a, int cu_count, hipStrea
     if (STREAM && a.frag == nullptr) return hipErrorInvalidValue;
     const int grid = persistent_grid(grid_r<R>(a.M, cu_count, a.K), tile_bound(a.S, a.K, false, TILE), 1, a.K, a.max_grid);
     if (grid > a.seg_slots) return hipErrorInvalidValue;
+    if constexpr (R == 4) {
+        if (use_pipe<R>(a.M)) {
+            k_adj_pipe<R><<<grid, 2 * R * WAVE, nb_lds_bytes<R>(a.M), st>>>(d, a);
+            return hipGetLastError();
+        }
+    }
     if (use_nb_lds<R>(a.M))
         k_adj_coop<R, BO, true, STREAM><<<grid, R / BO * WAVE, nb_lds_bytes<R>(a.M), st>>>(d, a);
     else
@@ -607,12 +998,22 @@ int adj_coop_slots(int NP, int M, int K, int cu_count) {
     }
 }
 
-int64_t adj_coop_seg_stride(int NP, int max_len) {
+bool adj_coop_pipelined(int NP, int M) {
+    switch (NP / 16) {
+        case 4: return use_pipe<4>(M);
+        case 6: return use_pipe<6>(M);
+        case 8: return use_pipe<8>(M);
+        default: return false;
+    }
+}
+
+int64_t adj_coop_seg_stride(int NP, int M, int max_len) {
     int L = 1;
     while ((int64_t)L * L < max_len) ++L;
     const int R = NP / 16, BO = adj_bo(R);
-    // float4 alphahat per owned block + e + o, per lane and wave
-    return (int64_t)L * (R / BO) * WAVE * (4 * BO + 2);
+    // float4 alphahat per owned block + e + o, per lane and wave; two halves
+    // (segment parity) for the pipelined kernel
+    return (int64_t)L * (R / BO) * WAVE * (4 * BO + 2) * (adj_coop_pipelined(NP, M) ? 2 : 1);
 }
 
 void launch_coop_frags(const float *A, float *frag, int K, int N, int NP, hipStream_t st) {

@@ -51,6 +51,18 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Workgroup barrier that orders LDS traffic only.  __syncthreads also makes
+// global memory coherent across the workgroup, which waits for every
+// outstanding global load and store of the wave before the barrier; a step
+// whose waves exchange data through LDS only would then lose the loads it
+// issued one step ahead.  Here the fences name the local address space, so
+// the barrier waits for LDS operations alone and global loads stay in flight.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Next item of a per-wave work queue: the old value of *head, the same in every
 // lane, after adding 1.  Every lane takes part in the atomic (lane 0 adds 1, the
 // others 0) and the result is read from the first lane, so the pop is not under

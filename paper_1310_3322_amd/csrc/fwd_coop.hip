@@ -180,7 +180,9 @@ __global__ void __launch_bounds__(R / BO * WAVE) k_fwd_coop(DevPtrs d, FwdLaunch
                         float4{x[b][0], x[b][1], x[b][2], x[b][3]};
                     if (g == 0) psum[(t & 1) * R * TILE + (r0 + b) * TILE + sl] = part;
                 }
-                __syncthreads();
+                // the waves exchange alphahat through LDS only: the emission rows and
+                // symbols requested for the next steps stay in flight across the barrier
+                lds_barrier();
             }
             if (has && g == 0 && w == 0) {
                 float r = (float)((double)E_end * LN2 + (double)logf(c_end));

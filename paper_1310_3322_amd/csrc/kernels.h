@@ -147,7 +147,8 @@ bool adj_coop_supported(int NP);
 bool adj_coop_streams(int NP);  // fragments streamed from the workspace (launch_coop_frags first)
 void launch_coop_frags(const float *A, float *frag, int K, int N, int NP, hipStream_t st);
 int adj_coop_slots(int NP, int M, int K, int cu_count);
-int64_t adj_coop_seg_stride(int NP, int max_len);
+int64_t adj_coop_seg_stride(int NP, int M, int max_len);
+bool adj_coop_pipelined(int NP, int M);  // the two-group pipelined backward serves this shape
 hipError_t launch_adj_coop(const DevPtrs &d, const AdjLaunch &a, int cu_count, hipStream_t st);
 int adj_mfma_slots(int NP, int M, int K, int cu_count);
 int64_t adj_mfma_seg_stride(int NP, int max_len);
