@@ -224,7 +224,7 @@ Layout make_layout(const hmm_bank *b, const hmm_batch *q, int op) {
         L.gstart = take((size_t)(groups + 1) * sizeof(int32_t));
         L.perm = take((size_t)S * sizeof(int32_t));
         L.bt = take((size_t)K * M * NP * sizeof(float));
-        if (op == HMM_OP_VITERBI) L.bp = take((size_t)q->total_symbols * NP);
+        if (op == HMM_OP_VITERBI) L.delta = take(((size_t)q->total_symbols * NP + 64) * sizeof(float));
         if (op == HMM_OP_GRAD) {
             int nck = 1;
             while ((int64_t)nck * nck < q->max_len) ++nck;
@@ -573,6 +573,7 @@ hmm_status hmm_viterbi(const hmm_bank *bank, const hmm_batch *batch, float *scor
     const int nbins = K * (batch->max_len + 1);
     launch_plan(d, K, S, K, batch->max_len, batch->total_symbols, nbins, w, L, stream);
     launch_log_transpose_b(bank->B, (float *)(w + L.bt), K, N, M, NP, stream);
+    launch_fill_i32((int32_t *)(w + L.queue) + K, (size_t)K, 0, stream);  // the traceback's queues
     if (hipGetLastError() != hipSuccess) return HMM_ERR_HIP;
     VitLaunch v;
     memset(&v, 0, sizeof(v));
@@ -588,7 +589,8 @@ hmm_status hmm_viterbi(const hmm_bank *bank, const hmm_batch *batch, float *scor
     v.queue = (int32_t *)(w + L.queue);
     v.err = (int32_t *)(w + L.err);
     v.lnbt = (const float *)(w + L.bt);
-    v.bp = (uint8_t *)(w + L.bp);
+    v.delta = (float *)(w + L.delta);
+    v.spill = v.delta + (size_t)batch->total_symbols * NP;
     v.score = score;
     v.path = path;
     const int cus = device_cu_count();

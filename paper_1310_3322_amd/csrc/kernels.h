@@ -23,7 +23,7 @@ struct Layout {
     size_t seg;      // float [slots][seg_stride] segment recompute buffers (gradient)
     size_t nbt;      // float [K][M][NP] symbol-major emission counts (cooperative gradient)
     size_t frag;     // float4 [K][2][NP^2 / 4] streamed MFMA fragments (cooperative gradient, NP > 128)
-    size_t bp;       // uint8 [total][NP] Viterbi back-pointers (bt then holds ln B transposed)
+    size_t delta;    // float [total][NP] Viterbi delta rows (bt then holds ln B transposed), then 64 spare floats
     size_t scan;     // time-parallel forward: chunk products, exponents, flags (ScanWs)
     int32_t scan_nch;    // chunks per pair of the time-parallel forward (0: not used)
     int32_t kind;        // kernel family of the call (HMM_KERNEL_*, after the tuning table)
@@ -161,7 +161,8 @@ struct VitLaunch {
     const int32_t *perm, *gstart;
     int32_t *queue, *err;
     const float *lnbt;  // [K][M][NP] ln B transposed, -inf beyond N
-    uint8_t *bp;        // [total][NP] back-pointers
+    float *delta;       // [total][NP] delta row of every step but the last, laid out like the symbols
+    float *spill;       // [64] target of the delta stores of empty slots (never read)
     float *score;       // [S]
     int32_t *path;      // [total]
     int max_grid;       // cap on the persistent grid (0: occupancy limit)

@@ -9,15 +9,20 @@
 // runs on the vector ALUs.  A wave holds 64 / NP length-sorted sequences of one
 // model; lane (slot, j) owns state j of its sequence and keeps the column
 // ln A[:, j] in registers.  Per step every lane publishes delta_{t-1}(j) in
-// LDS, reads the NP values of its sequence (four per read), forms the NP
-// candidates in index order and keeps the first maximum (strict comparison),
-// then adds ln B[j][o_t] from the log-emission table ln B^T [K][M][NP].  The
-// back-pointer psi_t(j) is one byte in a [sum T][NP] array in HBM laid out
-// like the symbols (sequence s owns rows offsets[s] .. offsets[s] + T - 1), so
-// the traceback of a sequence walks one contiguous region.  Every RN steps the
-// scores of a sequence are shifted by their maximum (a common shift changes no
-// arg-max) and the shifts add up in FP64, which keeps the FP32 values small
-// and the score accurate to a few ulps of its magnitude.
+// LDS, reads the NP values of its sequence (four per read) and forms the
+// maximum of the NP candidates (an add and half a three-way maximum each),
+// then adds ln B[j][o_t] from the log-emission table ln B^T [K][M][NP].  Every
+// RN steps the scores of a sequence are shifted by their maximum (a common
+// shift changes no arg-max) and the shifts add up in FP64, which keeps the FP32
+// values small and the score accurate to a few ulps of its magnitude.
+//
+// The decoder stores each step's delta row (the exact FP32 values the next
+// step reads) in a [sum T][NP] array laid out like the symbols, instead of an
+// arg-max per state: the arg-max is needed for one state per step only, the one
+// on the path, so the traceback recomputes it there from the same stored
+// operands with the same FP32 additions and takes the first lane attaining the
+// maximum.  psi_t(q_t) is therefore exactly the decoder's choice, and the
+// decoder does about a third of the vector work of tracking NP arg-maxes.
 #include <climits>
 
 #include "common.cuh"
@@ -47,6 +52,32 @@ template <int NP>
 __device__ __forceinline__ float group_max(float v) {
 #pragma unroll
     for (int m = 1; m < NP; m <<= 1) v = fmaxf(v, __shfl_xor(v, m, WAVE));
+    return v;
+}
+
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+// Maximum over the NP lanes of a group (NP = 16, 32, 64), in every lane of the
+// group, from row permutations (DPP: swap neighbours, swap pairs, mirror the
+// half-row, mirror the row) and the row and half-wave swaps of gfx950, so that
+// no level goes through the LDS crossbar.  A maximum is exact in any order.
+template <int NP>
+__device__ __forceinline__ float group_max_dpp(float v) {
+    v = fmaxf(v, dpp<0xB1>(v));   // quad_perm [1, 0, 3, 2]
+    v = fmaxf(v, dpp<0x4E>(v));   // quad_perm [2, 3, 0, 1]
+    v = fmaxf(v, dpp<0x141>(v));  // row_half_mirror
+    v = fmaxf(v, dpp<0x140>(v));  // row_mirror
+    if constexpr (NP >= 32) {
+        auto p = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+        v = fmaxf(__uint_as_float(p[0]), __uint_as_float(p[1]));
+    }
+    if constexpr (NP >= 64) {
+        auto p = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+        v = fmaxf(__uint_as_float(p[0]), __uint_as_float(p[1]));
+    }
     return v;
 }
 
@@ -96,40 +127,53 @@ __global__ void __launch_bounds__(VWAVES * WAVE) k_viterbi(DevPtrs d, VitLaunch 
             }
             const int Tmax = __builtin_amdgcn_readfirstlane(wave_max_int(T));
             const int32_t *sq = T > 0 ? d.symbols + off : d.symbols;
-            uint8_t *bp = v.bp + (T > 0 ? off : 0) * NP + j;
+            const int tlim = T > 0 ? T - 1 : 0;
+            // delta_t goes to row min(t, T - 1) of the sequence: the store is unconditional
+            // (a store under a lane-dependent branch makes the compiler wait for every
+            // outstanding memory operation at the next step), finished lanes rewrite
+            // their last row, which the traceback never reads, and empty slots write
+            // to a spare area
+            float *drow = T > 0 ? v.delta + off * NP + j : v.spill + lane;
+            const int rmax = T > 0 ? T - 1 : 0;
+            const size_t rstride = T > 0 ? NP : 0;
+            bool symbad = false;
             double shift = 0.0;
             float del = -INFINITY;
-            bool symbad = false;
             float fin_v = -INFINITY;
             int fin_i = 0;
             double fin_shift = 0.0;
-            for (int t = 0; t < Tmax; ++t) {
-                const bool live = t < T;
-                int o = live ? sq[t] : 0;
-                symbad |= live && (o < 0 || o >= M);
-                o = ((unsigned)o < (unsigned)M) ? o : 0;
-                const float lb = lbk[(size_t)o * NP + j];
+            // Software pipeline without loop-carried copies (a copy of a loaded
+            // register waits for every outstanding load and store of the wave):
+            // the step is unrolled by two and the symbol of step t + 2 and the
+            // emission term of step t + 1 go to the registers of the step's parity.
+            // A symbol is checked where it is used, one step after its load.
+            auto checked = [&](int o, int t) {
+                symbad |= (t < T) && (o < 0 || o >= M);
+                return ((unsigned)o < (unsigned)M) ? o : 0;
+            };
+            // (every lane reads symbols only when the wave has a step: with Tmax = 0
+            // the symbol array may be empty)
+            int oA = Tmax > 0 ? sq[0] : 0, oB = Tmax > 0 ? sq[1 < tlim ? 1 : tlim] : 0;
+            float lbA = lbk[(size_t)checked(oA, 0) * NP + j], lbB = 0.0f;
+            // step t: lb_t in lb_use; sym(t + 1) in o_n1 (loaded a step ago); loads lb_{t+1}
+            // into lb_n1 and sym(t + 2) into o_n2
+            auto step = [&](int t, const float &lb_use, float &lb_n1, const int &o_n1, int &o_n2, float *buf) {
+                lb_n1 = lbk[(size_t)checked(o_n1, t + 1) * NP + j];
+                o_n2 = sq[min(t + 2, tlim)];
                 if (t == 0) {
-                    del = lpi + lb;
+                    del = lpi + lb_use;
                 } else {
-                    float *buf = dl_all[wave][t & 1];
                     buf[lane] = del;
                     wave_lds_sync();
-                    const float4 *row = (const float4 *)(buf + slot * NP);
+                    const float4 *rw = (const float4 *)(buf + slot * NP);
                     float best = -INFINITY;
-                    int arg = 0;
 #pragma unroll
                     for (int i4 = 0; i4 < NP / 4; ++i4) {
-                        const float4 q = row[i4];
-                        const float c0 = q.x + la[4 * i4], c1 = q.y + la[4 * i4 + 1];
-                        const float c2 = q.z + la[4 * i4 + 2], c3 = q.w + la[4 * i4 + 3];
-                        if (c0 > best) { best = c0; arg = 4 * i4; }
-                        if (c1 > best) { best = c1; arg = 4 * i4 + 1; }
-                        if (c2 > best) { best = c2; arg = 4 * i4 + 2; }
-                        if (c3 > best) { best = c3; arg = 4 * i4 + 3; }
+                        const float4 q = rw[i4];
+                        best = fmaxf(fmaxf(best, q.x + la[4 * i4]), q.y + la[4 * i4 + 1]);
+                        best = fmaxf(fmaxf(best, q.z + la[4 * i4 + 2]), q.w + la[4 * i4 + 3]);
                     }
-                    del = best + lb;
-                    if (live) bp[(size_t)t * NP] = (uint8_t)arg;
+                    del = best + lb_use;
                 }
                 if (t == T - 1) {  // uniform within a sequence's lanes
                     fin_v = del;
@@ -143,6 +187,13 @@ __global__ void __launch_bounds__(VWAVES * WAVE) k_viterbi(DevPtrs d, VitLaunch 
                     del = del - m;
                     shift += (double)m;
                 }
+                // delta_t as step t + 1 reads it (after any shift)
+                drow[(size_t)min(t, rmax) * rstride] = del;
+            };
+            float *buf0 = dl_all[wave][0], *buf1 = dl_all[wave][1];
+            for (int t = 0; t < Tmax; t += 2) {
+                step(t, lbA, lbB, oB, oA, buf0);
+                if (t + 1 < Tmax) step(t + 1, lbB, lbA, oA, oB, buf1);
             }
             int sb = symbad ? 1 : 0;
 #pragma unroll
@@ -164,63 +215,99 @@ __global__ void __launch_bounds__(VWAVES * WAVE) k_viterbi(DevPtrs d, VitLaunch 
     }
 }
 
-// Traceback: follows the back-pointers from q_T (left in path by the decoding
-// kernel) down to q_1, one wave per sequence, sequences taken in the planner's
-// length-sorted order so that a round of waves has similar lengths; sequences
-// with an invalid symbol or model get -1 everywhere (their range is written
-// only when it is valid).  The back-pointer rows of 64 steps are copied to the
-// wave's LDS buffer at once (lane l brings the row of step t_hi - l, NP bytes),
-// with the next 64 rows in flight; the chase then reads one byte per step at a
-// wave-uniform LDS address, and lane l keeps q_{t_hi - l - 1} for one coalesced
-// store per chunk.
+// Traceback: from q_T (left in path by the decoder) down to q_1.  Workgroups
+// take models as the decoder does and stage ln A_k transposed in LDS
+// (lnat[q][i] = ln A_k[i][q]); each wave pops units of 64 / NP sequences of the
+// model in length order.  Per step, lane (slot, i) of a sequence forms the
+// candidate delta_{t-1}(i) + ln A_k[i][q_t] from the stored delta row and the
+// LDS row of q_t, the group takes the maximum, and the first lane whose
+// candidate equals it gives q_{t-1}.  The delta rows do not depend on the
+// path, so each lane keeps the rows of the next NP steps in flight.  Sequences with an invalid symbol or model get -1
+// everywhere (their range is written only when it is valid).
 template <int NP>
-__global__ void __launch_bounds__(VWAVES * WAVE) k_viterbi_trace_wave(DevPtrs d, VitLaunch v) {
-    constexpr int DW = NP / 4;
-    __shared__ uint32_t rowbuf[VWAVES][2][WAVE * DW];
+__global__ void __launch_bounds__(VWAVES * WAVE) k_viterbi_trace(DevPtrs d, VitLaunch v) {
+    constexpr int SPW = WAVE / NP;
+    __shared__ float lnat[NP * NP];
     const int lane = threadIdx.x & (WAVE - 1);
-    const int wave = threadIdx.x / WAVE;
-    const int64_t pos = (int64_t)blockIdx.x * VWAVES + wave;
-    if (pos >= v.S) return;
-    const int s = v.perm[pos];
-    const int32_t T = d.lengths[s];
-    const int64_t off = d.offsets[s];
-    if (seq_bad(T, off, v.max_len, v.total) || T == 0) return;
-    int32_t *q = v.path + off;
-    const float sc = v.score[s];
-    if (sc != sc) {
-        for (int32_t t = lane; t < T; t += WAVE) q[t] = -1;
-        return;
-    }
-    const uint32_t *bp = (const uint32_t *)(v.bp + off * NP);
-    uint32_t nxt[DW];
-    auto load_rows = [&](int t_hi) {
-        const int t = t_hi - lane;
-#pragma unroll
-        for (int u = 0; u < DW; ++u) nxt[u] = t >= 1 ? bp[(size_t)t * DW + u] : 0u;
-    };
-    auto store_rows = [&](int b) {
-#pragma unroll
-        for (int u = 0; u < DW; ++u) rowbuf[wave][b][lane * DW + u] = nxt[u];
-    };
-    int cur = __builtin_amdgcn_readfirstlane(q[T - 1]);
-    int t_hi = T - 1;
-    int buf = 0;
-    load_rows(t_hi);
-    store_rows(0);
-    while (t_hi >= 1) {
-        const int n = min(WAVE, t_hi);  // steps t_hi .. t_hi - n + 1 in this chunk
-        if (t_hi - n >= 1) load_rows(t_hi - n);
-        wave_lds_sync();
-        const uint8_t *rb = (const uint8_t *)rowbuf[wave][buf];
-        int mine = 0;  // q_{t_hi - lane - 1}, the state this lane decodes
-        for (int l = 0; l < n; ++l) {
-            cur = __builtin_amdgcn_readfirstlane((int)rb[l * NP + cur]);
-            if (lane == l) mine = cur;
+    const int slot = lane / NP, i = lane % NP;
+    const int K = v.K, N = v.N;
+    int32_t *queue = v.queue + K;  // the decoder pops [0, K)
+
+    const int G = gridDim.x;
+    const int k_first = G >= K ? (int)(blockIdx.x % K) : (int)blockIdx.x;
+    const int k_step = G >= K ? K : G;
+    for (int k = k_first; k < K; k += k_step) {
+        const int gbeg = v.gstart[k], gend = v.gstart[k + 1];
+        const int nunits = (gend - gbeg + SPW - 1) / SPW;
+        if (nunits == 0) continue;
+        __syncthreads();
+        {
+            const float *Ak = d.A + (size_t)k * N * N;
+            for (int idx = threadIdx.x; idx < NP * NP; idx += blockDim.x) {
+                const int q = idx / NP, ii = idx % NP;
+                lnat[idx] = (ii < N && q < N) ? logf(Ak[(size_t)ii * N + q]) : -INFINITY;
+            }
         }
-        if (lane < n) q[t_hi - lane - 1] = mine;
-        t_hi -= n;
-        buf ^= 1;
-        if (t_hi >= 1) store_rows(buf);
+        __syncthreads();
+        for (;;) {
+            const int unit = wave_pop(&queue[k]);
+            if (unit >= nunits) break;
+            const int pos = gbeg + unit * SPW + slot;
+            const bool has = pos < gend;
+            const int s = has ? v.perm[pos] : 0;
+            int32_t T = 0;
+            int64_t off = 0;
+            if (has) {
+                T = d.lengths[s];
+                off = d.offsets[s];
+                const int mk = d.model_of_seq[s];
+                if (seq_bad(T, off, v.max_len, v.total) || mk < 0 || mk >= K) T = 0;
+            }
+            int32_t *q = v.path + (T > 0 ? off : 0);
+            const float sc = T > 0 ? v.score[s] : 0.0f;
+            if (sc != sc) {  // invalid symbol: no path
+                for (int32_t t = i; t < T; t += NP) q[t] = -1;
+                T = 0;
+            }
+            const int Tmax = __builtin_amdgcn_readfirstlane(wave_max_int(T));
+            if (Tmax <= 1) continue;
+            int cur = T > 0 ? q[T - 1] : 0;
+            cur = ((unsigned)cur < (unsigned)NP) ? cur : 0;
+            // row r (0 <= r <= T - 2) of this lane's sequence holds delta_r(i).  Loads and
+            // stores are unconditional (rows clamped into the sequence, stores outside the
+            // chunk to a spare area), since a memory operation under a lane-dependent branch
+            // makes the compiler wait for every outstanding one at the next step
+            const float *drow = T > 1 ? v.delta + off * NP + i : v.spill + lane;
+            const int rmax = T > 1 ? T - 2 : 0;
+            const size_t rstride = T > 1 ? NP : 0;
+            auto row = [&](int r) { return drow[(size_t)min(max(r, 0), rmax) * rstride]; };
+            int32_t *sink = (int32_t *)v.spill + lane;
+            // Blocks of NP wave steps t = t0, t0 - 1, .., t0 - NP + 1, fully unrolled with no
+            // exit inside (steps below 1 are dead), so that the ring of delta rows (row t - 1
+            // for step t, refilled with the row NP steps further) stays in registers.  Lane i
+            // records the state q_{t0 - 1 - i} and the block ends with one coalesced store.
+            float ring[NP];
+#pragma unroll
+            for (int u = 0; u < NP; ++u) ring[u] = row(Tmax - 2 - u);
+            for (int t0 = Tmax - 1; t0 >= 1; t0 -= NP) {
+                int mine = 0;
+#pragma unroll
+                for (int u = 0; u < NP; ++u) {
+                    const int t = t0 - u;
+                    const float dprev = ring[u];
+                    ring[u] = row(t - 1 - NP);
+                    const bool live = t >= 1 && t < T;
+                    const float c = dprev + lnat[cur * NP + i];
+                    const float m = group_max_dpp<NP>(c);
+                    uint64_t bits = __ballot(live && c == m) >> (slot * NP);
+                    if constexpr (NP < 64) bits &= (1ull << NP) - 1;
+                    if (live) cur = bits ? __builtin_ctzll(bits) : 0;
+                    if (i == u) mine = cur;
+                }
+                const int st = t0 - 1 - i;
+                *((st >= 0 && st <= T - 2) ? q + st : sink) = mine;
+            }
+        }
     }
 }
 
@@ -234,7 +321,13 @@ hipError_t launch_t(const DevPtrs &d, const VitLaunch &v, int cu_count, hipStrea
     const int grid = persistent_grid(cu_count * per_cu, tile_bound(v.S, v.K, false, WAVE / NP), VWAVES, v.K, v.max_grid);
     hipLaunchKernelGGL(kern, dim3(grid), dim3(VWAVES * WAVE), 0, st, d, v);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_viterbi_trace_wave<NP>, dim3((v.S + VWAVES - 1) / VWAVES), dim3(VWAVES * WAVE), 0, st, d, v);
+    auto tk = k_viterbi_trace<NP>;
+    int per_cu_t = 0;
+    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_t, tk, VWAVES * WAVE, 0)) != hipSuccess) return e;
+    if (per_cu_t < 1) per_cu_t = 1;
+    const int grid_t =
+        persistent_grid(cu_count * per_cu_t, tile_bound(v.S, v.K, false, WAVE / NP), VWAVES, v.K, v.max_grid);
+    hipLaunchKernelGGL(tk, dim3(grid_t), dim3(VWAVES * WAVE), 0, st, d, v);
     return hipGetLastError();
 }
 

@@ -340,6 +340,43 @@ def test_counts_cooperative_state_counts(N, M):
     assert _counts_err(nB.cpu().numpy(), rB) <= GRAD_TOL
 
 
+@pytest.mark.parametrize("N,per_len", [(64, 16), (64, 13), (49, 13)])
+def test_counts_pipelined_segment_edges(N, per_len):
+    """The 49..64-state backward walks sqrt(T)-step segments in phases, one wave
+    group recomputing segment j - 1 while the other walks segment j.  One model,
+    per_len sequences of every length 1..40: with 16 per length every tile has
+    one length and the tiles' longest sequences take every value 1..40 (a
+    one-step last segment at T = 3, 7, 13, 21, 31, full squares at 4, 9, 16, 25,
+    36); with 13 per length tiles mix two lengths.  Plus sequence weights, an
+    impossible observation and an invalid symbol in the mixed case."""
+    print(f"[case] counts pipelined edges N={N} per_len={per_len}", flush=True)
+    rng = np.random.default_rng([21, N, per_len])
+    lengths = np.repeat(np.arange(1, 41), per_len).astype(np.int32)
+    rng.shuffle(lengths)
+    w = workloads.random_lengths_workload(rng, K=1, N=N, M=23, lengths=lengths, all_pairs=False, conc=0.5)
+    sym = w.symbols.copy()
+    if per_len != 16:
+        w.B[0, :, 22] = 0.0
+        w.B[0] /= w.B[0].sum(axis=1, keepdims=True)
+        sym[sym == 22] = 0  # symbol 22 becomes impossible; keep it in one sequence only
+        s_dead = int(np.flatnonzero(w.lengths == 31)[0])
+        sym[w.offsets[s_dead] + 30] = 22  # impossible at the last step
+        s_bad = int(np.flatnonzero(w.lengths == 21)[0])
+        sym[w.offsets[s_bad] + 20] = 99  # invalid symbol
+    wts = rng.uniform(0.5, 1.5, size=w.S).astype(np.float32)
+    p = hmm.Problem(dev(w.pi), dev(w.A), dev(w.B), dev(sym), dev(w.offsets), dev(w.lengths), dev(w.owner),
+                    max_len=w.max_len, total_symbols=w.total_symbols)
+    ll, (npi, nA, nB), ws = hmm.forward_backward_grad(p, seq_weight=dev(wts))
+    rll, rpi, rA, rB = O.counts(w.pi, w.A, w.B, sym, w.offsets, w.lengths, w.owner, weights=wts)
+    assert rel_err(ll.cpu().numpy(), rll) <= LL_TOL
+    assert _counts_err(npi.cpu().numpy(), rpi) <= GRAD_TOL
+    assert _counts_err(nA.cpu().numpy(), rA) <= GRAD_TOL
+    assert _counts_err(nB.cpu().numpy(), rB) <= GRAD_TOL
+    if per_len != 16:
+        assert np.isneginf(rll[s_dead]) and np.isnan(rll[s_bad])
+        assert hmm.workspace_error(ws) == s_bad
+
+
 def test_counts_c5_subset():
     """The N=256 bank's gradient (long sequences: several checkpoint segments) against the oracle."""
     print("[case] counts c5 subset", flush=True)
