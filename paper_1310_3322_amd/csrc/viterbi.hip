@@ -143,57 +143,64 @@ __global__ void __launch_bounds__(VWAVES * WAVE) k_viterbi(DevPtrs d, VitLaunch 
             int fin_i = 0;
             double fin_shift = 0.0;
             // Software pipeline without loop-carried copies (a copy of a loaded
-            // register waits for every outstanding load and store of the wave):
-            // the step is unrolled by two and the symbol of step t + 2 and the
-            // emission term of step t + 1 go to the registers of the step's parity.
-            // A symbol is checked where it is used, one step after its load.
+            // register waits for every outstanding load and store of the wave): the
+            // step loop is unrolled by U; ring[u] holds the symbol of step t0 + u and is
+            // reloaded with the symbol of step t0 + U + u once read, so that symbols
+            // arrive U - 1 steps ahead; the emission term of step t + 1 is requested in
+            // step t into the register of the other parity.  Steps past Tmax (at most
+            // U - 1 per unit) change nothing that is read: their delta stores go to the
+            // last row, their shift and final-state updates are never taken.  A symbol
+            // is checked where it is used, one step before its own step.
+            constexpr int U = 8;
             auto checked = [&](int o, int t) {
                 symbad |= (t < T) && (o < 0 || o >= M);
                 return ((unsigned)o < (unsigned)M) ? o : 0;
             };
-            // (every lane reads symbols only when the wave has a step: with Tmax = 0
-            // the symbol array may be empty)
-            int oA = Tmax > 0 ? sq[0] : 0, oB = Tmax > 0 ? sq[1 < tlim ? 1 : tlim] : 0;
-            float lbA = lbk[(size_t)checked(oA, 0) * NP + j], lbB = 0.0f;
-            // step t: lb_t in lb_use; sym(t + 1) in o_n1 (loaded a step ago); loads lb_{t+1}
-            // into lb_n1 and sym(t + 2) into o_n2
-            auto step = [&](int t, const float &lb_use, float &lb_n1, const int &o_n1, int &o_n2, float *buf) {
-                lb_n1 = lbk[(size_t)checked(o_n1, t + 1) * NP + j];
-                o_n2 = sq[min(t + 2, tlim)];
-                if (t == 0) {
-                    del = lpi + lb_use;
-                } else {
-                    buf[lane] = del;
-                    wave_lds_sync();
-                    const float4 *rw = (const float4 *)(buf + slot * NP);
-                    float best = -INFINITY;
+            int ring[U];
 #pragma unroll
-                    for (int i4 = 0; i4 < NP / 4; ++i4) {
-                        const float4 q = rw[i4];
-                        best = fmaxf(fmaxf(best, q.x + la[4 * i4]), q.y + la[4 * i4 + 1]);
-                        best = fmaxf(fmaxf(best, q.z + la[4 * i4 + 2]), q.w + la[4 * i4 + 3]);
+            for (int u = 0; u < U; ++u) ring[u] = Tmax > 0 ? sq[min(u, tlim)] : 0;
+            float lbv[2];
+            lbv[0] = lbk[(size_t)checked(ring[0], 0) * NP + j];
+            lbv[1] = 0.0f;
+            for (int t0 = 0; t0 < Tmax; t0 += U) {
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int t = t0 + u;
+                    const float lb = lbv[u & 1];
+                    const int on = ring[(u + 1) % U];  // symbol of step t + 1 (for u = U - 1: reloaded in step 0)
+                    lbv[(u + 1) & 1] = lbk[(size_t)checked(on, t + 1) * NP + j];
+                    ring[u] = sq[min(t + U, tlim)];
+                    if (t == 0) {
+                        del = lpi + lb;
+                    } else {
+                        float *buf = dl_all[wave][u & 1];
+                        buf[lane] = del;
+                        wave_lds_sync();
+                        const float4 *rw = (const float4 *)(buf + slot * NP);
+                        float best = -INFINITY;
+#pragma unroll
+                        for (int i4 = 0; i4 < NP / 4; ++i4) {
+                            const float4 q = rw[i4];
+                            best = fmaxf(fmaxf(best, q.x + la[4 * i4]), q.y + la[4 * i4 + 1]);
+                            best = fmaxf(fmaxf(best, q.z + la[4 * i4 + 2]), q.w + la[4 * i4 + 3]);
+                        }
+                        del = best + lb;
                     }
-                    del = best + lb_use;
+                    if (t == T - 1) {  // uniform within a sequence's lanes
+                        fin_v = del;
+                        fin_i = j;
+                        fin_shift = shift;
+                        group_argmax<NP>(fin_v, fin_i);
+                    }
+                    if (((t + 1) % RN) == 0) {
+                        float m = group_max<NP>(del);
+                        if (!(m > -INFINITY && m < INFINITY)) m = 0.0f;
+                        del = del - m;
+                        shift += (double)m;
+                    }
+                    // delta_t as step t + 1 reads it (after any shift)
+                    drow[(size_t)min(t, rmax) * rstride] = del;
                 }
-                if (t == T - 1) {  // uniform within a sequence's lanes
-                    fin_v = del;
-                    fin_i = j;
-                    fin_shift = shift;
-                    group_argmax<NP>(fin_v, fin_i);
-                }
-                if (((t + 1) % RN) == 0) {
-                    float m = group_max<NP>(del);
-                    if (!(m > -INFINITY && m < INFINITY)) m = 0.0f;
-                    del = del - m;
-                    shift += (double)m;
-                }
-                // delta_t as step t + 1 reads it (after any shift)
-                drow[(size_t)min(t, rmax) * rstride] = del;
-            };
-            float *buf0 = dl_all[wave][0], *buf1 = dl_all[wave][1];
-            for (int t = 0; t < Tmax; t += 2) {
-                step(t, lbA, lbB, oB, oA, buf0);
-                if (t + 1 < Tmax) step(t + 1, lbB, lbA, oA, oB, buf1);
             }
             int sb = symbad ? 1 : 0;
 #pragma unroll
