@@ -55,30 +55,40 @@ __device__ __forceinline__ float group_max(float v) {
     return v;
 }
 
-template <int CTRL>
-__device__ __forceinline__ float dpp(float v) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+// Order-preserving integer key of a float (no NaN): negative values have
+// their magnitude bits flipped, so signed comparison of keys is float
+// comparison, and equal keys are equal floats (-0 aside, which the recursion
+// never produces: it adds logarithms and subtracts a maximum from itself).
+__device__ __forceinline__ int order_key(float x) {
+    const int b = __float_as_int(x);
+    return b ^ ((b >> 31) & 0x7fffffff);
 }
 
-// Maximum over the NP lanes of a group (NP = 16, 32, 64), in every lane of the
-// group, from row permutations (DPP: swap neighbours, swap pairs, mirror the
-// half-row, mirror the row) and the row and half-wave swaps of gfx950, so that
-// no level goes through the LDS crossbar.  A maximum is exact in any order.
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v) {
+    return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, true);
+}
+
+// Maximum of the keys over the NP lanes of a group (NP = 16, 32, 64), in every
+// lane of the group: row permutations (DPP: swap neighbours, swap pairs,
+// mirror the half-row, mirror the row; each fused into one max instruction)
+// and the row and half-wave swaps of gfx950, so that no level goes through the
+// LDS crossbar.  A maximum is exact in any order.
 template <int NP>
-__device__ __forceinline__ float group_max_dpp(float v) {
-    v = fmaxf(v, dpp<0xB1>(v));   // quad_perm [1, 0, 3, 2]
-    v = fmaxf(v, dpp<0x4E>(v));   // quad_perm [2, 3, 0, 1]
-    v = fmaxf(v, dpp<0x141>(v));  // row_half_mirror
-    v = fmaxf(v, dpp<0x140>(v));  // row_mirror
+__device__ __forceinline__ int group_max_key(int k) {
+    k = max(k, dpp_i<0xB1>(k));   // quad_perm [1, 0, 3, 2]
+    k = max(k, dpp_i<0x4E>(k));   // quad_perm [2, 3, 0, 1]
+    k = max(k, dpp_i<0x141>(k));  // row_half_mirror
+    k = max(k, dpp_i<0x140>(k));  // row_mirror
     if constexpr (NP >= 32) {
-        auto p = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
-        v = fmaxf(__uint_as_float(p[0]), __uint_as_float(p[1]));
+        auto p = __builtin_amdgcn_permlane16_swap(k, k, false, false);
+        k = max((int)p[0], (int)p[1]);
     }
     if constexpr (NP >= 64) {
-        auto p = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
-        v = fmaxf(__uint_as_float(p[0]), __uint_as_float(p[1]));
+        auto p = __builtin_amdgcn_permlane32_swap(k, k, false, false);
+        k = max((int)p[0], (int)p[1]);
     }
-    return v;
+    return k;
 }
 
 template <int NP>
@@ -286,8 +296,7 @@ __global__ void __launch_bounds__(VWAVES * WAVE) k_viterbi_trace(DevPtrs d, VitL
             // makes the compiler wait for every outstanding one at the next step
             const float *drow = T > 1 ? v.delta + off * NP + i : v.spill + lane;
             const int rmax = T > 1 ? T - 2 : 0;
-            const size_t rstride = T > 1 ? NP : 0;
-            auto row = [&](int r) { return drow[(size_t)min(max(r, 0), rmax) * rstride]; };
+            auto row = [&](int r) { return drow[(uint32_t)min(max(r, 0), rmax) * NP]; };
             int32_t *sink = (int32_t *)v.spill + lane;
             // Blocks of NP wave steps t = t0, t0 - 1, .., t0 - NP + 1, fully unrolled with no
             // exit inside (steps below 1 are dead), so that the ring of delta rows (row t - 1
@@ -304,11 +313,17 @@ __global__ void __launch_bounds__(VWAVES * WAVE) k_viterbi_trace(DevPtrs d, VitL
                     const float dprev = ring[u];
                     ring[u] = row(t - 1 - NP);
                     const bool live = t >= 1 && t < T;
-                    const float c = dprev + lnat[cur * NP + i];
-                    const float m = group_max_dpp<NP>(c);
-                    uint64_t bits = __ballot(live && c == m) >> (slot * NP);
-                    if constexpr (NP < 64) bits &= (1ull << NP) - 1;
-                    if (live) cur = bits ? __builtin_ctzll(bits) : 0;
+                    const int kc = order_key(dprev + lnat[cur * NP + i]);
+                    // first lane of each group whose candidate is the group's maximum
+                    const uint64_t hit = __ballot(kc == group_max_key<NP>(kc));
+                    int nq = 0;
+#pragma unroll
+                    for (int gq = 0; gq < SPW; ++gq) {
+                        const uint64_t bg = NP < 64 ? ((hit >> (gq * NP)) | (1ull << (NP & 63))) : hit;
+                        const int qg = bg ? (int)__builtin_ctzll(bg) : 0;
+                        nq = (gq == 0 || slot == gq) ? qg : nq;
+                    }
+                    if (live) cur = nq;
                     if (i == u) mine = cur;
                 }
                 const int st = t0 - 1 - i;
