@@ -257,7 +257,7 @@ hmm_status hmm_call_kernel(const hmm_bank *bank, const hmm_batch *batch, int32_t
 #define HMM_PROF_FWD_BATCHED 0   /* length-sorted MFMA forward            */
 #define HMM_PROF_ADJ_BATCHED 1   /* checkpointed MFMA backward            */
 #define HMM_PROF_FWD_PLAIN 2     /* plain per-pair forward                */
-#define HMM_PROF_VITERBI 3       /* max-plus decoding (without traceback)  */
+#define HMM_PROF_VITERBI 3       /* Viterbi decoding and traceback         */
 hmm_status hmm_profile_enable(int32_t on);
 hmm_status hmm_profile_read(int32_t kernel, double *total_ms, int32_t *launches);
 

@@ -181,3 +181,64 @@ def test_selector_overrides_table():
     hmm.select_kernel(hmm.KERNEL_BATCHED)
     ref = O.forward(w.pi, w.A, w.B, w.symbols, w.offsets, w.lengths, None)
     assert rel_err(hmm.forward_loglik(p).cpu().numpy(), ref) <= LL_TOL
+
+
+def _replay_matches_eager(fn, outs):
+    """Captures fn(stream) once and replays it three times with eager work in between;
+    every replay must reproduce the eager outputs bit for bit."""
+    fn(torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    ref = [o.clone() for o in outs]
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            fn(s)
+    torch.cuda.current_stream().wait_stream(s)
+    for rep in range(3):
+        for o in outs:
+            o.fill_(-3)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for o, r in zip(outs, ref):
+            assert torch.equal(o, r), rep
+        _ = (outs[0].float() * 2).sum().item()
+
+
+def test_tuned_choices_replay_from_a_graph():
+    """Tuned entries are read on the host when a call is captured: a graph of a
+    call whose entry picks the time-parallel forward, one with capped 16-sequence
+    tiles and one with a capped decoder all replay to the eager results."""
+    print("[case] tuned choices in graphs", flush=True)
+    w = short_workload(11, K=2, N=8, M=10, S=3, tmax=300, all_pairs=False)
+    p = problem(w, True)
+    hmm.tune_set(hmm.tune_key(p.bank, p.batch, hmm.OP_FORWARD), hmm.KERNEL_SCAN, 0)
+    assert hmm.call_kernel(p.bank, p.batch, hmm.OP_FORWARD) == hmm.KERNEL_SCAN
+    ws = p.workspace(hmm.OP_FORWARD)
+    ll = torch.empty(p.S, device="cuda")
+    _replay_matches_eager(lambda st: hmm.forward_loglik(p, out=ll, ws=ws, stream=st), [ll])
+    ref = O.forward(w.pi, w.A, w.B, w.symbols, w.offsets, w.lengths, w.owner)
+    assert rel_err(ll.cpu().numpy(), ref) <= LL_TOL
+
+    w2 = short_workload(12, K=12, N=16, M=20, S=2000, tmax=60, all_pairs=True)
+    p2 = problem(w2, False)
+    b2 = p2.batch_without_models()
+    hmm.tune_set(hmm.tune_key(p2.bank, b2, hmm.OP_CLASSIFY), hmm.KERNEL_TILE16, 2)
+    ws2 = p2.workspace(hmm.OP_CLASSIFY, b2)
+    lab = torch.empty(p2.S, dtype=torch.int32, device="cuda")
+    ll2 = torch.empty((p2.S, p2.K), device="cuda")
+    _replay_matches_eager(lambda st: hmm.classify(p2, labels=lab, loglik=ll2, ws=ws2, stream=st), [lab, ll2])
+    ref2 = O.forward(w2.pi, w2.A, w2.B, w2.symbols, w2.offsets, w2.lengths, None)
+    assert rel_err(ll2.cpu().numpy(), ref2) <= LL_TOL
+
+    w3 = short_workload(13, K=3, N=32, M=20, S=900, tmax=80, all_pairs=False)
+    p3 = problem(w3, True)
+    hmm.tune_set(hmm.tune_key(p3.bank, p3.batch, hmm.OP_VITERBI), hmm.KERNEL_BATCHED, 1)
+    ws3 = p3.workspace(hmm.OP_VITERBI)
+    sc = torch.empty(p3.S, device="cuda")
+    pa = torch.empty(p3.total_symbols, dtype=torch.int32, device="cuda")
+    _replay_matches_eager(lambda st: hmm.viterbi(p3, score=sc, path=pa, ws=ws3, stream=st), [sc, pa])
+    rs, _, _ = O.viterbi(w3.pi, w3.A, w3.B, w3.symbols, w3.offsets, w3.lengths, w3.owner)
+    assert rel_err(sc.cpu().numpy(), rs) <= LL_TOL
