@@ -112,7 +112,7 @@ __global__ void __launch_bounds__(R / BO * WAVE) k_adj_coop(DevPtrs d, AdjLaunch
     __shared__ int32_t tile_sh;
     float *nbl = (float *)smem;  // [M][NP] emission-count partial when NBLDS
     // [NW][M] bytes after the partial: per-wave table that finds repeated symbols in a step
-    volatile uint8_t *duptab = (volatile uint8_t *)(smem + (size_t)a.M * NP * 4);
+    uint8_t *duptab = smem + (size_t)a.M * NP * 4;
 
     const int lane = threadIdx.x & (WAVE - 1);
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
@@ -429,8 +429,11 @@ __global__ void __launch_bounds__(R / BO * WAVE) k_adj_coop(DevPtrs d, AdjLaunch
                             // this step's emission counts wait in registers for the next step.
                             // Repeated symbols: every slot writes its index at its symbol's entry
                             // of the wave's table and reads the entry back; exactly one slot per
-                            // symbol finds its own index (volatile: the read is not folded)
+                            // symbol finds its own index (the wave-level LDS fence keeps the read
+                            // from being folded into the lane's own write; a volatile access would
+                            // lose the LDS address space and wait for all outstanding global loads)
                             duptab[w * M + ot] = (uint8_t)sl;
+                            wave_lds_sync();
                             const int first = duptab[w * M + ot];
 #pragma unroll
                             for (int b = 0; b < BO; ++b) {
@@ -539,7 +542,7 @@ __global__ void __launch_bounds__(2 * R * WAVE) k_adj_pipe(DevPtrs d, AdjLaunch 
     __shared__ int32_t tile_sh;
     float *nbl = (float *)smem;  // [M][NP] emission-count partial
     // [R][M] bytes after the partial: per-wave table that finds repeated symbols in a step
-    volatile uint8_t *duptab = (volatile uint8_t *)(smem + (size_t)a.M * NP * 4);
+    uint8_t *duptab = smem + (size_t)a.M * NP * 4;
 
     const int lane = threadIdx.x & (WAVE - 1);
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
@@ -720,6 +723,7 @@ __global__ void __launch_bounds__(2 * R * WAVE) k_adj_pipe(DevPtrs d, AdjLaunch 
                                 // this step's emission counts wait in registers for the next step
                                 // (repeated symbols in the wave's 16 slots take atomics, as in k_adj_coop)
                                 duptab[w * M + ot] = (uint8_t)sl;
+                                wave_lds_sync();
                                 const int first = duptab[w * M + ot];
                                 float gm[4];
 #pragma unroll
