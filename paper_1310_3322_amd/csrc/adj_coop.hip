@@ -38,6 +38,7 @@ namespace hmm {
 namespace {
 
 constexpr int ACH = 32;      // symbols per staging chunk
+constexpr int PACH = 16;     // symbols per staging chunk of the pipelined kernel (its LDS is full)
 constexpr int STREAM_D = 2;  // blocks of streamed fragments in flight
 
 // Blocks per wave: as in the forward (one up to 8 blocks, two above).
@@ -522,12 +523,13 @@ __global__ void __launch_bounds__(R / BO * WAVE) k_adj_coop(DevPtrs d, AdjLaunch
 // walks segment j backwards: betahat, the emission counts and w_t, as in
 // k_adj_coop.  The recompute group (waves R .. 2R-1, wave R + w owning block w)
 // meanwhile recomputes segment j - 1 from its checkpoint into the other half of
-// the segment buffer and, for each backward step t of segment j, adds its rows
-// of C += X^T W from alphahat_t (its own entries of the previous phase) and
-// w_{t+1} (the exchange row the backward group reads in the same step).  A
-// tile thus takes nseg + 1 phases of at most L steps instead of 2 nseg, and the
-// two groups' matrix-core chains share each SIMD.  Every quantity is formed by
-// the same operations in the same order as in k_adj_coop.
+// the segment buffer.  For each backward step t of segment j both groups add
+// to C += X^T W for their rows, the backward group the first R / 2 column
+// blocks and the recompute group the others, from alphahat_t and w_{t+1} (the
+// exchange row both read in that step), so that neither group's step carries
+// all of it.  A tile thus takes nseg + 1 phases of at most L steps instead of
+// 2 nseg, and the two groups' matrix-core chains share each SIMD.  Every
+// quantity is formed by the same operations in the same order as in k_adj_coop.
 template <int R>
 __global__ void __launch_bounds__(2 * R * WAVE) k_adj_pipe(DevPtrs d, AdjLaunch a) {
     using SH = AdjCoopShape<R, 1>;
@@ -536,8 +538,8 @@ __global__ void __launch_bounds__(2 * R * WAVE) k_adj_pipe(DevPtrs d, AdjLaunch 
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ __align__(16) float xch[SH::xch_floats];
     __shared__ __align__(16) float wex[SH::w_floats];
-    __shared__ float atile_all[SH::at_floats];
-    __shared__ int32_t sym[2][ACH * TILE];
+    __shared__ float atile_all[2 * SH::at_floats];  // one transposition tile per wave of both groups
+    __shared__ int32_t sym[2][PACH * TILE];
     __shared__ float mlast[TILE];  // m_T of each sequence of the tile
     __shared__ int32_t tile_sh;
     float *nbl = (float *)smem;  // [M][NP] emission-count partial
@@ -553,7 +555,7 @@ __global__ void __launch_bounds__(2 * R * WAVE) k_adj_pipe(DevPtrs d, AdjLaunch 
     const int swz = nb_swz(NP);
     float *xbuf = xch;
     float *psum = xch + CoopShape<R>::x_floats;
-    float *atile = atile_all + w * TILE * 17;  // [16 s][17] own alphahat block, transposed reads (recompute group)
+    float *atile = atile_all + wid * TILE * 17;  // [16 s][17] own alphahat block, transposed reads
 
     // segment buffer: two halves (segment parity), each alphahat [Lcap][R][64]
     // float4, then e and o [Lcap][R][64] int32
@@ -580,9 +582,34 @@ __global__ void __launch_bounds__(2 * R * WAVE) k_adj_pipe(DevPtrs d, AdjLaunch 
         if (ntiles > 0) {
             AdjFrags<R, 1, false> fr;
             fr.load(Ak, N, w, g, sl, nullptr, 0);
-            floatx4 C[R];  // recompute group: rows 16 w + 4 g + v, columns 16 rj + sl
+            // each group adds half of the transition counts: rows 16 w + 4 g + v,
+            // columns 16 (rj0 + rj) + sl, rj0 = 0 (backward group) or R / 2
+            constexpr int RH = R / 2;
+            const int rj0 = rec ? RH : 0;
+            floatx4 C[RH];
 #pragma unroll
-            for (int rj = 0; rj < R; ++rj) C[rj] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+            for (int rj = 0; rj < RH; ++rj) C[rj] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+            // C[own rows][half] += X^T W for backward step t: alphahat_t of the own block,
+            // weighted, through the wave's transposition tile; w_{t+1} from the exchange row
+            auto c_update = [&](const float (&al)[4], bool trans, float wgt_, const float *wrow) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) atile[sl * 17 + 4 * g + v] = trans ? wgt_ * al[v] : 0.0f;
+                wave_lds_sync();
+                float xa[4], wb[4][RH];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int s = 4 * q + g;
+                    xa[q] = atile[s * 17 + sl];
+#pragma unroll
+                    for (int rj = 0; rj < RH; ++rj) wb[q][rj] = wrow[s * XROW + 16 * (rj0 + rj) + sl];
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+#pragma unroll
+                    for (int rj = 0; rj < RH; ++rj)
+                        C[rj] = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[q], wb[q][rj], C[rj], 0, 0, 0);
+                wave_lds_sync();
+            };
 
             for (;;) {
                 if (threadIdx.x == 0) tile_sh = atomicAdd(&a.queue[k], 1);
@@ -639,21 +666,21 @@ __global__ void __launch_bounds__(2 * R * WAVE) k_adj_pipe(DevPtrs d, AdjLaunch 
                 if (threadIdx.x < TILE) mlast[threadIdx.x] = 1.0f;
 
                 // recompute group state: symbols staged by its first wave, chunk c in sym[c & 1]
-                int32_t nxt[ACH / 4];
+                int32_t nxt[PACH / 4];
                 float x[4] = {};
                 int e = 0, e_prev = 0;
                 int t0B = 0;
                 auto load_chunk = [&](int s0) {
 #pragma unroll
-                    for (int u = 0; u < ACH / 4; ++u) nxt[u] = sbase[min(s0 + 4 * u + g, tlim)];
+                    for (int u = 0; u < PACH / 4; ++u) nxt[u] = sbase[min(s0 + 4 * u + g, tlim)];
                 };
                 auto store_chunk = [&](int c) {
 #pragma unroll
-                    for (int u = 0; u < ACH / 4; ++u) sym[c & 1][u * WAVE + lane] = nxt[u];
+                    for (int u = 0; u < PACH / 4; ++u) sym[c & 1][u * WAVE + lane] = nxt[u];
                 };
                 auto read_sym = [&](int t) {
-                    const int tl = t - t0B, pp = tl % ACH;
-                    int o = sym[(tl / ACH) & 1][(pp / 4) * WAVE + 16 * (pp % 4) + sl];
+                    const int tl = t - t0B, pp = tl % PACH;
+                    int o = sym[(tl / PACH) & 1][(pp / 4) * WAVE + 16 * (pp % 4) + sl];
                     return ((unsigned)o < (unsigned)M) ? o : 0;
                 };
                 // entry 0 of a recomputed segment: the checkpoint itself
@@ -714,6 +741,7 @@ __global__ void __launch_bounds__(2 * R * WAVE) k_adj_pipe(DevPtrs d, AdjLaunch 
                                     fr.bwd(wex + ((t + 1) & 1) * TILE * XROW, g, sl, u);
 #pragma unroll
                                     for (int v = 0; v < 4; ++v) be[v] = u[0][v];
+                                    c_update(al, act && t + 1 < T, wgt, wex + ((t + 1) & 1) * TILE * XROW);
                                 }
                                 if (t == T - 1) {
                                     const float inv = 1.0f / mlast[sl];
@@ -751,9 +779,9 @@ __global__ void __launch_bounds__(2 * R * WAVE) k_adj_pipe(DevPtrs d, AdjLaunch 
                                     if (w == 0) {
                                         load_chunk(t0B);
                                         store_chunk(0);
-                                        load_chunk(t0B + ACH);
+                                        load_chunk(t0B + PACH);
                                         store_chunk(1);
-                                        load_chunk(t0B + 2 * ACH);
+                                        load_chunk(t0B + 2 * PACH);
                                     }
                                     // alphahat at the checkpoint of segment jB
                                     if (t0B < T) {
@@ -782,9 +810,9 @@ __global__ void __launch_bounds__(2 * R * WAVE) k_adj_pipe(DevPtrs d, AdjLaunch 
                                         store_entry0(jB);
                                     else
                                         finish(jB, tr - 1);
-                                    if (w == 0 && (it % ACH) == 0 && it >= ACH) {
-                                        store_chunk(it / ACH + 1);
-                                        load_chunk(tr + 2 * ACH);
+                                    if (w == 0 && (it % PACH) == 0 && it >= PACH) {
+                                        store_chunk(it / PACH + 1);
+                                        load_chunk(tr + 2 * PACH);
                                     }
                                     const int o = read_sym(tr);
                                     seg_o(jB)[sidx(it)] = o;
@@ -799,29 +827,10 @@ __global__ void __launch_bounds__(2 * R * WAVE) k_adj_pipe(DevPtrs d, AdjLaunch 
                                 }
                             }
                             if (it < LA && t + 1 < Tmax) {
-                                // C[own rows][all] += X^T W for backward step t
                                 const int tl = t - t0A;
                                 const float al[4] = {aq_n.x, aq_n.y, aq_n.z, aq_n.w};
                                 aq_n = seg_alpha(jA)[sidx(tl > 0 ? tl - 1 : 0)];
-                                const bool trans = act && t + 1 < T;
-                                const float *wrow = wex + ((t + 1) & 1) * TILE * XROW;
-#pragma unroll
-                                for (int v = 0; v < 4; ++v) atile[sl * 17 + 4 * g + v] = trans ? wgt * al[v] : 0.0f;
-                                wave_lds_sync();
-                                float xa[4], wb[4][R];
-#pragma unroll
-                                for (int q = 0; q < 4; ++q) {
-                                    const int s = 4 * q + g;
-                                    xa[q] = atile[s * 17 + sl];
-#pragma unroll
-                                    for (int rj = 0; rj < R; ++rj) wb[q][rj] = wrow[s * XROW + 16 * rj + sl];
-                                }
-#pragma unroll
-                                for (int q = 0; q < 4; ++q)
-#pragma unroll
-                                    for (int rj = 0; rj < R; ++rj)
-                                        C[rj] = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[q], wb[q][rj], C[rj], 0, 0, 0);
-                                wave_lds_sync();
+                                c_update(al, act && t + 1 < T, wgt, wex + ((t + 1) & 1) * TILE * XROW);
                             } else if (it < LA) {
                                 const int tl = t - t0A;
                                 aq_n = seg_alpha(jA)[sidx(tl > 0 ? tl - 1 : 0)];
@@ -848,13 +857,13 @@ __global__ void __launch_bounds__(2 * R * WAVE) k_adj_pipe(DevPtrs d, AdjLaunch 
                     }
                 }
             }
-            if (rec) {
-                // n_A = A o C for this wave's rows of model k
+            {
+                // n_A = A o C for this wave's rows and half of the columns of model k
 #pragma unroll
-                for (int rj = 0; rj < R; ++rj)
+                for (int rj = 0; rj < RH; ++rj)
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
-                        const int i = 16 * w + 4 * g + v, jj = 16 * rj + sl;
+                        const int i = 16 * w + 4 * g + v, jj = 16 * (rj0 + rj) + sl;
                         if (i < N && jj < N) {
                             const float c = C[rj][v];
                             if (c != 0.0f) atomicAdd(&a.cnt_A[((size_t)k * N + i) * N + jj], Ak[(size_t)i * N + jj] * c);
@@ -895,7 +904,9 @@ bool use_pipe(int M) {
     if constexpr (R != 4) {
         return false;
     } else {
-        return nb_lds_bytes<R>(M) + AdjCoopShape<R, 1>::small_bytes + TILE * 4 + 64 <= COOP_LDS_LIMIT;
+        using SH = AdjCoopShape<R, 1>;
+        const size_t small = (SH::xch_floats + SH::w_floats + 2 * SH::at_floats) * 4 + 2 * PACH * TILE * 4 + TILE * 4;
+        return nb_lds_bytes<R>(M) + small + 64 <= COOP_LDS_LIMIT;
     }
 }
 
