@@ -197,8 +197,8 @@ def main():
                     help="JSON tuning cache: install the choices stored there instead of tuning, store new ones")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(sharding over sequences is described in DESIGN.md).", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path (sequences would be "
+              "sharded over GPUs, each running the same launch on its share).", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -62,7 +62,7 @@ typedef enum {
     HMM_ERR_NULL = -1,        /* a required pointer is NULL                        */
     HMM_ERR_SHAPE = -2,       /* K, N, M, S, max_len or total_symbols out of range */
     HMM_ERR_WORKSPACE = -3,   /* workspace NULL, misaligned or too small           */
-    HMM_ERR_UNSUPPORTED = -4, /* valid request this build cannot run               */
+    HMM_ERR_UNSUPPORTED = -4, /* valid request the library cannot run             */
     HMM_ERR_HIP = -5,         /* a HIP runtime call or kernel launch failed        */
     HMM_ERR_ARG = -6          /* an enumerated argument has an unknown value       */
 } hmm_status;
