@@ -39,7 +39,7 @@ namespace {
 
 constexpr int ACH = 32;      // symbols per staging chunk
 constexpr int PACH = 16;     // symbols per staging chunk of the pipelined kernel (its LDS is full)
-constexpr int STREAM_D = 2;  // blocks of streamed fragments in flight
+constexpr int STREAM_D = 3;  // blocks of streamed fragments in flight
 
 // Blocks per wave: as in the forward (one up to 8 blocks, two above).
 constexpr int adj_bo(int R) { return R > 8 ? 2 : 1; }
