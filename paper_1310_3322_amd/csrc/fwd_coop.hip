@@ -105,7 +105,6 @@ __global__ void __launch_bounds__(R / BO * WAVE) k_fwd_coop(DevPtrs d, FwdLaunch
                 store_chunk(0);
                 load_chunk(CCH);
                 store_chunk(1);
-                load_chunk(2 * CCH);
             }
             __syncthreads();
 
@@ -113,14 +112,16 @@ __global__ void __launch_bounds__(R / BO * WAVE) k_fwd_coop(DevPtrs d, FwdLaunch
             int o = read_sym(0);
             symbad |= (0 < T) && (o < 0 || o >= M);
             o = ((unsigned)o < (unsigned)M) ? o : 0;
-            float4 b_nx[BO];
+            float4 bA[BO], bB[BO];
 #pragma unroll
-            for (int b = 0; b < BO; ++b) b_nx[b] = *(const float4 *)&btk[(size_t)o * NP + 16 * (r0 + b) + 4 * g];
+            for (int b = 0; b < BO; ++b) bA[b] = *(const float4 *)&btk[(size_t)o * NP + 16 * (r0 + b) + 4 * g];
             float x[BO][4] = {};
             int E = 0, E_end = 0;
             float c_end = 1.0f;
-            for (int t = 0; t <= Tmax; ++t) {
-                // ---- read phase: finish step t-1 (its sum, exponent, checkpoint)
+            int ck_t = 0, ck_c = 0;  // next checkpointed step and its index
+            // Read phase of step t: finishes step t - 1 (its sum, exponent and
+            // checkpoint) and returns that step's exponent (0 at t = 0).
+            auto read_phase = [&](int t) -> int {
                 int e = 0;
                 if (t > 0) {
                     const float cs = coop_step_sum<R>(psum + ((t - 1) & 1) * R * TILE, sl);
@@ -130,37 +131,43 @@ __global__ void __launch_bounds__(R / BO * WAVE) k_fwd_coop(DevPtrs d, FwdLaunch
                         c_end = cs;
                     }
                     E += e;
-                    if (CKPT && ((t - 1) % L) == 0 && t - 1 < T) {
-                        const int c = (t - 1) / L;
+                    if (CKPT && t - 1 == ck_t) {  // t - 1 = L ck_c
+                        if (t - 1 < T) {
 #pragma unroll
-                        for (int b = 0; b < BO; ++b) {
-                            float *dst = f.ckpt + ((size_t)pos * f.nck + c) * NP + 16 * (r0 + b) + 4 * g;
-                            *(float4 *)dst = float4{ldexp_f(x[b][0], -e), ldexp_f(x[b][1], -e), ldexp_f(x[b][2], -e),
-                                                    ldexp_f(x[b][3], -e)};
+                            for (int b = 0; b < BO; ++b) {
+                                float *dst = f.ckpt + ((size_t)pos * f.nck + ck_c) * NP + 16 * (r0 + b) + 4 * g;
+                                *(float4 *)dst = float4{ldexp_f(x[b][0], -e), ldexp_f(x[b][1], -e),
+                                                        ldexp_f(x[b][2], -e), ldexp_f(x[b][3], -e)};
+                            }
+                            if (w == 0 && g == 0) f.ckexp[(size_t)pos * f.nck + ck_c] = e;
                         }
-                        if (w == 0 && g == 0) f.ckexp[(size_t)pos * f.nck + c] = e;
+                        ck_t += L;
+                        ++ck_c;
                     }
                 }
-                if (t == Tmax) break;
-                // ---- compute phase of step t
-                float4 bcur[BO];
+                return e;
+            };
+            // Step t < Tmax: read phase, then the compute phase.
+            // bcur holds the emission rows of step t, bnext receives
+            // those of step t + 1.  The loop below alternates the two register
+            // sets, so no copy carries a pending load across the loop latch (the
+            // compiler would wait for every outstanding load there); the load
+            // into bnext is issued every step (a valid row when t + 1 = Tmax) so
+            // that the wait before its use in the next step can count it.
+            // Chunk c + 1 >= 2 is loaded by wave 0 at step 32 c (always the first
+            // step of a pair) and stored at step 32 c + 1 (the second), into the
+            // buffer of chunk c - 1, whose last reader, step 32 c - 2, every wave
+            // has passed; the barrier of step 32 c + 1 publishes it long before
+            // its first reader, step 32 c + 31.  Loading and storing inside one
+            // iteration keeps the staging registers out of the loop latch.
+            auto step = [&](int t, const float4 (&bcur)[BO], float4 (&bnext)[BO], bool chunk_ld, bool chunk_st) {
+                const int e = read_phase(t);
+                if (chunk_ld) load_chunk(t + CCH);
+                int on = read_sym(t + 1);  // any value at t + 1 = Tmax, clamped below
+                symbad |= (t + 1 < T) && (on < 0 || on >= M);
+                on = ((unsigned)on < (unsigned)M) ? on : 0;
 #pragma unroll
-                for (int b = 0; b < BO; ++b) bcur[b] = b_nx[b];
-                if (t + 1 < Tmax) {
-                    if (w == 0 && ((t + 1) % CCH) == 0) {
-                        // every wave has passed step t - 1, the last reader of chunk
-                        // (t+1)/CCH - 1; its buffer takes chunk (t+1)/CCH + 1, which the
-                        // barriers of the next CCH - 1 steps publish before it is read
-                        store_chunk((t + 1) / CCH + 1);
-                        load_chunk(t + 1 + 2 * CCH);
-                    }
-                    int on = read_sym(t + 1);
-                    symbad |= (t + 1 < T) && (on < 0 || on >= M);
-                    on = ((unsigned)on < (unsigned)M) ? on : 0;
-#pragma unroll
-                    for (int b = 0; b < BO; ++b)
-                        b_nx[b] = *(const float4 *)&btk[(size_t)on * NP + 16 * (r0 + b) + 4 * g];
-                }
+                for (int b = 0; b < BO; ++b) bnext[b] = *(const float4 *)&btk[(size_t)on * NP + 16 * (r0 + b) + 4 * g];
                 floatx4 u[BO];
                 if (t == 0) {
 #pragma unroll
@@ -180,10 +187,19 @@ __global__ void __launch_bounds__(R / BO * WAVE) k_fwd_coop(DevPtrs d, FwdLaunch
                         float4{x[b][0], x[b][1], x[b][2], x[b][3]};
                     if (g == 0) psum[(t & 1) * R * TILE + (r0 + b) * TILE + sl] = part;
                 }
+                if (chunk_st) store_chunk(t / CCH + 1);
                 // the waves exchange alphahat through LDS only: the emission rows and
                 // symbols requested for the next steps stay in flight across the barrier
                 lds_barrier();
+            };
+            int t = 0;
+            for (; t + 1 < Tmax; t += 2) {
+                const bool chunk = w == 0 && t > 0 && (t % CCH) == 0;
+                step(t, bA, bB, chunk, false);
+                step(t + 1, bB, bA, false, chunk);
             }
+            if (t < Tmax) step(t++, bA, bB, false, false);
+            read_phase(t);
             if (has && g == 0 && w == 0) {
                 float r = (float)((double)E_end * LN2 + (double)logf(c_end));
                 if (bad || symbad) r = NAN;
