@@ -37,7 +37,7 @@
 namespace hmm {
 namespace {
 
-constexpr int ACH = 32;      // symbols per staging chunk
+constexpr int SSEG = 64;     // steps of symbols staged at a time (a whole segment up to T = 4096)
 constexpr int PACH = 16;     // symbols per staging chunk of the pipelined kernel (its LDS is full)
 constexpr int STREAM_D = 3;  // blocks of streamed fragments in flight
 
@@ -52,7 +52,7 @@ struct AdjCoopShape {
     static constexpr int xch_floats = CoopShape<R>::floats;  // recompute exchange
     static constexpr int w_floats = 2 * TILE * XROW;         // w exchange, double-buffered
     static constexpr int at_floats = NW * BO * TILE * 17;    // per-wave transposition tiles
-    static constexpr int small_bytes = (xch_floats + w_floats + at_floats) * 4 + 2 * ACH * TILE * 4;
+    static constexpr int small_bytes = (xch_floats + w_floats + at_floats) * 4 + SSEG * TILE * 4;
 };
 
 // LDS partial of the emission counts: state i of symbol o at o * NP + (i ^ (4 o & 12)).
@@ -109,7 +109,7 @@ __global__ void __launch_bounds__(R / BO * WAVE) k_adj_coop(DevPtrs d, AdjLaunch
     __shared__ __align__(16) float xch[SH::xch_floats];
     __shared__ __align__(16) float wex[SH::w_floats];
     __shared__ float atile_all[SH::at_floats];
-    __shared__ int32_t sym[2][ACH * TILE];
+    __shared__ int32_t symseg[SSEG * TILE];
     __shared__ int32_t tile_sh;
     float *nbl = (float *)smem;  // [M][NP] emission-count partial when NBLDS
     // [NW][M] bytes after the partial: per-wave table that finds repeated symbols in a step
@@ -231,29 +231,19 @@ __global__ void __launch_bounds__(R / BO * WAVE) k_adj_coop(DevPtrs d, AdjLaunch
                 for (int j = nseg - 1; j >= 0; --j) {
                     const int t0 = j * L;
                     const int t1 = min(t0 + L, Tmax);
-                    // ---- symbols of the segment: wave 0 stages them, chunk c in sym[c & 1]
-                    int32_t nxt[ACH / 4];
-                    auto load_chunk = [&](int s0) {
-#pragma unroll
-                        for (int u = 0; u < ACH / 4; ++u) nxt[u] = sbase[min(s0 + 4 * u + g, tlim)];
-                    };
-                    auto store_chunk = [&](int c) {
-#pragma unroll
-                        for (int u = 0; u < ACH / 4; ++u) sym[c & 1][u * WAVE + lane] = nxt[u];
+                    // ---- symbols of the segment, SSEG steps at a time, staged by every
+                    // wave (one load round trip per block; no staging registers live
+                    // across the steps)
+                    auto stage_syms = [&](int s0) {
+                        for (int s = w * 4 + g; s < SSEG; s += NW * 4)
+                            symseg[s * TILE + sl] = sbase[min(s0 + s, tlim)];
                     };
                     auto read_sym = [&](int t) {
-                        const int tl = t - t0, pp = tl % ACH;
-                        int o = sym[(tl / ACH) & 1][(pp / 4) * WAVE + 16 * (pp % 4) + sl];
+                        const int o = symseg[((t - t0) % SSEG) * TILE + sl];
                         return ((unsigned)o < (unsigned)M) ? o : 0;
                     };
                     __syncthreads();
-                    if (w == 0) {
-                        load_chunk(t0);
-                        store_chunk(0);
-                        load_chunk(t0 + ACH);
-                        store_chunk(1);
-                        load_chunk(t0 + 2 * ACH);
-                    }
+                    stage_syms(t0);
                     // ---- recompute alphahat over [t0, t1) from checkpoint j
                     float x[BO][4];
 #pragma unroll
@@ -303,9 +293,10 @@ __global__ void __launch_bounds__(R / BO * WAVE) k_adj_coop(DevPtrs d, AdjLaunch
                             if (t - 1 == T - 1) m_last = ldexp_f(cs, -e);
                         }
                         if (t == t1) break;
-                        if (w == 0 && ((t - t0) % ACH) == 0 && t - t0 >= ACH) {
-                            store_chunk((t - t0) / ACH + 1);
-                            load_chunk(t + 2 * ACH);
+                        if (((t - t0) % SSEG) == 0) {  // segments longer than SSEG steps
+                            __syncthreads();
+                            stage_syms(t);
+                            __syncthreads();
                         }
                         const int o = read_sym(t);
                         seg_o[sidx(t - t0)] = o;
@@ -361,13 +352,46 @@ __global__ void __launch_bounds__(R / BO * WAVE) k_adj_coop(DevPtrs d, AdjLaunch
                         const bool trans = act && t + 1 < T;
                         const float *wrow = wex + ((t + 1) & 1) * TILE * XROW;  // w_{t+1}, all states
                         float be[BO][4] = {};
-                        if (t + 1 < Tmax) {
+                        const bool more = t + 1 < Tmax;
+                        // The w row of step Tmax is zero, so the streamed variant runs the
+                        // product there too (its result is unused: at t = Tmax - 1 beta is
+                        // 1 / m_T or the sequence has ended); every path then issues the
+                        // fragment loads, and the wait for the segment entries requested
+                        // above can count them instead of waiting for every load.
+                        if (STREAM || more) {
                             floatx4 u[BO];
                             fr.bwd(wrow, g, sl, u);
 #pragma unroll
                             for (int b = 0; b < BO; ++b)
 #pragma unroll
                                 for (int v = 0; v < 4; ++v) be[b][v] = u[b][v];
+                        }
+                        if (t == T - 1) {
+                            const float inv = 1.0f / m_last;
+#pragma unroll
+                            for (int b = 0; b < BO; ++b)
+#pragma unroll
+                                for (int v = 0; v < 4; ++v) be[b][v] = inv;
+                        }
+                        if (!DEFER && live) {
+                            // emission counts before the C update, whose MFMAs cover the
+                            // atomics' latency before the next step's first load is awaited
+#pragma unroll
+                            for (int b = 0; b < BO; ++b)
+#pragma unroll
+                                for (int v = 0; v < 4; ++v) {
+                                    const int i = 16 * (r0 + b) + 4 * g + v;
+                                    const float gm = wgt * al[b][v] * be[b][v];
+                                    if (i < N) {
+                                        if (NBLDS)
+                                            atomicAdd(&nbl[ot * NP + (i ^ (ot * 4 & swz))], gm);
+                                        else
+                                            atomicAdd(&nbt[(size_t)ot * NP + i], gm);
+                                    }
+                                    if (t == 0) gpi[b][v] = gm;
+                                }
+                        }
+                        if (more) {
                             // C[own rows][all] += X^T W: X (own blocks) through the wave's tiles
 #pragma unroll
                             for (int b = 0; b < BO; ++b)
@@ -419,13 +443,6 @@ __global__ void __launch_bounds__(R / BO * WAVE) k_adj_coop(DevPtrs d, AdjLaunch
                         } else if (DEFER) {
                             flush_pending();
                         }
-                        if (t == T - 1) {
-                            const float inv = 1.0f / m_last;
-#pragma unroll
-                            for (int b = 0; b < BO; ++b)
-#pragma unroll
-                                for (int v = 0; v < 4; ++v) be[b][v] = inv;
-                        }
                         if (DEFER) {
                             // this step's emission counts wait in registers for the next step.
                             // Repeated symbols: every slot writes its index at its symbol's entry
@@ -450,21 +467,6 @@ __global__ void __launch_bounds__(R / BO * WAVE) k_adj_coop(DevPtrs d, AdjLaunch
                             }
                             pend_on = live;
                             pend_dup = first != sl;
-                        } else if (live) {
-#pragma unroll
-                            for (int b = 0; b < BO; ++b)
-#pragma unroll
-                                for (int v = 0; v < 4; ++v) {
-                                    const int i = 16 * (r0 + b) + 4 * g + v;
-                                    const float gm = wgt * al[b][v] * be[b][v];
-                                    if (i < N) {
-                                        if (NBLDS)
-                                            atomicAdd(&nbl[ot * NP + (i ^ (ot * 4 & swz))], gm);
-                                        else
-                                            atomicAdd(&nbt[(size_t)ot * NP + i], gm);
-                                    }
-                                    if (t == 0) gpi[b][v] = gm;
-                                }
                         }
                         // w_t = b_t o betahat_t 2^-e_t; zero where the sequence has ended or
                         // takes no part (its values may be inf / NaN and w enters the
