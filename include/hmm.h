@@ -162,11 +162,14 @@ hmm_status hmm_forward_backward_grad(const hmm_bank *bank, const hmm_batch *batc
  * state index, both for the last state and for every back-pointer.
  * T = 0 gives score 0; an impossible observation gives score -inf (and the
  * path the tie rule produces); an invalid symbol or model index gives score
- * NaN, path entries -1 and the error word in ws.  Supports N <= 64
- * (HMM_ERR_UNSUPPORTED above).  The workspace (op HMM_OP_VITERBI) holds the
- * FP32 delta row of every step (states padded to 16, 32 or 64): about
- * total_symbols * 256 bytes at most.  The sequences must not overlap in
- * `symbols`: their delta rows and path entries take the symbols' layout. */
+ * NaN, path entries -1 and the error word in ws.  Every N up to
+ * HMM_MAX_STATES: up to 64 states one wave decodes 64 / N sequences, above a
+ * workgroup decodes one sequence.  The workspace (op HMM_OP_VITERBI) holds the
+ * FP32 delta row of every step (states padded to 16, 32, 64, 128 or 256):
+ * total_symbols * 4 * padded states bytes, up to 1 KiB per symbol at 256
+ * states, plus ln A transposed above 64 states.  The sequences must not
+ * overlap in `symbols`: their delta rows and path entries take the symbols'
+ * layout. */
 hmm_status hmm_viterbi(const hmm_bank *bank, const hmm_batch *batch, float *score, int32_t *path,
                        void *ws, size_t ws_bytes, hipStream_t stream);
 

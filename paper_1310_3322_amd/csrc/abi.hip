@@ -165,8 +165,11 @@ inline int padded_states(int N) { return N <= 64 ? pad16(N) : ((N + 31) / 32) * 
 // blocks) from 64 to 256 states.
 inline bool grad_uses_coop(int NP) { return NP >= 64; }
 
-// States padded for the decoder: its lane groups divide a wave.
-inline int viterbi_states(int N) { return N <= 16 ? 16 : N <= 32 ? 32 : N <= 64 ? 64 : 0; }
+// States padded for the decoder: lane groups that divide a wave up to 64
+// states, a workgroup of 4 threads per state above.
+inline int viterbi_states(int N) {
+    return N <= 16 ? 16 : N <= 32 ? 32 : N <= 64 ? 64 : N <= 128 ? 128 : N <= 256 ? 256 : 0;
+}
 
 bool batched_capable(const hmm_bank *b, const hmm_batch *q, int op) {
     if (op == HMM_OP_VITERBI) {
@@ -224,7 +227,10 @@ Layout make_layout(const hmm_bank *b, const hmm_batch *q, int op) {
         L.gstart = take((size_t)(groups + 1) * sizeof(int32_t));
         L.perm = take((size_t)S * sizeof(int32_t));
         L.bt = take((size_t)K * M * NP * sizeof(float));
-        if (op == HMM_OP_VITERBI) L.delta = take(((size_t)q->total_symbols * NP + 64) * sizeof(float));
+        if (op == HMM_OP_VITERBI) {
+            L.delta = take(((size_t)q->total_symbols * NP + 64) * sizeof(float));
+            if (NP > 64) L.lnat = take((size_t)K * b->N * NP * sizeof(float));
+        }
         if (op == HMM_OP_GRAD) {
             int nck = 1;
             while ((int64_t)nck * nck < q->max_len) ++nck;
@@ -573,6 +579,8 @@ hmm_status hmm_viterbi(const hmm_bank *bank, const hmm_batch *batch, float *scor
     const int nbins = K * (batch->max_len + 1);
     launch_plan(d, K, S, K, batch->max_len, batch->total_symbols, nbins, w, L, stream);
     launch_log_transpose_b(bank->B, (float *)(w + L.bt), K, N, M, NP, stream);
+    // ln A transposed: the same transpose with A's N columns in place of B's M
+    if (NP > 64) launch_log_transpose_b(bank->A, (float *)(w + L.lnat), K, N, N, NP, stream);
     launch_fill_i32((int32_t *)(w + L.queue) + K, (size_t)K, 0, stream);  // the traceback's queues
     if (hipGetLastError() != hipSuccess) return HMM_ERR_HIP;
     VitLaunch v;
@@ -589,6 +597,7 @@ hmm_status hmm_viterbi(const hmm_bank *bank, const hmm_batch *batch, float *scor
     v.queue = (int32_t *)(w + L.queue);
     v.err = (int32_t *)(w + L.err);
     v.lnbt = (const float *)(w + L.bt);
+    v.lnat = NP > 64 ? (const float *)(w + L.lnat) : nullptr;
     v.delta = (float *)(w + L.delta);
     v.spill = v.delta + (size_t)batch->total_symbols * NP;
     v.score = score;

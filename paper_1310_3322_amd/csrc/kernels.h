@@ -24,6 +24,7 @@ struct Layout {
     size_t nbt;      // float [K][M][NP] symbol-major emission counts (cooperative gradient)
     size_t frag;     // float4 [K][2][NP^2 / 4] streamed MFMA fragments (cooperative gradient, NP > 128)
     size_t delta;    // float [total][NP] Viterbi delta rows (bt then holds ln B transposed), then 64 spare floats
+    size_t lnat;     // float [K][N][NP] ln A transposed (Viterbi, NP > 64)
     size_t scan;     // time-parallel forward: chunk products, exponents, flags (ScanWs)
     int32_t scan_nch;    // chunks per pair of the time-parallel forward (0: not used)
     int32_t kind;        // kernel family of the call (HMM_KERNEL_*, after the tuning table)
@@ -161,6 +162,7 @@ struct VitLaunch {
     const int32_t *perm, *gstart;
     int32_t *queue, *err;
     const float *lnbt;  // [K][M][NP] ln B transposed, -inf beyond N
+    const float *lnat;  // [K][N][NP] ln A transposed, lnat[k][j][i] = ln A_k[i][j], -inf beyond N (NP > 64)
     float *delta;       // [total][NP] delta row of every step but the last, laid out like the symbols
     float *spill;       // [64] target of the delta stores of empty slots (never read)
     float *score;       // [S]

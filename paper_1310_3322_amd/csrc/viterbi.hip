@@ -333,6 +333,277 @@ __global__ void __launch_bounds__(VWAVES * WAVE) k_viterbi_trace(DevPtrs d, VitL
     }
 }
 
+// Decoder for 64 < N <= 256 (NP = 128 or 256), where a column of ln A no
+// longer fits one lane: one sequence per workgroup of WQ NP threads.  Thread
+// (j, q) = (threadIdx.x / WQ, threadIdx.x % WQ) owns state j and the quarter q
+// of the predecessors, i = q NP / WQ .. (q + 1) NP / WQ - 1, with ln A[i][j]
+// for those i in registers.  Per step it takes the maximum of its candidates
+// delta_{t-1}(i) + ln A[i][j] from the LDS row, the WQ threads of a state
+// (neighbouring lanes) combine their maxima with two lane exchanges, and each
+// adds ln B[j][o_t].  Recursion, shift period and stored rows are those of the
+// per-wave decoder; the maximum for a shift and the final arg-max go through
+// the waves' partial results in LDS.  ln A is read from the transposed log
+// table lnat[k][j][i] that the traceback reads too, so both form the
+// candidates from identical FP32 operands.
+constexpr int WQ = 4;     // predecessor quarters per state
+constexpr int WSCH = 64;  // symbols per staged chunk
+
+template <int NP>
+__global__ void __launch_bounds__(WQ * NP) k_viterbi_wg(DevPtrs d, VitLaunch v) {
+    constexpr int IQ = NP / WQ;            // predecessors per thread
+    constexpr int NWV = WQ * NP / WAVE;    // waves per workgroup
+    __shared__ __align__(16) float dl[2][NP];
+    __shared__ int32_t syms[2][WSCH];
+    __shared__ float red_v[NWV];
+    __shared__ int red_i[NWV];
+    __shared__ int unit_sh;
+    const int tid = threadIdx.x;
+    const int lane = tid & (WAVE - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(tid / WAVE);
+    const int j = tid / WQ, q = tid % WQ;
+    const int K = v.K, N = v.N, M = v.M;
+
+    const int G = gridDim.x;
+    const int k_first = G >= K ? (int)(blockIdx.x % K) : (int)blockIdx.x;
+    const int k_step = G >= K ? K : G;
+    for (int k = k_first; k < K; k += k_step) {
+        const int gbeg = v.gstart[k], gend = v.gstart[k + 1];
+        const int nseq = gend - gbeg;
+        if (nseq == 0) continue;
+        // ln A[i][j] for this thread's quarter of i (states beyond N are impossible)
+        float la[IQ];
+        {
+            const float4 *row = (const float4 *)(v.lnat + ((size_t)k * N + (j < N ? j : 0)) * NP + q * IQ);
+#pragma unroll
+            for (int i4 = 0; i4 < IQ / 4; ++i4) {
+                const float4 x = row[i4];
+                la[4 * i4] = j < N ? x.x : -INFINITY;
+                la[4 * i4 + 1] = j < N ? x.y : -INFINITY;
+                la[4 * i4 + 2] = j < N ? x.z : -INFINITY;
+                la[4 * i4 + 3] = j < N ? x.w : -INFINITY;
+            }
+        }
+        const float lpi = j < N ? logf(d.pi[(size_t)k * N + j]) : -INFINITY;
+        const float *lbk = v.lnbt + (size_t)k * M * NP;
+
+        // The loop's exit and the step loop's bound are scalar (readfirstlane): a
+        // bound the compiler takes for a per-lane value turns these loops, which
+        // contain barriers, into exec-masked loops, and with the pop and the output
+        // both under tid == 0 it then let lanes 1..63 of wave 0 re-enter the
+        // sequence loop without lane 0, re-reading a head that never advanced.
+        for (;;) {
+            if (tid == 0) unit_sh = atomicAdd(&v.queue[k], 1);
+            __syncthreads();
+            const int unit = __builtin_amdgcn_readfirstlane(unit_sh);
+            __syncthreads();
+            if (unit >= nseq) break;
+
+            const int seq = v.perm[gbeg + unit];
+            const int32_t Tin = d.lengths[seq];
+            const int64_t off = d.offsets[seq];
+            const int mk = d.model_of_seq[seq];
+            const bool bad = seq_bad(Tin, off, v.max_len, v.total) || mk < 0 || mk >= K;
+            const int32_t T = __builtin_amdgcn_readfirstlane(bad ? 0 : Tin);
+            const int32_t *sq = T > 0 ? d.symbols + off : d.symbols;
+            const int tlim = T > 0 ? T - 1 : 0;
+            // row t of the sequence's delta rows (the values step t + 1 reads); the WQ
+            // threads of a state store the same value
+            float *drow = v.delta + (T > 0 ? off : 0) * NP + j;
+            bool symbad = false;
+            double shift = 0.0;
+            float del = -INFINITY;
+            float fin_v = -INFINITY;
+            double fin_shift = 0.0;
+            if (T > 0) {
+                if (tid < WSCH) {
+                    syms[0][tid] = sq[min(tid, tlim)];
+                    syms[1][tid] = sq[min(WSCH + tid, tlim)];
+                }
+                __syncthreads();
+                for (int t = 0; t < T; ++t) {
+                    if (t >= WSCH && (t % WSCH) == 0 && tid < WSCH) {
+                        // chunk t / WSCH + 1 into the buffer of chunk t / WSCH - 1, whose last
+                        // reader, step t - 1, every thread has passed; read from step t + WSCH on
+                        syms[((t / WSCH) + 1) & 1][tid] = sq[min(t + WSCH + tid, tlim)];
+                    }
+                    int o = syms[(t / WSCH) & 1][t % WSCH];
+                    symbad |= (o < 0 || o >= M);
+                    o = ((unsigned)o < (unsigned)M) ? o : 0;
+                    const float lb = lbk[(size_t)o * NP + j];
+                    if (t == 0) {
+                        del = lpi + lb;
+                    } else {
+                        const float4 *pr = (const float4 *)(dl[(t - 1) & 1] + q * IQ);
+                        float best = -INFINITY;
+#pragma unroll
+                        for (int i4 = 0; i4 < IQ / 4; ++i4) {
+                            const float4 x = pr[i4];
+                            best = fmaxf(fmaxf(best, x.x + la[4 * i4]), x.y + la[4 * i4 + 1]);
+                            best = fmaxf(fmaxf(best, x.z + la[4 * i4 + 2]), x.w + la[4 * i4 + 3]);
+                        }
+                        best = fmaxf(best, __shfl_xor(best, 1, WAVE));
+                        best = fmaxf(best, __shfl_xor(best, 2, WAVE));
+                        del = best + lb;
+                    }
+                    if (t == T - 1) {
+                        fin_v = del;
+                        fin_shift = shift;
+                    }
+                    if (((t + 1) % RN) == 0) {
+                        float m = group_max<WAVE>(del);
+                        if (lane == 0) red_v[wave] = m;
+                        __syncthreads();
+                        m = red_v[0];
+#pragma unroll
+                        for (int w2 = 1; w2 < NWV; ++w2) m = fmaxf(m, red_v[w2]);
+                        if (!(m > -INFINITY && m < INFINITY)) m = 0.0f;
+                        del = del - m;
+                        shift += (double)m;
+                    }
+                    dl[t & 1][j] = del;
+                    drow[(size_t)t * NP] = del;
+                    lds_barrier();
+                }
+            }
+            // last state: the first state attaining the maximum of delta_T
+            float fv = fin_v;
+            int fi = j;
+            group_argmax<WAVE>(fv, fi);
+            if (lane == 0) {
+                red_v[wave] = fv;
+                red_i[wave] = fi;
+            }
+            __syncthreads();
+            if (tid == 0) {
+                float bv = red_v[0];
+                int bi = red_i[0];
+                for (int w2 = 1; w2 < NWV; ++w2)  // waves hold increasing states
+                    if (red_v[w2] > bv) {
+                        bv = red_v[w2];
+                        bi = red_i[w2];
+                    }
+                float sc;
+                if (bad || symbad) {
+                    sc = NAN;
+                    atomicMin(v.err, seq);
+                } else if (T == 0) {
+                    sc = 0.0f;
+                } else {
+                    sc = (float)(fin_shift + (double)bv);
+                }
+                v.score[seq] = sc;
+                if (T > 0) v.path[off + T - 1] = (bad || symbad) ? -1 : bi;
+            }
+            __syncthreads();  // the outputs of tid 0 stay apart from its next pop
+        }
+    }
+}
+
+// Traceback for 64 < N <= 256: one wave per sequence, lane l holding the
+// predecessors i = 64 c + l (c < NP / 64).  Per step the candidates
+// delta_{t-1}(i) + ln A[i][q_t] come from the stored row and the row q_t of
+// the transposed log table; the first state attaining their maximum is
+// q_{t-1}.  Rows are requested TU steps ahead (they do not depend on the
+// path); lane u of a block of TU steps records q_{t0 - 1 - u}, and the block
+// ends with one store.
+constexpr int TU = 8;
+
+template <int NP>
+__global__ void __launch_bounds__(VWAVES * WAVE) k_viterbi_trace_wg(DevPtrs d, VitLaunch v) {
+    constexpr int C = NP / WAVE;
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int K = v.K, N = v.N;
+    int32_t *queue = v.queue + K;  // the decoder pops [0, K)
+
+    const int G = gridDim.x;
+    const int k_first = G >= K ? (int)(blockIdx.x % K) : (int)blockIdx.x;
+    const int k_step = G >= K ? K : G;
+    for (int k = k_first; k < K; k += k_step) {
+        const int gbeg = v.gstart[k], gend = v.gstart[k + 1];
+        const int nseq = gend - gbeg;
+        if (nseq == 0) continue;
+        const float *lnk = v.lnat + (size_t)k * N * NP;
+        for (;;) {
+            const int unit = wave_pop(&queue[k]);
+            if (unit >= nseq) break;
+            const int s = v.perm[gbeg + unit];
+            int32_t T = d.lengths[s];
+            const int64_t off = d.offsets[s];
+            const int mk = d.model_of_seq[s];
+            if (seq_bad(T, off, v.max_len, v.total) || mk < 0 || mk >= K) T = 0;
+            int32_t *qp = v.path + (T > 0 ? off : 0);
+            const float sc = T > 0 ? v.score[s] : 0.0f;
+            if (sc != sc) {  // invalid symbol: no path
+                for (int32_t t = lane; t < T; t += WAVE) qp[t] = -1;
+                T = 0;
+            }
+            T = __builtin_amdgcn_readfirstlane(T);  // one sequence per wave: scalar loop bounds
+            if (T <= 1) continue;
+            int cur = __builtin_amdgcn_readfirstlane(qp[T - 1]);
+            cur = ((unsigned)cur < (unsigned)N) ? cur : 0;
+            const float *drow = v.delta + off * NP + lane;
+            auto row = [&](int r, int c) { return drow[(size_t)max(r, 0) * NP + c * WAVE]; };
+            int32_t *sink = (int32_t *)v.spill + lane;
+            float ring[TU][C];
+#pragma unroll
+            for (int u = 0; u < TU; ++u)
+#pragma unroll
+                for (int c = 0; c < C; ++c) ring[u][c] = row(T - 2 - u, c);
+            for (int t0 = T - 1; t0 >= 1; t0 -= TU) {
+                int mine = 0;
+#pragma unroll
+                for (int u = 0; u < TU; ++u) {
+                    const int t = t0 - u;
+                    float dprev[C];
+#pragma unroll
+                    for (int c = 0; c < C; ++c) {
+                        dprev[c] = ring[u][c];
+                        ring[u][c] = row(t - 1 - TU, c);
+                    }
+                    const float *lr = lnk + (size_t)cur * NP + lane;
+                    int kc[C];
+                    int m = INT_MIN;
+#pragma unroll
+                    for (int c = 0; c < C; ++c) {
+                        kc[c] = order_key(dprev[c] + lr[c * WAVE]);
+                        m = max(m, kc[c]);
+                    }
+                    m = group_max_key<WAVE>(m);
+                    int nq = -1;
+#pragma unroll
+                    for (int c = C - 1; c >= 0; --c) {  // the lowest block with a hit wins
+                        const uint64_t h = __ballot(kc[c] == m);
+                        if (h) nq = c * WAVE + (int)__builtin_ctzll(h);
+                    }
+                    if (t >= 1) cur = nq >= 0 ? nq : 0;
+                    if (lane == u) mine = cur;
+                }
+                const int st = t0 - 1 - lane;
+                *((lane < TU && st >= 0) ? qp + st : sink) = mine;
+            }
+        }
+    }
+}
+
+template <int NP>
+hipError_t launch_wg(const DevPtrs &d, const VitLaunch &v, int cu_count, hipStream_t st) {
+    auto kern = k_viterbi_wg<NP>;
+    int per_cu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, WQ * NP, 0);
+    if (e != hipSuccess) return e;
+    if (per_cu < 1) per_cu = 1;
+    const int grid = persistent_grid(cu_count * per_cu, tile_bound(v.S, v.K, false, 1), 1, v.K, v.max_grid);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(WQ * NP), 0, st, d, v);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    auto tk = k_viterbi_trace_wg<NP>;
+    int per_cu_t = 0;
+    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_t, tk, VWAVES * WAVE, 0)) != hipSuccess) return e;
+    if (per_cu_t < 1) per_cu_t = 1;
+    const int grid_t = persistent_grid(cu_count * per_cu_t, tile_bound(v.S, v.K, false, 1), VWAVES, v.K, v.max_grid);
+    hipLaunchKernelGGL(tk, dim3(grid_t), dim3(VWAVES * WAVE), 0, st, d, v);
+    return hipGetLastError();
+}
+
 template <int NP>
 hipError_t launch_t(const DevPtrs &d, const VitLaunch &v, int cu_count, hipStream_t st) {
     auto kern = k_viterbi<NP>;
@@ -355,7 +626,7 @@ hipError_t launch_t(const DevPtrs &d, const VitLaunch &v, int cu_count, hipStrea
 
 }  // namespace
 
-bool viterbi_supported(int NP) { return NP == 16 || NP == 32 || NP == 64; }
+bool viterbi_supported(int NP) { return NP == 16 || NP == 32 || NP == 64 || NP == 128 || NP == 256; }
 
 hipError_t launch_viterbi(const DevPtrs &d, const VitLaunch &v, int cu_count, hipStream_t st) {
     if (v.S == 0) return hipSuccess;
@@ -363,6 +634,8 @@ hipError_t launch_viterbi(const DevPtrs &d, const VitLaunch &v, int cu_count, hi
         case 16: return launch_t<16>(d, v, cu_count, st);
         case 32: return launch_t<32>(d, v, cu_count, st);
         case 64: return launch_t<64>(d, v, cu_count, st);
+        case 128: return launch_wg<128>(d, v, cu_count, st);
+        case 256: return launch_wg<256>(d, v, cu_count, st);
         default: return hipErrorInvalidValue;
     }
 }

@@ -103,16 +103,20 @@ def test_host_side_errors_enqueue_nothing(lib):
     need = lib.hmm_workspace_size(ctypes.byref(big), ctypes.byref(ql), 2)
     assert lib.hmm_forward_backward_grad(ctypes.byref(big), ctypes.byref(ql), None, out, out, out, out, 0, ws_al,
                                          need, None) == -4
-    # Viterbi: model_of_seq, score and path required; more than 64 states reported, not attempted
+    # Viterbi: model_of_seq, score and path required; a plan beyond the bin limit reported, not attempted
     assert lib.hmm_viterbi(ctypes.byref(b), ctypes.byref(q), out, out, ws_al, 1 << 40, None) == -1
     assert lib.hmm_viterbi(ctypes.byref(b), ctypes.byref(qm), None, out, ws_al, 1 << 40, None) == -1
     assert lib.hmm_viterbi(ctypes.byref(b), ctypes.byref(qm), out, None, ws_al, 1 << 40, None) == -1
     need = lib.hmm_workspace_size(ctypes.byref(b), ctypes.byref(qm), 3)
     assert need >= 5000 * 16  # one back-pointer byte per padded state and symbol
     assert lib.hmm_viterbi(ctypes.byref(b), ctypes.byref(qm), out, out, ws_al, need - 1, None) == -3
-    wide = hmm.Bank(4, 65, 32, 0x1000, 0x2000, 0x3000)
-    need = lib.hmm_workspace_size(ctypes.byref(wide), ctypes.byref(qm), 3)
-    assert lib.hmm_viterbi(ctypes.byref(wide), ctypes.byref(qm), out, out, ws_al, need, None) == -4
+    # every state count up to HMM_MAX_STATES decodes: the workspace holds the delta rows
+    # (states padded to 128 / 256) and, above 64 states, ln A transposed
+    for n, np_ in ((65, 128), (256, 256)):
+        wide = hmm.Bank(4, n, 32, 0x1000, 0x2000, 0x3000)
+        assert lib.hmm_workspace_size(ctypes.byref(wide), ctypes.byref(qm), 3) >= 5000 * np_ * 4 + 4 * n * np_ * 4
+    need = lib.hmm_workspace_size(ctypes.byref(big), ctypes.byref(ql), 3)
+    assert lib.hmm_viterbi(ctypes.byref(big), ctypes.byref(ql), out, out, ws_al, need, None) == -4
     assert lib.hmm_reestimate_rows(out, out, out, -1, 4, None) == -2
     assert lib.hmm_reestimate_rows(None, out, out, 3, 4, None) == -1
     # softmax / logit-grad shape checks
@@ -261,8 +265,11 @@ def test_call_kernel_resolution(lib):
         assert hmm.call_kernel(hmm.Bank(8, 32, 64, 1, 2, 3), hmm.Batch(9000, 4, 5, 6, 7, 100, 1 << 20),
                                hmm.OP_GRAD) == hmm.KERNEL_TILE16
         assert hmm.call_kernel(hmm.Bank(8, 32, 64, 1, 2, 3), one, hmm.OP_VITERBI) == hmm.KERNEL_BATCHED
-        with pytest.raises(hmm.HMMError) as e:
-            hmm.call_kernel(hmm.Bank(8, 100, 64, 1, 2, 3), one, hmm.OP_VITERBI)
+        # above 64 states the workgroup decoder (the batched family as well)
+        assert hmm.call_kernel(hmm.Bank(8, 100, 64, 1, 2, 3), one, hmm.OP_VITERBI) == hmm.KERNEL_BATCHED
+        with pytest.raises(hmm.HMMError) as e:  # a plan beyond the bin limit
+            hmm.call_kernel(hmm.Bank(64, 100, 64, 1, 2, 3), hmm.Batch(100, 4, 5, 6, 7, 1 << 20, 5000),
+                            hmm.OP_VITERBI)
         assert e.value.status == -4
         # the table
         hmm.tune_set(hmm.tune_key(c3b, c3q, hmm.OP_CLASSIFY), hmm.KERNEL_TILE16, 2)

@@ -88,12 +88,14 @@ def test_viterbi_parity_workloads(cfg, scale):
         assert n > 0  # the exact comparison is exercised
 
 
-@pytest.mark.parametrize("N", [1, 2, 5, 16, 17, 31, 32, 33, 48, 64])
+@pytest.mark.parametrize("N", [1, 2, 5, 16, 17, 31, 32, 33, 48, 64, 65, 100, 128, 129, 200, 256])
 def test_viterbi_state_counts_and_ragged_lengths(N):
-    """Every padding of the state axis; lengths around the shift period (16), T = 0 and 1."""
+    """Every padding of the state axis (lane groups up to 64 states, workgroups of 4 threads
+    per state above); lengths around the shift period (16) and the workgroup decoder's
+    symbol chunk (64), T = 0 and 1."""
     print(f"[case] viterbi N={N}", flush=True)
     rng = np.random.default_rng([31, N])
-    lengths = np.concatenate([[0, 1, 2, 15, 16, 17, 31, 32, 33, 300], rng.integers(1, 120, size=30)])
+    lengths = np.concatenate([[0, 1, 2, 15, 16, 17, 31, 32, 33, 63, 64, 65, 129, 300], rng.integers(1, 120, size=26)])
     w = workloads.random_lengths_workload(rng, K=3, N=N, M=11, lengths=lengths, all_pairs=False, conc=0.4)
     check(w)
 
@@ -140,15 +142,46 @@ def test_viterbi_full_c3_sampled():
             assert np.array_equal(path[off:off + T], rp[so:so + T]), s
 
 
-def test_viterbi_unsupported_and_determinism():
+def test_viterbi_determinism():
+    """Repeated calls give identical scores and paths, for the per-wave decoder (c2) and
+    the workgroup decoder (65 states)."""
     rng = np.random.default_rng(3)
-    w = workloads.random_lengths_workload(rng, K=2, N=65, M=4, lengths=np.array([5, 6]), all_pairs=False)
-    with pytest.raises(hmm.HMMError) as e:
-        hmm.viterbi(problem(w))
-    assert e.value.status == -4
+    big = workloads.random_lengths_workload(rng, K=2, N=65, M=4, lengths=np.array([5, 6, 70, 0, 1]), all_pairs=False)
+    check(big)
     w = workloads.make_workload("c2", scale=0.05)
     w.all_pairs = False
-    p = problem(w)
-    a = hmm.viterbi(p)
-    b = hmm.viterbi(p)
-    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+    for x in (w, big):
+        p = problem(x)
+        a = hmm.viterbi(p)
+        b = hmm.viterbi(p)
+        assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+
+
+def test_viterbi_c5_bank_sampled():
+    """The c5 bank (256 states, 1024 symbols, banded transitions) on a 5 % sample of its
+    sequences (lengths 256..4096), each with its owner: sampled sequences vs the oracle."""
+    print("[case] viterbi c5 sample", flush=True)
+    w = workloads.make_workload("c5", scale=0.05)
+    w.all_pairs = False
+    sc, path = hmm.viterbi(problem(w))
+    sc, path = sc.cpu().numpy(), path.cpu().numpy()
+    assert np.all(np.isfinite(sc))
+    order = np.argsort(-w.lengths, kind="stable")
+    rng = np.random.default_rng(5)
+    pick = np.unique(np.concatenate([order[:2], order[-2:], rng.choice(w.S, 6, replace=False)]))
+    sub = w.subset(pick)
+    rs, rp, rm = O.viterbi(sub.pi, sub.A, sub.B, sub.symbols, sub.offsets, sub.lengths, sub.owner)
+    err = np.max(np.abs(sc[pick] - rs) / np.maximum(np.abs(rs), 1.0))
+    assert err <= TOL, err
+    exact = 0
+    for i, s in enumerate(pick):
+        T, off, so = int(w.lengths[s]), int(w.offsets[s]), int(sub.offsets[i])
+        g = path[off:off + T]
+        if rm[i] > 1e-5 * max(1.0, abs(rs[i])) + 1e-4:
+            assert np.array_equal(g, rp[so:so + T]), s
+            exact += 1
+        else:
+            assert np.all((g >= 0) & (g < w.N)), s
+            lp = path_logprob(sub, i, g, sub.symbols)
+            assert abs(lp - rs[i]) <= TOL * max(1.0, abs(rs[i])), (s, lp, rs[i])
+    print(f"  {exact} of {len(pick)} paths compared exactly", flush=True)
