@@ -18,7 +18,8 @@ time.  Printed as one JSON line, with:
                 6 algorithmic FLOPs per state-step;
   large_states  the N=256 bank (16 models, M=1024, 16,384 sequences, T in
                 [256, 4096], own model): forward, and forward + adjoint, on the
-                cooperative kernels;
+                cooperative kernels, and Viterbi decoding on the workgroup
+                decoder;
   latency       the small workloads, whose time is the serial chain of steps
                 (c1: one sequence of 64 steps; c2: 4096 sequences x 12 models,
                 T up to 400, with labels): microseconds per call, eager and as a
@@ -347,8 +348,26 @@ def main():
         large["fwd_bwd"] = {"value": u5 / gs5, "unit": "state-steps/s", "ms_per_step": gs5 * 1e3,
                             "fwd_kernel_ms": f5_ms / max(f5_n, 1), "adj_kernel_ms": a5_ms / max(a5_n, 1),
                             "frac_fp32_peak": 6.0 * u5 / gs5 / 1e12 / FP32_PEAK_TFLOPS}
+        del ws5g, cnt5
+        # Viterbi on the same bank and sequences (workgroup decoder: 256 states)
+        wsv5 = p5.workspace(hmm.OP_VITERBI)
+        scv5 = torch.empty(w5.S, dtype=torch.float32, device="cuda")
+        pav5 = torch.empty(w5.total_symbols, dtype=torch.int32, device="cuda")
+        fv5 = lambda: hmm.viterbi(p5, score=scv5, path=pav5, ws=wsv5)
+        fv5()
+        torch.cuda.synchronize()
+        hmm.profile_enable(True)
+        sv5 = time_steps(fv5, 2, 0, torch)
+        kv5_ms, kv5_n = hmm.profile_read(hmm.PROF_VITERBI)
+        hmm.profile_enable(False)
+        kv5_s = kv5_ms / max(kv5_n, 1) / 1e3
+        large["viterbi"] = {"value": u5 / sv5, "unit": "state-steps/s", "ms_per_step": sv5 * 1e3,
+                            "kernels_ms": kv5_s * 1e3,  # decoder + traceback
+                            "roofline": {"bound": "alu", "achieved": round(2.0 * u5 / kv5_s / 1e12, 3),
+                                         "peak": VALU_PEAK_TOPS, "unit": "Tops/s",
+                                         "frac": round(2.0 * u5 / kv5_s / 1e12 / VALU_PEAK_TOPS, 4)}}
         result["large_states"] = large
-        del p5, ws5g, cnt5
+        del p5, wsv5, scv5, pav5
 
         log("latency-bound workloads c1 and c2")
         hmm.select_kernel(hmm.KERNEL_AUTO)
