@@ -334,24 +334,41 @@ __global__ void __launch_bounds__(VWAVES * WAVE) k_viterbi_trace(DevPtrs d, VitL
 }
 
 // Decoder for 64 < N <= 256 (NP = 128 or 256), where a column of ln A no
-// longer fits one lane: one sequence per workgroup of WQ NP threads.  Thread
-// (j, q) = (threadIdx.x / WQ, threadIdx.x % WQ) owns state j and the quarter q
-// of the predecessors, i = q NP / WQ .. (q + 1) NP / WQ - 1, with ln A[i][j]
-// for those i in registers.  Per step it takes the maximum of its candidates
-// delta_{t-1}(i) + ln A[i][j] from the LDS row, the WQ threads of a state
-// (neighbouring lanes) combine their maxima with two lane exchanges, and each
-// adds ln B[j][o_t].  Recursion, shift period and stored rows are those of the
-// per-wave decoder; the maximum for a shift and the final arg-max go through
-// the waves' partial results in LDS.  ln A is read from the transposed log
-// table lnat[k][j][i] that the traceback reads too, so both form the
-// candidates from identical FP32 operands.
-constexpr int WQ = 4;     // predecessor quarters per state
+// longer fits one lane: one sequence per workgroup of 4 NP threads.  The 16
+// lanes of a DPP row share a group of WJ = 4 consecutive states j = 4 g + c;
+// lane r of the row holds the slice i = r NP / 16 .. (r + 1) NP / 16 - 1 of
+// the predecessors, with ln A[i][j] for its slice and the group's 4 states in
+// registers (NP / 4 values).  Per step it reads its slice of delta_{t-1} from
+// LDS once for the 4 states (four times fewer LDS reads than one state per
+// thread), forms the 4 maxima over its slice of delta_{t-1}(i) + ln A[i][j],
+// and the row combines them with row-local permutations fused into max
+// instructions; lane r then finishes state 4 g + (r & 3) with ln B[j][o_t].
+// Recursion, shift period and stored rows are those of the per-wave decoder;
+// the maximum for a shift and the final arg-max go through the waves' partial
+// results in LDS.  ln A is read from the transposed log table lnat[k][j][i]
+// that the traceback reads too, so both form the candidates from identical
+// FP32 operands.
+constexpr int WJ = 4;     // states per row of 16 lanes
+constexpr int WR = 16;    // predecessor slices (the lanes of a row)
 constexpr int WSCH = 64;  // symbols per staged chunk
 
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+
+// Maximum over the 16 lanes of a row, in every lane of the row (exact in any order).
+__device__ __forceinline__ float row_max(float v) {
+    v = fmaxf(v, dpp_f<0xB1>(v));   // quad_perm [1, 0, 3, 2]
+    v = fmaxf(v, dpp_f<0x4E>(v));   // quad_perm [2, 3, 0, 1]
+    v = fmaxf(v, dpp_f<0x141>(v));  // row_half_mirror
+    return fmaxf(v, dpp_f<0x140>(v));  // row_mirror
+}
+
 template <int NP>
-__global__ void __launch_bounds__(WQ * NP) k_viterbi_wg(DevPtrs d, VitLaunch v) {
-    constexpr int IQ = NP / WQ;            // predecessors per thread
-    constexpr int NWV = WQ * NP / WAVE;    // waves per workgroup
+__global__ void __launch_bounds__(WR * NP / WJ) k_viterbi_wg(DevPtrs d, VitLaunch v) {
+    constexpr int IS = NP / WR;                // predecessors per lane
+    constexpr int NWV = WR * NP / WJ / WAVE;   // waves per workgroup
     __shared__ __align__(16) float dl[2][NP];
     __shared__ int32_t syms[2][WSCH];
     __shared__ float red_v[NWV];
@@ -360,7 +377,8 @@ __global__ void __launch_bounds__(WQ * NP) k_viterbi_wg(DevPtrs d, VitLaunch v) 
     const int tid = threadIdx.x;
     const int lane = tid & (WAVE - 1);
     const int wave = __builtin_amdgcn_readfirstlane(tid / WAVE);
-    const int j = tid / WQ, q = tid % WQ;
+    const int jg = tid / WR, r = tid % WR;
+    const int j = WJ * jg + (r & (WJ - 1));  // the state this lane finishes
     const int K = v.K, N = v.N, M = v.M;
 
     const int G = gridDim.x;
@@ -370,17 +388,19 @@ __global__ void __launch_bounds__(WQ * NP) k_viterbi_wg(DevPtrs d, VitLaunch v) 
         const int gbeg = v.gstart[k], gend = v.gstart[k + 1];
         const int nseq = gend - gbeg;
         if (nseq == 0) continue;
-        // ln A[i][j] for this thread's quarter of i (states beyond N are impossible)
-        float la[IQ];
-        {
-            const float4 *row = (const float4 *)(v.lnat + ((size_t)k * N + (j < N ? j : 0)) * NP + q * IQ);
+        // ln A[i][4 jg + c] for this lane's slice of i (states beyond N are impossible)
+        float la[WJ][IS];
 #pragma unroll
-            for (int i4 = 0; i4 < IQ / 4; ++i4) {
+        for (int c = 0; c < WJ; ++c) {
+            const int jc = WJ * jg + c;
+            const float4 *row = (const float4 *)(v.lnat + ((size_t)k * N + (jc < N ? jc : 0)) * NP + r * IS);
+#pragma unroll
+            for (int i4 = 0; i4 < IS / 4; ++i4) {
                 const float4 x = row[i4];
-                la[4 * i4] = j < N ? x.x : -INFINITY;
-                la[4 * i4 + 1] = j < N ? x.y : -INFINITY;
-                la[4 * i4 + 2] = j < N ? x.z : -INFINITY;
-                la[4 * i4 + 3] = j < N ? x.w : -INFINITY;
+                la[c][4 * i4] = jc < N ? x.x : -INFINITY;
+                la[c][4 * i4 + 1] = jc < N ? x.y : -INFINITY;
+                la[c][4 * i4 + 2] = jc < N ? x.z : -INFINITY;
+                la[c][4 * i4 + 3] = jc < N ? x.w : -INFINITY;
             }
         }
         const float lpi = j < N ? logf(d.pi[(size_t)k * N + j]) : -INFINITY;
@@ -406,8 +426,8 @@ __global__ void __launch_bounds__(WQ * NP) k_viterbi_wg(DevPtrs d, VitLaunch v) 
             const int32_t T = __builtin_amdgcn_readfirstlane(bad ? 0 : Tin);
             const int32_t *sq = T > 0 ? d.symbols + off : d.symbols;
             const int tlim = T > 0 ? T - 1 : 0;
-            // row t of the sequence's delta rows (the values step t + 1 reads); the WQ
-            // threads of a state store the same value
+            // row t of the sequence's delta rows (the values step t + 1 reads); the
+            // lanes that finish the same state store the same value
             float *drow = v.delta + (T > 0 ? off : 0) * NP + j;
             bool symbad = false;
             double shift = 0.0;
@@ -433,17 +453,24 @@ __global__ void __launch_bounds__(WQ * NP) k_viterbi_wg(DevPtrs d, VitLaunch v) 
                     if (t == 0) {
                         del = lpi + lb;
                     } else {
-                        const float4 *pr = (const float4 *)(dl[(t - 1) & 1] + q * IQ);
-                        float best = -INFINITY;
+                        const float4 *pr = (const float4 *)(dl[(t - 1) & 1] + r * IS);
+                        float best[WJ];
 #pragma unroll
-                        for (int i4 = 0; i4 < IQ / 4; ++i4) {
+                        for (int c = 0; c < WJ; ++c) best[c] = -INFINITY;
+#pragma unroll
+                        for (int i4 = 0; i4 < IS / 4; ++i4) {
                             const float4 x = pr[i4];
-                            best = fmaxf(fmaxf(best, x.x + la[4 * i4]), x.y + la[4 * i4 + 1]);
-                            best = fmaxf(fmaxf(best, x.z + la[4 * i4 + 2]), x.w + la[4 * i4 + 3]);
+#pragma unroll
+                            for (int c = 0; c < WJ; ++c) {
+                                best[c] = fmaxf(fmaxf(best[c], x.x + la[c][4 * i4]), x.y + la[c][4 * i4 + 1]);
+                                best[c] = fmaxf(fmaxf(best[c], x.z + la[c][4 * i4 + 2]), x.w + la[c][4 * i4 + 3]);
+                            }
                         }
-                        best = fmaxf(best, __shfl_xor(best, 1, WAVE));
-                        best = fmaxf(best, __shfl_xor(best, 2, WAVE));
-                        del = best + lb;
+#pragma unroll
+                        for (int c = 0; c < WJ; ++c) best[c] = row_max(best[c]);
+                        const int cs = r & (WJ - 1);
+                        const float bs = cs == 0 ? best[0] : cs == 1 ? best[1] : cs == 2 ? best[2] : best[3];
+                        del = bs + lb;
                     }
                     if (t == T - 1) {
                         fin_v = del;
@@ -589,11 +616,11 @@ template <int NP>
 hipError_t launch_wg(const DevPtrs &d, const VitLaunch &v, int cu_count, hipStream_t st) {
     auto kern = k_viterbi_wg<NP>;
     int per_cu = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, WQ * NP, 0);
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, WR * NP / WJ, 0);
     if (e != hipSuccess) return e;
     if (per_cu < 1) per_cu = 1;
     const int grid = persistent_grid(cu_count * per_cu, tile_bound(v.S, v.K, false, 1), 1, v.K, v.max_grid);
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(WQ * NP), 0, st, d, v);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(WR * NP / WJ), 0, st, d, v);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     auto tk = k_viterbi_trace_wg<NP>;
     int per_cu_t = 0;
