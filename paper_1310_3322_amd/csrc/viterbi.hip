@@ -369,7 +369,8 @@ template <int NP>
 __global__ void __launch_bounds__(WR * NP / WJ) k_viterbi_wg(DevPtrs d, VitLaunch v) {
     constexpr int IS = NP / WR;                // predecessors per lane
     constexpr int NWV = WR * NP / WJ / WAVE;   // waves per workgroup
-    __shared__ __align__(16) float dl[2][NP];
+    constexpr int SLP = IS + 4;                // padded slice: the 16 slices start on different banks
+    __shared__ __align__(16) float dl[2][WR * SLP];
     __shared__ int32_t syms[2][WSCH];
     __shared__ float red_v[NWV];
     __shared__ int red_i[NWV];
@@ -453,7 +454,7 @@ __global__ void __launch_bounds__(WR * NP / WJ) k_viterbi_wg(DevPtrs d, VitLaunc
                     if (t == 0) {
                         del = lpi + lb;
                     } else {
-                        const float4 *pr = (const float4 *)(dl[(t - 1) & 1] + r * IS);
+                        const float4 *pr = (const float4 *)(dl[(t - 1) & 1] + r * SLP);
                         float best[WJ];
 #pragma unroll
                         for (int c = 0; c < WJ; ++c) best[c] = -INFINITY;
@@ -487,7 +488,7 @@ __global__ void __launch_bounds__(WR * NP / WJ) k_viterbi_wg(DevPtrs d, VitLaunc
                         del = del - m;
                         shift += (double)m;
                     }
-                    dl[t & 1][j] = del;
+                    dl[t & 1][j + (j / IS) * (SLP - IS)] = del;
                     drow[(size_t)t * NP] = del;
                     lds_barrier();
                 }
