@@ -108,10 +108,13 @@ def test_every_gradient_table_choice(N, S):
         assert counts_err([c.cpu().numpy() for c in cnt], cnt_ref) <= GRAD_TOL, cap
 
 
-def test_every_viterbi_table_choice():
-    """N=32: 8 sequences per workgroup, 4100 sequences -> 513 units per cap-1 grid of 256."""
-    print("[case] tune viterbi choices", flush=True)
-    w = short_workload(7, K=4, N=32, M=20, S=4100, tmax=30, all_pairs=False)
+@pytest.mark.parametrize("N,S", [(32, 4100), (200, 700)])
+def test_every_viterbi_table_choice(N, S):
+    """N=32: 8 sequences per workgroup, 4100 sequences -> 513 units per cap-1 grid of 256;
+    N=200: the workgroup decoder, one sequence per workgroup, 700 sequences on grids of
+    256 to 1024 workgroups."""
+    print(f"[case] tune viterbi choices N={N}", flush=True)
+    w = short_workload(7, K=4, N=N, M=20, S=S, tmax=30, all_pairs=False)
     rs, rp, rm = O.viterbi(w.pi, w.A, w.B, w.symbols, w.offsets, w.lengths, w.owner)
     p = problem(w, True)
     key = hmm.tune_key(p.bank, p.batch, hmm.OP_VITERBI)

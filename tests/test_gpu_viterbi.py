@@ -100,10 +100,14 @@ def test_viterbi_state_counts_and_ragged_lengths(N):
     check(w)
 
 
-def test_viterbi_special_inputs():
+@pytest.mark.parametrize("N", [6, 150])
+def test_viterbi_special_inputs(N):
+    """An impossible observation (score -inf), an invalid symbol (NaN, path -1, error word),
+    T = 0 (score 0), for the per-wave decoder (N=6) and the workgroup decoder (N=150)."""
+    print(f"[case] viterbi special inputs N={N}", flush=True)
     rng = np.random.default_rng(41)
     lengths = np.array([0, 1, 5, 40, 7, 12, 3], np.int32)
-    w = workloads.random_lengths_workload(rng, K=2, N=6, M=5, lengths=lengths, all_pairs=False)
+    w = workloads.random_lengths_workload(rng, K=2, N=N, M=5, lengths=lengths, all_pairs=False)
     w.B[1, :, 4] = 0.0
     w.B[1] /= w.B[1].sum(axis=1, keepdims=True)
     sym = w.symbols.copy()
