@@ -6,8 +6,9 @@
 //   score = max_j delta_T(j),  q_T = first j attaining it,  q_{t-1} = psi_t(q_t).
 //
 // The step is a max-plus product, which the matrix cores do not execute, so it
-// runs on the vector ALUs.  A wave holds 64 / NP length-sorted sequences of one
-// model; lane (slot, j) owns state j of its sequence and keeps the column
+// runs on the vector ALUs.  Up to 64 states a wave holds 64 / NP length-sorted
+// sequences of one model (larger banks: the workgroup decoder further down);
+// lane (slot, j) owns state j of its sequence and keeps the column
 // ln A[:, j] in registers.  Per step every lane publishes delta_{t-1}(j) in
 // LDS, reads the NP values of its sequence (four per read) and forms the
 // maximum of the NP candidates (an add and half a three-way maximum each),
