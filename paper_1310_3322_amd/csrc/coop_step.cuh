@@ -81,13 +81,15 @@ __device__ __forceinline__ float coop_step_sum(const float *psum, int sl) {
 // single accumulator in block order; the operands of block rp + 1 are loaded
 // while the MFMAs of block rp issue, and scheduling barriers keep the compiler
 // from hoisting every load.
+// q0 is the lane's first float4 of the row (block rp = 0), which a caller may
+// request before it forms e (the two LDS reads then overlap).
 template <int R, int BO>
-__device__ __forceinline__ void coop_matvec(const float (&f)[BO][R][4], const float *xrow_base, int e, int g, int sl,
-                                            floatx4 (&u)[BO]) {
+__device__ __forceinline__ void coop_matvec_q0(const float (&f)[BO][R][4], const float *xrow_base, float4 q0, int e,
+                                               int g, int sl, floatx4 (&u)[BO]) {
 #pragma unroll
     for (int b = 0; b < BO; ++b) u[b] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
     const float *row = xrow_base + sl * CoopShape<R>::XROW + 4 * g;
-    float4 qn = *(const float4 *)&row[0];
+    float4 qn = q0;
 #pragma unroll
     for (int rp = 0; rp < R; ++rp) {
         const float4 q = qn;
@@ -99,6 +101,13 @@ __device__ __forceinline__ void coop_matvec(const float (&f)[BO][R][4], const fl
             for (int b = 0; b < BO; ++b) u[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(f[b][rp][v], in[v], u[b], 0, 0, 0);
         __builtin_amdgcn_sched_barrier(0);
     }
+}
+
+template <int R, int BO>
+__device__ __forceinline__ void coop_matvec(const float (&f)[BO][R][4], const float *xrow_base, int e, int g, int sl,
+                                            floatx4 (&u)[BO]) {
+    const float4 q0 = *(const float4 *)&xrow_base[sl * CoopShape<R>::XROW + 4 * g];
+    coop_matvec_q0<R, BO>(f, xrow_base, q0, e, g, sl, u);
 }
 
 // Fragments streamed from memory instead of registers, for state counts whose

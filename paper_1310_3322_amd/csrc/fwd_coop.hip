@@ -161,6 +161,9 @@ __global__ void __launch_bounds__(R / BO * WAVE) k_fwd_coop(DevPtrs d, FwdLaunch
             // its first reader, step 32 c + 31.  Loading and storing inside one
             // iteration keeps the staging registers out of the loop latch.
             auto step = [&](int t, const float4 (&bcur)[BO], float4 (&bnext)[BO], bool chunk_ld, bool chunk_st) {
+                // first operand of this step's product, requested with the block sums
+                const float *xprev = xbuf + ((t - 1) & 1) * TILE * XROW;
+                const float4 q0 = *(const float4 *)&xprev[sl * XROW + 4 * g];
                 const int e = read_phase(t);
                 if (chunk_ld) load_chunk(t + CCH);
                 int on = read_sym(t + 1);  // any value at t + 1 = Tmax, clamped below
@@ -178,7 +181,7 @@ __global__ void __launch_bounds__(R / BO * WAVE) k_fwd_coop(DevPtrs d, FwdLaunch
                             u[b][v] = i < N ? pik[i] : 0.0f;
                         }
                 } else {
-                    coop_matvec<R, BO>(af, xbuf + ((t - 1) & 1) * TILE * XROW, e, g, sl, u);
+                    coop_matvec_q0<R, BO>(af, xprev, q0, e, g, sl, u);
                 }
 #pragma unroll
                 for (int b = 0; b < BO; ++b) {
