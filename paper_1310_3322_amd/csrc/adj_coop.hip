@@ -72,8 +72,8 @@ struct AdjFrags<R, BO, false> {
         coop_load_fwd_fragments<R, BO>(af, Ak, N, r0, g, sl);
         coop_load_bwd_fragments<R, BO>(ab, Ak, N, r0, g, sl);
     }
-    __device__ __forceinline__ void fwd(const float *x, int e, int g, int sl, floatx4 (&u)[BO]) const {
-        coop_matvec<R, BO>(af, x, e, g, sl, u);
+    __device__ __forceinline__ void fwd(const float *x, float4 q0, int e, int g, int sl, floatx4 (&u)[BO]) const {
+        coop_matvec_q0<R, BO>(af, x, q0, e, g, sl, u);
     }
     __device__ __forceinline__ void bwd(const float *x, int g, int sl, floatx4 (&u)[BO]) const {
         coop_matvec<R, BO>(ab, x, 0, g, sl, u);
@@ -89,8 +89,8 @@ struct AdjFrags<R, BO, true> {
         faf = frag_k + lane_w;
         fab = frag_k + set + lane_w;
     }
-    __device__ __forceinline__ void fwd(const float *x, int e, int g, int sl, floatx4 (&u)[BO]) const {
-        coop_matvec_stream<R, BO, STREAM_D>(faf, x, e, g, sl, u);
+    __device__ __forceinline__ void fwd(const float *x, float4 q0, int e, int g, int sl, floatx4 (&u)[BO]) const {
+        coop_matvec_stream_q0<R, BO, STREAM_D>(faf, x, q0, e, g, sl, u);
     }
     __device__ __forceinline__ void bwd(const float *x, int g, int sl, floatx4 (&u)[BO]) const {
         coop_matvec_stream<R, BO, STREAM_D>(fab, x, 0, g, sl, u);
@@ -280,6 +280,9 @@ __global__ void __launch_bounds__(R / BO * WAVE) k_adj_coop(DevPtrs d, AdjLaunch
                     seg_o[sidx(0)] = read_sym(t0);
                     if (t0 == T - 1) m_last = coop_step_sum<R>(psum + (t0 & 1) * R * TILE, sl);
                     for (int t = t0 + 1; t <= t1; ++t) {
+                        // first operand of this step's product, requested with the block sums
+                        const float *xprev = xbuf + ((t - 1) & 1) * TILE * XROW;
+                        const float4 q0 = *(const float4 *)&xprev[sl * XROW + 4 * g];
                         int e = 0;
                         if (t > t0 + 1) {
                             // finish step t - 1: its sum and exponent, store alphahat_{t-1}
@@ -306,7 +309,7 @@ __global__ void __launch_bounds__(R / BO * WAVE) k_adj_coop(DevPtrs d, AdjLaunch
                         for (int b = 0; b < BO; ++b) bb[b] = *(const float4 *)&btk[(size_t)o * NP + 16 * (r0 + b) + 4 * g];
                         floatx4 u[BO];
                         // the checkpoint row enters unscaled (exponent 0), later rows by 2^-e
-                        fr.fwd(xbuf + ((t - 1) & 1) * TILE * XROW, (t == t0 + 1) ? 0 : e, g, sl, u);
+                        fr.fwd(xprev, q0, (t == t0 + 1) ? 0 : e, g, sl, u);
 #pragma unroll
                         for (int b = 0; b < BO; ++b) {
                             const float part = coop_emit(u[b], bb[b], x[b]);
@@ -808,6 +811,9 @@ __global__ void __launch_bounds__(2 * R * WAVE) k_adj_pipe(DevPtrs d, AdjLaunch 
                                     if (g == 0) psum[(t0B & 1) * R * TILE + w * TILE + sl] = part;
                                 } else {
                                     const int tr = t0B + it;  // recomputed step
+                                    // first operand of this step's product, requested with the block sums
+                                    const float *xprev = xbuf + ((tr - 1) & 1) * TILE * XROW;
+                                    const float4 q0 = *(const float4 *)&xprev[sl * XROW + 4 * g];
                                     if (it == 1)
                                         store_entry0(jB);
                                     else
@@ -821,7 +827,7 @@ __global__ void __launch_bounds__(2 * R * WAVE) k_adj_pipe(DevPtrs d, AdjLaunch 
                                     const float4 bb = *(const float4 *)&btk[(size_t)o * NP + 16 * w + 4 * g];
                                     floatx4 u[1];
                                     // the checkpoint row enters unscaled (exponent 0), later rows by 2^-e
-                                    fr.fwd(xbuf + ((tr - 1) & 1) * TILE * XROW, it == 1 ? 0 : e, g, sl, u);
+                                    fr.fwd(xprev, q0, it == 1 ? 0 : e, g, sl, u);
                                     const float part = coop_emit(u[0], bb, x);
                                     *(float4 *)&xbuf[(tr & 1) * TILE * XROW + sl * XROW + 16 * w + 4 * g] =
                                         float4{x[0], x[1], x[2], x[3]};

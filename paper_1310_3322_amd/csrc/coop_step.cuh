@@ -119,8 +119,8 @@ __device__ __forceinline__ void coop_matvec(const float (&f)[BO][R][4], const fl
 // the step loop as one register pair per block).  Same chains and order as
 // coop_matvec, so the results are bit-identical to it.
 template <int R, int BO, int D>
-__device__ __forceinline__ void coop_matvec_stream(const float4 *fr, const float *xrow_base, int e, int g, int sl,
-                                                   floatx4 (&u)[BO]) {
+__device__ __forceinline__ void coop_matvec_stream_q0(const float4 *fr, const float *xrow_base, float4 q0, int e, int g,
+                                                      int sl, floatx4 (&u)[BO]) {
 #pragma unroll
     for (int b = 0; b < BO; ++b) u[b] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
     const float *row = xrow_base + sl * CoopShape<R>::XROW + 4 * g;
@@ -129,7 +129,7 @@ __device__ __forceinline__ void coop_matvec_stream(const float4 *fr, const float
     for (int dd = 0; dd < D; ++dd)
 #pragma unroll
         for (int b = 0; b < BO; ++b) ring[dd][b] = fr[opaque(dd * WAVE * BO + b)];
-    float4 qn = *(const float4 *)&row[0];
+    float4 qn = q0;
 #pragma unroll
     for (int rp = 0; rp < R; ++rp) {
         const float4 q = qn;
@@ -151,6 +151,13 @@ __device__ __forceinline__ void coop_matvec_stream(const float4 *fr, const float
             }
         __builtin_amdgcn_sched_barrier(0);
     }
+}
+
+template <int R, int BO, int D>
+__device__ __forceinline__ void coop_matvec_stream(const float4 *fr, const float *xrow_base, int e, int g, int sl,
+                                                   floatx4 (&u)[BO]) {
+    const float4 q0 = *(const float4 *)&xrow_base[sl * CoopShape<R>::XROW + 4 * g];
+    coop_matvec_stream_q0<R, BO, D>(fr, xrow_base, q0, e, g, sl, u);
 }
 
 // alpha~ block = u o b, its share of the per-sequence sum (identical in the 4
