@@ -620,6 +620,14 @@ def test_graph_replay_gradient_viterbi_scan():
     sc = torch.empty(w2.S, device="cuda")
     pa = torch.empty(w2.total_symbols, dtype=torch.int32, device="cuda")
     _graph_replays(lambda st: hmm.viterbi(p2, score=sc, path=pa, ws=ws2, stream=st), [sc, pa], exact=True)
+    # the workgroup decoder (150 states): its queues and ln A table are rebuilt inside the call
+    wb = workloads.random_lengths_workload(np.random.default_rng(22), K=3, N=150, M=9,
+                                           lengths=np.array([0, 1, 65, 200, 17, 130, 64]), all_pairs=False)
+    pb = problem(wb, True)
+    wsb = pb.workspace(hmm.OP_VITERBI)
+    scb = torch.empty(wb.S, device="cuda")
+    pab = torch.empty(wb.total_symbols, dtype=torch.int32, device="cuda")
+    _graph_replays(lambda st: hmm.viterbi(pb, score=scb, path=pab, ws=wsb, stream=st), [scb, pab], exact=True)
     rng = np.random.default_rng(21)
     w3 = workloads.random_lengths_workload(rng, K=2, N=8, M=7, lengths=np.array([300, 64, 1, 0, 129]),
                                            all_pairs=False)
