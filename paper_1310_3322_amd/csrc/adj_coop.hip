@@ -378,18 +378,23 @@ __global__ void __launch_bounds__(R / BO * WAVE) k_adj_coop(DevPtrs d, AdjLaunch
                         }
                         if (!DEFER && live) {
                             // emission counts before the C update, whose MFMAs cover the
-                            // atomics' latency before the next step's first load is awaited
+                            // atomics' latency before the next step's first load is awaited.
+                            // Global counts: one address per step, the lane's states at
+                            // immediate offsets from it (per-state addresses were spilled
+                            // to scratch, and each reload waited for every outstanding load)
+                            const int ib = 16 * r0 + 4 * g;
+                            float *dst = nbt + (uint32_t)(ot * NP + ib);
 #pragma unroll
                             for (int b = 0; b < BO; ++b)
 #pragma unroll
                                 for (int v = 0; v < 4; ++v) {
-                                    const int i = 16 * (r0 + b) + 4 * g + v;
+                                    const int i = ib + 16 * b + v;
                                     const float gm = wgt * al[b][v] * be[b][v];
                                     if (i < N) {
                                         if (NBLDS)
                                             atomicAdd(&nbl[ot * NP + (i ^ (ot * 4 & swz))], gm);
                                         else
-                                            atomicAdd(&nbt[(size_t)ot * NP + i], gm);
+                                            atomicAdd(dst + 16 * b + v, gm);
                                     }
                                     if (t == 0) gpi[b][v] = gm;
                                 }
