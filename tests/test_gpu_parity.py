@@ -361,6 +361,24 @@ def test_counts_parity(cfg, scale):
     assert _counts_err(nB.cpu().numpy(), rB) <= GRAD_TOL
 
 
+
+@pytest.mark.parametrize("N", [64, 100, 200])
+def test_counts_cooperative_long_sequences(N):
+    """Sequences longer than 4096 steps: checkpoint segments of more than 64 steps, so the
+    cooperative adjoint stages each segment's symbols in several blocks (pipelined kernel at
+    64 states, register fragments at 100, streamed fragments at 200)."""
+    print(f"[case] counts cooperative long N={N}", flush=True)
+    rng = np.random.default_rng([19, N])
+    lengths = np.array([5000, 4200, 130, 1, 70], np.int64)
+    w = workloads.random_lengths_workload(rng, K=2, N=N, M=11, lengths=lengths, all_pairs=False, conc=0.5)
+    ll, (npi, nA, nB), _ = hmm.forward_backward_grad(problem(w))
+    rll, rpi, rA, rB = O.counts(w.pi, w.A, w.B, w.symbols, w.offsets, w.lengths, w.owner)
+    assert rel_err(ll.cpu().numpy(), rll) <= LL_TOL
+    assert _counts_err(npi.cpu().numpy(), rpi) <= GRAD_TOL
+    assert _counts_err(nA.cpu().numpy(), rA) <= GRAD_TOL
+    assert _counts_err(nB.cpu().numpy(), rB) <= GRAD_TOL
+
+
 @pytest.mark.parametrize("N,M", [(49, 17), (64, 17), (80, 17), (96, 17), (128, 17), (128, 700), (129, 17),
                                  (160, 17), (200, 40), (255, 300), (256, 17), (256, 1024)])
 def test_counts_cooperative_state_counts(N, M):
