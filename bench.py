@@ -119,8 +119,9 @@ def time_steps(fn, steps, warmup, torch):
     return (time.perf_counter() - t0) / max(steps, 1)
 
 
-def graph_ms(fn, reps, torch):
-    """Mean milliseconds of `reps` replays of fn captured as one HIP graph (after 3 warm-up replays)."""
+def graph_stats(fn, reps, torch):
+    """fn captured once as a HIP graph and replayed: 3 warm-up replays, then `reps` replays
+    each bracketed by its own events on the stream; milliseconds per replay (median, min, mean)."""
     fn()
     torch.cuda.synchronize()
     side = torch.cuda.Stream()
@@ -135,14 +136,53 @@ def graph_ms(fn, reps, torch):
     for _ in range(3):
         g.replay()
     torch.cuda.synchronize()
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
-    t0.record()
-    for _ in range(reps):
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b in ev:
+        a.record()
         g.replay()
-    t1.record()
+        b.record()
     torch.cuda.synchronize()
-    return t0.elapsed_time(t1) / reps
+    t = np.array([a.elapsed_time(b) for a, b in ev])
+    return {"median_ms": float(np.median(t)), "min_ms": float(np.min(t)), "mean_ms": float(np.mean(t)),
+            "replays": reps}
+
+
+def eager_stats(fn, reps, torch):
+    """Milliseconds per eager call on the stream (median, min, mean of `reps` calls, each
+    bracketed by its own events, after 3 warm-up calls)."""
+    for _ in range(3):
+        fn()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b in ev:
+        a.record()
+        fn()
+        b.record()
+    torch.cuda.synchronize()
+    t = np.array([a.elapsed_time(b) for a, b in ev])
+    return {"median_ms": float(np.median(t)), "min_ms": float(np.min(t)), "mean_ms": float(np.mean(t)),
+            "calls": reps}
+
+
+def h2d_copy(w, torch):
+    """The host-to-device term of a call (the CPU-GPU transfer of the paper's cost model,
+    Eq. 1): the bank and the batch copied from pinned host memory to HBM, timed with
+    events on the stream (median of 5 copies)."""
+    host = [torch.from_numpy(np.ascontiguousarray(a)).pin_memory()
+            for a in (w.pi, w.A, w.B, w.symbols, w.offsets, w.lengths)]
+    devs = [torch.empty_like(h, device="cuda") for h in host]
+    nbytes = sum(h.numel() * h.element_size() for h in host)
+    times = []
+    for _ in range(6):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for h, d in zip(host, devs):
+            d.copy_(h, non_blocking=True)
+        b.record()
+        torch.cuda.synchronize()
+        times.append(a.elapsed_time(b))
+    ms = float(np.median(times[1:]))
+    return {"bytes": int(nbytes), "ms": ms, "GB_per_s": nbytes / (ms / 1e3) / 1e9}
 
 
 def cpu_oracle_counts(w, target_s: float = 5.0):
@@ -379,11 +419,14 @@ def main():
         ll1 = torch.empty(w1.S, dtype=torch.float32, device="cuda")
         f1 = lambda: hmm.forward_loglik(p1, out=ll1, ws=ws1)
         e1 = time_steps(f1, 50, 5, torch)
+        es1, gs1 = eager_stats(f1, 50, torch), graph_stats(f1, 50, torch)
         lat["c1"] = {"workload": "c1: 1 HMM N=8 M=16, one sequence T=64, forward (tuned choice: "
                                  f"{tune.KERNEL_NAMES[hmm.call_kernel(p1.bank, p1.batch, hmm.OP_FORWARD)]})",
-                     "us_per_call": e1 * 1e6, "us_per_call_graph": graph_ms(f1, 50, torch) * 1e3,
-                     "ns_per_step_graph": None}
-        lat["c1"]["ns_per_step_graph"] = lat["c1"]["us_per_call_graph"] * 1e3 / int(w1.lengths.max())
+                     "us_per_call": e1 * 1e6,
+                     "us_per_call_stream_median": es1["median_ms"] * 1e3, "us_per_call_stream_min": es1["min_ms"] * 1e3,
+                     "us_per_call_graph": gs1["median_ms"] * 1e3, "us_per_call_graph_min": gs1["min_ms"] * 1e3,
+                     "graph_replays": gs1["replays"],
+                     "ns_per_step_graph": gs1["median_ms"] * 1e6 / int(w1.lengths.max())}
         hmm.select_kernel(hmm.KERNEL_TILE16)
         lat["c1"]["us_per_call_tiles"] = time_steps(f1, 50, 5, torch) * 1e6
         hmm.select_kernel(hmm.KERNEL_AUTO)
@@ -409,9 +452,13 @@ def main():
         ll2 = torch.empty((w2.S, w2.K), dtype=torch.float32, device="cuda")
         f2 = lambda: hmm.classify(p2, labels=lab2, loglik=ll2, ws=ws2)
         e2 = time_steps(f2, 20, 3, torch)
-        g2 = graph_ms(f2, 20, torch)
+        es2, gs2 = eager_stats(f2, 20, torch), graph_stats(f2, 20, torch)
+        g2 = gs2["median_ms"]
         lat["c2"] = {"workload": "c2: 12 HMMs N=16 M=64, 4096 sequences, T in [50,400], all pairs + labels",
-                     "us_per_call": e2 * 1e6, "us_per_call_graph": g2 * 1e3,
+                     "us_per_call": e2 * 1e6,
+                     "us_per_call_stream_median": es2["median_ms"] * 1e3, "us_per_call_stream_min": es2["min_ms"] * 1e3,
+                     "us_per_call_graph": g2 * 1e3, "us_per_call_graph_min": gs2["min_ms"] * 1e3,
+                     "graph_replays": gs2["replays"],
                      "ns_per_step_graph": g2 * 1e6 / int(w2.lengths.max()),
                      "state_steps_per_s_graph": w2.units() / (g2 / 1e3)}
         result["latency"] = lat
@@ -450,8 +497,16 @@ def main():
         del p4e
 
     if not args.no_extra:
-        result["graph"] = {"ms_per_step": graph_ms(step, 10, torch),
-                           "note": "the same recognition step captured once as a HIP graph, mean of 10 replays"}
+        gs = graph_stats(step, 20, torch)
+        result["graph"] = {"ms_per_step": gs["median_ms"], "min_ms": gs["min_ms"], "mean_ms": gs["mean_ms"],
+                           "replays": gs["replays"],
+                           "note": "the same recognition step captured once as a HIP graph: median, min and mean "
+                                   "of 20 replays, each timed with its own events"}
+        h2d = h2d_copy(w, torch)
+        h2d["note"] = ("bank + symbols + offsets + lengths of the recognition workload, pinned host memory to HBM "
+                       "(not part of `value`, whose inputs are resident in HBM)")
+        h2d["state_steps_per_s_including_h2d"] = units / (sec + h2d["ms"] / 1e3)
+        result["h2d"] = h2d
 
     if args.copy_calibration:
         log("copy calibration: 4 x 512 MiB device-to-device")
@@ -462,6 +517,12 @@ def main():
         torch.cuda.synchronize()
         result["copy_calibration_bytes"] = src.numel() * 4
 
+    result["provenance"] = {
+        "inputs": "numpy default_rng(SeedSequence([1310, 3322, tag, 0])) per workload, regenerated each run; "
+                  "tag = index in (brute, c1, paper, c2, c3, c4, c5)",
+        "numpy": np.__version__, "torch": torch.__version__, "hip": getattr(torch.version, "hip", None),
+        "device": torch.cuda.get_device_name(0), "host_cores": len(os.sched_getaffinity(0)),
+        "library": os.path.relpath(hmm.LIB_PATH, ROOT)}
     if not args.no_tune:
         result["tuning"] = tuning
         if args.tune_cache and tuned_now:

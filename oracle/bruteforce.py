@@ -87,3 +87,32 @@ def best_paths(pi, A, B, o):
         elif p == best:
             arg.append(q)
     return best, arg
+
+
+def path_margin(pi, A, B, o, q):
+    """ln P(Q = q, O) minus the largest ln P(Q, O) over every other state path Q != q
+    (+inf when q is the only path, -inf .. 0 when another path is at least as likely).
+
+    For q the decoded most likely path this is the decoding margin: how much the
+    log-probability would have to move before another path wins.  It is zero when the
+    most likely path is not unique.  Floats only (logarithms)."""
+    import math
+
+    N = len(pi)
+    T = len(o)
+    q = tuple(q)
+    own = joint(pi, A, B, q, o)
+    other = None
+    for p in itertools.product(range(N), repeat=T):
+        if p == q:
+            continue
+        v = joint(pi, A, B, p, o)
+        if other is None or v > other:
+            other = v
+    if other is None:
+        return math.inf
+    lo = math.log(own) if own > 0 else -math.inf
+    lx = math.log(other) if other > 0 else -math.inf
+    if lo == -math.inf and lx == -math.inf:
+        return 0.0
+    return lo - lx

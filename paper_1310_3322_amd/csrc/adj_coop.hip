@@ -162,7 +162,7 @@ __global__ void __launch_bounds__(R / BO * WAVE) k_adj_coop(DevPtrs d, AdjLaunch
             for (;;) {
                 if (threadIdx.x == 0) tile_sh = atomicAdd(&a.queue[k], 1);
                 __syncthreads();
-                const int tile = tile_sh;
+                const int tile = __builtin_amdgcn_readfirstlane(tile_sh);  // scalar exit: the loop holds barriers
                 __syncthreads();
                 if (tile >= ntiles) break;
 
@@ -624,7 +624,7 @@ __global__ void __launch_bounds__(2 * R * WAVE) k_adj_pipe(DevPtrs d, AdjLaunch 
             for (;;) {
                 if (threadIdx.x == 0) tile_sh = atomicAdd(&a.queue[k], 1);
                 __syncthreads();
-                const int tile = tile_sh;
+                const int tile = __builtin_amdgcn_readfirstlane(tile_sh);  // scalar exit: the loop holds barriers
                 __syncthreads();
                 if (tile >= ntiles) break;
 

@@ -52,7 +52,7 @@ __global__ void __launch_bounds__(R / BO * WAVE) k_fwd_coop(DevPtrs d, FwdLaunch
         for (;;) {
             if (threadIdx.x == 0) tile_sh = atomicAdd(&f.queue[k], 1);
             __syncthreads();
-            const int tile = tile_sh;
+            const int tile = __builtin_amdgcn_readfirstlane(tile_sh);  // scalar exit: the loop holds barriers
             __syncthreads();
             if (tile >= ntiles) break;
 

@@ -1,11 +1,20 @@
 """Viterbi decoding on the GPU vs the FP64 oracle, through the C ABI (MI355X only).
 
-score  |s_gpu - s_oracle| / max(|s_oracle|, 1) <= 1e-5, infinities and NaNs equal
-path   equal to the oracle's wherever the oracle's smallest decision margin on its
-       path exceeds the FP32 rounding of the decoder (1e-5 |score| + 1e-4); elsewhere
-       (near-ties, where several paths are optimal to rounding) the GPU path must be a
-       valid state path whose FP64 log-probability is within the score tolerance of the
-       oracle's optimum.
+score  |s_gpu - s_oracle| / max(|s_oracle|, 1) <= 1e-5, infinities and NaNs equal.
+path   The decoder takes its arg-max decisions on FP32 values, so the path is unique
+       only up to that rounding.  rounding_bound() below bounds, per sequence, the
+       error E of every FP32 delta value near the row maximum (ln A, ln B and ln pi
+       from logf, one rounding per addition, a shift by the row maximum every 16
+       steps).  Then:
+         - where the oracle's margin (log-probability of its path minus that of the
+           best other path) exceeds 2E, the GPU path must be the oracle's, index
+           for index;
+         - every other GPU path must be a valid state path whose FP64 log-probability
+           is within 2E of the oracle's optimum (the decoder maximised an FP32
+           evaluation of it that is within E of the exact value, and the optimum's
+           FP32 evaluation is within E of the optimum);
+         - each workload must have at least a stated share of index-exact paths, and
+           the test prints how many paths were gated, exact, and near-ties.
 """
 import math
 
@@ -19,6 +28,8 @@ from paper_1310_3322_amd import hmm, workloads
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-5
+U32 = 2.0 ** -24          # unit roundoff of FP32
+SHIFT_PERIOD = 16         # steps between the decoder's shifts by the row maximum
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -47,33 +58,98 @@ def path_logprob(w, s, q, sym):
     return lp
 
 
-def check(w, symbols=None):
+def rounding_bound(w, s, sym):
+    """Bound E on the error of the decoder's FP32 delta values near the row maximum for
+    sequence s (derivation: the Viterbi readings of the design notes).
+
+    With M_t = max_j delta_t(j) (exact, FP64 max-plus here) and S_t the decoder's
+    accumulated shift (M at the last shift step), a value within 1 of the row maximum
+    has magnitude at most D_t = |M_t - S_{t-1}| + 1 in the frame it is computed in, and
+    the logarithms on its best incoming edge satisfy |ln a| + |ln b| <= L_t =
+    M_{t-1} - M_t + 1 (both are <= 0 and they bridge the two maxima).  Step t then adds
+    at most u (D_{t-1} + L_t) for the candidate sum, u D_t for the emission sum, u D_t
+    for a shift, and 2 ulp = 4 u L_t for the two FP32 logarithms; E is the sum over
+    the steps.  A maximum of perturbed values moves by at most the largest perturbation,
+    so the bound carries over from step to step."""
+    k, T, off = int(w.owner[s]), int(w.lengths[s]), int(w.offsets[s])
+    if T == 0:
+        return 0.0
+    o = sym[off:off + T]
+    with np.errstate(divide="ignore"):
+        la = np.log(w.A[k].astype(np.float64))
+        lb = np.log(w.B[k].astype(np.float64))
+        d = np.log(w.pi[k].astype(np.float64)) + lb[:, o[0]]
+    Mprev = float(np.max(d))
+    shift = 0.0
+    E = U32 * (abs(Mprev) + 1.0) + 4 * U32 * (abs(Mprev) + 1.0)
+    Dprev = abs(Mprev) + 1.0
+    if SHIFT_PERIOD == 1:
+        shift = Mprev
+    for t in range(1, T):
+        d = np.max(d[:, None] + la, axis=0) + lb[:, o[t]]
+        Mt = float(np.max(d))
+        if not math.isfinite(Mt):
+            return math.inf
+        Dt = abs(Mt - shift) + 1.0
+        Lt = (Mprev - Mt) + 1.0
+        E += U32 * (Dprev + Lt) + U32 * Dt + 4 * U32 * Lt
+        if (t + 1) % SHIFT_PERIOD == 0:
+            E += U32 * Dt
+            shift = Mt
+        Dprev = abs(Mt - shift) + 1.0
+        Mprev = Mt
+    return E
+
+
+def check(w, symbols=None, min_exact_share=None, label=""):
     sym = w.symbols if symbols is None else symbols
     sc, path = hmm.viterbi(problem(w, sym))
     sc, path = sc.cpu().numpy().astype(np.float64), path.cpu().numpy()
     rs, rp, rm = O.viterbi(w.pi, w.A, w.B, sym, w.offsets, w.lengths, w.owner)
-    assert np.array_equal(np.isnan(sc), np.isnan(rs))
-    assert np.array_equal(sc[np.isinf(rs)], rs[np.isinf(rs)])
+    return compare(w, np.arange(w.S), sc, path, w, sym, rs, rp, rm, min_exact_share, label)
+
+
+def compare(w, seqs, sc, path, ref_w, ref_sym, rs, rp, rm, min_exact_share, label):
+    """GPU scores and paths (sc, path, laid out as w) of the sequences `seqs` of w against
+    the oracle's results rs / rp / rm for the same sequences laid out as ref_w with
+    symbols ref_sym (w itself, or a subset of it)."""
+    assert np.array_equal(np.isnan(sc[seqs]), np.isnan(rs))
+    assert np.array_equal(sc[seqs][np.isinf(rs)], rs[np.isinf(rs)])
     fin = np.isfinite(rs)
     if fin.any():
-        err = np.max(np.abs(sc[fin] - rs[fin]) / np.maximum(np.abs(rs[fin]), 1.0))
+        err = np.max(np.abs(sc[seqs][fin] - rs[fin]) / np.maximum(np.abs(rs[fin]), 1.0))
         assert err <= TOL, err
-    exact = 0
-    for s in range(w.S):
-        T, off = int(w.lengths[s]), int(w.offsets[s])
-        g, r = path[off:off + T], rp[off:off + T]
-        if not np.isfinite(rs[s]):
-            if np.isnan(rs[s]):
+    gated = exact = ties = 0
+    for i, s in enumerate(seqs):
+        T, off, ro = int(w.lengths[s]), int(w.offsets[s]), int(ref_w.offsets[i])
+        g, r = path[off:off + T], rp[ro:ro + T]
+        if not np.isfinite(rs[i]):
+            if np.isnan(rs[i]):
                 assert np.all(g == -1), s
             continue
-        if rm[s] > 1e-5 * max(1.0, abs(rs[s])) + 1e-4:
-            assert np.array_equal(g, r), (s, T)
+        if np.array_equal(g, r):
             exact += 1
+        E = rounding_bound(ref_w, i, ref_sym)
+        if rm[i] > 2 * E:
+            gated += 1
+            assert np.array_equal(g, r), (label, int(s), T, rm[i], E)
         else:
+            ties += 1
             assert np.all((g >= 0) & (g < w.N)), s
-            lp = path_logprob(w, s, g, sym)
-            assert abs(lp - rs[s]) <= TOL * max(1.0, abs(rs[s])), (s, lp, rs[s])
+            lp = path_logprob(ref_w, i, g, ref_sym)
+            assert rs[i] - lp <= 2 * E + 1e-12 * max(1.0, abs(rs[i])), (label, int(s), lp, rs[i], E)
+    n = int(np.sum(fin))
+    print(f"  {label}: {n} finite paths, {gated} with margin > 2E (all index-exact), {ties} within 2E of a tie, "
+          f"{exact} index-exact overall", flush=True)
+    if min_exact_share is not None and n > 0:
+        assert exact >= min_exact_share * n, (label, exact, n)
     return exact
+
+
+# Smallest share of index-exact paths per workload (of the paths with a finite score).
+# The decoder's FP32 rounding is about sqrt(T) u |delta| in practice, far below the
+# worst-case bound 2E, so the paths differ from the oracle's only at near-ties.
+EXACT_SHARE = 0.9
 
 
 @pytest.mark.parametrize("cfg,scale", [("brute", 1.0), ("c1", 1.0), ("paper", 1.0), ("c2", 0.1), ("c3", 0.004)])
@@ -82,10 +158,7 @@ def test_viterbi_parity_workloads(cfg, scale):
     w = workloads.make_workload(cfg, scale=scale)
     if w.all_pairs:
         w.all_pairs = False
-    n = check(w)
-    print(f"  {n} of {w.S} paths compared exactly", flush=True)
-    if w.S >= 10:
-        assert n > 0  # the exact comparison is exercised
+    check(w, min_exact_share=EXACT_SHARE, label=f"{cfg}x{scale}")
 
 
 @pytest.mark.parametrize("N", [1, 2, 5, 16, 17, 31, 32, 33, 48, 64, 65, 100, 128, 129, 200, 256])
@@ -97,7 +170,7 @@ def test_viterbi_state_counts_and_ragged_lengths(N):
     rng = np.random.default_rng([31, N])
     lengths = np.concatenate([[0, 1, 2, 15, 16, 17, 31, 32, 33, 63, 64, 65, 129, 300], rng.integers(1, 120, size=26)])
     w = workloads.random_lengths_workload(rng, K=3, N=N, M=11, lengths=lengths, all_pairs=False, conc=0.4)
-    check(w)
+    check(w, min_exact_share=EXACT_SHARE, label=f"N={N}")
 
 
 @pytest.mark.parametrize("N", [6, 150])
@@ -122,7 +195,16 @@ def test_viterbi_special_inputs(N):
     assert hmm.workspace_error(ws) == 3
     sc = sc.cpu().numpy()
     assert np.isneginf(sc[s_imp]) and np.isnan(sc[3]) and sc[0] == 0.0
-    check(w, sym)
+    check(w, sym, label=f"special N={N}")
+
+
+def _sampled(w, pick, label, min_exact_share):
+    sc, path = hmm.viterbi(problem(w))
+    sc, path = sc.cpu().numpy().astype(np.float64), path.cpu().numpy()
+    assert np.all(np.isfinite(sc))
+    sub = w.subset(pick)
+    rs, rp, rm = O.viterbi(sub.pi, sub.A, sub.B, sub.symbols, sub.offsets, sub.lengths, sub.owner)
+    compare(w, pick, sc, path, sub, sub.symbols, rs, rp, rm, min_exact_share, label)
 
 
 def test_viterbi_full_c3_sampled():
@@ -130,20 +212,10 @@ def test_viterbi_full_c3_sampled():
     print("[case] viterbi c3 full", flush=True)
     w = workloads.make_workload("c3")
     w.all_pairs = False
-    sc, path = hmm.viterbi(problem(w))
-    sc, path = sc.cpu().numpy(), path.cpu().numpy()
-    assert np.all(np.isfinite(sc))
     order = np.argsort(-w.lengths, kind="stable")
     rng = np.random.default_rng(9)
     pick = np.unique(np.concatenate([order[:8], order[-8:], rng.choice(w.S, 40, replace=False)]))
-    sub = w.subset(pick)
-    rs, rp, rm = O.viterbi(sub.pi, sub.A, sub.B, sub.symbols, sub.offsets, sub.lengths, sub.owner)
-    err = np.max(np.abs(sc[pick] - rs) / np.maximum(np.abs(rs), 1.0))
-    assert err <= TOL, err
-    for i, s in enumerate(pick):
-        T, off, so = int(w.lengths[s]), int(w.offsets[s]), int(sub.offsets[i])
-        if rm[i] > 1e-5 * max(1.0, abs(rs[i])) + 1e-4:
-            assert np.array_equal(path[off:off + T], rp[so:so + T]), s
+    _sampled(w, pick, "c3 full, sampled", EXACT_SHARE)
 
 
 def test_viterbi_determinism():
@@ -151,7 +223,7 @@ def test_viterbi_determinism():
     the workgroup decoder (65 states)."""
     rng = np.random.default_rng(3)
     big = workloads.random_lengths_workload(rng, K=2, N=65, M=4, lengths=np.array([5, 6, 70, 0, 1]), all_pairs=False)
-    check(big)
+    check(big, label="N=65 small")
     w = workloads.make_workload("c2", scale=0.05)
     w.all_pairs = False
     for x in (w, big):
@@ -167,25 +239,7 @@ def test_viterbi_c5_bank_sampled():
     print("[case] viterbi c5 sample", flush=True)
     w = workloads.make_workload("c5", scale=0.05)
     w.all_pairs = False
-    sc, path = hmm.viterbi(problem(w))
-    sc, path = sc.cpu().numpy(), path.cpu().numpy()
-    assert np.all(np.isfinite(sc))
     order = np.argsort(-w.lengths, kind="stable")
     rng = np.random.default_rng(5)
     pick = np.unique(np.concatenate([order[:2], order[-2:], rng.choice(w.S, 6, replace=False)]))
-    sub = w.subset(pick)
-    rs, rp, rm = O.viterbi(sub.pi, sub.A, sub.B, sub.symbols, sub.offsets, sub.lengths, sub.owner)
-    err = np.max(np.abs(sc[pick] - rs) / np.maximum(np.abs(rs), 1.0))
-    assert err <= TOL, err
-    exact = 0
-    for i, s in enumerate(pick):
-        T, off, so = int(w.lengths[s]), int(w.offsets[s]), int(sub.offsets[i])
-        g = path[off:off + T]
-        if rm[i] > 1e-5 * max(1.0, abs(rs[i])) + 1e-4:
-            assert np.array_equal(g, rp[so:so + T]), s
-            exact += 1
-        else:
-            assert np.all((g >= 0) & (g < w.N)), s
-            lp = path_logprob(sub, i, g, sub.symbols)
-            assert abs(lp - rs[i]) <= TOL * max(1.0, abs(rs[i])), (s, lp, rs[i])
-    print(f"  {exact} of {len(pick)} paths compared exactly", flush=True)
+    _sampled(w, pick, "c5 5% batch, sampled", None)

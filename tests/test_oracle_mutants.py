@@ -47,6 +47,12 @@ MUTANTS = {
                                     "dt[j] = best + log(Bk[(size_t)j * M + o[t - 1]]);"),
     "viterbi_step_tie_last": ("if (cand > best) {", "if (cand >= best) {"),
     "viterbi_final_tie_last": ("if (dl[j] > best) {", "if (dl[j] >= best) {"),
+    "viterbi_margin_drop_A": ("const double chosen = dp[c] + log(Ak[(size_t)c * N + j]);",
+                              "const double chosen = dp[c];"),
+    "viterbi_margin_final_only": ("for (int32_t t = T - 1; t > 0; --t) {\n                    const double *dp",
+                                  "for (int32_t t = 0; t > 0; --t) {\n                    const double *dp"),
+    "viterbi_margin_row_index": ("const double *dp = delta + (size_t)(t - 1) * N;\n                    const int j = q[t]",
+                                 "const double *dp = delta + (size_t)t * N;\n                    const int j = q[t]"),
 }
 
 
@@ -149,7 +155,24 @@ def pin_viterbi(lib):
     return path.tolist() == [0] * T
 
 
-PINS = [pin_bruteforce, pin_trace_invariant, pin_axiom, pin_impossible, pin_classify, pin_viterbi]
+def pin_viterbi_margin(lib):
+    rng = _rng(5)
+    for N, M, T in [(3, 4, 6), (2, 3, 5), (3, 3, 4)]:
+        for _ in range(3):
+            pi = workloads.dirichlet_rows(rng, (1,), N, 0.5)
+            A = workloads.dirichlet_rows(rng, (1, N), N, 0.5)
+            B = workloads.dirichlet_rows(rng, (1, N), M, 0.5)
+            o = rng.integers(0, M, size=T).astype(np.int32)
+            sc, path, mg = O.viterbi(pi, A, B, o, np.zeros(1, np.int64), np.array([T], np.int32),
+                                     np.zeros(1, np.int32), lib=lib)
+            ref = bruteforce.path_margin(pi[0].tolist(), A[0].tolist(), B[0].tolist(), o.tolist(), path.tolist())
+            if not abs(mg[0] - ref) <= 1e-10 * max(1.0, abs(sc[0])):
+                return False
+    return True
+
+
+PINS = [pin_bruteforce, pin_trace_invariant, pin_axiom, pin_impossible, pin_classify, pin_viterbi,
+        pin_viterbi_margin]
 
 
 def test_real_oracle_passes_every_predicate():

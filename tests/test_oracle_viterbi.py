@@ -45,6 +45,53 @@ def test_viterbi_matches_path_enumeration(oracle_mod, N, M, T):
             assert tuple(path.tolist()) == args[0]
 
 
+@pytest.mark.parametrize("N,M,T", [(3, 4, 6), (2, 3, 7), (3, 2, 1), (3, 3, 2), (2, 2, 5)])
+def test_viterbi_margin_matches_second_best_path(oracle_mod, N, M, T):
+    """The margin the oracle reports (smallest gap over the final choice and every
+    backtracking choice on its path) equals, by enumeration of all N^T paths, the
+    log-probability of the decoded path minus that of the best other path."""
+    rng = np.random.default_rng([29, N, M, T])
+    for rep in range(6):
+        conc = 0.3 if rep % 2 else 1.0
+        pi = workloads.dirichlet_rows(rng, (1,), N, conc)[0]
+        A = workloads.dirichlet_rows(rng, (N,), N, conc)
+        B = workloads.dirichlet_rows(rng, (N,), M, conc)
+        o = rng.integers(0, M, size=T).astype(np.int32)
+        sc, path, mg = one(oracle_mod, pi, A, B, o)
+        ref = bruteforce.path_margin(pi.tolist(), A.tolist(), B.tolist(), o.tolist(), path.tolist())
+        assert ref >= 0.0
+        assert abs(mg - ref) <= 1e-10 * max(1.0, abs(sc)), (rep, mg, ref)
+
+
+def test_viterbi_margin_special_cases(oracle_mod):
+    """Zero where the best path is not unique (a tie at the final state or at one
+    backtracking step), +inf for one state, and the exact gap of a model whose two
+    best paths differ by a known factor."""
+    # tie at the final choice only: two end states equally likely, predecessors unique
+    pi = np.array([0.6, 0.4])
+    A = np.array([[0.5, 0.5], [0.5, 0.5]])
+    B = np.array([[0.5, 0.5], [0.5, 0.5]])
+    _, path, mg = one(oracle_mod, pi, A, B, [0, 1])
+    assert mg == 0.0 and path.tolist() == [0, 0]
+    # tie at a backtracking choice only: both predecessors of state 1 give the same value
+    pi = np.array([0.5, 0.5])
+    A = np.array([[0.2, 0.8], [0.2, 0.8]])
+    B = np.array([[0.5, 0.5], [0.5, 0.5]])
+    _, path, mg = one(oracle_mod, pi, A, B, [0, 0])
+    assert mg == 0.0 and path.tolist() == [0, 1]
+    # one state: the only path, infinite margin
+    _, _, mg = one(oracle_mod, np.array([1.0]), np.array([[1.0]]), np.array([[0.25, 0.75]]), [1, 0, 1])
+    assert mg == math.inf
+    # dyadic bank: best path 0,0 has P = 1/2 * 3/4 * 1/2 * 1/2, second best differs by ln 3 exactly
+    pi = np.array([0.5, 0.5])
+    A = np.array([[0.75, 0.25], [0.5, 0.5]])
+    B = np.array([[0.5, 0.5], [0.25, 0.75]])
+    sc, path, mg = one(oracle_mod, pi, A, B, [0, 0])
+    ref = bruteforce.path_margin(pi.tolist(), A.tolist(), B.tolist(), [0, 0], path.tolist())
+    assert path.tolist() == [0, 0]
+    assert abs(mg - math.log(3.0)) <= 1e-14 and abs(ref - math.log(3.0)) <= 1e-14
+
+
 def test_viterbi_exact_rational_enumeration(oracle_mod):
     """A bank of small dyadic rationals (exact in FP64): the max over paths is exact."""
     pi = [Fraction(1, 4), Fraction(1, 2), Fraction(1, 4)]
