@@ -133,6 +133,23 @@ hmm_status hmm_forward_loglik(const hmm_bank *bank, const hmm_batch *batch, floa
 hmm_status hmm_classify(const hmm_bank *bank, const hmm_batch *batch, int32_t *labels,
                         float *loglik_opt, void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* hmm_classify without a caller workspace, for callers that cannot allocate
+ * device memory (code under HIP graph capture with no workspace prepared,
+ * serving loops that must not call the allocator, harnesses that forbid it).
+ * The scratch memory is a static device array of HMM_STATIC_SCRATCH_BYTES
+ * inside the library: one per GPU, reserved when the library's code is loaded
+ * on that GPU and held until the process ends; this call allocates nothing.
+ * Arguments, results and errors are those of hmm_classify, plus
+ * HMM_ERR_WORKSPACE (nothing enqueued) when hmm_workspace_size(bank, batch,
+ * HMM_OP_CLASSIFY) exceeds HMM_STATIC_SCRATCH_BYTES (32 MiB: the 64-model,
+ * 65,536-sequence recognition batch with lengths up to 2048 needs 19 MB).
+ * Every call on one GPU uses that GPU's one array, which keeps the contents of
+ * the last call (each call initialises what it reads): two calls that overlap
+ * on one GPU (two streams, two host threads) race and give undefined results. */
+#define HMM_STATIC_SCRATCH_BYTES ((size_t)32 << 20)
+hmm_status hmm_classify_noalloc(const hmm_bank *bank, const hmm_batch *batch, int32_t *labels,
+                                float *loglik_opt, hipStream_t stream);
+
 /* Gradient / Baum-Welch E-step (Sec. 2.7 "BalmWelch") for each sequence with
  * its own model (batch->model_of_seq is required).
  * seq_weight: [S] weight w_s of sequence s (dL/dloglik_s), or NULL = all ones.

@@ -33,6 +33,29 @@ int device_cu_count() {
     return n;
 }
 
+// ---- static scratch area of hmm_classify_noalloc: one array per GPU, in the
+// library's code object (reserved by the loader, never by a call).  In host
+// code `scratch` only names the array; its device address on the current GPU
+// comes from hipGetSymbolAddress, taken once per device on the first call there
+// and kept in g_scratch_ptr.  Kernels and fill launches receive that address.
+static __device__ __align__(256) unsigned char scratch[HMM_STATIC_SCRATCH_BYTES];
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[MAX_DEVICES];
+
+hmm_status static_scratch(void **out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return HMM_ERR_HIP;
+    if (dev < 0 || dev >= MAX_DEVICES) return HMM_ERR_UNSUPPORTED;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return HMM_ERR_HIP;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return HMM_OK;
+}
+
 // ---- tuning table (hmm_tune_*): call shape -> kernel family and grid cap
 struct TuneEntry {
     hmm_tune_key key;
@@ -437,6 +460,16 @@ hmm_status hmm_forward_loglik(const hmm_bank *bank, const hmm_batch *batch, floa
     const Layout L = make_layout(bank, batch, HMM_OP_FORWARD);
     if ((rc = check_ws(ws, ws_bytes, L)) != HMM_OK) return rc;
     return run_forward(bank, batch, HMM_OP_FORWARD, loglik, (unsigned char *)ws, L, stream);
+}
+
+hmm_status hmm_classify_noalloc(const hmm_bank *bank, const hmm_batch *batch, int32_t *labels,
+                                float *loglik_opt, hipStream_t stream) {
+    hmm_status rc = check_shapes(bank, batch);
+    if (rc != HMM_OK) return rc;
+    if (make_layout(bank, batch, HMM_OP_CLASSIFY).total > HMM_STATIC_SCRATCH_BYTES) return HMM_ERR_WORKSPACE;
+    void *ws = nullptr;
+    if ((rc = static_scratch(&ws)) != HMM_OK) return rc;
+    return hmm_classify(bank, batch, labels, loglik_opt, ws, HMM_STATIC_SCRATCH_BYTES, stream);
 }
 
 hmm_status hmm_classify(const hmm_bank *bank, const hmm_batch *batch, int32_t *labels, float *loglik_opt,

@@ -22,11 +22,12 @@ STATUS = {0: "HMM_OK", -1: "HMM_ERR_NULL", -2: "HMM_ERR_SHAPE", -3: "HMM_ERR_WOR
           -4: "HMM_ERR_UNSUPPORTED", -5: "HMM_ERR_HIP", -6: "HMM_ERR_ARG"}
 OP_FORWARD, OP_CLASSIFY, OP_GRAD, OP_VITERBI = 0, 1, 2, 3
 KERNEL_AUTO, KERNEL_PLAIN, KERNEL_BATCHED, KERNEL_TILE16, KERNEL_TILE32, KERNEL_COOP, KERNEL_SCAN = 0, 1, 2, 3, 4, 5, 6
-EXPORTS = ("hmm_workspace_size", "hmm_forward_loglik", "hmm_classify", "hmm_forward_backward_grad",
+EXPORTS = ("hmm_workspace_size", "hmm_forward_loglik", "hmm_classify", "hmm_classify_noalloc", "hmm_forward_backward_grad",
            "hmm_viterbi", "hmm_reestimate_rows", "hmm_softmax_rows", "hmm_logit_grad", "hmm_workspace_error", "hmm_select_kernel",
            "hmm_tune_key_of", "hmm_tune_set", "hmm_tune_get", "hmm_tune_clear", "hmm_call_kernel",
            "hmm_profile_enable", "hmm_profile_read", "hmm_status_string")
 TUNE_MAX, TUNE_MAX_WG = 256, 64
+STATIC_SCRATCH_BYTES = 32 << 20  # HMM_STATIC_SCRATCH_BYTES
 PROF_FWD_BATCHED, PROF_ADJ_BATCHED, PROF_FWD_PLAIN, PROF_VITERBI = 0, 1, 2, 3
 
 
@@ -80,6 +81,8 @@ def load_library(path: str = LIB_PATH):
     lib.hmm_forward_loglik.argtypes = [BP, QP, P, P, ctypes.c_size_t, P]
     lib.hmm_classify.restype = st
     lib.hmm_classify.argtypes = [BP, QP, P, P, P, ctypes.c_size_t, P]
+    lib.hmm_classify_noalloc.restype = st
+    lib.hmm_classify_noalloc.argtypes = [BP, QP, P, P, P]
     lib.hmm_forward_backward_grad.restype = st
     lib.hmm_forward_backward_grad.argtypes = [BP, QP, P, P, P, P, P, ctypes.c_int32, P, ctypes.c_size_t, P]
     lib.hmm_viterbi.restype = st
@@ -267,6 +270,25 @@ def classify(p: Problem, labels: Optional[torch.Tensor] = None, loglik: Optional
     rc = load_library().hmm_classify(ctypes.byref(p.bank), ctypes.byref(b), _ptr(labels), _ptr(loglik),
                                      _ptr(ws), ws.numel(), _stream(stream))
     _check("hmm_classify", rc)
+    return labels
+
+
+def classify_noalloc(p: Problem, labels: torch.Tensor, loglik: Optional[torch.Tensor] = None,
+                     stream=None) -> torch.Tensor:
+    """classify() on the library's static scratch array instead of a workspace; the caller
+    passes the outputs, so nothing is allocated (the array is shared by every call on one
+    GPU: calls must not overlap there)."""
+    _dev(labels, torch.int32, "labels")
+    if labels.shape[0] != p.S:
+        raise ValueError("labels must be [S]")
+    if loglik is not None:
+        _dev(loglik, torch.float32, "loglik")
+        if tuple(loglik.shape) != (p.S, p.K):
+            raise ValueError("loglik must be [S][K]")
+    b = p.batch_without_models()
+    rc = load_library().hmm_classify_noalloc(ctypes.byref(p.bank), ctypes.byref(b), _ptr(labels), _ptr(loglik),
+                                             _stream(stream))
+    _check("hmm_classify_noalloc", rc)
     return labels
 
 
