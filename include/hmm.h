@@ -281,8 +281,8 @@ hmm_status hmm_call_kernel(const hmm_bank *bank, const hmm_batch *batch, int32_t
 hmm_status hmm_profile_enable(int32_t on);
 hmm_status hmm_profile_read(int32_t kernel, double *total_ms, int32_t *launches);
 
-/* Human-readable status name. */
-const char *hmm_status_string(hmm_status status);
+/* Human-readable name of a status code; "HMM_ERR_UNKNOWN" for any other value. */
+const char *hmm_status_string(int32_t status);
 
 #ifdef __cplusplus
 }

@@ -788,7 +788,8 @@ hmm_status hmm_profile_read(int32_t kernel, double *total_ms, int32_t *launches)
     return HMM_OK;
 }
 
-const char *hmm_status_string(hmm_status s) {
+const char *hmm_status_string(int32_t s) {
+    // an int, not the enum: any value may arrive through the C ABI
     switch (s) {
         case HMM_OK: return "HMM_OK";
         case HMM_ERR_NULL: return "HMM_ERR_NULL";
