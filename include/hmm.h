@@ -210,6 +210,20 @@ hmm_status hmm_logit_grad(const float *n, const float *probs, float *grad, int64
 hmm_status hmm_reestimate_rows(const float *n, const float *old, float *out, int64_t rows, int32_t cols,
                                hipStream_t stream);
 
+/* The work list the batched kernels of `op` follow (the HMMs of all actions are
+ * independent and run side by side, Sec. 3 item 3; the list groups the pairs
+ * and sorts them by length so that tiles of consecutive entries advance in
+ * step).  order [S]: sequence indices grouped by owning model (one group when
+ * op is HMM_OP_CLASSIFY or HMM_OP_FORWARD without model_of_seq), each group
+ * sorted by decreasing length, equal lengths in increasing index order (a
+ * stable sort, so the list and every tile of it depend on the batch alone).
+ * An invalid sequence sorts as length 0 of its group (of group 0 when its model
+ * index is out of range) and is recorded in the workspace error word.
+ * group_start [groups + 1]: first entry of each group, then S.  Uses the
+ * workspace of `op` (hmm_workspace_size); enqueues only, like the calls above. */
+hmm_status hmm_plan_order(const hmm_bank *bank, const hmm_batch *batch, int32_t op, int32_t *order,
+                          int32_t *group_start, void *ws, size_t ws_bytes, hipStream_t stream);
+
 /* Synchronises `stream`, then reads the workspace error word: *first_bad_seq
  * is the smallest sequence index the last call flagged, or -1 if none. */
 hmm_status hmm_workspace_error(const void *ws, hipStream_t stream, int32_t *first_bad_seq);

@@ -245,8 +245,9 @@ Layout make_layout(const hmm_bank *b, const hmm_batch *q, int op) {
         const int groups = plan_groups(b, q, op);
         const size_t nbins = (size_t)groups * ((size_t)q->max_len + 1);
         L.queue = take((size_t)2 * K * sizeof(int32_t));
-        L.hist = take(nbins * sizeof(int32_t));
-        L.cursor = take(nbins * sizeof(int32_t));
+        plan_chunking(S, (int64_t)nbins, &L.plan_chunk, &L.plan_nchunks);
+        L.hist = take(nbins * (size_t)L.plan_nchunks * sizeof(int32_t));
+        L.scanb = take((nbins * (size_t)L.plan_nchunks + 8191) / 8192 * sizeof(int32_t));
         L.gstart = take((size_t)(groups + 1) * sizeof(int32_t));
         L.perm = take((size_t)S * sizeof(int32_t));
         L.bt = take((size_t)K * M * NP * sizeof(float));
@@ -262,10 +263,19 @@ Layout make_layout(const hmm_bank *b, const hmm_batch *q, int op) {
             L.ckexp = take((size_t)S * nck * sizeof(int32_t));
             L.flag = take((size_t)S * sizeof(int32_t));
             const bool coop = grad_uses_coop(NP);
-            L.seg_slots = coop ? adj_coop_slots(NP, M, K, device_cu_count()) : adj_mfma_slots(NP, M, K, device_cu_count());
-            L.seg_stride = coop ? adj_coop_seg_stride(NP, M, q->max_len) : adj_mfma_seg_stride(NP, q->max_len);
+            const int cus = device_cu_count();
+            L.seg_slots = coop ? adj_coop_slots(NP, M, S, K, cus) : adj_mfma_slots(NP, M, S, K, cus);
+            L.seg_stride = coop ? adj_coop_seg_stride(NP, M, S, K, q->max_len) : adj_mfma_seg_stride(NP, q->max_len);
             L.seg = take((size_t)L.seg_slots * L.seg_stride * sizeof(float));
-            if (coop) L.nbt = take((size_t)K * M * NP * sizeof(float));
+            L.slab_on = (coop ? adj_coop_slab(NP, M, S, K) : adj_mfma_slab(NP, M, S, K)) ? 1 : 0;
+            L.pi64 = take((size_t)K * b->N * 8);
+            L.A64 = take((size_t)K * b->N * b->N * 8);
+            if (L.slab_on)
+                L.slab = take((size_t)slab_slots(S, K) * M * NP * sizeof(float));
+            else
+                L.B64 = take((size_t)K * M * NP * 8);
+            L.nanflag = take((size_t)K * sizeof(int32_t));
+            L.wmax = take(sizeof(uint32_t));
             if (coop && adj_coop_streams(NP)) L.frag = take((size_t)K * 2 * NP * NP * sizeof(float));
         }
     }
@@ -542,20 +552,16 @@ hmm_status hmm_forward_backward_grad(const hmm_bank *bank, const hmm_batch *batc
     }
     if (phase == 1) return HMM_OK;
     const bool coop = grad_uses_coop(NP);
-    float *nbt = coop ? (float *)(w + L.nbt) : nullptr;
-    launch_fill_f32(cnt_pi, (size_t)K * N, 0.0f, stream);
-    launch_fill_f32(cnt_A, (size_t)K * N * N, 0.0f, stream);
-    if (coop)
-        launch_fill_f32(nbt, (size_t)K * M * NP, 0.0f, stream);
-    else
-        launch_fill_f32(cnt_B, (size_t)K * N * M, 0.0f, stream);
+    const bool slab = L.slab_on != 0;
+    // the fixed-point count sums start at zero (fill kernels: no memset nodes in a captured graph)
+    launch_fill_i32((int32_t *)(w + L.pi64), (size_t)2 * K * N, 0, stream);
+    launch_fill_i32((int32_t *)(w + L.A64), (size_t)2 * K * N * N, 0, stream);
+    if (!slab) launch_fill_i32((int32_t *)(w + L.B64), (size_t)2 * K * M * NP, 0, stream);
+    launch_fill_i32((int32_t *)(w + L.nanflag), (size_t)K, 0, stream);
+    launch_weight_max(seq_weight, S, (uint32_t *)(w + L.wmax), stream);
     int32_t *queue2 = (int32_t *)(w + L.queue) + K;
     launch_fill_i32(queue2, (size_t)K, 0, stream);
     if (hipGetLastError() != hipSuccess) return HMM_ERR_HIP;
-    if (S == 0) {
-        if (coop) launch_counts_transpose(nbt, cnt_B, K, N, M, NP, stream);
-        return hipGetLastError() == hipSuccess ? HMM_OK : HMM_ERR_HIP;
-    }
     AdjLaunch a;
     memset(&a, 0, sizeof(a));
     a.K = K;
@@ -578,21 +584,25 @@ hmm_status hmm_forward_backward_grad(const hmm_bank *bank, const hmm_batch *batc
     a.seg_stride = L.seg_stride;
     a.seg_slots = L.seg_slots;
     a.weight = seq_weight;
-    a.cnt_pi = cnt_pi;
-    a.cnt_A = cnt_A;
-    a.cnt_B = cnt_B;
-    a.nbt = nbt;
+    a.pi64 = (unsigned long long *)(w + L.pi64);
+    a.A64 = (unsigned long long *)(w + L.A64);
+    a.B64 = slab ? nullptr : (unsigned long long *)(w + L.B64);
+    a.slab = slab ? (float *)(w + L.slab) : nullptr;
+    a.nanflag = (int32_t *)(w + L.nanflag);
+    a.wmax = (const uint32_t *)(w + L.wmax);
     a.max_grid = max_grid(L.wg_per_cu, cus);
-    if (coop && adj_coop_streams(NP)) {
-        float *frag = (float *)(w + L.frag);
-        launch_coop_frags(bank->A, frag, K, N, NP, stream);
-        a.frag = frag;
+    if (S > 0) {
+        if (coop && adj_coop_streams(NP)) {
+            float *frag = (float *)(w + L.frag);
+            launch_coop_frags(bank->A, frag, K, N, NP, stream);
+            a.frag = frag;
+        }
+        const int pr = prof_begin(stream, HMM_PROF_ADJ_BATCHED);
+        const hipError_t e = coop ? launch_adj_coop(d, a, cus, stream) : launch_adj_mfma(d, a, cus, stream);
+        prof_end(stream, pr);
+        if (e != hipSuccess) return HMM_ERR_HIP;
     }
-    const int pr = prof_begin(stream, HMM_PROF_ADJ_BATCHED);
-    const hipError_t e = coop ? launch_adj_coop(d, a, cus, stream) : launch_adj_mfma(d, a, cus, stream);
-    prof_end(stream, pr);
-    if (e != hipSuccess) return HMM_ERR_HIP;
-    if (coop) launch_counts_transpose(nbt, cnt_B, K, N, M, NP, stream);
+    launch_counts_finish(a, slab, cnt_pi, cnt_A, cnt_B, stream);
     return hipGetLastError() == hipSuccess ? HMM_OK : HMM_ERR_HIP;
 }
 
@@ -641,6 +651,28 @@ hmm_status hmm_viterbi(const hmm_bank *bank, const hmm_batch *batch, float *scor
     const hipError_t e = launch_viterbi(d, v, cus, stream);
     prof_end(stream, pr);
     return e == hipSuccess ? HMM_OK : HMM_ERR_HIP;
+}
+
+hmm_status hmm_plan_order(const hmm_bank *bank, const hmm_batch *batch, int32_t op, int32_t *order,
+                          int32_t *group_start, void *ws, size_t ws_bytes, hipStream_t stream) {
+    if (op < HMM_OP_FORWARD || op > HMM_OP_VITERBI) return HMM_ERR_ARG;
+    hmm_status rc = check_shapes(bank, batch);
+    if (rc != HMM_OK) return rc;
+    if (batch->S > 0 && (!batch->offsets || !batch->lengths)) return HMM_ERR_NULL;
+    if ((op == HMM_OP_GRAD || op == HMM_OP_VITERBI) && batch->S > 0 && !batch->model_of_seq) return HMM_ERR_NULL;
+    if (!group_start || (batch->S > 0 && !order)) return HMM_ERR_NULL;
+    const Layout L = make_layout(bank, batch, op);
+    if ((rc = check_ws(ws, ws_bytes, L)) != HMM_OK) return rc;
+    if (!batched_capable(bank, batch, op)) return HMM_ERR_UNSUPPORTED;
+    const int groups = plan_groups(bank, batch, op);
+    const bool own = groups > 1;
+    DevPtrs d = dev_ptrs(bank, batch, own);
+    unsigned char *w = (unsigned char *)ws;
+    launch_plan(d, bank->K, batch->S, groups, batch->max_len, batch->total_symbols,
+                groups * (batch->max_len + 1), w, L, stream);
+    launch_copy_i32((const int32_t *)(w + L.perm), order, (size_t)batch->S, stream);
+    launch_copy_i32((const int32_t *)(w + L.gstart), group_start, (size_t)groups + 1, stream);
+    return hipGetLastError() == hipSuccess ? HMM_OK : HMM_ERR_HIP;
 }
 
 hmm_status hmm_reestimate_rows(const float *n, const float *old, float *out, int64_t rows, int32_t cols,

@@ -26,8 +26,13 @@
 // tile) exceed the register file of a CU, so the fragments are streamed from a
 // pre-arranged copy in the workspace ([K][2][waves][R][64][BO] float4; 2 NP^2
 // floats per model, resident in the XCD's L2) a few blocks ahead of use.
-// Emission counts go to an LDS partial [M][NP] when it fits, else straight to
-// the symbol-major global buffer (one contiguous NP-float row per symbol).
+// Emission counts go to an LDS partial [M][NP] when it fits (one 16-state block
+// per wave), written after each tile to the tile's slot of a slab of per-tile
+// partials, else straight to the symbol-major global counts.  Every global count
+// is a 64-bit fixed-point sum (common.cuh), and every sum inside a tile is formed
+// in an order fixed by the tile's data (MFMA accumulation in step order; adds to
+// the LDS partial in slot-rank rounds), so the counts do not depend on which
+// workgroup takes which tile or when.
 #include <climits>
 
 #include "common.cuh"
@@ -101,7 +106,8 @@ template <int R, int BO, bool NBLDS, bool STREAM>
 __global__ void __launch_bounds__(R / BO * WAVE) k_adj_coop(DevPtrs d, AdjLaunch a) {
     using SH = AdjCoopShape<R, BO>;
     // emission counts into the LDS partial one step late, overlapped with the next step's MFMAs
-    constexpr bool DEFER = NBLDS && !STREAM;
+    static_assert(!(NBLDS && STREAM), "the LDS partial serves one-block waves");
+    constexpr bool DEFER = NBLDS;
     constexpr int NP = SH::NP;
     constexpr int NW = SH::NW;
     constexpr int XROW = SH::XROW;
@@ -112,8 +118,8 @@ __global__ void __launch_bounds__(R / BO * WAVE) k_adj_coop(DevPtrs d, AdjLaunch
     __shared__ int32_t symseg[SSEG * TILE];
     __shared__ int32_t tile_sh;
     float *nbl = (float *)smem;  // [M][NP] emission-count partial when NBLDS
-    // [NW][M] bytes after the partial: per-wave table that finds repeated symbols in a step
-    uint8_t *duptab = smem + (size_t)a.M * NP * 4;
+    // [NW][M] words after the partial: per-wave slot masks of the symbols of a step
+    uint32_t *ranktab = (uint32_t *)(smem + (size_t)a.M * NP * 4);
 
     const int lane = threadIdx.x & (WAVE - 1);
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
@@ -121,6 +127,7 @@ __global__ void __launch_bounds__(R / BO * WAVE) k_adj_coop(DevPtrs d, AdjLaunch
     const int sl = lane & 15, g = lane >> 4;
     const int K = a.K, N = a.N, M = a.M;
     const int swz = nb_swz(NP);
+    const int F = fixed_exponent(*a.wmax, a.S, a.max_len);
     float *xbuf = xch;
     float *psum = xch + CoopShape<R>::x_floats;
     float *atile = atile_all + w * BO * TILE * 17;  // [BO][16 s][17] own alphahat blocks, transposed reads
@@ -142,10 +149,11 @@ __global__ void __launch_bounds__(R / BO * WAVE) k_adj_coop(DevPtrs d, AdjLaunch
         const int gbeg = a.gstart[k], gend = a.gstart[k + 1];
         const int ntiles = (gend - gbeg + TILE - 1) / TILE;
         const float *btk = a.bt + (size_t)k * M * NP;
-        float *nbt = a.nbt + (size_t)k * M * NP;  // [M][NP] symbol-major counts of model k
+        unsigned long long *B64k = a.B64 + (size_t)k * M * NP;  // [M][NP] symbol-major counts of model k
         if (NBLDS) {
             __syncthreads();
             for (int i = threadIdx.x; i < M * NP; i += blockDim.x) nbl[i] = 0.0f;
+            for (int i = threadIdx.x; i < NW * M; i += blockDim.x) ranktab[i] = 0u;
             __syncthreads();
         }
         const float *Ak = d.A + (size_t)k * N * N;
@@ -153,11 +161,7 @@ __global__ void __launch_bounds__(R / BO * WAVE) k_adj_coop(DevPtrs d, AdjLaunch
             AdjFrags<R, BO, STREAM> fr;
             fr.load(Ak, N, r0, g, sl, STREAM ? (const float4 *)a.frag + (size_t)k * 2 * R * R * WAVE : nullptr,
                     (w * R * WAVE + lane) * BO);
-            floatx4 C[BO][R];  // rows 16 (r0 + b) + 4 g + v, columns 16 rj + sl
-#pragma unroll
-            for (int b = 0; b < BO; ++b)
-#pragma unroll
-                for (int rj = 0; rj < R; ++rj) C[b][rj] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+            floatx4 C[BO][R];  // rows 16 (r0 + b) + 4 g + v, columns 16 rj + sl; per tile
 
             for (;;) {
                 if (threadIdx.x == 0) tile_sh = atomicAdd(&a.queue[k], 1);
@@ -181,7 +185,12 @@ __global__ void __launch_bounds__(R / BO * WAVE) k_adj_coop(DevPtrs d, AdjLaunch
                     act = !bad && T > 0 && a.flag[pos] == 0;
                 }
                 const int Tmax = __builtin_amdgcn_readfirstlane(wave_max_int(T));
-                if (Tmax == 0) continue;
+                if (Tmax > 0) {
+#pragma unroll
+                for (int b = 0; b < BO; ++b)
+#pragma unroll
+                    for (int rj = 0; rj < R; ++rj) C[b][rj] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+                bool lane_nan = false;  // a non-finite count (from a non-finite weight) in this lane
                 int L = 1;
                 while (L * L < Tmax) ++L;
                 const int nseg = (Tmax + L - 1) / L;
@@ -194,34 +203,31 @@ __global__ void __launch_bounds__(R / BO * WAVE) k_adj_coop(DevPtrs d, AdjLaunch
                 float gpi[BO][4] = {};
                 // Emission counts of the previous backward step, added to the LDS partial
                 // during the next step.  A lane adds its 4 consecutive states of one symbol
-                // with a plain 16-byte read-add-write when no other sequence of the tile
-                // has that symbol at that step (the lanes of a wave then touch disjoint
-                // addresses, and other waves own other state blocks); a lane whose symbol
-                // repeats in an earlier slot adds with atomics instead, issued after the
-                // plain writes (in order within the wave).
+                // with a plain 16-byte read-add-write (other waves own other state
+                // blocks).  Slots of the tile that share a symbol at that step add in
+                // rounds of their slot rank (the first occurrence in round 0, the second
+                // in round 1, ...), so colliding lanes never add in the same instruction
+                // and the sum is formed in slot order.
                 float4 pend_gm[BO];
                 int pend_ix[BO] = {};
-                bool pend_on = false, pend_dup = false;
-                auto flush_pending = [&]() {
-                    if (pend_on && !pend_dup) {
+                bool pend_on = false;
+                int pend_rank = 0;
+                auto rmw = [&]() {
 #pragma unroll
-                        for (int b = 0; b < BO; ++b) {
-                            float4 q = *(const float4 *)&nbl[pend_ix[b]];
-                            q.x += pend_gm[b].x;
-                            q.y += pend_gm[b].y;
-                            q.z += pend_gm[b].z;
-                            q.w += pend_gm[b].w;
-                            *(float4 *)&nbl[pend_ix[b]] = q;
-                        }
+                    for (int b = 0; b < BO; ++b) {
+                        float4 q = *(const float4 *)&nbl[pend_ix[b]];
+                        q.x += pend_gm[b].x;
+                        q.y += pend_gm[b].y;
+                        q.z += pend_gm[b].z;
+                        q.w += pend_gm[b].w;
+                        *(float4 *)&nbl[pend_ix[b]] = q;
                     }
-                    if (pend_on && pend_dup) {
-#pragma unroll
-                        for (int b = 0; b < BO; ++b) {
-                            atomicAdd(&nbl[pend_ix[b]], pend_gm[b].x);
-                            atomicAdd(&nbl[pend_ix[b] + 1], pend_gm[b].y);
-                            atomicAdd(&nbl[pend_ix[b] + 2], pend_gm[b].z);
-                            atomicAdd(&nbl[pend_ix[b] + 3], pend_gm[b].w);
-                        }
+                };
+                auto flush_pending = [&]() {
+                    if (pend_on && pend_rank == 0) rmw();
+                    for (int r = 1; __ballot(pend_on && pend_rank >= r) != 0; ++r) {
+                        wave_lds_sync();
+                        if (pend_on && pend_rank == r) rmw();
                     }
                     pend_on = false;
                 };
@@ -383,19 +389,16 @@ __global__ void __launch_bounds__(R / BO * WAVE) k_adj_coop(DevPtrs d, AdjLaunch
                             // immediate offsets from it (per-state addresses were spilled
                             // to scratch, and each reload waited for every outstanding load)
                             const int ib = 16 * r0 + 4 * g;
-                            float *dst = nbt + (uint32_t)(ot * NP + ib);
+                            unsigned long long *dst = B64k + (uint32_t)(ot * NP + ib);
 #pragma unroll
                             for (int b = 0; b < BO; ++b)
 #pragma unroll
                                 for (int v = 0; v < 4; ++v) {
                                     const int i = ib + 16 * b + v;
                                     const float gm = wgt * al[b][v] * be[b][v];
-                                    if (i < N) {
-                                        if (NBLDS)
-                                            atomicAdd(&nbl[ot * NP + (i ^ (ot * 4 & swz))], gm);
-                                        else
-                                            atomicAdd(dst + 16 * b + v, gm);
-                                    }
+                                    const bool fin = __builtin_isfinite(gm);
+                                    lane_nan |= !fin;
+                                    if (i < N) atomicAdd(dst + 16 * b + v, to_fixed(fin ? gm : 0.0f, F));
                                     if (t == 0) gpi[b][v] = gm;
                                 }
                         }
@@ -452,15 +455,9 @@ __global__ void __launch_bounds__(R / BO * WAVE) k_adj_coop(DevPtrs d, AdjLaunch
                             flush_pending();
                         }
                         if (DEFER) {
-                            // this step's emission counts wait in registers for the next step.
-                            // Repeated symbols: every slot writes its index at its symbol's entry
-                            // of the wave's table and reads the entry back; exactly one slot per
-                            // symbol finds its own index (the wave-level LDS fence keeps the read
-                            // from being folded into the lane's own write; a volatile access would
-                            // lose the LDS address space and wait for all outstanding global loads)
-                            duptab[w * M + ot] = (uint8_t)sl;
-                            wave_lds_sync();
-                            const int first = duptab[w * M + ot];
+                            // this step's emission counts wait in registers for the next step,
+                            // with the slot rank of their symbol among the tile's slots
+                            const int rank = slot_rank(ranktab + w * M, ot, sl);
 #pragma unroll
                             for (int b = 0; b < BO; ++b) {
                                 float gm[4];
@@ -469,12 +466,13 @@ __global__ void __launch_bounds__(R / BO * WAVE) k_adj_coop(DevPtrs d, AdjLaunch
                                     const int i = 16 * (r0 + b) + 4 * g + v;
                                     gm[v] = (i < N) ? wgt * al[b][v] * be[b][v] : 0.0f;
                                     if (live && t == 0) gpi[b][v] = gm[v];
+                                    lane_nan |= live && !__builtin_isfinite(gm[v]);
                                 }
                                 pend_gm[b] = float4{gm[0], gm[1], gm[2], gm[3]};
                                 pend_ix[b] = ot * NP + ((16 * (r0 + b) + 4 * g) ^ (ot * 4 & swz));
                             }
                             pend_on = live;
-                            pend_dup = first != sl;
+                            pend_rank = rank;
                         }
                         // w_t = b_t o betahat_t 2^-e_t; zero where the sequence has ended or
                         // takes no part (its values may be inf / NaN and w enters the
@@ -492,36 +490,41 @@ __global__ void __launch_bounds__(R / BO * WAVE) k_adj_coop(DevPtrs d, AdjLaunch
                     }
                 }
                 if (DEFER) flush_pending();
+                // this tile's initial counts and n_A = A o C for this wave's rows; the row
+                // base is opaque so that the flush's addresses are formed here and not kept
+                // live across the tile loop
+                {
+                    const int rb = opaque(k * N + 16 * r0 + 4 * g);  // global row of (b, v) = rb + 16 b + v
+                    const int ib = 16 * r0 + 4 * g;
 #pragma unroll
-                for (int b = 0; b < BO; ++b)
+                    for (int b = 0; b < BO; ++b)
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        const int i = 16 * (r0 + b) + 4 * g + v;
-                        if (i < N && gpi[b][v] != 0.0f) atomicAdd(&a.cnt_pi[(size_t)k * N + i], gpi[b][v]);
+                        for (int v = 0; v < 4; ++v)
+                            if (ib + 16 * b + v < N) add_fixed(&a.pi64[rb + 16 * b + v], gpi[b][v], F, &a.nanflag[k]);
+#pragma unroll
+                    for (int b = 0; b < BO; ++b)
+#pragma unroll
+                        for (int rj = 0; rj < R; ++rj)
+#pragma unroll
+                            for (int v = 0; v < 4; ++v) {
+                                const int jj = 16 * rj + sl;
+                                const size_t e = (size_t)(rb + 16 * b + v) * N + jj;
+                                if (ib + 16 * b + v < N && jj < N)
+                                    add_fixed(&a.A64[e], d.A[e] * C[b][rj][v], F, &a.nanflag[k]);
+                            }
+                }
+                if (lane_nan) atomicOr(&a.nanflag[k], 1);
+                }  // Tmax > 0
+                if (NBLDS) {
+                    // the tile's emission partial into its slab slot (zeros for an empty tile)
+                    __syncthreads();
+                    float *dst = a.slab + (size_t)slab_slot(gbeg, k, tile) * M * NP;
+                    for (int idx = threadIdx.x; idx < M * NP; idx += blockDim.x) {
+                        const int o = idx / NP, ic = idx % NP;
+                        dst[(size_t)o * NP + (ic ^ (o * 4 & swz))] = nbl[idx];
+                        nbl[idx] = 0.0f;
                     }
-            }
-            // n_A = A o C for this wave's rows of model k
-#pragma unroll
-            for (int b = 0; b < BO; ++b)
-#pragma unroll
-                for (int rj = 0; rj < R; ++rj)
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        const int i = 16 * (r0 + b) + 4 * g + v, jj = 16 * rj + sl;
-                        if (i < N && jj < N) {
-                            const float c = C[b][rj][v];
-                            if (c != 0.0f)
-                                atomicAdd(&a.cnt_A[((size_t)k * N + i) * N + jj], Ak[(size_t)i * N + jj] * c);
-                        }
-                    }
-        }
-        if (NBLDS) {
-            __syncthreads();
-            for (int idx = threadIdx.x; idx < M * NP; idx += blockDim.x) {
-                const int o = idx / NP, ic = idx % NP;
-                const int i = ic ^ (o * 4 & swz);
-                const float v = nbl[idx];
-                if (i < N && v != 0.0f) atomicAdd(&nbt[(size_t)o * NP + i], v);
+                }
             }
         }
     }
@@ -553,8 +556,8 @@ __global__ void __launch_bounds__(2 * R * WAVE) k_adj_pipe(DevPtrs d, AdjLaunch 
     __shared__ float mlast[TILE];  // m_T of each sequence of the tile
     __shared__ int32_t tile_sh;
     float *nbl = (float *)smem;  // [M][NP] emission-count partial
-    // [R][M] bytes after the partial: per-wave table that finds repeated symbols in a step
-    uint8_t *duptab = smem + (size_t)a.M * NP * 4;
+    // [R][M] words after the partial: per-wave slot masks of the symbols of a step
+    uint32_t *ranktab = (uint32_t *)(smem + (size_t)a.M * NP * 4);
 
     const int lane = threadIdx.x & (WAVE - 1);
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
@@ -563,6 +566,7 @@ __global__ void __launch_bounds__(2 * R * WAVE) k_adj_pipe(DevPtrs d, AdjLaunch 
     const int sl = lane & 15, g = lane >> 4;
     const int K = a.K, N = a.N, M = a.M;
     const int swz = nb_swz(NP);
+    const int F = fixed_exponent(*a.wmax, a.S, a.max_len);
     float *xbuf = xch;
     float *psum = xch + CoopShape<R>::x_floats;
     float *atile = atile_all + wid * TILE * 17;  // [16 s][17] own alphahat block, transposed reads
@@ -584,21 +588,19 @@ __global__ void __launch_bounds__(2 * R * WAVE) k_adj_pipe(DevPtrs d, AdjLaunch 
         const int gbeg = a.gstart[k], gend = a.gstart[k + 1];
         const int ntiles = (gend - gbeg + TILE - 1) / TILE;
         const float *btk = a.bt + (size_t)k * M * NP;
-        float *nbt = a.nbt + (size_t)k * M * NP;
         __syncthreads();
         for (int i = threadIdx.x; i < M * NP; i += blockDim.x) nbl[i] = 0.0f;
+        for (int i = threadIdx.x; i < R * M; i += blockDim.x) ranktab[i] = 0u;
         __syncthreads();
         const float *Ak = d.A + (size_t)k * N * N;
         if (ntiles > 0) {
             AdjFrags<R, 1, false> fr;
             fr.load(Ak, N, w, g, sl, nullptr, 0);
             // each group adds half of the transition counts: rows 16 w + 4 g + v,
-            // columns 16 (rj0 + rj) + sl, rj0 = 0 (backward group) or R / 2
+            // columns 16 (rj0 + rj) + sl, rj0 = 0 (backward group) or R / 2; per tile
             constexpr int RH = R / 2;
             const int rj0 = rec ? RH : 0;
             floatx4 C[RH];
-#pragma unroll
-            for (int rj = 0; rj < RH; ++rj) C[rj] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
             // C[own rows][half] += X^T W for backward step t: alphahat_t of the own block,
             // weighted, through the wave's transposition tile; w_{t+1} from the exchange row
             auto c_update = [&](const float (&al)[4], bool trans, float wgt_, const float *wrow) {
@@ -643,32 +645,36 @@ __global__ void __launch_bounds__(2 * R * WAVE) k_adj_pipe(DevPtrs d, AdjLaunch 
                     act = !bad && T > 0 && a.flag[pos] == 0;
                 }
                 const int Tmax = __builtin_amdgcn_readfirstlane(wave_max_int(T));
-                if (Tmax == 0) continue;
+                if (Tmax > 0) {
+#pragma unroll
+                for (int rj = 0; rj < RH; ++rj) C[rj] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+                bool lane_nan = false;  // a non-finite count (from a non-finite weight) in this lane
                 int L = 1;
                 while (L * L < Tmax) ++L;
                 const int nseg = (Tmax + L - 1) / L;
                 const float wgt = act ? (a.weight ? a.weight[seq] : 1.0f) : 0.0f;
                 const int32_t *sbase = T > 0 ? d.symbols + off : d.symbols;
                 const int tlim = T > 0 ? T - 1 : 0;
-                // backward group: gamma_1 (added after the tile) and the deferred emission counts
+                // backward group: gamma_1 (added after the tile) and the deferred emission
+                // counts, added in slot-rank rounds as in k_adj_coop
                 float gpi[4] = {};
                 float4 pend_gm = {0.0f, 0.0f, 0.0f, 0.0f};
                 int pend_ix = 0;
-                bool pend_on = false, pend_dup = false;
+                bool pend_on = false;
+                int pend_rank = 0;
+                auto rmw = [&]() {
+                    float4 q = *(const float4 *)&nbl[pend_ix];
+                    q.x += pend_gm.x;
+                    q.y += pend_gm.y;
+                    q.z += pend_gm.z;
+                    q.w += pend_gm.w;
+                    *(float4 *)&nbl[pend_ix] = q;
+                };
                 auto flush_pending = [&]() {
-                    if (pend_on && !pend_dup) {
-                        float4 q = *(const float4 *)&nbl[pend_ix];
-                        q.x += pend_gm.x;
-                        q.y += pend_gm.y;
-                        q.z += pend_gm.z;
-                        q.w += pend_gm.w;
-                        *(float4 *)&nbl[pend_ix] = q;
-                    }
-                    if (pend_on && pend_dup) {
-                        atomicAdd(&nbl[pend_ix], pend_gm.x);
-                        atomicAdd(&nbl[pend_ix + 1], pend_gm.y);
-                        atomicAdd(&nbl[pend_ix + 2], pend_gm.z);
-                        atomicAdd(&nbl[pend_ix + 3], pend_gm.w);
+                    if (pend_on && pend_rank == 0) rmw();
+                    for (int r = 1; __ballot(pend_on && pend_rank >= r) != 0; ++r) {
+                        wave_lds_sync();
+                        if (pend_on && pend_rank == r) rmw();
                     }
                     pend_on = false;
                 };
@@ -758,22 +764,21 @@ __global__ void __launch_bounds__(2 * R * WAVE) k_adj_pipe(DevPtrs d, AdjLaunch 
 #pragma unroll
                                     for (int v = 0; v < 4; ++v) be[v] = inv;
                                 }
-                                // this step's emission counts wait in registers for the next step
-                                // (repeated symbols in the wave's 16 slots take atomics, as in k_adj_coop)
-                                duptab[w * M + ot] = (uint8_t)sl;
-                                wave_lds_sync();
-                                const int first = duptab[w * M + ot];
+                                // this step's emission counts wait in registers for the next step,
+                                // with the slot rank of their symbol among the tile's slots
+                                const int rank = slot_rank(ranktab + w * M, ot, sl);
                                 float gm[4];
 #pragma unroll
                                 for (int v = 0; v < 4; ++v) {
                                     const int i = 16 * w + 4 * g + v;
                                     gm[v] = (i < N) ? wgt * al[v] * be[v] : 0.0f;
                                     if (live && t == 0) gpi[v] = gm[v];
+                                    lane_nan |= live && !__builtin_isfinite(gm[v]);
                                 }
                                 pend_gm = float4{gm[0], gm[1], gm[2], gm[3]};
                                 pend_ix = ot * NP + ((16 * w + 4 * g) ^ (ot * 4 & swz));
                                 pend_on = live;
-                                pend_dup = first != sl;
+                                pend_rank = rank;
                                 // w_t = b_t o betahat_t 2^-e_t; zero where the sequence has ended or takes no part
                                 const float wn0 = live ? ldexp_f(bb.x * be[0], -et) : 0.0f;
                                 const float wn1 = live ? ldexp_f(bb.y * be[1], -et) : 0.0f;
@@ -866,46 +871,54 @@ __global__ void __launch_bounds__(2 * R * WAVE) k_adj_pipe(DevPtrs d, AdjLaunch 
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
                         const int i = 16 * w + 4 * g + v;
-                        if (i < N && gpi[v] != 0.0f) atomicAdd(&a.cnt_pi[(size_t)k * N + i], gpi[v]);
+                        if (i < N) add_fixed(&a.pi64[(size_t)k * N + i], gpi[v], F, &a.nanflag[k]);
                     }
+                    if (lane_nan) atomicOr(&a.nanflag[k], 1);
+                }
+                // this tile's n_A = A o C for this wave's rows and half of the columns (row
+                // base opaque: the flush's addresses are not kept live across the tile loop)
+                {
+                    const int rb = opaque(k * N + 16 * w + 4 * g);
+                    const int ib = 16 * w + 4 * g;
+#pragma unroll
+                    for (int rj = 0; rj < RH; ++rj)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            const int jj = 16 * (rj0 + rj) + sl;
+                            const size_t e = (size_t)(rb + v) * N + jj;
+                            if (ib + v < N && jj < N) add_fixed(&a.A64[e], d.A[e] * C[rj][v], F, &a.nanflag[k]);
+                        }
+                }
+                }  // Tmax > 0
+                // the tile's emission partial into its slab slot (zeros for an empty tile)
+                __syncthreads();
+                float *dst = a.slab + (size_t)slab_slot(gbeg, k, tile) * M * NP;
+                for (int idx = threadIdx.x; idx < M * NP; idx += blockDim.x) {
+                    const int o = idx / NP, ic = idx % NP;
+                    dst[(size_t)o * NP + (ic ^ (o * 4 & swz))] = nbl[idx];
+                    nbl[idx] = 0.0f;
                 }
             }
-            {
-                // n_A = A o C for this wave's rows and half of the columns of model k
-#pragma unroll
-                for (int rj = 0; rj < RH; ++rj)
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        const int i = 16 * w + 4 * g + v, jj = 16 * (rj0 + rj) + sl;
-                        if (i < N && jj < N) {
-                            const float c = C[rj][v];
-                            if (c != 0.0f) atomicAdd(&a.cnt_A[((size_t)k * N + i) * N + jj], Ak[(size_t)i * N + jj] * c);
-                        }
-                    }
-            }
-        }
-        __syncthreads();
-        for (int idx = threadIdx.x; idx < M * NP; idx += blockDim.x) {
-            const int o = idx / NP, ic = idx % NP;
-            const int i = ic ^ (o * 4 & swz);
-            const float v = nbl[idx];
-            if (i < N && v != 0.0f) atomicAdd(&nbt[(size_t)o * NP + i], v);
         }
     }
 }
 
 constexpr size_t COOP_LDS_LIMIT = 160 * 1024;
 
-// Dynamic LDS of the partial variant: the [M][NP] partial, then the [waves][M] byte table.
+// Dynamic LDS of the partial variant: the [M][NP] partial, then the [waves][M] slot-mask table.
 template <int R>
 size_t nb_lds_bytes(int M) {
     constexpr int BO = adj_bo(R);
-    return ((size_t)M * 16 * R * 4 + (size_t)(R / BO) * M + 15) / 16 * 16;
+    return ((size_t)M * 16 * R * 4 + (size_t)(R / BO) * M * 4 + 15) / 16 * 16;
 }
 
+// The LDS partial serves one-block waves (up to 128 states) whose partial fits,
+// when the slab of per-tile partials stays within SLAB_MAX_BYTES.
 template <int R>
-bool use_nb_lds(int M) {
+bool use_nb_lds(int M, int S, int K) {
     constexpr int BO = adj_bo(R);
+    if (BO > 1) return false;
+    if (slab_slots(S, K) * M * 16 * R * 4 > SLAB_MAX_BYTES) return false;
     return nb_lds_bytes<R>(M) + AdjCoopShape<R, BO>::small_bytes + 64 <= COOP_LDS_LIMIT;
 }
 
@@ -913,11 +926,12 @@ bool use_nb_lds(int M) {
 // its buffers.  (With 6 or 8 blocks its 12 or 16 waves leave fewer than 170
 // registers per wave, and the step spills.)
 template <int R>
-bool use_pipe(int M) {
+bool use_pipe(int M, int S, int K) {
     if constexpr (R != 4) {
         return false;
     } else {
         using SH = AdjCoopShape<R, 1>;
+        if (slab_slots(S, K) * M * 16 * R * 4 > SLAB_MAX_BYTES) return false;
         const size_t small = (SH::xch_floats + SH::w_floats + 2 * SH::at_floats) * 4 + 2 * PACH * TILE * 4 + TILE * 4;
         return nb_lds_bytes<R>(M) + small + 64 <= COOP_LDS_LIMIT;
     }
@@ -943,7 +957,8 @@ int grid_pipe(int M, int cu_count, int K) {
 template <int R, bool NBLDS>
 int grid_t(int M, int cu_count, int K) {
     constexpr int BO = adj_bo(R);
-    auto kern = k_adj_coop<R, BO, NBLDS, (BO > 1)>;
+    if constexpr (NBLDS && BO > 1) return 0;  // not instantiated: the partial serves one-block waves
+    auto kern = k_adj_coop<R, BO, NBLDS && BO == 1, (BO > 1)>;
     const size_t dyn = NBLDS ? nb_lds_bytes<R>(M) : 0;
     if (dyn > 0) (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
     int per_cu = 0;
@@ -955,9 +970,9 @@ int grid_t(int M, int cu_count, int K) {
 }
 
 template <int R>
-int grid_r(int M, int cu_count, int K) {
-    if (use_pipe<R>(M)) return grid_pipe<R>(M, cu_count, K);
-    return use_nb_lds<R>(M) ? grid_t<R, true>(M, cu_count, K) : grid_t<R, false>(M, cu_count, K);
+int grid_r(int M, int S, int cu_count, int K) {
+    if (use_pipe<R>(M, S, K)) return grid_pipe<R>(M, cu_count, K);
+    return use_nb_lds<R>(M, S, K) ? grid_t<R, true>(M, cu_count, K) : grid_t<R, false>(M, cu_count, K);
 }
 
 template <int R>
@@ -965,18 +980,25 @@ hipError_t launch_r(const DevPtrs &d, const AdjLaunch &a, int cu_count, hipStrea
     constexpr int BO = adj_bo(R);
     constexpr bool STREAM = BO > 1;
     if (STREAM && a.frag == nullptr) return hipErrorInvalidValue;
-    const int grid = persistent_grid(grid_r<R>(a.M, cu_count, a.K), tile_bound(a.S, a.K, false, TILE), 1, a.K, a.max_grid);
+    const int grid =
+        persistent_grid(grid_r<R>(a.M, a.S, cu_count, a.K), tile_bound(a.S, a.K, false, TILE), 1, a.K, a.max_grid);
     if (grid > a.seg_slots) return hipErrorInvalidValue;
     if constexpr (R == 4) {
-        if (use_pipe<R>(a.M)) {
+        if (use_pipe<R>(a.M, a.S, a.K)) {
+            if (a.slab == nullptr) return hipErrorInvalidValue;
             k_adj_pipe<R><<<grid, 2 * R * WAVE, nb_lds_bytes<R>(a.M), st>>>(d, a);
             return hipGetLastError();
         }
     }
-    if (use_nb_lds<R>(a.M))
-        k_adj_coop<R, BO, true, STREAM><<<grid, R / BO * WAVE, nb_lds_bytes<R>(a.M), st>>>(d, a);
-    else
-        k_adj_coop<R, BO, false, STREAM><<<grid, R / BO * WAVE, 0, st>>>(d, a);
+    if constexpr (!STREAM) {
+        if (use_nb_lds<R>(a.M, a.S, a.K)) {
+            if (a.slab == nullptr) return hipErrorInvalidValue;
+            k_adj_coop<R, BO, true, false><<<grid, R / BO * WAVE, nb_lds_bytes<R>(a.M), st>>>(d, a);
+            return hipGetLastError();
+        }
+    }
+    if (a.B64 == nullptr) return hipErrorInvalidValue;
+    k_adj_coop<R, BO, false, STREAM><<<grid, R / BO * WAVE, 0, st>>>(d, a);
     return hipGetLastError();
 }
 
@@ -1013,35 +1035,42 @@ bool adj_coop_supported(int NP) { return NP >= 64 && NP <= 256 && NP % 32 == 0; 
 
 bool adj_coop_streams(int NP) { return adj_bo(NP / 16) > 1; }
 
-int adj_coop_slots(int NP, int M, int K, int cu_count) {
+int adj_coop_slots(int NP, int M, int S, int K, int cu_count) {
     switch (NP / 16) {
-        case 4: return grid_r<4>(M, cu_count, K);
-        case 6: return grid_r<6>(M, cu_count, K);
-        case 8: return grid_r<8>(M, cu_count, K);
-        case 10: return grid_r<10>(M, cu_count, K);
-        case 12: return grid_r<12>(M, cu_count, K);
-        case 14: return grid_r<14>(M, cu_count, K);
-        case 16: return grid_r<16>(M, cu_count, K);
+        case 4: return grid_r<4>(M, S, cu_count, K);
+        case 6: return grid_r<6>(M, S, cu_count, K);
+        case 8: return grid_r<8>(M, S, cu_count, K);
+        case 10: return grid_r<10>(M, S, cu_count, K);
+        case 12: return grid_r<12>(M, S, cu_count, K);
+        case 14: return grid_r<14>(M, S, cu_count, K);
+        case 16: return grid_r<16>(M, S, cu_count, K);
         default: return 0;
     }
 }
 
-bool adj_coop_pipelined(int NP, int M) {
+bool adj_coop_pipelined(int NP, int M, int S, int K) {
     switch (NP / 16) {
-        case 4: return use_pipe<4>(M);
-        case 6: return use_pipe<6>(M);
-        case 8: return use_pipe<8>(M);
+        case 4: return use_pipe<4>(M, S, K);
         default: return false;
     }
 }
 
-int64_t adj_coop_seg_stride(int NP, int M, int max_len) {
+bool adj_coop_slab(int NP, int M, int S, int K) {
+    switch (NP / 16) {
+        case 4: return use_pipe<4>(M, S, K) || use_nb_lds<4>(M, S, K);
+        case 6: return use_nb_lds<6>(M, S, K);
+        case 8: return use_nb_lds<8>(M, S, K);
+        default: return false;
+    }
+}
+
+int64_t adj_coop_seg_stride(int NP, int M, int S, int K, int max_len) {
     int L = 1;
     while ((int64_t)L * L < max_len) ++L;
     const int R = NP / 16, BO = adj_bo(R);
     // float4 alphahat per owned block + e + o, per lane and wave; two halves
     // (segment parity) for the pipelined kernel
-    return (int64_t)L * (R / BO) * WAVE * (4 * BO + 2) * (adj_coop_pipelined(NP, M) ? 2 : 1);
+    return (int64_t)L * (R / BO) * WAVE * (4 * BO + 2) * (adj_coop_pipelined(NP, M, S, K) ? 2 : 1);
 }
 
 void launch_coop_frags(const float *A, float *frag, int K, int N, int NP, hipStream_t st) {

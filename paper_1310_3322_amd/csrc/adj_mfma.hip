@@ -24,8 +24,14 @@
 //   C += X^T W                       X = w_s alphahat_t, W = w_{t+1}: transposed
 //                                    through a per-wave LDS tile so the 16
 //                                    sequences become the MFMA contraction axis
-//   n_B^T[o_t][i] += w_s gamma_t(i)  LDS float atomics into the workgroup's
-//                                    partial (or global atomics if it does not fit)
+//   n_B^T[o_t][i] += w_s gamma_t(i)  into the wave's LDS partial (slots that share
+//                                    a symbol add in slot-rank rounds), written to
+//                                    the tile's slab slot after each tile; or, when
+//                                    the partial does not fit, to the global counts
+//
+// Global counts are 64-bit fixed-point sums (common.cuh) and each tile's sums are
+// formed in an order fixed by its data, so the counts do not depend on which
+// wave takes which tile.
 #include <climits>
 
 #include "common.cuh"
@@ -47,10 +53,37 @@ struct AdjShape {
     static constexpr int per_wave_bytes = tile_floats * 4 + sym_ints * 4;
 };
 
+// Emission counts of a step into the LDS partial: the lane's 4 consecutive states
+// of each 16-state block at (16 r + 4 g) ^ (4 o & swz) of symbol o's row, in rounds
+// of the slot rank of the lane's symbol.
+template <int R>
+__device__ __forceinline__ void partial_add(float *nbl, int ot, int swz, int g, bool live, int rank,
+                                            const float (&gm)[R][4]) {
+    constexpr int NP = 16 * R;
+    auto rmw = [&]() {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            float *q = &nbl[ot * NP + ((16 * r + 4 * g) ^ (ot * 4 & swz))];
+            float4 x = *(const float4 *)q;
+            x.x += gm[r][0];
+            x.y += gm[r][1];
+            x.z += gm[r][2];
+            x.w += gm[r][3];
+            *(float4 *)q = x;
+        }
+    };
+    if (live && rank == 0) rmw();
+    for (int rr = 1; __ballot(live && rank >= rr) != 0; ++rr) {
+        wave_lds_sync();
+        if (live && rank == rr) rmw();
+    }
+}
+
 __host__ __device__ inline int nb_swizzle_mask(int NP) { return (NP & (NP - 1)) == 0 ? NP - 4 : 0; }
 
 template <int R, int WAVES, bool NBLDS>
 __global__ void __launch_bounds__(WAVES * WAVE) k_adj_mfma(DevPtrs d, AdjLaunch a) {
+    static_assert(!NBLDS || WAVES == 1, "the LDS partial holds one tile's counts");
     using SH = AdjShape<R>;
     constexpr int NP = SH::NP;
     constexpr int XS = SH::XS;
@@ -60,8 +93,10 @@ __global__ void __launch_bounds__(WAVES * WAVE) k_adj_mfma(DevPtrs d, AdjLaunch 
     const int sl = lane & 15, g = lane >> 4;
     const int K = a.K, N = a.N, M = a.M;
     const int swz = nb_swizzle_mask(NP);
+    const int F = fixed_exponent(*a.wmax, a.S, a.max_len);
     float *nbl = (float *)smem;                                        // [M][NP] when NBLDS
-    unsigned char *wbase = smem + (NBLDS ? (size_t)M * NP * 4 : 0) + (size_t)wave * SH::per_wave_bytes;
+    uint32_t *ranktab = (uint32_t *)(smem + (NBLDS ? (size_t)M * NP * 4 : 0));  // [M] slot masks when NBLDS
+    unsigned char *wbase = smem + (NBLDS ? (size_t)M * NP * 4 + (size_t)M * 4 : 0) + (size_t)wave * SH::per_wave_bytes;
     float *xt = (float *)wbase;                                        // [16][XS]
     float *wt = xt + TILE * XS;                                        // [16][XS]
     int32_t *sym = (int32_t *)(wt + TILE * XS);                        // [2][16][ADJ_SYM_STRIDE]
@@ -80,22 +115,18 @@ __global__ void __launch_bounds__(WAVES * WAVE) k_adj_mfma(DevPtrs d, AdjLaunch 
         const int gbeg = a.gstart[k], gend = a.gstart[k + 1];
         const int ntiles = (gend - gbeg + TILE - 1) / TILE;
         const float *btk = a.bt + (size_t)k * M * NP;
-        float *cnt_B = a.cnt_B + (size_t)k * N * M;
+        unsigned long long *B64k = a.B64 + (size_t)k * M * NP;  // [M][NP] symbol-major global counts
         if (NBLDS) {
-            __syncthreads();
-            for (int i = threadIdx.x; i < M * NP; i += blockDim.x) nbl[i] = 0.0f;
-            __syncthreads();
+            for (int i = lane; i < M * NP; i += WAVE) nbl[i] = 0.0f;
+            for (int i = lane; i < M; i += WAVE) ranktab[i] = 0u;
+            wave_lds_sync();
         }
         if (ntiles > 0) {
             const float *Ak = d.A + (size_t)k * N * N;
             float af[R][R][4], ab[R][R][4];
             load_fwd_fragments<R>(af, Ak, N, g, sl);
             load_bwd_fragments<R>(ab, Ak, N, g, sl);
-            floatx4 C[R][R];
-#pragma unroll
-            for (int ri = 0; ri < R; ++ri)
-#pragma unroll
-                for (int rj = 0; rj < R; ++rj) C[ri][rj] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+            floatx4 C[R][R];  // per tile
 
             for (;;) {
                 const int tile = wave_pop(&a.queue[k]);
@@ -117,7 +148,12 @@ __global__ void __launch_bounds__(WAVES * WAVE) k_adj_mfma(DevPtrs d, AdjLaunch 
                 }
                 // the checkpoint grid uses the forward kernel's tile maximum
                 const int Tmax = wave_max_int(T);
-                if (Tmax == 0) continue;
+                if (Tmax > 0) {
+#pragma unroll
+                for (int ri = 0; ri < R; ++ri)
+#pragma unroll
+                    for (int rj = 0; rj < R; ++rj) C[ri][rj] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+                bool lane_nan = false;
                 int L = 1;
                 while (L * L < Tmax) ++L;
                 const int nseg = (Tmax + L - 1) / L;
@@ -264,21 +300,37 @@ __global__ void __launch_bounds__(WAVES * WAVE) k_adj_mfma(DevPtrs d, AdjLaunch 
                                 for (int v = 0; v < 4; ++v) be[r][v] = inv;
                         }
                         // gamma_t -> emission counts (and initial counts at t = 0)
-                        if (live) {
+                        {
+                            float gm[R][4];
 #pragma unroll
                             for (int r = 0; r < R; ++r)
 #pragma unroll
                                 for (int v = 0; v < 4; ++v) {
                                     const int i = 16 * r + 4 * g + v;
-                                    const float gm = wgt * al[r][v] * be[r][v];
-                                    if (i < N) {
-                                        if (NBLDS)
-                                            atomicAdd(&nbl[ot * NP + (i ^ (ot * 4 & swz))], gm);
-                                        else
-                                            atomicAdd(&cnt_B[(size_t)i * M + ot], gm);
-                                        if (t == 0) atomicAdd(&a.cnt_pi[(size_t)k * N + i], gm);
-                                    }
+                                    gm[r][v] = (live && i < N) ? wgt * al[r][v] * be[r][v] : 0.0f;
+                                    lane_nan |= !__builtin_isfinite(gm[r][v]);
                                 }
+                            if (NBLDS) {
+                                partial_add<R>(nbl, ot, swz, g, live, slot_rank(ranktab, ot, sl), gm);
+                            } else if (live) {
+#pragma unroll
+                                for (int r = 0; r < R; ++r)
+#pragma unroll
+                                    for (int v = 0; v < 4; ++v) {
+                                        const int i = 16 * r + 4 * g + v;
+                                        const float x = __builtin_isfinite(gm[r][v]) ? gm[r][v] : 0.0f;
+                                        if (i < N) atomicAdd(&B64k[(size_t)ot * NP + i], to_fixed(x, F));
+                                    }
+                            }
+                            if (live && t == 0) {
+#pragma unroll
+                                for (int r = 0; r < R; ++r)
+#pragma unroll
+                                    for (int v = 0; v < 4; ++v) {
+                                        const int i = 16 * r + 4 * g + v;
+                                        if (i < N) add_fixed(&a.pi64[(size_t)k * N + i], gm[r][v], F, &a.nanflag[k]);
+                                    }
+                            }
                         }
                         // w_t = b_t o betahat_t 2^-e_t for the step before
                         float4 b[R];
@@ -292,28 +344,34 @@ __global__ void __launch_bounds__(WAVES * WAVE) k_adj_mfma(DevPtrs d, AdjLaunch 
                         }
                     }
                 }
-            }
-            // n_A = A o C for this wave's share of model k
+                // this tile's n_A = A o C (row base opaque: the flush's addresses are formed
+                // here, not kept live across the tile loop)
+                {
+                    const int rb = opaque(k * N + 4 * g);
 #pragma unroll
-            for (int ri = 0; ri < R; ++ri)
+                    for (int ri = 0; ri < R; ++ri)
 #pragma unroll
-                for (int rj = 0; rj < R; ++rj)
+                        for (int rj = 0; rj < R; ++rj)
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        const int i = 16 * ri + 4 * g + v, jj = 16 * rj + sl;
-                        if (i < N && jj < N) {
-                            const float c = C[ri][rj][v];
-                            if (c != 0.0f) atomicAdd(&a.cnt_A[((size_t)k * N + i) * N + jj], Ak[(size_t)i * N + jj] * c);
-                        }
+                            for (int v = 0; v < 4; ++v) {
+                                const int i = 16 * ri + 4 * g + v, jj = 16 * rj + sl;
+                                const size_t e = (size_t)(rb + 16 * ri + v) * N + jj;
+                                if (i < N && jj < N) add_fixed(&a.A64[e], d.A[e] * C[ri][rj][v], F, &a.nanflag[k]);
+                            }
+                }
+                if (lane_nan) atomicOr(&a.nanflag[k], 1);
+                }  // Tmax > 0
+                if (NBLDS) {
+                    // the tile's emission partial into its slab slot (zeros for an empty tile)
+                    wave_lds_sync();
+                    float *dst = a.slab + (size_t)slab_slot(gbeg, k, tile) * M * NP;
+                    for (int idx = lane; idx < M * NP; idx += WAVE) {
+                        const int o = idx / NP, ic = idx % NP;
+                        dst[(size_t)o * NP + (ic ^ (o * 4 & swz))] = nbl[idx];
+                        nbl[idx] = 0.0f;
                     }
-        }
-        if (NBLDS) {
-            __syncthreads();
-            for (int idx = threadIdx.x; idx < M * NP; idx += blockDim.x) {
-                const int o = idx / NP, ic = idx % NP;
-                const int i = ic ^ (o * 4 & swz);
-                const float v = nbl[idx];
-                if (i < N && v != 0.0f) atomicAdd(&cnt_B[(size_t)i * M + o], v);
+                    wave_lds_sync();
+                }
             }
         }
     }
@@ -321,7 +379,7 @@ __global__ void __launch_bounds__(WAVES * WAVE) k_adj_mfma(DevPtrs d, AdjLaunch 
 
 template <int R, int WAVES, bool NBLDS>
 size_t adj_lds_bytes(int M) {
-    return (NBLDS ? (size_t)M * 16 * R * 4 : 0) + (size_t)WAVES * AdjShape<R>::per_wave_bytes;
+    return (NBLDS ? (size_t)M * 16 * R * 4 + (size_t)M * 4 : 0) + (size_t)WAVES * AdjShape<R>::per_wave_bytes;
 }
 
 template <int R, int WAVES, bool NBLDS>
@@ -340,38 +398,37 @@ int occupancy_grid(int M, int cu_count, int K, bool set_attr) {
 
 constexpr size_t LDS_LIMIT = 160 * 1024;
 
-// Which variant a shape takes: n_B partial in LDS with 4 or 2 waves, else global atomics.
+// Which variant a shape takes: a one-wave workgroup with the emission partial in
+// LDS (when it fits and the slab of per-tile partials stays within
+// SLAB_MAX_BYTES), else four waves adding to the global counts.
 template <int R>
-int pick_variant(int M) {
-    if (adj_lds_bytes<R, 4, true>(M) <= LDS_LIMIT) return 0;
-    if (adj_lds_bytes<R, 2, true>(M) <= LDS_LIMIT) return 1;
-    return 2;
+bool use_partial(int M, int S, int K) {
+    if (slab_slots(S, K) * M * 16 * R * 4 > SLAB_MAX_BYTES) return false;
+    return adj_lds_bytes<R, 1, true>(M) <= LDS_LIMIT;
 }
 
 template <int R>
-int grid_for(int M, int cu_count, int K, bool set_attr, int *waves) {
-    switch (pick_variant<R>(M)) {
-        case 0: *waves = 4; return occupancy_grid<R, 4, true>(M, cu_count, K, set_attr);
-        case 1: *waves = 2; return occupancy_grid<R, 2, true>(M, cu_count, K, set_attr);
-        default: *waves = 4; return occupancy_grid<R, 4, false>(M, cu_count, K, set_attr);
+int grid_for(int M, int S, int cu_count, int K, bool set_attr, int *waves) {
+    if (use_partial<R>(M, S, K)) {
+        *waves = 1;
+        return occupancy_grid<R, 1, true>(M, cu_count, K, set_attr);
     }
+    *waves = 4;
+    return occupancy_grid<R, 4, false>(M, cu_count, K, set_attr);
 }
 
 template <int R>
 hipError_t launch_r(const DevPtrs &d, const AdjLaunch &a, int cu_count, hipStream_t st) {
     int waves = 4;
-    const int full = grid_for<R>(a.M, cu_count, a.K, true, &waves);
+    const int full = grid_for<R>(a.M, a.S, cu_count, a.K, true, &waves);
     const int grid = persistent_grid(full, tile_bound(a.S, a.K, false, TILE), waves, a.K, a.max_grid);
     if (grid * waves > a.seg_slots) return hipErrorInvalidValue;
-    switch (pick_variant<R>(a.M)) {
-        case 0:
-            k_adj_mfma<R, 4, true><<<grid, 4 * WAVE, adj_lds_bytes<R, 4, true>(a.M), st>>>(d, a);
-            break;
-        case 1:
-            k_adj_mfma<R, 2, true><<<grid, 2 * WAVE, adj_lds_bytes<R, 2, true>(a.M), st>>>(d, a);
-            break;
-        default:
-            k_adj_mfma<R, 4, false><<<grid, 4 * WAVE, adj_lds_bytes<R, 4, false>(a.M), st>>>(d, a);
+    if (use_partial<R>(a.M, a.S, a.K)) {
+        if (a.slab == nullptr) return hipErrorInvalidValue;
+        k_adj_mfma<R, 1, true><<<grid, WAVE, adj_lds_bytes<R, 1, true>(a.M), st>>>(d, a);
+    } else {
+        if (a.B64 == nullptr) return hipErrorInvalidValue;
+        k_adj_mfma<R, 4, false><<<grid, 4 * WAVE, adj_lds_bytes<R, 4, false>(a.M), st>>>(d, a);
     }
     return hipGetLastError();
 }
@@ -380,13 +437,23 @@ hipError_t launch_r(const DevPtrs &d, const AdjLaunch &a, int cu_count, hipStrea
 
 bool adj_mfma_supported(int NP) { return NP == 16 || NP == 32 || NP == 48 || NP == 64; }
 
-int adj_mfma_slots(int NP, int M, int K, int cu_count) {
+bool adj_mfma_slab(int NP, int M, int S, int K) {
+    switch (NP / 16) {
+        case 1: return use_partial<1>(M, S, K);
+        case 2: return use_partial<2>(M, S, K);
+        case 3: return use_partial<3>(M, S, K);
+        case 4: return use_partial<4>(M, S, K);
+        default: return false;
+    }
+}
+
+int adj_mfma_slots(int NP, int M, int S, int K, int cu_count) {
     int waves = 4, grid = 0;
     switch (NP / 16) {
-        case 1: grid = grid_for<1>(M, cu_count, K, true, &waves); break;
-        case 2: grid = grid_for<2>(M, cu_count, K, true, &waves); break;
-        case 3: grid = grid_for<3>(M, cu_count, K, true, &waves); break;
-        case 4: grid = grid_for<4>(M, cu_count, K, true, &waves); break;
+        case 1: grid = grid_for<1>(M, S, cu_count, K, true, &waves); break;
+        case 2: grid = grid_for<2>(M, S, cu_count, K, true, &waves); break;
+        case 3: grid = grid_for<3>(M, S, cu_count, K, true, &waves); break;
+        case 4: grid = grid_for<4>(M, S, cu_count, K, true, &waves); break;
         default: return 0;
     }
     return grid * waves;

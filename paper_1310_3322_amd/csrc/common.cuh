@@ -89,6 +89,63 @@ __device__ __forceinline__ int opaque(int v) {
 __device__ __forceinline__ int frexp_exp(float x) { return __builtin_amdgcn_frexp_expf(x); }
 __device__ __forceinline__ float ldexp_f(float x, int e) { return __builtin_amdgcn_ldexpf(x, e); }
 
+// ---- Order-independent count sums.  Expected counts are added as 64-bit
+// fixed-point integers, v -> round(v 2^F): integer addition is associative, so
+// a sum does not depend on the order in which waves and workgroups add to it,
+// and the counts are the same from run to run.  Every count is bounded by
+// sum_s |w_s| T_s <= S max_len max_s |w_s| (each step adds at most |w_s| to an
+// entry: gamma and xi are probabilities), so with
+//   F = 62 - ceil(log2 S) - ceil(log2 max_len) - e,  max_s |w_s| < 2^e,
+// no sum reaches 2^62 and the resolution is 2^-62 of that bound.
+__device__ __forceinline__ int ceil_log2_u(uint32_t x) { return x <= 1 ? 0 : 32 - __clz(x - 1); }
+
+__device__ __forceinline__ int fixed_exponent(uint32_t wmax_bits, int S, int max_len) {
+    const float wmax = __uint_as_float(wmax_bits);
+    if (!(wmax > 0.0f) || !(wmax <= 3.0e38f)) return 0;  // no weight to add, or none finite
+    return 62 - ceil_log2_u((uint32_t)S) - ceil_log2_u((uint32_t)max(max_len, 1)) - frexp_exp(wmax);
+}
+
+// round(v 2^F) as a two's-complement 64-bit integer, for |v 2^F| < 2^62: the
+// rounded magnitude x splits exactly into x = hi 2^32 + lo with hi = floor(x 2^-32)
+// and 0 <= lo < 2^32 (lo keeps only bits of x, at most 24 of them, so it is a
+// float without rounding); the sign is applied to the 64-bit result.
+__device__ __forceinline__ unsigned long long to_fixed(float v, int F) {
+    const float x = __builtin_rintf(ldexp_f(__builtin_fabsf(v), F));
+    const float hf = __builtin_floorf(x * 2.3283064365386963e-10f);  // 2^-32
+    const uint32_t lo = (uint32_t)__builtin_fmaf(hf, -4294967296.0f, x);
+    const unsigned long long u = ((unsigned long long)(uint32_t)hf << 32) | lo;
+    return v < 0.0f ? (unsigned long long)0 - u : u;
+}
+
+__device__ __forceinline__ float from_fixed(unsigned long long x, int F) {
+    return (float)__builtin_ldexp((double)(long long)x, -F);
+}
+
+// Adds v to a fixed-point count; a non-finite v (from a non-finite weight) marks
+// the model instead, whose counts then read NaN.
+__device__ __forceinline__ void add_fixed(unsigned long long *dst, float v, int F, int32_t *nan_flag) {
+    if (v == 0.0f) return;
+    if (__builtin_isfinite(v))
+        atomicAdd(dst, to_fixed(v, F));
+    else
+        atomicOr(nan_flag, 1);
+}
+
+// Slot order of repeated symbols in one step of a 16-sequence tile: each of the
+// wave's lanes of slot `sl` sets bit sl in the entry of its symbol in `tab`
+// (an LDS atomic OR, order-independent), reads the entry back and clears it;
+// returns how many lower slots share the symbol (0 for the first occurrence).
+// Adds to an LDS partial then go in rounds of equal rank, so the result does
+// not depend on how the LDS serialises lanes that collide.
+__device__ __forceinline__ int slot_rank(uint32_t *tab, int sym, int sl) {
+    atomicOr(&tab[sym], 1u << sl);
+    wave_lds_sync();
+    const uint32_t m = tab[sym];
+    wave_lds_sync();
+    tab[sym] = 0u;
+    return __popc(m & ((1u << sl) - 1u));
+}
+
 // Sequence checks shared by all kernels: returns true when sequence s is
 // malformed (length outside [0, max_len], range outside the symbol array).
 __device__ __forceinline__ bool seq_bad(int32_t T, int64_t off, int32_t max_len, int64_t total) {

@@ -11,8 +11,8 @@ namespace hmm {
 struct Layout {
     size_t err;      // int32 first bad sequence (INT32_MAX = none)
     size_t queue;    // int32 [K] per-model tile queue heads
-    size_t hist;     // int32 [nbins] length histogram
-    size_t cursor;   // int32 [nbins] scatter cursors
+    size_t hist;     // int32 [nbins][plan_nchunks] per-chunk bin counts, scanned into placement cursors
+    size_t scanb;    // int32 [ceil(nbins * plan_nchunks / 8192)] block sums of that scan
     size_t gstart;   // int32 [groups + 1] start of each group in perm
     size_t perm;     // int32 [S] sequence ids, grouped by model, longest first
     size_t bt;       // float [K][M][NP] transposed, zero-padded emission matrix
@@ -21,7 +21,13 @@ struct Layout {
     size_t ckexp;    // int32 [S][nck] exponents of the checkpointed steps
     size_t flag;     // int32 [S] per sorted position: sequence has no finite likelihood
     size_t seg;      // float [slots][seg_stride] segment recompute buffers (gradient)
-    size_t nbt;      // float [K][M][NP] symbol-major emission counts (cooperative gradient)
+    size_t pi64;     // uint64 [K][N] fixed-point initial counts (gradient)
+    size_t A64;      // uint64 [K][N][N] fixed-point transition counts (gradient)
+    size_t B64;      // uint64 [K][M][NP] fixed-point emission counts (gradient, global-count kernels)
+    size_t slab;     // float [slab_slots][M][NP] per-tile emission partials (gradient, LDS-partial kernels)
+    size_t nanflag;  // int32 [K] models with a non-finite count (gradient)
+    size_t wmax;     // uint32 bits of max_s |w_s| (gradient)
+    int32_t slab_on;     // the gradient's backward kernel writes per-tile partials into the slab
     size_t frag;     // float4 [K][2][NP^2 / 4] streamed MFMA fragments (cooperative gradient, NP > 128)
     size_t delta;    // float [total][NP] Viterbi delta rows (bt then holds ln B transposed), then 64 spare floats
     size_t lnat;     // float [K][N][NP] ln A transposed (Viterbi, NP > 64)
@@ -30,6 +36,8 @@ struct Layout {
     int32_t kind;        // kernel family of the call (HMM_KERNEL_*, after the tuning table)
     int32_t wg_per_cu;   // cap on resident workgroups per CU of persistent launches (0: none)
     size_t total;
+    int32_t plan_chunk;    // sequences per chunk of the stable counting sort
+    int32_t plan_nchunks;  // chunks of the stable counting sort
     int32_t nck;         // checkpoints per sequence slot
     int32_t seg_slots;   // persistent waves of the gradient kernel
     int64_t seg_stride;  // floats per segment slot
@@ -68,13 +76,17 @@ struct DevPtrs {
 };
 
 // planner.hip
+// Entries of the planner's [bins][chunks] count matrix are capped at this (the
+// chunks grow beyond PLAN_SUB sequences when the bins are many).
+constexpr int64_t PLAN_MATRIX_MAX = (int64_t)1 << 24;
+void plan_chunking(int S, int64_t nbins, int *chunk, int *nchunks);
 void launch_plan(const DevPtrs &d, int K, int S, int groups, int max_len, int64_t total, int nbins,
                  unsigned char *ws, const Layout &L, hipStream_t st);
 void launch_transpose_b(const float *B, float *bt, int K, int N, int M, int NP, hipStream_t st);
 void launch_argmax(const float *ll, int32_t *labels, int S, int K, hipStream_t st);
-void launch_counts_transpose(const float *nbt, float *cnt_B, int K, int N, int M, int NP, hipStream_t st);
 void launch_fill_f32(float *p, size_t n, float v, hipStream_t st);
 void launch_fill_i32(int32_t *p, size_t n, int32_t v, hipStream_t st);
+void launch_copy_i32(const int32_t *src, int32_t *dst, size_t n, hipStream_t st);
 void launch_softmax_rows(const float *z, float *p, int64_t rows, int cols, hipStream_t st);
 void launch_logit_grad(const float *n, const float *p, float *g, int64_t rows, int cols, hipStream_t st);
 void launch_reestimate_rows(const float *n, const float *old, float *out, int64_t rows, int cols, hipStream_t st);
@@ -137,21 +149,41 @@ struct AdjLaunch {
     int64_t seg_stride;
     int seg_slots;
     const float *weight;
-    float *cnt_pi, *cnt_A, *cnt_B;
-    float *nbt;         // [K][M][NP] zeroed symbol-major emission counts (cooperative kernel)
+    // Counts, as order-independent 64-bit fixed-point sums (zeroed before the launch):
+    unsigned long long *pi64;  // [K][N]
+    unsigned long long *A64;   // [K][N][N] n_A = A o C, added tile by tile
+    unsigned long long *B64;   // [K][M][NP] symbol-major emission counts (global-count kernels)
+    float *slab;               // [tiles][M][NP] per-tile emission partials (LDS-partial kernels)
+    int32_t *nanflag;          // [K] set when a model received a non-finite count
+    const uint32_t *wmax;      // bits of max_s |w_s| (the fixed-point scale)
     const float *frag;  // pre-arranged fragments when the cooperative kernel streams them
     int max_grid;       // cap on the persistent grid (0: occupancy limit)
 };
+// Slab slot of tile `tile` of the model whose group starts at gbeg: unique, below
+// S / 16 + K + 1 (the group's tiles follow floor(gbeg / 16) + k).
+__host__ __device__ inline int64_t slab_slot(int gbeg, int k, int tile) { return (int64_t)(gbeg / 16) + k + tile; }
+inline int64_t slab_slots(int S, int K) { return (int64_t)S / 16 + K + 1; }
 bool adj_mfma_supported(int NP);
+// Whether the backward of a shape accumulates emission counts in an LDS partial
+// flushed per tile into the slab (true) or in the global fixed-point counts.
+bool adj_mfma_slab(int NP, int M, int S, int K);
+bool adj_coop_slab(int NP, int M, int S, int K);
+// Largest slab of per-tile emission partials a call reserves; beyond it the
+// kernels add emission counts to the global fixed-point sums instead.
+constexpr int64_t SLAB_MAX_BYTES = (int64_t)1 << 30;
+// Final counts: n_pi and n_A from the fixed-point sums, n_B from the slab (tiles of
+// each model summed in tile order) or the fixed-point sums, NaN for flagged models.
+void launch_counts_finish(const AdjLaunch &a, bool slab, float *cnt_pi, float *cnt_A, float *cnt_B, hipStream_t st);
+void launch_weight_max(const float *w, int S, uint32_t *wmax, hipStream_t st);
 // adj_coop.hip: cooperative-tile backward (one wave per 16-state block)
 bool adj_coop_supported(int NP);
 bool adj_coop_streams(int NP);  // fragments streamed from the workspace (launch_coop_frags first)
 void launch_coop_frags(const float *A, float *frag, int K, int N, int NP, hipStream_t st);
-int adj_coop_slots(int NP, int M, int K, int cu_count);
-int64_t adj_coop_seg_stride(int NP, int M, int max_len);
-bool adj_coop_pipelined(int NP, int M);  // the two-group pipelined backward serves this shape
+int adj_coop_slots(int NP, int M, int S, int K, int cu_count);
+int64_t adj_coop_seg_stride(int NP, int M, int S, int K, int max_len);
+bool adj_coop_pipelined(int NP, int M, int S, int K);  // the two-group pipelined backward serves this shape
 hipError_t launch_adj_coop(const DevPtrs &d, const AdjLaunch &a, int cu_count, hipStream_t st);
-int adj_mfma_slots(int NP, int M, int K, int cu_count);
+int adj_mfma_slots(int NP, int M, int S, int K, int cu_count);
 int64_t adj_mfma_seg_stride(int NP, int max_len);
 hipError_t launch_adj_mfma(const DevPtrs &d, const AdjLaunch &a, int cu_count, hipStream_t st);
 

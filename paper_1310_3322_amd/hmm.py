@@ -23,7 +23,7 @@ STATUS = {0: "HMM_OK", -1: "HMM_ERR_NULL", -2: "HMM_ERR_SHAPE", -3: "HMM_ERR_WOR
 OP_FORWARD, OP_CLASSIFY, OP_GRAD, OP_VITERBI = 0, 1, 2, 3
 KERNEL_AUTO, KERNEL_PLAIN, KERNEL_BATCHED, KERNEL_TILE16, KERNEL_TILE32, KERNEL_COOP, KERNEL_SCAN = 0, 1, 2, 3, 4, 5, 6
 EXPORTS = ("hmm_workspace_size", "hmm_forward_loglik", "hmm_classify", "hmm_classify_noalloc", "hmm_forward_backward_grad",
-           "hmm_viterbi", "hmm_reestimate_rows", "hmm_softmax_rows", "hmm_logit_grad", "hmm_workspace_error", "hmm_select_kernel",
+           "hmm_viterbi", "hmm_plan_order", "hmm_reestimate_rows", "hmm_softmax_rows", "hmm_logit_grad", "hmm_workspace_error", "hmm_select_kernel",
            "hmm_tune_key_of", "hmm_tune_set", "hmm_tune_get", "hmm_tune_clear", "hmm_call_kernel",
            "hmm_profile_enable", "hmm_profile_read", "hmm_status_string")
 TUNE_MAX, TUNE_MAX_WG = 256, 64
@@ -87,6 +87,8 @@ def load_library(path: str = LIB_PATH):
     lib.hmm_forward_backward_grad.argtypes = [BP, QP, P, P, P, P, P, ctypes.c_int32, P, ctypes.c_size_t, P]
     lib.hmm_viterbi.restype = st
     lib.hmm_viterbi.argtypes = [BP, QP, P, P, P, ctypes.c_size_t, P]
+    lib.hmm_plan_order.restype = st
+    lib.hmm_plan_order.argtypes = [BP, QP, ctypes.c_int32, P, P, P, ctypes.c_size_t, P]
     lib.hmm_reestimate_rows.restype = st
     lib.hmm_reestimate_rows.argtypes = [P, P, P, ctypes.c_int64, ctypes.c_int32, P]
     lib.hmm_softmax_rows.restype = st
@@ -344,6 +346,28 @@ def viterbi(p: Problem, score: Optional[torch.Tensor] = None, path: Optional[tor
                                     ws.numel(), _stream(stream))
     _check("hmm_viterbi", rc)
     return score, path
+
+
+def plan_order(p: Problem, op: int, all_pairs: Optional[bool] = None, ws: Optional[torch.Tensor] = None,
+               stream=None):
+    """The batched kernels' work list for `op`: (order [S], group_start [groups + 1]) int32.
+
+    all_pairs (forward only): score every sequence against every model (one group);
+    default: own model when the problem has model_of_seq."""
+    own = p.model_of_seq is not None if all_pairs is None else not all_pairs
+    if op == OP_CLASSIFY:
+        own = False
+    b = p.batch if own else p.batch_without_models()
+    groups = p.K if own else 1
+    dev = p.pi.device
+    order = torch.empty(p.S, dtype=torch.int32, device=dev)
+    gstart = torch.empty(groups + 1, dtype=torch.int32, device=dev)
+    if ws is None:
+        ws = p.workspace(op, b)
+    rc = load_library().hmm_plan_order(ctypes.byref(p.bank), ctypes.byref(b), int(op), _ptr(order), _ptr(gstart),
+                                       _ptr(ws), ws.numel(), _stream(stream))
+    _check("hmm_plan_order", rc)
+    return order, gstart
 
 
 def reestimate_rows(n: torch.Tensor, old: torch.Tensor, out: Optional[torch.Tensor] = None,
