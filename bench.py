@@ -230,13 +230,26 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-extra", action="store_true", help="skip the plain and fwd+bwd legs")
+    ap.add_argument("--no-extra", action="store_true", help="skip every leg but the recognition step")
+    ap.add_argument("--legs", default="all",
+                    help="comma-separated legs after the recognition step: plain, grad (c4 forward + adjoint), "
+                         "large (c5 forward and forward + adjoint), large_viterbi (c5 Viterbi), latency (c1, c2), "
+                         "viterbi (c3 Viterbi), em, graph, h2d; default all")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run 4 device copies of 512 MiB (reference kernel for HBM counter scaling)")
     ap.add_argument("--no-tune", action="store_true", help="keep the built-in kernel heuristics (no autotuning)")
     ap.add_argument("--tune-cache", default=None,
                     help="JSON tuning cache: install the choices stored there instead of tuning, store new ones")
     args = ap.parse_args()
+    legs = {"plain", "grad", "large", "large_viterbi", "latency", "viterbi", "em", "graph", "h2d"}
+    chosen = set() if args.no_extra else (legs if args.legs == "all" else set(args.legs.split(",")))
+    if chosen - legs:
+        print(f"unknown legs: {sorted(chosen - legs)}", file=sys.stderr)
+        sys.exit(2)
+
+    def want(leg):
+        return leg in chosen
+
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path (sequences would be "
               "sharded over GPUs, each running the same launch on its share).", file=sys.stderr)
@@ -313,15 +326,16 @@ def main():
                          "sum_T": int(w.lengths.sum()), "state_steps_per_step": units},
               "roofline": roofline}
 
-    if not args.no_extra:
+    if want("plain"):
         log("plain per-pair kernel on the same workload")
         hmm.select_kernel(hmm.KERNEL_PLAIN)
         psec = time_steps(step, 2, 1, torch)
         hmm.select_kernel(hmm.KERNEL_AUTO)
         result["plain"] = {"value": units / psec, "ms_per_step": psec * 1e3,
                            "speedup_batched_over_plain": psec / sec}
+    w4 = workloads.make_workload("c4") if (want("grad") or want("em")) else None
+    if want("grad"):
         log("forward + adjoint on the gradient workload (8 models, N=64, M=512, 8192 sequences)")
-        w4 = workloads.make_workload("c4")
         p4 = to_dev(w4, torch, own=True)
         autotune("c4_grad", p4, hmm.OP_GRAD)
         ws4 = p4.workspace(hmm.OP_GRAD)
@@ -356,23 +370,26 @@ def main():
             result["fwd_bwd"]["cpu_oracle"] = cpu_oracle_counts(w4)
         del p4, ws4, cnt
 
-        log("the N=256 bank (16 models, M=1024, 16384 sequences): forward, then forward + adjoint")
+    if want("large") or want("large_viterbi"):
+        log("the N=256 bank (16 models, M=1024, 16384 sequences)")
         w5 = workloads.make_workload("c5")
         p5 = to_dev(w5, torch, own=True)
+        u5 = w5.units()
+        ll5 = torch.empty(w5.S, dtype=torch.float32, device="cuda")
+        large = {"workload": "c5: 16 HMMs N=256 M=1024 (A = Dirichlet(0.1) + band of 8), 16384 sequences, "
+                             "T in [256,4096], own model, cooperative kernels"}
+    if want("large"):
+        log("c5 forward, then forward + adjoint")
         autotune("c5_forward", p5, hmm.OP_FORWARD, warmup=0, reps=2)
         ws5 = p5.workspace(hmm.OP_FORWARD)
-        ll5 = torch.empty(w5.S, dtype=torch.float32, device="cuda")
         hmm.profile_enable(True)
         s5 = time_steps(lambda: hmm.forward_loglik(p5, out=ll5, ws=ws5), 3, 1, torch)
         k5_ms, k5_n = hmm.profile_read(hmm.PROF_FWD_BATCHED)
         hmm.profile_enable(False)
         del ws5
-        u5 = w5.units()
-        large = {"workload": "c5: 16 HMMs N=256 M=1024 (A = Dirichlet(0.1) + band of 8), 16384 sequences, "
-                             "T in [256,4096], own model, cooperative kernels",
-                 "value": u5 / s5, "unit": "state-steps/s", "ms_per_step": s5 * 1e3,
-                 "kernel_ms": k5_ms / max(k5_n, 1),
-                 "frac_fp32_peak": 2.0 * u5 / (k5_ms / max(k5_n, 1) / 1e3) / 1e12 / FP32_PEAK_TFLOPS}
+        large.update({"value": u5 / s5, "unit": "state-steps/s", "ms_per_step": s5 * 1e3,
+                      "kernel_ms": k5_ms / max(k5_n, 1),
+                      "frac_fp32_peak": 2.0 * u5 / (k5_ms / max(k5_n, 1) / 1e3) / 1e12 / FP32_PEAK_TFLOPS})
         autotune("c5_grad", p5, hmm.OP_GRAD, warmup=0, reps=2)
         ws5g = p5.workspace(hmm.OP_GRAD)
         cnt5 = (torch.empty((w5.K, w5.N), device="cuda"), torch.empty((w5.K, w5.N, w5.N), device="cuda"),
@@ -389,7 +406,8 @@ def main():
                             "fwd_kernel_ms": f5_ms / max(f5_n, 1), "adj_kernel_ms": a5_ms / max(a5_n, 1),
                             "frac_fp32_peak": 6.0 * u5 / gs5 / 1e12 / FP32_PEAK_TFLOPS}
         del ws5g, cnt5
-        # Viterbi on the same bank and sequences (workgroup decoder: 256 states)
+    if want("large_viterbi"):
+        log("c5 Viterbi (workgroup decoder: 256 states)")
         wsv5 = p5.workspace(hmm.OP_VITERBI)
         scv5 = torch.empty(w5.S, dtype=torch.float32, device="cuda")
         pav5 = torch.empty(w5.total_symbols, dtype=torch.int32, device="cuda")
@@ -406,9 +424,12 @@ def main():
                             "roofline": {"bound": "alu", "achieved": round(2.0 * u5 / kv5_s / 1e12, 3),
                                          "peak": VALU_PEAK_TOPS, "unit": "Tops/s",
                                          "frac": round(2.0 * u5 / kv5_s / 1e12 / VALU_PEAK_TOPS, 4)}}
+        del wsv5, scv5, pav5
+    if want("large") or want("large_viterbi"):
         result["large_states"] = large
-        del p5, wsv5, scv5, pav5
+        del p5
 
+    if want("latency"):
         log("latency-bound workloads c1 and c2")
         hmm.select_kernel(hmm.KERNEL_AUTO)
         lat = {}
@@ -463,6 +484,7 @@ def main():
                      "state_steps_per_s_graph": w2.units() / (g2 / 1e3)}
         result["latency"] = lat
 
+    if want("viterbi"):
         log("Viterbi decoding of the c3 sequences with their owner models")
         p3o = to_dev(w, torch, own=True)
         autotune("c3_viterbi", p3o, hmm.OP_VITERBI, warmup=0, reps=2)
@@ -487,6 +509,7 @@ def main():
                                           "frac": round(2.0 * uv / kv_s / 1e12 / VALU_PEAK_TOPS, 4)}}
         del p3o, wsv, scv, pav
 
+    if want("em"):
         log("one Baum-Welch iteration on c4")
         p4e = to_dev(w4, torch, own=True)
         hmm.baum_welch(p4e, 1)
@@ -496,12 +519,13 @@ def main():
                         "value": w4.units() / se, "unit": "state-steps/s", "ms_per_iteration": se * 1e3}
         del p4e
 
-    if not args.no_extra:
+    if want("graph"):
         gs = graph_stats(step, 20, torch)
         result["graph"] = {"ms_per_step": gs["median_ms"], "min_ms": gs["min_ms"], "mean_ms": gs["mean_ms"],
                            "replays": gs["replays"],
                            "note": "the same recognition step captured once as a HIP graph: median, min and mean "
                                    "of 20 replays, each timed with its own events"}
+    if want("h2d"):
         h2d = h2d_copy(w, torch)
         h2d["note"] = ("bank + symbols + offsets + lengths of the recognition workload, pinned host memory to HBM "
                        "(not part of `value`, whose inputs are resident in HBM)")

@@ -164,7 +164,11 @@ hmm_status hmm_classify_noalloc(const hmm_bank *bank, const hmm_batch *batch, in
  *            bank, batch and ws left behind (loglik untouched, may be NULL).
  * The forward pass keeps alpha every ceil(sqrt(T)) steps (T the longest
  * sequence of the length-sorted tile of 16 sequences) and the backward pass
- * recomputes each segment, so memory grows with sqrt(T). */
+ * recomputes each segment, so memory grows with sqrt(T).
+ * The counts are deterministic: the same bank, batch and weights give the same
+ * counts bit for bit, whatever the tuning choice or the order in which the
+ * device runs the work.  A non-finite weight makes every count of its
+ * sequence's model NaN. */
 hmm_status hmm_forward_backward_grad(const hmm_bank *bank, const hmm_batch *batch,
                                      const float *seq_weight, float *loglik, float *cnt_pi,
                                      float *cnt_A, float *cnt_B, int32_t phase, void *ws,
@@ -241,9 +245,9 @@ hmm_status hmm_select_kernel(int32_t kind);
  * applies the same entry, so query it after tuning (a choice can need a larger
  * workspace; a call then returns HMM_ERR_WORKSPACE rather than run).  The table
  * lives in host memory, process-wide, at most HMM_TUNE_MAX entries; calls read
- * it on the host only, so they stay capturable into graphs.  Entries change no
- * result beyond the summation order of count accumulation: every choice runs
- * kernels held to the same accuracy.  Thread-safe; a call that races with a
+ * it on the host only, so they stay capturable into graphs.  Every choice runs
+ * kernels held to the same accuracy; the grid cap changes no result, the
+ * family may change the rounding of log-likelihoods within that accuracy.  Thread-safe; a call that races with a
  * change of its own entry takes either the old or the new choice. */
 #define HMM_TUNE_MAX 256
 #define HMM_TUNE_MAX_WG 64

@@ -239,18 +239,21 @@ Layout make_layout(const hmm_bank *b, const hmm_batch *q, int op) {
     L.kind = cc.kind;
     L.wg_per_cu = cc.wg_per_cu;
     L.err = take(64);
-    if (op == HMM_OP_CLASSIFY) L.ll = take((size_t)S * K * sizeof(float));
+    // all pairs: staging buffer of the sorted-position values (or the rows, without a caller buffer)
+    if (op == HMM_OP_CLASSIFY || (op == HMM_OP_FORWARD && q->model_of_seq == nullptr))
+        L.ll = take((size_t)S * K * sizeof(float));
     if (op == HMM_OP_GRAD) L.ll = take((size_t)S * sizeof(float));
     if (batched_capable(b, q, op)) {
         const int groups = plan_groups(b, q, op);
         const size_t nbins = (size_t)groups * ((size_t)q->max_len + 1);
-        L.queue = take((size_t)2 * K * sizeof(int32_t));
+        L.queue = take((size_t)(queue_heads(K) + K) * sizeof(int32_t));  // forward slices, then the adjoint
         plan_chunking(S, (int64_t)nbins, &L.plan_chunk, &L.plan_nchunks);
         L.hist = take(nbins * (size_t)L.plan_nchunks * sizeof(int32_t));
         L.scanb = take((nbins * (size_t)L.plan_nchunks + 8191) / 8192 * sizeof(int32_t));
         L.gstart = take((size_t)(groups + 1) * sizeof(int32_t));
         L.perm = take((size_t)S * sizeof(int32_t));
         L.bt = take((size_t)K * M * NP * sizeof(float));
+        L.bmin = take((size_t)K * sizeof(uint32_t));
         if (op == HMM_OP_VITERBI) {
             L.delta = take(((size_t)q->total_symbols * NP + 64) * sizeof(float));
             if (NP > 64) L.lnat = take((size_t)K * b->N * NP * sizeof(float));
@@ -373,8 +376,14 @@ hmm_status forward_family(const hmm_bank *b, const hmm_batch *q, int op, int kin
     return HMM_OK;
 }
 
-hmm_status run_forward(const hmm_bank *b, const hmm_batch *q, int op, float *out, unsigned char *ws, const Layout &L,
-                       hipStream_t st) {
+// The forward of a call, then, for recognition, the labels.  out: [S][K] all
+// pairs or [S]; may be NULL for recognition (labels only).  The length-sorted
+// families write all-pairs values by sorted position into the workspace's
+// staging buffer (rows of each tile contiguous) and one pass writes the
+// caller's rows and the labels from it; the plain and time-parallel kernels
+// write the rows directly (into the staging buffer when out is NULL).
+hmm_status run_forward(const hmm_bank *b, const hmm_batch *q, int op, float *out, int32_t *labels, unsigned char *ws,
+                       const Layout &L, hipStream_t st) {
     const bool all_pairs = (op == HMM_OP_CLASSIFY) || q->model_of_seq == nullptr;
     int fam = HMM_KERNEL_PLAIN;
     hmm_status rc = forward_family(b, q, op, L.kind, &fam);
@@ -383,13 +392,20 @@ hmm_status run_forward(const hmm_bank *b, const hmm_batch *q, int op, float *out
     DevPtrs d = dev_ptrs(b, q, !all_pairs);
     int32_t *err = (int32_t *)(ws + L.err);
     const int K = b->K, N = b->N, M = b->M, S = q->S;
+    float *staging = all_pairs ? (float *)(ws + L.ll) : nullptr;
+    float *direct = out ? out : staging;  // target of the kernels that write rows themselves
+    auto finish_direct = [&](hipError_t e) {
+        if (e != hipSuccess) return HMM_ERR_HIP;
+        if (labels) launch_argmax(direct, labels, S, K, st);
+        return hipGetLastError() == hipSuccess ? HMM_OK : HMM_ERR_HIP;
+    };
     if (!batched) {
         launch_fill_i32(err, 1, INT32_MAX, st);
         const int pr = prof_begin(st, HMM_PROF_FWD_PLAIN);
-        const hipError_t e = launch_fwd_plain(d, K, N, M, S, all_pairs ? 1 : 0, q->max_len, q->total_symbols, out,
+        const hipError_t e = launch_fwd_plain(d, K, N, M, S, all_pairs ? 1 : 0, q->max_len, q->total_symbols, direct,
                                               err, st);
         prof_end(st, pr);
-        return e == hipSuccess ? HMM_OK : HMM_ERR_HIP;
+        return finish_direct(e);
     }
     const int NP = padded_states(N);
     const int cus = device_cu_count();
@@ -407,7 +423,7 @@ hmm_status run_forward(const hmm_bank *b, const hmm_batch *q, int op, float *out
             f.max_len = q->max_len;
             f.total = q->total_symbols;
             f.err = err;
-            f.ll = out;
+            f.ll = direct;
             const int64_t pairs = all_pairs ? (int64_t)S * K : (int64_t)S;
             ScanWs sw;
             sw.nch = L.scan_nch;
@@ -417,13 +433,13 @@ hmm_status run_forward(const hmm_bank *b, const hmm_batch *q, int op, float *out
             const int pr = prof_begin(st, HMM_PROF_FWD_BATCHED);
             const hipError_t e = launch_fwd_scan(d, f, sw, st);
             prof_end(st, pr);
-            return e == hipSuccess ? HMM_OK : HMM_ERR_HIP;
+            return finish_direct(e);
         }
     }
     const int groups = all_pairs ? 1 : K;
     const int nbins = groups * (q->max_len + 1);
     launch_plan(d, K, S, groups, q->max_len, q->total_symbols, nbins, ws, L, st);
-    launch_transpose_b(b->B, (float *)(ws + L.bt), K, N, M, NP, st);
+    launch_transpose_b(b->B, (float *)(ws + L.bt), K, N, M, NP, st, (uint32_t *)(ws + L.bmin));
     if (hipGetLastError() != hipSuccess) return HMM_ERR_HIP;
     FwdLaunch f;
     memset(&f, 0, sizeof(f));
@@ -441,6 +457,8 @@ hmm_status run_forward(const hmm_bank *b, const hmm_batch *q, int op, float *out
     f.err = err;
     f.bt = (const float *)(ws + L.bt);
     f.ll = out;
+    f.llpos = staging;
+    f.bmin = (const uint32_t *)(ws + L.bmin);
     f.max_grid = max_grid(L.wg_per_cu, cus);
     if (S == 0) return HMM_OK;
     const int pr = prof_begin(st, HMM_PROF_FWD_BATCHED);
@@ -448,7 +466,9 @@ hmm_status run_forward(const hmm_bank *b, const hmm_batch *q, int op, float *out
                          : fam == HMM_KERNEL_TILE32 ? launch_fwd_mfma32(d, f, cus, st)
                                                     : launch_fwd_mfma(d, f, cus, st);
     prof_end(st, pr);
-    return e == hipSuccess ? HMM_OK : HMM_ERR_HIP;
+    if (e != hipSuccess) return HMM_ERR_HIP;
+    if (all_pairs) launch_rows_from_sorted(staging, f.perm, S, K, out, labels, st);
+    return hipGetLastError() == hipSuccess ? HMM_OK : HMM_ERR_HIP;
 }
 
 }  // namespace
@@ -469,7 +489,7 @@ hmm_status hmm_forward_loglik(const hmm_bank *bank, const hmm_batch *batch, floa
     if (batch->S > 0 && !loglik) return HMM_ERR_NULL;
     const Layout L = make_layout(bank, batch, HMM_OP_FORWARD);
     if ((rc = check_ws(ws, ws_bytes, L)) != HMM_OK) return rc;
-    return run_forward(bank, batch, HMM_OP_FORWARD, loglik, (unsigned char *)ws, L, stream);
+    return run_forward(bank, batch, HMM_OP_FORWARD, loglik, nullptr, (unsigned char *)ws, L, stream);
 }
 
 hmm_status hmm_classify_noalloc(const hmm_bank *bank, const hmm_batch *batch, int32_t *labels,
@@ -490,12 +510,7 @@ hmm_status hmm_classify(const hmm_bank *bank, const hmm_batch *batch, int32_t *l
     if (batch->S > 0 && !labels) return HMM_ERR_NULL;
     const Layout L = make_layout(bank, batch, HMM_OP_CLASSIFY);
     if ((rc = check_ws(ws, ws_bytes, L)) != HMM_OK) return rc;
-    unsigned char *w = (unsigned char *)ws;
-    float *ll = loglik_opt ? loglik_opt : (float *)(w + L.ll);
-    rc = run_forward(bank, batch, HMM_OP_CLASSIFY, ll, w, L, stream);
-    if (rc != HMM_OK) return rc;
-    launch_argmax(ll, labels, batch->S, bank->K, stream);
-    return hipGetLastError() == hipSuccess ? HMM_OK : HMM_ERR_HIP;
+    return run_forward(bank, batch, HMM_OP_CLASSIFY, loglik_opt, labels, (unsigned char *)ws, L, stream);
 }
 
 hmm_status hmm_forward_backward_grad(const hmm_bank *bank, const hmm_batch *batch, const float *seq_weight,
@@ -559,7 +574,7 @@ hmm_status hmm_forward_backward_grad(const hmm_bank *bank, const hmm_batch *batc
     if (!slab) launch_fill_i32((int32_t *)(w + L.B64), (size_t)2 * K * M * NP, 0, stream);
     launch_fill_i32((int32_t *)(w + L.nanflag), (size_t)K, 0, stream);
     launch_weight_max(seq_weight, S, (uint32_t *)(w + L.wmax), stream);
-    int32_t *queue2 = (int32_t *)(w + L.queue) + K;
+    int32_t *queue2 = (int32_t *)(w + L.queue) + queue_heads(K);
     launch_fill_i32(queue2, (size_t)K, 0, stream);
     if (hipGetLastError() != hipSuccess) return HMM_ERR_HIP;
     AdjLaunch a;
@@ -624,7 +639,7 @@ hmm_status hmm_viterbi(const hmm_bank *bank, const hmm_batch *batch, float *scor
     launch_log_transpose_b(bank->B, (float *)(w + L.bt), K, N, M, NP, stream);
     // ln A transposed: the same transpose with A's N columns in place of B's M
     if (NP > 64) launch_log_transpose_b(bank->A, (float *)(w + L.lnat), K, N, N, NP, stream);
-    launch_fill_i32((int32_t *)(w + L.queue) + K, (size_t)K, 0, stream);  // the traceback's queues
+    launch_fill_i32((int32_t *)(w + L.queue) + queue_heads(K), (size_t)K, 0, stream);  // the traceback's queues
     if (hipGetLastError() != hipSuccess) return HMM_ERR_HIP;
     VitLaunch v;
     memset(&v, 0, sizeof(v));

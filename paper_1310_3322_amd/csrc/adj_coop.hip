@@ -118,8 +118,9 @@ __global__ void __launch_bounds__(R / BO * WAVE) k_adj_coop(DevPtrs d, AdjLaunch
     __shared__ int32_t symseg[SSEG * TILE];
     __shared__ int32_t tile_sh;
     float *nbl = (float *)smem;  // [M][NP] emission-count partial when NBLDS
-    // [NW][M] words after the partial: per-wave slot masks of the symbols of a step
+    // [2][ceil(M / 2)] words after the partial: slot masks of the symbols of a step
     uint32_t *ranktab = (uint32_t *)(smem + (size_t)a.M * NP * 4);
+    const int m2 = (a.M + 1) / 2;
 
     const int lane = threadIdx.x & (WAVE - 1);
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
@@ -142,9 +143,8 @@ __global__ void __launch_bounds__(R / BO * WAVE) k_adj_coop(DevPtrs d, AdjLaunch
     auto aidx = [&](int tl, int b) { return (((size_t)tl * NW + w) * BO + b) * WAVE + lane; };
     auto sidx = [&](int tl) { return ((size_t)tl * NW + w) * WAVE + lane; };
 
-    const int G = gridDim.x;
-    const int k_first = G >= K ? (int)(blockIdx.x % K) : (int)blockIdx.x;
-    const int k_step = G >= K ? K : G;
+    int k_first, k_step;
+    model_walk(K, (int)gridDim.x, (int)blockIdx.x, &k_first, &k_step);
     for (int k = k_first; k < K; k += k_step) {
         const int gbeg = a.gstart[k], gend = a.gstart[k + 1];
         const int ntiles = (gend - gbeg + TILE - 1) / TILE;
@@ -153,7 +153,7 @@ __global__ void __launch_bounds__(R / BO * WAVE) k_adj_coop(DevPtrs d, AdjLaunch
         if (NBLDS) {
             __syncthreads();
             for (int i = threadIdx.x; i < M * NP; i += blockDim.x) nbl[i] = 0.0f;
-            for (int i = threadIdx.x; i < NW * M; i += blockDim.x) ranktab[i] = 0u;
+            for (int i = threadIdx.x; i < 2 * m2; i += blockDim.x) ranktab[i] = 0u;
             __syncthreads();
         }
         const float *Ak = d.A + (size_t)k * N * N;
@@ -212,6 +212,8 @@ __global__ void __launch_bounds__(R / BO * WAVE) k_adj_coop(DevPtrs d, AdjLaunch
                 int pend_ix[BO] = {};
                 bool pend_on = false;
                 int pend_rank = 0;
+                int rank_prev = 0;      // symbol of the previous backward step (its mask entry is cleared next)
+                bool rank_has_prev = false;
                 auto rmw = [&]() {
 #pragma unroll
                     for (int b = 0; b < BO; ++b) {
@@ -388,8 +390,10 @@ __global__ void __launch_bounds__(R / BO * WAVE) k_adj_coop(DevPtrs d, AdjLaunch
                             // Global counts: one address per step, the lane's states at
                             // immediate offsets from it (per-state addresses were spilled
                             // to scratch, and each reload waited for every outstanding load)
+                            // (the counts' quad-transposed layout puts the four lanes of a
+                            // sequence on four adjacent words in each instruction)
                             const int ib = 16 * r0 + 4 * g;
-                            unsigned long long *dst = B64k + (uint32_t)(ot * NP + ib);
+                            unsigned long long *dst = B64k + (uint32_t)(ot * NP + 16 * r0 + g);
 #pragma unroll
                             for (int b = 0; b < BO; ++b)
 #pragma unroll
@@ -398,7 +402,7 @@ __global__ void __launch_bounds__(R / BO * WAVE) k_adj_coop(DevPtrs d, AdjLaunch
                                     const float gm = wgt * al[b][v] * be[b][v];
                                     const bool fin = __builtin_isfinite(gm);
                                     lane_nan |= !fin;
-                                    if (i < N) atomicAdd(dst + 16 * b + v, to_fixed(fin ? gm : 0.0f, F));
+                                    if (i < N) atomicAdd(dst + 16 * b + 4 * v, to_fixed(fin ? gm : 0.0f, F));
                                     if (t == 0) gpi[b][v] = gm;
                                 }
                         }
@@ -457,7 +461,9 @@ __global__ void __launch_bounds__(R / BO * WAVE) k_adj_coop(DevPtrs d, AdjLaunch
                         if (DEFER) {
                             // this step's emission counts wait in registers for the next step,
                             // with the slot rank of their symbol among the tile's slots
-                            const int rank = slot_rank(ranktab + w * M, ot, sl);
+                            const int rank = slot_rank_shared(ranktab, m2, ot, t & 1, rank_prev, rank_has_prev, sl);
+                            rank_prev = ot;
+                            rank_has_prev = true;
 #pragma unroll
                             for (int b = 0; b < BO; ++b) {
                                 float gm[4];
@@ -489,7 +495,10 @@ __global__ void __launch_bounds__(R / BO * WAVE) k_adj_coop(DevPtrs d, AdjLaunch
                         lds_barrier();
                     }
                 }
-                if (DEFER) flush_pending();
+                if (DEFER) {
+                    flush_pending();
+                    if (rank_has_prev) ranktab[rank_prev >> 1] = 0u;  // the last step (t = 0) used half 0
+                }
                 // this tile's initial counts and n_A = A o C for this wave's rows; the row
                 // base is opaque so that the flush's addresses are formed here and not kept
                 // live across the tile loop
@@ -556,8 +565,9 @@ __global__ void __launch_bounds__(2 * R * WAVE) k_adj_pipe(DevPtrs d, AdjLaunch 
     __shared__ float mlast[TILE];  // m_T of each sequence of the tile
     __shared__ int32_t tile_sh;
     float *nbl = (float *)smem;  // [M][NP] emission-count partial
-    // [R][M] words after the partial: per-wave slot masks of the symbols of a step
+    // [2][ceil(M / 2)] words after the partial: slot masks of the symbols of a step
     uint32_t *ranktab = (uint32_t *)(smem + (size_t)a.M * NP * 4);
+    const int m2 = (a.M + 1) / 2;
 
     const int lane = threadIdx.x & (WAVE - 1);
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
@@ -581,16 +591,15 @@ __global__ void __launch_bounds__(2 * R * WAVE) k_adj_pipe(DevPtrs d, AdjLaunch 
     auto seg_o = [&](int j) { return (int32_t *)(segf + (j & 1) * half + (int64_t)Lcap * R * WAVE * 5); };
     auto sidx = [&](int tl) { return ((size_t)tl * R + w) * WAVE + lane; };
 
-    const int G = gridDim.x;
-    const int k_first = G >= K ? (int)(blockIdx.x % K) : (int)blockIdx.x;
-    const int k_step = G >= K ? K : G;
+    int k_first, k_step;
+    model_walk(K, (int)gridDim.x, (int)blockIdx.x, &k_first, &k_step);
     for (int k = k_first; k < K; k += k_step) {
         const int gbeg = a.gstart[k], gend = a.gstart[k + 1];
         const int ntiles = (gend - gbeg + TILE - 1) / TILE;
         const float *btk = a.bt + (size_t)k * M * NP;
         __syncthreads();
         for (int i = threadIdx.x; i < M * NP; i += blockDim.x) nbl[i] = 0.0f;
-        for (int i = threadIdx.x; i < R * M; i += blockDim.x) ranktab[i] = 0u;
+        for (int i = threadIdx.x; i < 2 * m2; i += blockDim.x) ranktab[i] = 0u;
         __syncthreads();
         const float *Ak = d.A + (size_t)k * N * N;
         if (ntiles > 0) {
@@ -662,6 +671,8 @@ __global__ void __launch_bounds__(2 * R * WAVE) k_adj_pipe(DevPtrs d, AdjLaunch 
                 int pend_ix = 0;
                 bool pend_on = false;
                 int pend_rank = 0;
+                int rank_prev = 0;      // symbol of the previous backward step (its mask entry is cleared next)
+                bool rank_has_prev = false;
                 auto rmw = [&]() {
                     float4 q = *(const float4 *)&nbl[pend_ix];
                     q.x += pend_gm.x;
@@ -766,7 +777,10 @@ __global__ void __launch_bounds__(2 * R * WAVE) k_adj_pipe(DevPtrs d, AdjLaunch 
                                 }
                                 // this step's emission counts wait in registers for the next step,
                                 // with the slot rank of their symbol among the tile's slots
-                                const int rank = slot_rank(ranktab + w * M, ot, sl);
+                                const int rank =
+                                    slot_rank_shared(ranktab, m2, ot, t & 1, rank_prev, rank_has_prev, sl);
+                                rank_prev = ot;
+                                rank_has_prev = true;
                                 float gm[4];
 #pragma unroll
                                 for (int v = 0; v < 4; ++v) {
@@ -868,6 +882,7 @@ __global__ void __launch_bounds__(2 * R * WAVE) k_adj_pipe(DevPtrs d, AdjLaunch 
                 }
                 if (!rec) {
                     flush_pending();
+                    if (rank_has_prev) ranktab[rank_prev >> 1] = 0u;  // the last step (t = 0) used half 0
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
                         const int i = 16 * w + 4 * g + v;
@@ -905,11 +920,10 @@ __global__ void __launch_bounds__(2 * R * WAVE) k_adj_pipe(DevPtrs d, AdjLaunch 
 
 constexpr size_t COOP_LDS_LIMIT = 160 * 1024;
 
-// Dynamic LDS of the partial variant: the [M][NP] partial, then the [waves][M] slot-mask table.
+// Dynamic LDS of the partial variant: the [M][NP] partial, then the [2][ceil(M / 2)] slot-mask table.
 template <int R>
 size_t nb_lds_bytes(int M) {
-    constexpr int BO = adj_bo(R);
-    return ((size_t)M * 16 * R * 4 + (size_t)(R / BO) * M * 4 + 15) / 16 * 16;
+    return ((size_t)M * 16 * R * 4 + (size_t)2 * ((M + 1) / 2) * 4 + 15) / 16 * 16;
 }
 
 // The LDS partial serves one-block waves (up to 128 states) whose partial fits,

@@ -319,7 +319,7 @@ __global__ void __launch_bounds__(WAVES * WAVE) k_adj_mfma(DevPtrs d, AdjLaunch 
                                     for (int v = 0; v < 4; ++v) {
                                         const int i = 16 * r + 4 * g + v;
                                         const float x = __builtin_isfinite(gm[r][v]) ? gm[r][v] : 0.0f;
-                                        if (i < N) atomicAdd(&B64k[(size_t)ot * NP + i], to_fixed(x, F));
+                                        if (i < N) atomicAdd(&B64k[(size_t)ot * NP + quad_t(i)], to_fixed(x, F));
                                     }
                             }
                             if (live && t == 0) {

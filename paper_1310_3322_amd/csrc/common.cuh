@@ -146,6 +146,25 @@ __device__ __forceinline__ int slot_rank(uint32_t *tab, int sym, int sl) {
     return __popc(m & ((1u << sl) - 1u));
 }
 
+// The same for the waves of a cooperative tile, which all hold the tile's 16
+// slots and advance step by step between workgroup barriers: one table for all
+// of them, two 16-bit masks per word (symbols o and o ^ 1), two halves used by
+// alternate steps.  Every wave sets the same bits, so a wave's own OR completes
+// the mask it reads.  The entry of the previous step (other half, which no wave
+// touches during this step) is cleared here; the caller clears the last step's
+// entry after a tile's last step, before the barrier that ends the tile.
+// tab: [2][m2] words, m2 = ceil(M / 2); parity = step index & 1.
+__device__ __forceinline__ int slot_rank_shared(uint32_t *tab, int m2, int sym, int parity, int prev_sym,
+                                                bool has_prev, int sl) {
+    uint32_t *cur = tab + parity * m2;
+    if (has_prev) tab[(parity ^ 1) * m2 + (prev_sym >> 1)] = 0u;
+    const int sh = (sym & 1) << 4;
+    atomicOr(&cur[sym >> 1], 1u << (sh + sl));
+    wave_lds_sync();
+    const uint32_t m = (cur[sym >> 1] >> sh) & 0xffffu;
+    return __popc(m & ((1u << sl) - 1u));
+}
+
 // Sequence checks shared by all kernels: returns true when sequence s is
 // malformed (length outside [0, max_len], range outside the symbol array).
 __device__ __forceinline__ bool seq_bad(int32_t T, int64_t off, int32_t max_len, int64_t total) {

@@ -11,8 +11,8 @@
 // every wave writes its block of alpha~ = u o b and its block's share of the
 // per-sequence sum; after one barrier every wave reads all blocks and all
 // shares, forms c_t and its exponent e_t (identically in every wave, fixed
-// summation order), and scales alpha~ by 2^-e_t while loading the next
-// step's B operand.
+// summation order) while the next step's product runs on the unscaled alpha~,
+// and scales the product by 2^-e_t.
 //
 // Lane layout inside a wave is the one of the 16x16x4 result tile: lane l
 // holds sequence l % 16 and the four states 16 r + 4 (l / 16) + 0..3 of each
@@ -76,8 +76,11 @@ __device__ __forceinline__ float coop_step_sum(const float *psum, int sl) {
     return cs;
 }
 
-// u[b] = frag-matrix[b] . (X * 2^-e) over all NP states for each owned block
-// b, X read from the exchange buffer rows (layout [16][XROW]).  Each chain is a
+// u[b] = (frag-matrix[b] . X) 2^-e over all NP states for each owned block b, X
+// read from the exchange buffer rows (layout [16][XROW]).  Scaling the product
+// rather than its operand gives the same values (a power of two commutes with
+// FP32 rounding away from the subnormal range), takes 4 BO ldexps per lane
+// instead of 4 R, and lets the chain start before e is known.  Each chain is a
 // single accumulator in block order; the operands of block rp + 1 are loaded
 // while the MFMAs of block rp issue, and scheduling barriers keep the compiler
 // from hoisting every load.
@@ -94,13 +97,17 @@ __device__ __forceinline__ void coop_matvec_q0(const float (&f)[BO][R][4], const
     for (int rp = 0; rp < R; ++rp) {
         const float4 q = qn;
         if (rp + 1 < R) qn = *(const float4 *)&row[16 * (rp + 1)];
-        const float in[4] = {ldexp_f(q.x, -e), ldexp_f(q.y, -e), ldexp_f(q.z, -e), ldexp_f(q.w, -e)};
+        const float in[4] = {q.x, q.y, q.z, q.w};
 #pragma unroll
         for (int v = 0; v < 4; ++v)
 #pragma unroll
             for (int b = 0; b < BO; ++b) u[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(f[b][rp][v], in[v], u[b], 0, 0, 0);
         __builtin_amdgcn_sched_barrier(0);
     }
+#pragma unroll
+    for (int b = 0; b < BO; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) u[b][v] = ldexp_f(u[b][v], -e);
 }
 
 template <int R, int BO>
@@ -141,7 +148,7 @@ __device__ __forceinline__ void coop_matvec_stream_q0(const float4 *fr, const fl
 #pragma unroll
             for (int b = 0; b < BO; ++b) ring[rp % D][b] = fr[opaque((rp + D) * WAVE * BO + b)];
         }
-        const float in[4] = {ldexp_f(q.x, -e), ldexp_f(q.y, -e), ldexp_f(q.z, -e), ldexp_f(q.w, -e)};
+        const float in[4] = {q.x, q.y, q.z, q.w};
 #pragma unroll
         for (int v = 0; v < 4; ++v)
 #pragma unroll
@@ -151,6 +158,10 @@ __device__ __forceinline__ void coop_matvec_stream_q0(const float4 *fr, const fl
             }
         __builtin_amdgcn_sched_barrier(0);
     }
+#pragma unroll
+    for (int b = 0; b < BO; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) u[b][v] = ldexp_f(u[b][v], -e);
 }
 
 template <int R, int BO, int D>

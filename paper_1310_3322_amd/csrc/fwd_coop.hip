@@ -75,7 +75,7 @@ __global__ void __launch_bounds__(R / BO * WAVE) k_fwd_coop(DevPtrs d, FwdLaunch
             const int Tmax = __builtin_amdgcn_readfirstlane(wave_max_int(T));
             if (Tmax == 0) {
                 if (has && g == 0 && w == 0) {
-                    f.ll[f.all_pairs ? (size_t)seq * K + k : (size_t)seq] = bad ? NAN : 0.0f;
+                    store_ll(f, seq, pos, k, bad ? NAN : 0.0f);
                     if (bad) atomicMin(f.err, seq);
                     if (CKPT) f.flag[pos] = bad ? 1 : 0;
                 }
@@ -206,7 +206,7 @@ __global__ void __launch_bounds__(R / BO * WAVE) k_fwd_coop(DevPtrs d, FwdLaunch
             if (has && g == 0 && w == 0) {
                 float r = (float)((double)E_end * LN2 + (double)logf(c_end));
                 if (bad || symbad) r = NAN;
-                f.ll[f.all_pairs ? (size_t)seq * K + k : (size_t)seq] = r;
+                store_ll(f, seq, pos, k, r);
                 if (bad || symbad) atomicMin(f.err, seq);
                 if (CKPT) f.flag[pos] = (r > -INFINITY && r < INFINITY) ? 0 : 1;
             }

@@ -194,7 +194,7 @@ __global__ void __launch_bounds__(FWD_WAVES * WAVE) k_fwd_mfma(DevPtrs d, FwdLau
             if (has && g == 0) {
                 float r = (float)((double)E_end * LN2 + (double)logf(c_end));
                 if (bad || symbad) r = NAN;
-                f.ll[f.all_pairs ? (size_t)seq * K + k : (size_t)seq] = r;
+                store_ll(f, seq, pos, k, r);
                 if (bad || symbad) atomicMin(f.err, seq);
                 // the backward pass skips sequences without a finite likelihood
                 if (CKPT) f.flag[pos] = (r > -INFINITY && r < INFINITY) ? 0 : 1;

@@ -47,13 +47,20 @@ k_fwd_mfma32(DevPtrs d, FwdLaunch f) {
     float *btl = (float *)smem;
     int32_t *sym = sym_all + wave * SYM32;
 
-    const int G = gridDim.x;
-    const int k_first = G >= K ? (int)(blockIdx.x % K) : (int)blockIdx.x;
+    // Scoring all pairs, the tiles are split over the XCDs (workgroup b runs on
+    // XCD b mod 8): slice x takes tiles x, x + 8, ... of every model, so each
+    // tile's symbols are read into one XCD's L2 and serve all the models there.
+    // Own-model calls keep one model per workgroup.
+    const int XS = xcd_slices(f.all_pairs, gridDim.x, K);
+    const int x = (int)(blockIdx.x % XS);
+    const int G = (int)gridDim.x / XS, gi = (int)blockIdx.x / XS;
+    const int k_first = G >= K ? gi % K : gi;
     const int k_step = G >= K ? K : G;
     for (int k = k_first; k < K; k += k_step) {
         const int grp = f.all_pairs ? 0 : k;
         const int gbeg = f.gstart[grp], gend = f.gstart[grp + 1];
-        const int ntiles = (gend - gbeg + T32 - 1) / T32;
+        const int ntiles_all = (gend - gbeg + T32 - 1) / T32;
+        const int ntiles = (ntiles_all - x + XS - 1) / XS;  // tiles x, x + XS, ... of this slice
         const float *btk = f.bt + (size_t)k * M * NP;
         if (BLDS) {
             __syncthreads();
@@ -82,10 +89,16 @@ k_fwd_mfma32(DevPtrs d, FwdLaunch f) {
                     }
         }
         const float *pik = d.pi + (size_t)k * N;
+        // Rescaling every other step is safe when every emission probability of the
+        // model is at least 2^-60: a step then multiplies the sum of a normalised
+        // alpha by at least 2^-61 (rows of A sum to 1), so two steps keep it above
+        // 2^-122, in the normal range.
+        const bool lazy = f.bmin != nullptr && __uint_as_float(f.bmin[k]) >= 8.673617379884035e-19f;
 
         for (;;) {
-            const int tile = wave_pop(&f.queue[k]);
-            if (tile >= ntiles) break;
+            const int jt = wave_pop(&f.queue[k * XS + x]);
+            if (jt >= ntiles) break;
+            const int tile = x + XS * jt;
 
             const int pos = gbeg + tile * T32 + sl;
             const bool has = pos < gend;
@@ -151,7 +164,7 @@ k_fwd_mfma32(DevPtrs d, FwdLaunch f) {
                 // one step: bcur holds the emission row of step t, bnext receives the
                 // one of step t + 1 (the loop below alternates the two buffers, so no
                 // copy is needed between steps)
-                auto step = [&](int t, const float4 (&bcur)[R][4], float4 (&bnext)[R][4]) {
+                auto step = [&](int t, const float4 (&bcur)[R][4], float4 (&bnext)[R][4], bool full) {
                     const int tn = t + 1;
                     if (tn < Tmax) {
                         if ((tn % CH32) == 0) {
@@ -194,6 +207,13 @@ k_fwd_mfma32(DevPtrs d, FwdLaunch f) {
 #pragma unroll
                                 for (int v = 0; v < 16; ++v) x[r][v] = acc[r][v] * bcur[r][v / 4][v % 4];
                         }
+                        if (!full) {
+#pragma unroll
+                            for (int r = 0; r < R; ++r)
+#pragma unroll
+                                for (int v = 0; v < 16; ++v) acur[r][v] = x[r][v];
+                            return;
+                        }
                         part = x[0][0];
 #pragma unroll
                         for (int r = 0; r < R; ++r)
@@ -216,8 +236,8 @@ k_fwd_mfma32(DevPtrs d, FwdLaunch f) {
                 float4 bA[R][4], bB[R][4];
                 gather(read_sym(0), bA);
                 for (int t = 0; t < Tmax; t += 2) {
-                    step(t, bA, bB);
-                    if (t + 1 < Tmax) step(t + 1, bB, bA);
+                    step(t, bA, bB, !lazy || t + 1 >= Tmin);
+                    if (t + 1 < Tmax) step(t + 1, bB, bA, true);
                 }
             }
             int sb = symbad ? 1 : 0;
@@ -225,7 +245,7 @@ k_fwd_mfma32(DevPtrs d, FwdLaunch f) {
             if (has && h == 0) {
                 float r = (float)((double)E_end * LN2 + (double)logf(c_end));
                 if (bad || sb) r = NAN;
-                f.ll[f.all_pairs ? (size_t)seq * K + k : (size_t)seq] = r;
+                store_ll(f, seq, pos, k, r);
                 if (bad || sb) atomicMin(f.err, seq);
             }
         }

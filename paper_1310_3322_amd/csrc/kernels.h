@@ -16,7 +16,8 @@ struct Layout {
     size_t gstart;   // int32 [groups + 1] start of each group in perm
     size_t perm;     // int32 [S] sequence ids, grouped by model, longest first
     size_t bt;       // float [K][M][NP] transposed, zero-padded emission matrix
-    size_t ll;       // float [S][K] log-likelihoods for classify without loglik_opt
+    size_t bmin;     // uint32 [K] bits of each model's smallest emission probability (forward)
+    size_t ll;       // float [K][S] all-pairs values by sorted position (or [S][K] rows), [S] for the gradient
     size_t ckpt;     // float [S][nck][NP] alpha checkpoints (gradient)
     size_t ckexp;    // int32 [S][nck] exponents of the checkpointed steps
     size_t flag;     // int32 [S] per sorted position: sequence has no finite likelihood
@@ -61,6 +62,31 @@ inline int persistent_grid(int occ_grid, int64_t items_bound, int items_per_wg, 
     return grid > 0 ? grid : 1;
 }
 
+// XCDs of MI355X; workgroup b of a launch runs on XCD b mod XCDS.
+constexpr int XCDS = 8;
+// Tile slices of an all-pairs forward: one per XCD when every (model, XCD) pair
+// gets at least one workgroup of a grid that divides evenly, else 1.
+__host__ __device__ inline int xcd_slices(int all_pairs, int grid, int K) {
+    return (all_pairs && grid >= XCDS * K && grid % XCDS == 0) ? XCDS : 1;
+}
+// Models served by workgroup b of a persistent own-model launch of G
+// workgroups: first, first + step, ...  When K and G are multiples of the XCD
+// count, the workgroups of XCD x take models x, x + XCDS, ... one after the
+// other, sharing each model's tile queue, so that an XCD's L2 holds the tables
+// and counts of one model at a time; otherwise workgroup b takes models b mod K
+// (or b, b + G, ... when G < K).
+__host__ __device__ inline void model_walk(int K, int G, int b, int *first, int *step) {
+    if (K % XCDS == 0 && G % XCDS == 0 && G >= K) {
+        *first = b % XCDS;
+        *step = XCDS;
+    } else {
+        *first = G >= K ? b % K : b;
+        *step = G >= K ? K : G;
+    }
+}
+// Entries of the forward's tile-queue heads: one per model and XCD slice.
+__host__ __device__ inline int64_t queue_heads(int K) { return (int64_t)XCDS * K; }
+
 // Upper bound on the tiles of `tile` sequences the planner can form.
 inline int64_t tile_bound(int S, int K, bool all_pairs, int tile) {
     const int64_t t = ((int64_t)S + tile - 1) / tile;
@@ -79,11 +105,19 @@ struct DevPtrs {
 // Entries of the planner's [bins][chunks] count matrix are capped at this (the
 // chunks grow beyond PLAN_SUB sequences when the bins are many).
 constexpr int64_t PLAN_MATRIX_MAX = (int64_t)1 << 24;
+// With one wave (64 sequences) per chunk the matrix may take up to this many
+// entries (128 MiB); beyond it the chunks are sorted in LDS, 2048 at a time.
+constexpr int64_t PLAN_WAVE_MAX = (int64_t)1 << 25;
 void plan_chunking(int S, int64_t nbins, int *chunk, int *nchunks);
 void launch_plan(const DevPtrs &d, int K, int S, int groups, int max_len, int64_t total, int nbins,
                  unsigned char *ws, const Layout &L, hipStream_t st);
-void launch_transpose_b(const float *B, float *bt, int K, int N, int M, int NP, hipStream_t st);
+void launch_transpose_b(const float *B, float *bt, int K, int N, int M, int NP, hipStream_t st,
+                        uint32_t *bmin = nullptr);
 void launch_argmax(const float *ll, int32_t *labels, int S, int K, hipStream_t st);
+// out[perm[p]][k] = llpos[k][p] (out may be NULL) and labels[perm[p]] = the arg-max over k
+// of the same values (labels may be NULL).
+void launch_rows_from_sorted(const float *llpos, const int32_t *perm, int S, int K, float *out, int32_t *labels,
+                             hipStream_t st);
 void launch_fill_f32(float *p, size_t n, float v, hipStream_t st);
 void launch_fill_i32(int32_t *p, size_t n, int32_t v, hipStream_t st);
 void launch_copy_i32(const int32_t *src, int32_t *dst, size_t n, hipStream_t st);
@@ -102,13 +136,22 @@ struct FwdLaunch {
     const int32_t *perm, *gstart;
     int32_t *queue, *err;
     const float *bt;
-    float *ll;
+    float *ll;        // [S][K] all pairs (unless llpos), else [S]
+    float *llpos;     // [K][S] by sorted position: all-pairs staging, written in tile rows (or NULL)
+    const uint32_t *bmin;  // [K] bits of each model's smallest emission probability (or NULL)
     float *ckpt;      // NULL unless checkpointing for the gradient
     int32_t *ckexp;
     int32_t *flag;    // [S] per sorted position: 1 = no finite likelihood (gradient only)
     int nck;
     int max_grid;     // cap on the persistent grid (0: occupancy limit)
 };
+// The log-likelihood of sequence seq (sorted position pos) under model k.
+__device__ __forceinline__ void store_ll(const FwdLaunch &f, int seq, int pos, int k, float r) {
+    if (f.llpos)
+        f.llpos[(size_t)k * f.S + pos] = r;
+    else
+        f.ll[f.all_pairs ? (size_t)seq * f.K + k : (size_t)seq] = r;
+}
 bool fwd_mfma_supported(int NP);
 hipError_t launch_fwd_mfma(const DevPtrs &d, const FwdLaunch &f, int cu_count, hipStream_t st);
 
@@ -152,13 +195,19 @@ struct AdjLaunch {
     // Counts, as order-independent 64-bit fixed-point sums (zeroed before the launch):
     unsigned long long *pi64;  // [K][N]
     unsigned long long *A64;   // [K][N][N] n_A = A o C, added tile by tile
-    unsigned long long *B64;   // [K][M][NP] symbol-major emission counts (global-count kernels)
+    unsigned long long *B64;   // [K][M][NP] symbol-major emission counts (global-count kernels), state i
+                               // of a row at quad_t(i)
     float *slab;               // [tiles][M][NP] per-tile emission partials (LDS-partial kernels)
     int32_t *nanflag;          // [K] set when a model received a non-finite count
     const uint32_t *wmax;      // bits of max_s |w_s| (the fixed-point scale)
     const float *frag;  // pre-arranged fragments when the cooperative kernel streams them
     int max_grid;       // cap on the persistent grid (0: occupancy limit)
 };
+// Quad-transposed position of state i in a row of the global emission counts:
+// within each 16-state block, i = 4 g + v goes to 4 v + g.  A lane of the
+// backward kernels holds states 4 g + v (v = 0..3) of a sequence, so the four
+// lanes of a sequence (g = 0..3) add to four adjacent words in each instruction.
+__host__ __device__ inline int quad_t(int i) { return (i & ~15) | ((i & 3) << 2) | ((i >> 2) & 3); }
 // Slab slot of tile `tile` of the model whose group starts at gbeg: unique, below
 // S / 16 + K + 1 (the group's tiles follow floor(gbeg / 16) + k).
 __host__ __device__ inline int64_t slab_slot(int gbeg, int k, int tile) { return (int64_t)(gbeg / 16) + k + tile; }

@@ -109,6 +109,28 @@ __global__ void __launch_bounds__(1024) k_plan_scan_top(int32_t *bsum, int nb) {
     }
 }
 
+// Small matrices (up to PLAN_SCAN_ONE entries): one workgroup, each thread a
+// contiguous run of at most 32 entries, in one launch.
+constexpr int64_t PLAN_SCAN_ONE = 32768;
+
+__global__ void __launch_bounds__(1024) k_plan_scan_one(int32_t *cnt, int64_t n, int nchunks, int bins_per_group,
+                                                        int groups, int32_t *gstart) {
+    __shared__ int32_t part[1024];
+    const int64_t per = (n + 1023) / 1024;
+    const int64_t e0 = min(n, (int64_t)threadIdx.x * per), e1 = min(n, e0 + per);
+    int32_t local = 0;
+    for (int64_t e = e0; e < e1; ++e) local += cnt[e];
+    int32_t run = block_inclusive_scan(part, local) - local;
+    for (int64_t e = e0; e < e1; ++e) {
+        const int32_t c = cnt[e];
+        cnt[e] = run;
+        const int64_t b = e / nchunks;
+        if (e % nchunks == 0 && b % bins_per_group == 0) gstart[b / bins_per_group] = run;
+        run += c;
+    }
+    if (threadIdx.x == 1023) gstart[groups] = part[1023];
+}
+
 __global__ void __launch_bounds__(1024) k_plan_scan_apply(int32_t *cnt, int64_t n, const int32_t *bsum, int nchunks,
                                                           int bins_per_group, int groups, int32_t *gstart) {
     __shared__ int32_t part[1024];
@@ -120,7 +142,7 @@ __global__ void __launch_bounds__(1024) k_plan_scan_apply(int32_t *cnt, int64_t 
         v[j] = base + j < n ? cnt[base + j] : 0;
         local += v[j];
     }
-    int32_t run = (bsum ? bsum[blockIdx.x] : 0) + block_inclusive_scan(part, local) - local;
+    int32_t run = bsum[blockIdx.x] + block_inclusive_scan(part, local) - local;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
         const int64_t e = base + j;
@@ -138,7 +160,7 @@ constexpr int PLAN_SUB = 2048;  // keys sorted at a time by a scatter workgroup 
 
 // One workgroup of 1024 threads per chunk; the chunk's sequences are taken
 // PLAN_SUB at a time in index order.  Keys (bin << 11 | index within the
-// sub-chunk) are unique, so the bitonic sort's result is fixed; a sequence's
+// sub-chunk) are unique, so the sort's result is fixed; a sequence's
 // rank within its bin is its sorted position minus the first position of its
 // bin (binary search), its place cnt[bin][chunk] + rank.  Between sub-chunks
 // the last sequence of each bin advances cnt[bin][chunk].
@@ -151,29 +173,59 @@ __global__ void __launch_bounds__(1024) k_plan_scatter(DevPtrs d, int S, int K, 
     const int cbeg = c * chunk, cend = min(S, cbeg + chunk);
     for (int base = cbeg; base < cend; base += PLAN_SUB) {
         const int n = min(PLAN_SUB, cend - base);
-        for (int i = tid; i < PLAN_SUB; i += 1024) {
-            uint64_t kv = ~(uint64_t)0;
+        // bitonic sort of the PLAN_SUB keys, thread t holding positions 2t and 2t + 1:
+        // distance 1 inside the thread, 2..64 across the lanes of a wave (shuffles),
+        // 128 and more through LDS (10 of the 66 stages need the workgroup barrier)
+        uint64_t kk[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int i = 2 * tid + h;
+            kk[h] = ~(uint64_t)0;
             if (i < n) {
                 bool bad;
                 const int b = plan_bin(d, base + i, K, groups, max_len, total, &bad);
-                kv = ((uint64_t)b << 11) | (uint64_t)i;
+                kk[h] = ((uint64_t)b << 11) | (uint64_t)i;
             }
-            key[i] = kv;
         }
-        __syncthreads();
         for (int k = 2; k <= PLAN_SUB; k <<= 1) {
             for (int j = k >> 1; j > 0; j >>= 1) {
-                const int i = (tid / j) * 2 * j + (tid % j);
-                const int p = i + j;
-                const uint64_t a = key[i], bv = key[p];
-                const bool up = (i & k) == 0;
-                if ((a > bv) == up) {
-                    key[i] = bv;
-                    key[p] = a;
+                if (j == 1) {
+                    const bool up = ((2 * tid) & k) == 0;
+                    if ((kk[0] > kk[1]) == up) {
+                        const uint64_t t = kk[0];
+                        kk[0] = kk[1];
+                        kk[1] = t;
+                    }
+                    continue;
                 }
-                __syncthreads();
+                uint64_t other[2];
+                if (j <= 64) {
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)kk[h], j >> 1, WAVE);
+                        const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(kk[h] >> 32), j >> 1, WAVE);
+                        other[h] = ((uint64_t)hi << 32) | lo;
+                    }
+                } else {
+                    __syncthreads();
+                    key[2 * tid] = kk[0];
+                    key[2 * tid + 1] = kk[1];
+                    __syncthreads();
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) other[h] = key[(2 * tid + h) ^ j];
+                }
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int pp = 2 * tid + h;
+                    const bool keep_min = ((pp & j) == 0) == ((pp & k) == 0);
+                    kk[h] = keep_min ? (kk[h] < other[h] ? kk[h] : other[h]) : (kk[h] > other[h] ? kk[h] : other[h]);
+                }
             }
         }
+        __syncthreads();
+        key[2 * tid] = kk[0];
+        key[2 * tid + 1] = kk[1];
+        __syncthreads();
         int last_bin[2] = {-1, -1};
         int last_pos[2] = {0, 0};
         for (int h = 0; h < 2; ++h) {
@@ -206,18 +258,63 @@ __global__ void __launch_bounds__(1024) k_plan_scatter(DevPtrs d, int S, int K, 
     }
 }
 
-// Bt[k][o][i] = B[k][i][o] for i < N, 0 for N <= i < NP (32x32 tiles through LDS).
-__global__ void k_transpose_b(const float *B, float *bt, int N, int M, int NP) {
+// Chunks of one wave (64 sequences), when the count matrix stays small enough:
+// a sequence's rank among the chunk's sequences of its bin comes from ballots,
+// one round per distinct bin of the wave (the first unplaced lane's bin, the
+// mask of lanes sharing it, the lane's position in that mask).  No LDS and no
+// barrier.  Four chunks per block of 256 threads.
+__global__ void __launch_bounds__(256) k_plan_scatter_wave(DevPtrs d, int S, int K, int groups, int max_len,
+                                                           int64_t total, int nchunks, const int32_t *cnt,
+                                                           int32_t *perm) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int c = blockIdx.x * 4 + (int)(threadIdx.x / WAVE);
+    if (c >= nchunks) return;  // wave-uniform
+    const int s = c * WAVE + lane;
+    const bool valid = s < S;
+    int b = -1;
+    if (valid) {
+        bool bad;
+        b = plan_bin(d, s, K, groups, max_len, total, &bad);
+    }
+    const uint64_t below = lane ? (~(uint64_t)0 >> (64 - lane)) : 0;  // lanes under this one
+    uint64_t todo = __ballot(valid);
+    int rank = 0;
+    while (todo) {
+        const int leader = __builtin_ctzll(todo);
+        const int lb = __builtin_amdgcn_readlane(b, leader);
+        const uint64_t m = __ballot(b == lb);
+        if (b == lb) rank = __popcll(m & below);
+        todo &= ~m;
+    }
+    if (valid) perm[cnt[(int64_t)b * nchunks + c] + rank] = s;
+}
+
+// Bt[k][o][i] = B[k][i][o] for i < N, 0 for N <= i < NP (32x32 tiles through LDS),
+// and, when bmin is given, bmin[k] = bits of the smallest B[k][i][o] (non-negative
+// floats order like their bit patterns; bmin starts at +inf).
+__global__ void k_transpose_b(const float *B, float *bt, int N, int M, int NP, uint32_t *bmin) {
     __shared__ float tile[32][33];
+    __shared__ uint32_t wmin[4];
     const int k = blockIdx.z;
     const int o0 = blockIdx.x * 32, i0 = blockIdx.y * 32;
     const float *Bk = B + (size_t)k * N * M;
     float *btk = bt + (size_t)k * M * NP;
+    uint32_t m = 0x7f800000u;
     for (int r = threadIdx.y; r < 32; r += 8) {
         int i = i0 + r, o = o0 + threadIdx.x;
-        tile[r][threadIdx.x] = (i < N && o < M) ? Bk[(size_t)i * M + o] : 0.0f;
+        const bool in = i < N && o < M;
+        const float x = in ? Bk[(size_t)i * M + o] : 0.0f;
+        tile[r][threadIdx.x] = x;
+        if (in) m = min(m, __float_as_uint(x));
+    }
+    if (bmin) {
+        for (int off = 32; off >= 1; off >>= 1) m = min(m, (uint32_t)__shfl_xor((int)m, off, WAVE));
+        const int t = threadIdx.y * 32 + threadIdx.x;
+        if ((t & (WAVE - 1)) == 0) wmin[t / WAVE] = m;
     }
     __syncthreads();
+    if (bmin && threadIdx.x == 0 && threadIdx.y == 0)
+        atomicMin(&bmin[k], min(min(wmin[0], wmin[1]), min(wmin[2], wmin[3])));
     for (int r = threadIdx.y; r < 32; r += 8) {
         int o = o0 + r, i = i0 + threadIdx.x;
         if (o < M && i < NP) btk[(size_t)o * NP + i] = tile[threadIdx.x][r];
@@ -265,7 +362,7 @@ __global__ void k_counts_finish_b(AdjLaunch a, int slab, float *cnt_B) {
                 for (int t = 0; t < nt; ++t) acc += (double)src[(size_t)t * M * NP];
                 v = (float)acc;
             } else {
-                v = from_fixed(a.B64[((size_t)k * M + o) * NP + i], F);
+                v = from_fixed(a.B64[((size_t)k * M + o) * NP + quad_t(i)], F);
             }
         }
         tile[r][threadIdx.x] = v;
@@ -307,6 +404,45 @@ __global__ void k_weight_max(const float *w, int S, uint32_t *wmax) {
     }
     for (int o = 32; o >= 1; o >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, o, WAVE));
     if ((threadIdx.x & (WAVE - 1)) == 0 && m != 0) atomicMax(wmax, m);
+}
+
+// Rows of the all-pairs log-likelihoods from the sorted-position staging
+// buffer, llpos[k][p] = value of pair (perm[p], k).  One block per 64
+// positions, 64 x 64 tiles through LDS: the staging buffer is read along
+// positions and out[perm[p]][:] written along models, each row by one wave in
+// one pass; the label of each position comes from the same values (smallest
+// index of the maximum, NaN skipped, -1 if all NaN).
+__global__ void __launch_bounds__(256) k_rows_from_sorted(const float *llpos, const int32_t *perm, int S, int K,
+                                                          float *out, int32_t *labels) {
+    __shared__ float tile[64][65];  // [position][model]
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const int p0 = blockIdx.x * 64;
+    const int np = min(64, S - p0);
+    int best = -1;
+    float bv = 0.0f;
+    for (int k0 = 0; k0 < K; k0 += 64) {
+        const int nk = min(64, K - k0);
+        __syncthreads();
+        for (int r = ty; r < nk; r += 4) tile[tx][r] = tx < np ? llpos[(size_t)(k0 + r) * S + p0 + tx] : 0.0f;
+        __syncthreads();
+        if (labels && ty == 0 && tx < np) {
+            for (int r = 0; r < nk; ++r) {
+                const float v = tile[tx][r];
+                if (v != v) continue;
+                if (best < 0 || v > bv) {
+                    best = k0 + r;
+                    bv = v;
+                }
+            }
+        }
+        if (out) {
+            for (int r = ty; r < np; r += 4) {
+                const int s = perm[p0 + r];
+                if (tx < nk) out[(size_t)s * K + k0 + tx] = tile[r][tx];
+            }
+        }
+    }
+    if (labels && ty == 0 && tx < np) labels[perm[p0 + tx]] = best;
 }
 
 // label[s] = smallest k attaining the maximum of ll[s][:], NaN skipped, -1 if all NaN.
@@ -399,8 +535,15 @@ inline int blocks_for(int64_t n, int bs) { return (int)((n + bs - 1) / bs); }
 }  // namespace
 
 void plan_chunking(int S, int64_t nbins, int *chunk, int *nchunks) {
+    const int64_t nb = nbins > 0 ? nbins : 1;
+    const int64_t waves = ((int64_t)S + WAVE - 1) / WAVE;
+    if (waves * nb <= PLAN_WAVE_MAX) {  // one wave per chunk
+        *chunk = WAVE;
+        *nchunks = (int)(waves > 0 ? waves : 1);
+        return;
+    }
     int64_t nc = ((int64_t)S + PLAN_SUB - 1) / PLAN_SUB;
-    const int64_t cap = PLAN_MATRIX_MAX / (nbins > 0 ? nbins : 1);
+    const int64_t cap = PLAN_MATRIX_MAX / nb;
     if (nc > cap) nc = cap;
     if (nc < 1) nc = 1;
     int64_t ch = ((int64_t)S + nc - 1) / nc;
@@ -420,30 +563,35 @@ void launch_plan(const DevPtrs &d, int K, int S, int groups, int max_len, int64_
     int32_t *perm = (int32_t *)(ws + L.perm);
     const int chunk = L.plan_chunk, nchunks = L.plan_nchunks;
     const int64_t n = (int64_t)nbins * nchunks;
-    const int64_t m = n > K ? n : K;
+    const int64_t m = n > queue_heads(K) ? n : queue_heads(K);
     int nb = blocks_for(m, 256);
     if (nb > 4096) nb = 4096;
-    hipLaunchKernelGGL(k_plan_init, dim3(nb), dim3(256), 0, st, cnt, n, queue, K, err);
+    hipLaunchKernelGGL(k_plan_init, dim3(nb), dim3(256), 0, st, cnt, n, queue, (int)queue_heads(K), err);
     if (S > 0)
         hipLaunchKernelGGL(k_plan_count, dim3(blocks_for(S, 256)), dim3(256), 0, st, d, S, K, groups, max_len, total,
                            chunk, nchunks, cnt, err);
-    const int nscan = (int)((n + PLAN_SCAN - 1) / PLAN_SCAN);
-    int32_t *bsum = nullptr;
-    if (nscan > 1) {
-        bsum = (int32_t *)(ws + L.scanb);
+    if (n <= PLAN_SCAN_ONE) {
+        hipLaunchKernelGGL(k_plan_scan_one, dim3(1), dim3(1024), 0, st, cnt, n, nchunks, max_len + 1, groups, gstart);
+    } else {
+        const int nscan = (int)((n + PLAN_SCAN - 1) / PLAN_SCAN);
+        int32_t *bsum = (int32_t *)(ws + L.scanb);
         hipLaunchKernelGGL(k_plan_scan_reduce, dim3(nscan), dim3(1024), 0, st, cnt, n, bsum);
         hipLaunchKernelGGL(k_plan_scan_top, dim3(1), dim3(1024), 0, st, bsum, nscan);
+        hipLaunchKernelGGL(k_plan_scan_apply, dim3(nscan), dim3(1024), 0, st, cnt, n, bsum, nchunks, max_len + 1,
+                           groups, gstart);
     }
-    hipLaunchKernelGGL(k_plan_scan_apply, dim3(nscan), dim3(1024), 0, st, cnt, n, bsum, nchunks, max_len + 1, groups,
-                       gstart);
-    if (S > 0)
+    if (S > 0 && chunk == WAVE)
+        hipLaunchKernelGGL(k_plan_scatter_wave, dim3((nchunks + 3) / 4), dim3(256), 0, st, d, S, K, groups, max_len,
+                           total, nchunks, cnt, perm);
+    else if (S > 0)
         hipLaunchKernelGGL(k_plan_scatter, dim3(nchunks), dim3(1024), 0, st, d, S, K, groups, max_len, total, chunk,
                            nchunks, cnt, perm);
 }
 
-void launch_transpose_b(const float *B, float *bt, int K, int N, int M, int NP, hipStream_t st) {
+void launch_transpose_b(const float *B, float *bt, int K, int N, int M, int NP, hipStream_t st, uint32_t *bmin) {
+    if (bmin) launch_fill_i32((int32_t *)bmin, (size_t)K, 0x7f800000, st);
     dim3 grid((M + 31) / 32, (NP + 31) / 32, K);
-    hipLaunchKernelGGL(k_transpose_b, grid, dim3(32, 8), 0, st, B, bt, N, M, NP);
+    hipLaunchKernelGGL(k_transpose_b, grid, dim3(32, 8), 0, st, B, bt, N, M, NP, bmin);
 }
 
 void launch_log_transpose_b(const float *B, float *lnbt, int K, int N, int M, int NP, hipStream_t st) {
@@ -471,6 +619,12 @@ void launch_weight_max(const float *w, int S, uint32_t *wmax, hipStream_t st) {
         if (nb > 1024) nb = 1024;
         hipLaunchKernelGGL(k_weight_max, dim3(nb), dim3(256), 0, st, w, S, wmax);
     }
+}
+
+void launch_rows_from_sorted(const float *llpos, const int32_t *perm, int S, int K, float *out, int32_t *labels,
+                             hipStream_t st) {
+    if (S > 0)
+        hipLaunchKernelGGL(k_rows_from_sorted, dim3(blocks_for(S, 64)), dim3(256), 0, st, llpos, perm, S, K, out, labels);
 }
 
 void launch_argmax(const float *ll, int32_t *labels, int S, int K, hipStream_t st) {

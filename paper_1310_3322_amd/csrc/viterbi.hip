@@ -249,7 +249,7 @@ __global__ void __launch_bounds__(VWAVES * WAVE) k_viterbi_trace(DevPtrs d, VitL
     const int lane = threadIdx.x & (WAVE - 1);
     const int slot = lane / NP, i = lane % NP;
     const int K = v.K, N = v.N;
-    int32_t *queue = v.queue + K;  // the decoder pops [0, K)
+    int32_t *queue = v.queue + queue_heads(K);  // the decoder pops [0, K)
 
     const int G = gridDim.x;
     const int k_first = G >= K ? (int)(blockIdx.x % K) : (int)blockIdx.x;
@@ -542,7 +542,7 @@ __global__ void __launch_bounds__(VWAVES * WAVE) k_viterbi_trace_wg(DevPtrs d, V
     constexpr int C = NP / WAVE;
     const int lane = threadIdx.x & (WAVE - 1);
     const int K = v.K, N = v.N;
-    int32_t *queue = v.queue + K;  // the decoder pops [0, K)
+    int32_t *queue = v.queue + queue_heads(K);  // the decoder pops [0, K)
 
     const int G = gridDim.x;
     const int k_first = G >= K ? (int)(blockIdx.x % K) : (int)blockIdx.x;

@@ -132,6 +132,37 @@ def test_every_batched_family(N):
     hmm.select_kernel(hmm.KERNEL_AUTO)
 
 
+@pytest.mark.parametrize("N", [32, 64])
+def test_tile32_tiny_emission_probabilities(N):
+    """The 32-sequence-tile forward rescales every other step only for models whose
+    emission probabilities are all at least 2^-60.  Model 1 gives symbol 0 a probability of
+    1e-22 in every state and the sequences hold runs of symbol 0 (two steps without a
+    rescale would take the sum to about 1e-44, below the FP32 normal range); model 0 is an
+    ordinary bank.  All pairs against the oracle, tile family forced."""
+    print(f"[case] tile32 tiny emissions N={N}", flush=True)
+    rng = np.random.default_rng([41, N])
+    lengths = rng.integers(20, 90, size=70)
+    w = workloads.random_lengths_workload(rng, K=2, N=N, M=5, lengths=lengths, all_pairs=True, conc=0.7)
+    B = w.B.astype(np.float64)
+    B[1, :, 0] = 1e-22
+    B[1, :, 1:] /= B[1, :, 1:].sum(axis=1, keepdims=True) / (1.0 - 1e-22)
+    w.B = B.astype(np.float32)
+    sym = w.symbols.copy()
+    for s in range(w.S):
+        off = w.offsets[s]
+        sym[off + 3:off + 9] = 0  # a run of six rare symbols early in every sequence
+    p = hmm.Problem(dev(w.pi), dev(w.A), dev(w.B), dev(sym), dev(w.offsets), dev(w.lengths), None,
+                    max_len=w.max_len, total_symbols=w.total_symbols)
+    ref = O.forward(w.pi, w.A, w.B, sym, w.offsets, w.lengths, None)
+    assert np.all(np.isfinite(ref))
+    hmm.select_kernel(hmm.KERNEL_TILE32)
+    try:
+        ll = hmm.forward_loglik(p).cpu().numpy()
+    finally:
+        hmm.select_kernel(hmm.KERNEL_AUTO)
+    assert rel_err(ll, ref) <= LL_TOL
+
+
 def test_brute_force_through_gpu():
     w = workloads.make_workload("brute")
     p = problem(w)
