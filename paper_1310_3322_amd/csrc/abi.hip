@@ -410,8 +410,7 @@ hmm_status run_forward(const hmm_bank *b, const hmm_batch *q, int op, float *out
     const int NP = padded_states(N);
     const int cus = device_cu_count();
     {
-        if (fam == HMM_KERNEL_SCAN) {
-            launch_fill_i32(err, 1, INT32_MAX, st);
+        if (fam == HMM_KERNEL_SCAN) {  // (the time-parallel kernels start the error word themselves)
             FwdLaunch f;
             memset(&f, 0, sizeof(f));
             f.K = K;
@@ -438,8 +437,8 @@ hmm_status run_forward(const hmm_bank *b, const hmm_batch *q, int op, float *out
     }
     const int groups = all_pairs ? 1 : K;
     const int nbins = groups * (q->max_len + 1);
-    launch_plan(d, K, S, groups, q->max_len, q->total_symbols, nbins, ws, L, st);
-    launch_transpose_b(b->B, (float *)(ws + L.bt), K, N, M, NP, st, (uint32_t *)(ws + L.bmin));
+    const TransposeJob tj{b->B, (float *)(ws + L.bt), N, M, NP, 0, (uint32_t *)(ws + L.bmin)};
+    launch_plan(d, K, S, groups, q->max_len, q->total_symbols, nbins, ws, L, st, &tj);
     if (hipGetLastError() != hipSuccess) return HMM_ERR_HIP;
     FwdLaunch f;
     memset(&f, 0, sizeof(f));
@@ -534,8 +533,8 @@ hmm_status hmm_forward_backward_grad(const hmm_bank *bank, const hmm_batch *batc
     const int cus = device_cu_count();
     if (phase != 2) {
         const int nbins = K * (batch->max_len + 1);
-        launch_plan(d, K, S, K, batch->max_len, batch->total_symbols, nbins, w, L, stream);
-        launch_transpose_b(bank->B, (float *)(w + L.bt), K, N, M, NP, stream);
+        const TransposeJob tj{bank->B, (float *)(w + L.bt), N, M, NP, 0, nullptr};
+        launch_plan(d, K, S, K, batch->max_len, batch->total_symbols, nbins, w, L, stream, &tj);
         if (hipGetLastError() != hipSuccess) return HMM_ERR_HIP;
         FwdLaunch f;
         memset(&f, 0, sizeof(f));
@@ -635,10 +634,10 @@ hmm_status hmm_viterbi(const hmm_bank *bank, const hmm_batch *batch, float *scor
     const int K = bank->K, N = bank->N, M = bank->M, S = batch->S, NP = viterbi_states(N);
     DevPtrs d = dev_ptrs(bank, batch, true);
     const int nbins = K * (batch->max_len + 1);
-    launch_plan(d, K, S, K, batch->max_len, batch->total_symbols, nbins, w, L, stream);
-    launch_log_transpose_b(bank->B, (float *)(w + L.bt), K, N, M, NP, stream);
+    const TransposeJob tj{bank->B, (float *)(w + L.bt), N, M, NP, 1, nullptr};
+    launch_plan(d, K, S, K, batch->max_len, batch->total_symbols, nbins, w, L, stream, &tj);
     // ln A transposed: the same transpose with A's N columns in place of B's M
-    if (NP > 64) launch_log_transpose_b(bank->A, (float *)(w + L.lnat), K, N, N, NP, stream);
+    if (NP > 64) launch_transpose(TransposeJob{bank->A, (float *)(w + L.lnat), N, N, NP, 1, nullptr}, K, stream);
     launch_fill_i32((int32_t *)(w + L.queue) + queue_heads(K), (size_t)K, 0, stream);  // the traceback's queues
     if (hipGetLastError() != hipSuccess) return HMM_ERR_HIP;
     VitLaunch v;

@@ -94,6 +94,8 @@ __global__ void __launch_bounds__(SC_WAVES * WAVE) k_scan_chunks(DevPtrs d, FwdL
     const int tid = threadIdx.x;
     const int lane = tid & (WAVE - 1);
     const int wave = __builtin_amdgcn_readfirstlane(tid / WAVE);
+    // the error word starts here (pass 2, after this launch, is its only writer)
+    if (blockIdx.x == 0 && blockIdx.y == 0 && tid == 0) *f.err = INT32_MAX;
     const int64_t p = blockIdx.y;
     const int c = blockIdx.x;
     const PairInfo q = pair_info(d, f, p);
@@ -227,9 +229,13 @@ int scan_chunks(int max_len) { return max_len > 1 ? (max_len - 1 + SCAN_CHUNK - 
 
 hipError_t launch_fwd_scan(const DevPtrs &d, const FwdLaunch &f, const ScanWs &w, hipStream_t st) {
     const int64_t pairs = f.all_pairs ? (int64_t)f.S * f.K : (int64_t)f.S;
-    if (pairs == 0) return hipSuccess;
+    if (pairs == 0) {
+        launch_fill_i32(f.err, 1, INT32_MAX, st);
+        return hipSuccess;
+    }
     if (pairs > 65535 && w.nch > 0) return hipErrorInvalidValue;  // grid.y limit of pass 1
     if (pairs > INT_MAX) return hipErrorInvalidValue;
+    if (w.nch == 0) launch_fill_i32(f.err, 1, INT32_MAX, st);
     if (w.nch > 0) {
         hipLaunchKernelGGL(k_scan_chunks, dim3((unsigned)w.nch, (unsigned)pairs), dim3(SC_WAVES * WAVE), 0, st, d, f,
                            w);

@@ -109,10 +109,21 @@ constexpr int64_t PLAN_MATRIX_MAX = (int64_t)1 << 24;
 // entries (128 MiB); beyond it the chunks are sorted in LDS, 2048 at a time.
 constexpr int64_t PLAN_WAVE_MAX = (int64_t)1 << 25;
 void plan_chunking(int S, int64_t nbins, int *chunk, int *nchunks);
+// Emission (or transition) table of every model transposed and padded:
+// dst[k][o][i] = B[k][i][o] for i < N (ln of it when lg), 0 (-inf) for N <= i < NP;
+// with bmin, bmin[k] = bits of the smallest B[k][i][o].
+struct TransposeJob {
+    const float *B;
+    float *dst;
+    int N, M, NP;
+    int lg;
+    uint32_t *bmin;
+};
+int transpose_blocks(const TransposeJob &j, int K);
+void launch_transpose(const TransposeJob &j, int K, hipStream_t st);
+// The plan (and, when tj is given, the transpose in the same launches).
 void launch_plan(const DevPtrs &d, int K, int S, int groups, int max_len, int64_t total, int nbins,
-                 unsigned char *ws, const Layout &L, hipStream_t st);
-void launch_transpose_b(const float *B, float *bt, int K, int N, int M, int NP, hipStream_t st,
-                        uint32_t *bmin = nullptr);
+                 unsigned char *ws, const Layout &L, hipStream_t st, const TransposeJob *tj = nullptr);
 void launch_argmax(const float *ll, int32_t *labels, int S, int K, hipStream_t st);
 // out[perm[p]][k] = llpos[k][p] (out may be NULL) and labels[perm[p]] = the arg-max over k
 // of the same values (labels may be NULL).
@@ -251,7 +262,6 @@ struct VitLaunch {
     int max_grid;       // cap on the persistent grid (0: occupancy limit)
 };
 bool viterbi_supported(int NP);
-void launch_log_transpose_b(const float *B, float *lnbt, int K, int N, int M, int NP, hipStream_t st);
 hipError_t launch_viterbi(const DevPtrs &d, const VitLaunch &v, int cu_count, hipStream_t st);
 
 }  // namespace hmm

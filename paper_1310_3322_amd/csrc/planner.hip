@@ -9,6 +9,7 @@
 // that order then hold sequences of nearly equal length, and the longest tiles
 // are handed out first.
 #include <climits>
+#include <cstring>
 
 #include "common.cuh"
 #include "kernels.h"
@@ -24,11 +25,13 @@ namespace {
 // each chunk places its own sequences by their rank among the chunk's
 // sequences of the same bin (a sort of (bin, index) keys in LDS).
 
-__global__ void k_plan_init(int32_t *cnt, int64_t n, int32_t *queue, int K, int32_t *err) {
+__global__ void k_plan_init(int32_t *cnt, int64_t n, int32_t *queue, int nq, int32_t *err, uint32_t *bmin, int K) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t b = i; b < n; b += stride) cnt[b] = 0;
-    for (int64_t k = i; k < K; k += stride) queue[k] = 0;
+    for (int64_t k = i; k < nq; k += stride) queue[k] = 0;
+    if (bmin)
+        for (int64_t k = i; k < K; k += stride) bmin[k] = 0x7f800000u;
     if (i == 0) *err = INT32_MAX;
 }
 
@@ -51,8 +54,58 @@ __device__ __forceinline__ int plan_bin(const DevPtrs &d, int s, int K, int grou
     return g * (max_len + 1) + (max_len - te);
 }
 
-__global__ void k_plan_count(DevPtrs d, int S, int K, int groups, int max_len, int64_t total, int chunk,
-                             int nchunks, int32_t *cnt, int32_t *err) {
+// One 32 x 32 tile (symbols o0.., states i0.. of model k) of the emission table
+// transposed through LDS: dst[k][o][i] = B[k][i][o] for i < N (ln B when `lg`),
+// padding 0 (-inf when `lg`) for N <= i < NP; with bmin, bmin[k] takes the bits of
+// the smallest B[k][i][o] (non-negative floats order like their bit patterns; bmin
+// starts at +inf).  256 threads, tx = t mod 32, ty = t / 32.
+__device__ __forceinline__ void transpose_tile(const TransposeJob &j, int k, int o0, int i0, int tx, int ty,
+                                               float (*tile)[33], uint32_t *wmin) {
+    const int N = j.N, M = j.M, NP = j.NP;
+    const float *Bk = j.B + (size_t)k * N * M;
+    float *dk = j.dst + (size_t)k * M * NP;
+    uint32_t m = 0x7f800000u;
+    for (int r = ty; r < 32; r += 8) {
+        const int i = i0 + r, o = o0 + tx;
+        const bool in = i < N && o < M;
+        const float x = in ? Bk[(size_t)i * M + o] : 0.0f;
+        tile[r][tx] = j.lg ? (in ? logf(x) : -INFINITY) : x;
+        if (in) m = min(m, __float_as_uint(x));
+    }
+    if (j.bmin) {
+        for (int off = 32; off >= 1; off >>= 1) m = min(m, (uint32_t)__shfl_xor((int)m, off, WAVE));
+        const int t = ty * 32 + tx;
+        if ((t & (WAVE - 1)) == 0) wmin[t / WAVE] = m;
+    }
+    __syncthreads();
+    if (j.bmin && tx == 0 && ty == 0) atomicMin(&j.bmin[k], min(min(wmin[0], wmin[1]), min(wmin[2], wmin[3])));
+    for (int r = ty; r < 32; r += 8) {
+        const int o = o0 + r, i = i0 + tx;
+        if (o < M && i < NP) dk[(size_t)o * NP + i] = tile[tx][r];
+    }
+}
+
+__device__ __forceinline__ void transpose_block(const TransposeJob &j, int blk, int tx, int ty) {
+    __shared__ float tile[32][33];
+    __shared__ uint32_t wmin[4];
+    const int bx = (j.M + 31) / 32, by = (j.NP + 31) / 32;
+    const int k = blk / (bx * by), r = blk % (bx * by);
+    transpose_tile(j, k, (r % bx) * 32, (r / bx) * 32, tx, ty, tile, wmin);
+}
+
+__global__ void __launch_bounds__(256) k_transpose(TransposeJob j) {
+    transpose_block(j, blockIdx.x, threadIdx.x & 31, threadIdx.x >> 5);
+}
+
+// Blocks below count_blocks count sequences into cnt; the blocks behind them
+// transpose the emission table (the two jobs are independent; one launch).
+__global__ void __launch_bounds__(256) k_plan_count(DevPtrs d, int S, int K, int groups, int max_len, int64_t total,
+                                                    int chunk, int nchunks, int32_t *cnt, int32_t *err,
+                                                    int count_blocks, TransposeJob tj) {
+    if ((int)blockIdx.x >= count_blocks) {
+        transpose_block(tj, blockIdx.x - count_blocks, threadIdx.x & 31, threadIdx.x >> 5);
+        return;
+    }
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= S) return;
     bool bad;
@@ -289,57 +342,6 @@ __global__ void __launch_bounds__(256) k_plan_scatter_wave(DevPtrs d, int S, int
     if (valid) perm[cnt[(int64_t)b * nchunks + c] + rank] = s;
 }
 
-// Bt[k][o][i] = B[k][i][o] for i < N, 0 for N <= i < NP (32x32 tiles through LDS),
-// and, when bmin is given, bmin[k] = bits of the smallest B[k][i][o] (non-negative
-// floats order like their bit patterns; bmin starts at +inf).
-__global__ void k_transpose_b(const float *B, float *bt, int N, int M, int NP, uint32_t *bmin) {
-    __shared__ float tile[32][33];
-    __shared__ uint32_t wmin[4];
-    const int k = blockIdx.z;
-    const int o0 = blockIdx.x * 32, i0 = blockIdx.y * 32;
-    const float *Bk = B + (size_t)k * N * M;
-    float *btk = bt + (size_t)k * M * NP;
-    uint32_t m = 0x7f800000u;
-    for (int r = threadIdx.y; r < 32; r += 8) {
-        int i = i0 + r, o = o0 + threadIdx.x;
-        const bool in = i < N && o < M;
-        const float x = in ? Bk[(size_t)i * M + o] : 0.0f;
-        tile[r][threadIdx.x] = x;
-        if (in) m = min(m, __float_as_uint(x));
-    }
-    if (bmin) {
-        for (int off = 32; off >= 1; off >>= 1) m = min(m, (uint32_t)__shfl_xor((int)m, off, WAVE));
-        const int t = threadIdx.y * 32 + threadIdx.x;
-        if ((t & (WAVE - 1)) == 0) wmin[t / WAVE] = m;
-    }
-    __syncthreads();
-    if (bmin && threadIdx.x == 0 && threadIdx.y == 0)
-        atomicMin(&bmin[k], min(min(wmin[0], wmin[1]), min(wmin[2], wmin[3])));
-    for (int r = threadIdx.y; r < 32; r += 8) {
-        int o = o0 + r, i = i0 + threadIdx.x;
-        if (o < M && i < NP) btk[(size_t)o * NP + i] = tile[threadIdx.x][r];
-    }
-}
-
-// lnbt[k][o][i] = ln B[k][i][o] for i < N, -inf for N <= i < NP (the emission
-// table of the log-domain decoder).
-__global__ void k_log_transpose_b(const float *B, float *lnbt, int N, int M, int NP) {
-    __shared__ float tile[32][33];
-    const int k = blockIdx.z;
-    const int o0 = blockIdx.x * 32, i0 = blockIdx.y * 32;
-    const float *Bk = B + (size_t)k * N * M;
-    float *dst = lnbt + (size_t)k * M * NP;
-    for (int r = threadIdx.y; r < 32; r += 8) {
-        const int i = i0 + r, o = o0 + threadIdx.x;
-        tile[r][threadIdx.x] = (i < N && o < M) ? logf(Bk[(size_t)i * M + o]) : -INFINITY;
-    }
-    __syncthreads();
-    for (int r = threadIdx.y; r < 32; r += 8) {
-        const int o = o0 + r, i = i0 + threadIdx.x;
-        if (o < M && i < NP) dst[(size_t)o * NP + i] = tile[threadIdx.x][r];
-    }
-}
-
 // cnt_B[k][i][o] for i < N, o < M from the symbol-major emission counts: the
 // per-tile partials of model k's tiles summed in tile order (slab), or the
 // fixed-point sums; NaN for a model flagged as having received a non-finite
@@ -555,7 +557,7 @@ void plan_chunking(int S, int64_t nbins, int *chunk, int *nchunks) {
 }
 
 void launch_plan(const DevPtrs &d, int K, int S, int groups, int max_len, int64_t total, int nbins,
-                 unsigned char *ws, const Layout &L, hipStream_t st) {
+                 unsigned char *ws, const Layout &L, hipStream_t st, const TransposeJob *tj) {
     int32_t *err = (int32_t *)(ws + L.err);
     int32_t *queue = (int32_t *)(ws + L.queue);
     int32_t *cnt = (int32_t *)(ws + L.hist);
@@ -566,10 +568,15 @@ void launch_plan(const DevPtrs &d, int K, int S, int groups, int max_len, int64_
     const int64_t m = n > queue_heads(K) ? n : queue_heads(K);
     int nb = blocks_for(m, 256);
     if (nb > 4096) nb = 4096;
-    hipLaunchKernelGGL(k_plan_init, dim3(nb), dim3(256), 0, st, cnt, n, queue, (int)queue_heads(K), err);
-    if (S > 0)
-        hipLaunchKernelGGL(k_plan_count, dim3(blocks_for(S, 256)), dim3(256), 0, st, d, S, K, groups, max_len, total,
-                           chunk, nchunks, cnt, err);
+    TransposeJob none;
+    memset(&none, 0, sizeof(none));
+    const TransposeJob &j = tj ? *tj : none;
+    hipLaunchKernelGGL(k_plan_init, dim3(nb), dim3(256), 0, st, cnt, n, queue, (int)queue_heads(K), err, j.bmin, K);
+    const int count_blocks = blocks_for(S, 256);
+    const int tblocks = tj ? transpose_blocks(*tj, K) : 0;
+    if (count_blocks + tblocks > 0)
+        hipLaunchKernelGGL(k_plan_count, dim3(count_blocks + tblocks), dim3(256), 0, st, d, S, K, groups, max_len,
+                           total, chunk, nchunks, cnt, err, count_blocks, j);
     if (n <= PLAN_SCAN_ONE) {
         hipLaunchKernelGGL(k_plan_scan_one, dim3(1), dim3(1024), 0, st, cnt, n, nchunks, max_len + 1, groups, gstart);
     } else {
@@ -588,15 +595,11 @@ void launch_plan(const DevPtrs &d, int K, int S, int groups, int max_len, int64_
                            nchunks, cnt, perm);
 }
 
-void launch_transpose_b(const float *B, float *bt, int K, int N, int M, int NP, hipStream_t st, uint32_t *bmin) {
-    if (bmin) launch_fill_i32((int32_t *)bmin, (size_t)K, 0x7f800000, st);
-    dim3 grid((M + 31) / 32, (NP + 31) / 32, K);
-    hipLaunchKernelGGL(k_transpose_b, grid, dim3(32, 8), 0, st, B, bt, N, M, NP, bmin);
-}
+int transpose_blocks(const TransposeJob &j, int K) { return ((j.M + 31) / 32) * ((j.NP + 31) / 32) * K; }
 
-void launch_log_transpose_b(const float *B, float *lnbt, int K, int N, int M, int NP, hipStream_t st) {
-    dim3 grid((M + 31) / 32, (NP + 31) / 32, K);
-    hipLaunchKernelGGL(k_log_transpose_b, grid, dim3(32, 8), 0, st, B, lnbt, N, M, NP);
+void launch_transpose(const TransposeJob &j, int K, hipStream_t st) {
+    if (j.bmin) launch_fill_i32((int32_t *)j.bmin, (size_t)K, 0x7f800000, st);
+    hipLaunchKernelGGL(k_transpose, dim3(transpose_blocks(j, K)), dim3(256), 0, st, j);
 }
 
 void launch_counts_finish(const AdjLaunch &a, bool slab, float *cnt_pi, float *cnt_A, float *cnt_B, hipStream_t st) {
