@@ -427,9 +427,17 @@ def main():
         kv5_s = kv5_ms / max(kv5_n, 1) / 1e3
         large["viterbi"] = {"value": u5 / sv5, "unit": "state-steps/s", "ms_per_step": sv5 * 1e3,
                             "kernels_ms": kv5_s * 1e3,  # decoder + traceback
+                            "workspace_bytes": wsv5.numel(),
                             "roofline": {"bound": "alu", "achieved": round(2.0 * u5 / kv5_s / 1e12, 3),
                                          "peak": VALU_PEAK_TOPS, "unit": "Tops/s",
                                          "frac": round(2.0 * u5 / kv5_s / 1e12 / VALU_PEAK_TOPS, 4)}}
+        # the same decode with room for every delta row (one round) for comparison
+        del wsv5
+        wsv5 = p5.viterbi_workspace(w5.total_symbols)
+        fv5()
+        torch.cuda.synchronize()
+        large["viterbi"]["one_round"] = {"ms_per_step": time_steps(fv5, 2, 0, torch) * 1e3,
+                                         "workspace_bytes": wsv5.numel()}
         del wsv5, scv5, pav5
     if want("large") or want("large_viterbi"):
         result["large_states"] = large
@@ -512,9 +520,16 @@ def main():
                                          "score + path (N=32)",
                              "value": uv / sv, "unit": "state-steps/s", "ms_per_step": sv * 1e3,
                              "kernels_ms": kv_s * 1e3,  # decoder + traceback, HIP events around both
+                             "workspace_bytes": wsv.numel(),
                              "roofline": {"bound": "alu", "achieved": round(2.0 * uv / kv_s / 1e12, 3),
                                           "peak": VALU_PEAK_TOPS, "unit": "Tops/s",
                                           "frac": round(2.0 * uv / kv_s / 1e12 / VALU_PEAK_TOPS, 4)}}
+        del wsv
+        wsv = p3o.viterbi_workspace(w.total_symbols)
+        fv()
+        torch.cuda.synchronize()
+        result["viterbi"]["one_round"] = {"ms_per_step": time_steps(fv, 5, 0, torch) * 1e3,
+                                          "workspace_bytes": wsv.numel()}
         del p3o, wsv, scv, pav
 
     if want("em"):

@@ -32,8 +32,9 @@
  *    synchronises, or reads device memory back, except hmm_workspace_error.
  *    Calls may therefore be captured into a HIP graph.
  *  - Scratch memory is the caller's workspace `ws` of `ws_bytes` bytes, at
- *    least hmm_workspace_size(...) for the same bank, batch and op, 256-byte
- *    aligned.  Two calls in flight at once need two workspaces.
+ *    least hmm_workspace_size(...) for the same bank, batch and op (Viterbi
+ *    decoding also takes less, see hmm_viterbi), 256-byte aligned.  Two calls
+ *    in flight at once need two workspaces.
  *  - Host-checkable problems (null pointer, shape out of range, workspace too
  *    small) return a negative status and enqueue nothing.
  *  - Data problems found on the device (a symbol outside [0, M), a negative
@@ -185,14 +186,28 @@ hmm_status hmm_forward_backward_grad(const hmm_bank *bank, const hmm_batch *batc
  * path the tie rule produces); an invalid symbol or model index gives score
  * NaN, path entries -1 and the error word in ws.  Every N up to
  * HMM_MAX_STATES: up to 64 states one wave decodes 64 / N sequences, above a
- * workgroup decodes one sequence.  The workspace (op HMM_OP_VITERBI) holds the
- * FP32 delta row of every step (states padded to 16, 32, 64, 128 or 256):
- * total_symbols * 4 * padded states bytes, up to 1 KiB per symbol at 256
- * states, plus ln A transposed above 64 states.  The sequences must not
- * overlap in `symbols`: their delta rows and path entries take the symbols'
- * layout. */
+ * workgroup decodes one sequence.  The traceback reads the FP32 delta row of
+ * every step (states padded to 16, 32, 64, 128 or 256; 1 KiB per step at 256
+ * states), which the workspace holds for as many steps as it has room for.
+ * With room for every row the batch is decoded in one round; otherwise the
+ * sequences are decoded longest first in rounds whose rows fit one half of
+ * the rows, each round traced back while the next one is decoded in the other
+ * half.  Any workspace from hmm_viterbi_workspace_size(bank, batch,
+ * min(total_symbols, 2 max_len)) up is accepted (ws_bytes decides the rounds;
+ * results do not depend on it).  hmm_workspace_size(..., HMM_OP_VITERBI)
+ * gives room for every row when they take at most 4 GiB, else for 1.8 GiB of
+ * rows.  The sequences must not overlap in `symbols`: their path entries take
+ * the symbols' layout (overlapping sequences may also be left undecoded,
+ * reported as invalid). */
 hmm_status hmm_viterbi(const hmm_bank *bank, const hmm_batch *batch, float *score, int32_t *path,
                        void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Bytes of workspace with which hmm_viterbi keeps `rows` delta rows per round
+ * (one row per decoded step; rows above total_symbols count as total_symbols).
+ * Returns 0 if the shapes are out of range or rows < min(total_symbols,
+ * 2 max_len) (one round, or two halves that each hold the longest
+ * sequence).  Host only. */
+size_t hmm_viterbi_workspace_size(const hmm_bank *bank, const hmm_batch *batch, int64_t rows);
 
 /* Row-wise softmax of FP32 logits: probs[r][c] = exp(z[r][c]) / sum_c' exp(z[r][c']).
  * The parameterisation of the gradient entry point's logits. */
@@ -218,7 +233,8 @@ hmm_status hmm_reestimate_rows(const float *n, const float *old, float *out, int
  * independent and run side by side, Sec. 3 item 3; the list groups the pairs
  * and sorts them by length so that tiles of consecutive entries advance in
  * step).  order [S]: sequence indices grouped by owning model (one group when
- * op is HMM_OP_CLASSIFY or HMM_OP_FORWARD without model_of_seq), each group
+ * op is HMM_OP_CLASSIFY, HMM_OP_FORWARD without model_of_seq or
+ * HMM_OP_VITERBI, whose decoders take each sequence's own model), each group
  * sorted by decreasing length, equal lengths in increasing index order (a
  * stable sort, so the list and every tile of it depend on the batch alone).
  * An invalid sequence sorts as length 0 of its group (of group 0 when its model

@@ -171,10 +171,12 @@ hmm_status check_pointers(const hmm_bank *b, const hmm_batch *q) {
     return HMM_OK;
 }
 
-// groups: 1 when every sequence meets every model, else K
+// groups: 1 when every sequence meets every model or, for Viterbi decoding,
+// when the work list holds every sequence longest first whatever its model;
+// else K
 int plan_groups(const hmm_bank *b, const hmm_batch *q, int op) {
-    if (op == HMM_OP_CLASSIFY) return 1;
-    if (op == HMM_OP_GRAD || op == HMM_OP_VITERBI) return b->K;
+    if (op == HMM_OP_CLASSIFY || op == HMM_OP_VITERBI) return 1;
+    if (op == HMM_OP_GRAD) return b->K;
     return q->model_of_seq ? b->K : 1;
 }
 
@@ -195,10 +197,7 @@ inline int viterbi_states(int N) {
 }
 
 bool batched_capable(const hmm_bank *b, const hmm_batch *q, int op) {
-    if (op == HMM_OP_VITERBI) {
-        const int64_t nbins = (int64_t)b->K * ((int64_t)q->max_len + 1);
-        return viterbi_states(b->N) > 0 && nbins <= MAX_PLAN_BINS;
-    }
+    if (op == HMM_OP_VITERBI) return viterbi_states(b->N) > 0 && (int64_t)q->max_len + 1 <= MAX_PLAN_BINS;
     const int NP = padded_states(b->N);
     if (!fwd_mfma_supported(NP) && !fwd_coop_supported(NP)) return false;
     if (op == HMM_OP_GRAD && !(grad_uses_coop(NP) ? adj_coop_supported(NP) : adj_mfma_supported(NP))) return false;
@@ -224,7 +223,28 @@ hmm_status scan_choice(const hmm_bank *b, const hmm_batch *q, int op, int kind, 
     return HMM_OK;
 }
 
-Layout make_layout(const hmm_bank *b, const hmm_batch *q, int op) {
+// Viterbi delta rows the workspace holds.  Every row (one round) when they
+// take at most VIT_ONE_ROUND_BYTES, else VIT_ROUND_BYTES' worth (rounds in
+// two halves); never fewer than viterbi_min_rows.
+constexpr size_t VIT_ONE_ROUND_BYTES = (size_t)4 << 30;   // 4 GiB
+constexpr size_t VIT_ROUND_BYTES = (size_t)1843 << 20;    // 1.8 GiB
+
+int64_t vit_min_rows(const hmm_batch *q) { return viterbi_min_rows(q->max_len, q->total_symbols); }
+
+int64_t vit_max_rows(const hmm_batch *q) {
+    const int64_t lo = vit_min_rows(q);
+    return q->total_symbols > lo ? q->total_symbols : lo;
+}
+
+int64_t vit_default_rows(const hmm_bank *b, const hmm_batch *q) {
+    const int NP = viterbi_states(b->N);
+    const size_t row = (size_t)(NP > 0 ? NP : 1) * sizeof(float);
+    if ((size_t)vit_max_rows(q) * row <= VIT_ONE_ROUND_BYTES) return vit_max_rows(q);
+    const int64_t rows = (int64_t)(VIT_ROUND_BYTES / row);
+    return rows > vit_min_rows(q) ? rows : vit_min_rows(q);
+}
+
+Layout make_layout(const hmm_bank *b, const hmm_batch *q, int op, int64_t vit_rows = -1) {
     Layout L;
     memset(&L, 0, sizeof(L));
     size_t o = 0;
@@ -255,8 +275,11 @@ Layout make_layout(const hmm_bank *b, const hmm_batch *q, int op) {
         L.bt = take((size_t)K * M * NP * sizeof(float));
         L.bmin = take((size_t)K * sizeof(uint32_t));
         if (op == HMM_OP_VITERBI) {
-            L.delta = take(((size_t)q->total_symbols * NP + 64) * sizeof(float));
-            if (NP > 64) L.lnat = take((size_t)K * b->N * NP * sizeof(float));
+            L.vit_rows = vit_rows >= 0 ? vit_rows : vit_default_rows(b, q);
+            L.delta = take(((size_t)L.vit_rows * NP + 64) * sizeof(float));
+            L.lnat = take((size_t)K * b->N * NP * sizeof(float));
+            L.rowpos = take(((size_t)S + 1) * sizeof(int64_t));
+            L.rowsum = take(((size_t)S + 8191) / 8192 * sizeof(int64_t) + sizeof(int64_t));
         }
         if (op == HMM_OP_GRAD) {
             int nck = 1;
@@ -620,6 +643,29 @@ hmm_status hmm_forward_backward_grad(const hmm_bank *bank, const hmm_batch *batc
     return hipGetLastError() == hipSuccess ? HMM_OK : HMM_ERR_HIP;
 }
 
+// Delta rows of the largest Viterbi layout that fits ws_bytes (every row at
+// most), or -1 when not even the smallest fits.
+int64_t vit_rows_for(const hmm_bank *b, const hmm_batch *q, size_t ws_bytes) {
+    int64_t lo = vit_min_rows(q), hi = vit_max_rows(q);
+    if (make_layout(b, q, HMM_OP_VITERBI, lo).total > ws_bytes) return -1;
+    if (make_layout(b, q, HMM_OP_VITERBI, hi).total <= ws_bytes) return hi;
+    while (hi - lo > 1) {  // the layout grows with the rows: fits at lo, not at hi
+        const int64_t mid = lo + (hi - lo) / 2;
+        if (make_layout(b, q, HMM_OP_VITERBI, mid).total <= ws_bytes)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+size_t hmm_viterbi_workspace_size(const hmm_bank *bank, const hmm_batch *batch, int64_t rows) {
+    if (check_shapes(bank, batch) != HMM_OK) return 0;
+    if (rows < vit_min_rows(batch)) return 0;
+    if (rows > vit_max_rows(batch)) rows = vit_max_rows(batch);
+    return make_layout(bank, batch, HMM_OP_VITERBI, rows).total;
+}
+
 hmm_status hmm_viterbi(const hmm_bank *bank, const hmm_batch *batch, float *score, int32_t *path, void *ws,
                        size_t ws_bytes, hipStream_t stream) {
     hmm_status rc = check_shapes(bank, batch);
@@ -627,18 +673,19 @@ hmm_status hmm_viterbi(const hmm_bank *bank, const hmm_batch *batch, float *scor
     if ((rc = check_pointers(bank, batch)) != HMM_OK) return rc;
     if (batch->S > 0 && (!batch->model_of_seq || !score)) return HMM_ERR_NULL;
     if (batch->total_symbols > 0 && !path) return HMM_ERR_NULL;
-    const Layout L = make_layout(bank, batch, HMM_OP_VITERBI);
-    if ((rc = check_ws(ws, ws_bytes, L)) != HMM_OK) return rc;
     if (!batched_capable(bank, batch, HMM_OP_VITERBI)) return HMM_ERR_UNSUPPORTED;
+    // the delta rows of a round: as many as the workspace holds
+    const int64_t rows = vit_rows_for(bank, batch, ws ? ws_bytes : 0);
+    const Layout L = make_layout(bank, batch, HMM_OP_VITERBI, rows < 0 ? vit_min_rows(batch) : rows);
+    if ((rc = check_ws(ws, ws_bytes, L)) != HMM_OK) return rc;
     unsigned char *w = (unsigned char *)ws;
     const int K = bank->K, N = bank->N, M = bank->M, S = batch->S, NP = viterbi_states(N);
     DevPtrs d = dev_ptrs(bank, batch, true);
-    const int nbins = K * (batch->max_len + 1);
+    const int nbins = batch->max_len + 1;
     const TransposeJob tj{bank->B, (float *)(w + L.bt), N, M, NP, 1, nullptr};
-    launch_plan(d, K, S, K, batch->max_len, batch->total_symbols, nbins, w, L, stream, &tj);
+    launch_plan(d, K, S, 1, batch->max_len, batch->total_symbols, nbins, w, L, stream, &tj);
     // ln A transposed: the same transpose with A's N columns in place of B's M
-    if (NP > 64) launch_transpose(TransposeJob{bank->A, (float *)(w + L.lnat), N, N, NP, 1, nullptr}, K, stream);
-    launch_fill_i32((int32_t *)(w + L.queue) + queue_heads(K), (size_t)K, 0, stream);  // the traceback's queues
+    launch_transpose(TransposeJob{bank->A, (float *)(w + L.lnat), N, N, NP, 1, nullptr}, K, stream);
     if (hipGetLastError() != hipSuccess) return HMM_ERR_HIP;
     VitLaunch v;
     memset(&v, 0, sizeof(v));
@@ -650,15 +697,17 @@ hmm_status hmm_viterbi(const hmm_bank *bank, const hmm_batch *batch, float *scor
     v.max_len = batch->max_len;
     v.total = batch->total_symbols;
     v.perm = (const int32_t *)(w + L.perm);
-    v.gstart = (const int32_t *)(w + L.gstart);
-    v.queue = (int32_t *)(w + L.queue);
+    v.rowpos = (const int64_t *)(w + L.rowpos);
+    v.rowsum = (int64_t *)(w + L.rowsum);
+    v.state = (int32_t *)(w + L.queue);  // zeroed by the planner
     v.err = (int32_t *)(w + L.err);
     v.lnbt = (const float *)(w + L.bt);
-    v.lnat = NP > 64 ? (const float *)(w + L.lnat) : nullptr;
+    v.lnat = (const float *)(w + L.lnat);
     v.delta = (float *)(w + L.delta);
-    v.spill = v.delta + (size_t)batch->total_symbols * NP;
+    v.spill = v.delta + (size_t)L.vit_rows * NP;
     v.score = score;
     v.path = path;
+    v.cap_rows = L.vit_rows;
     const int cus = device_cu_count();
     v.max_grid = max_grid(L.wg_per_cu, cus);
     const int pr = prof_begin(stream, HMM_PROF_VITERBI);

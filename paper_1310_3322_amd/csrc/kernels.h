@@ -30,8 +30,11 @@ struct Layout {
     size_t wmax;     // uint32 bits of max_s |w_s| (gradient)
     int32_t slab_on;     // the gradient's backward kernel writes per-tile partials into the slab
     size_t frag;     // float4 [K][2][NP^2 / 4] streamed MFMA fragments (cooperative gradient, NP > 128)
-    size_t delta;    // float [total][NP] Viterbi delta rows (bt then holds ln B transposed), then 64 spare floats
-    size_t lnat;     // float [K][N][NP] ln A transposed (Viterbi, NP > 64)
+    size_t delta;    // float [vit_rows][NP] Viterbi delta rows of one round (bt then holds ln B transposed), then 64 spare floats
+    size_t lnat;     // float [K][N][NP] ln A transposed (Viterbi)
+    size_t rowpos;   // int64 [S + 1] rows stored before each work-list entry (Viterbi)
+    size_t rowsum;   // int64 [ceil(S / 8192)] block sums of that prefix (Viterbi)
+    int64_t vit_rows;    // delta rows one Viterbi round may store
     size_t scan;     // time-parallel forward: chunk products, exponents, flags (ScanWs)
     int32_t scan_nch;    // chunks per pair of the time-parallel forward (0: not used)
     int32_t kind;        // kernel family of the call (HMM_KERNEL_*, after the tuning table)
@@ -251,17 +254,24 @@ hipError_t launch_adj_mfma(const DevPtrs &d, const AdjLaunch &a, int cu_count, h
 struct VitLaunch {
     int K, N, M, NP, S, max_len;
     int64_t total;
-    const int32_t *perm, *gstart;
-    int32_t *queue, *err;
+    const int32_t *perm;     // [S] work list: sequence ids, longest first (all models together)
+    const int64_t *rowpos;   // [S + 1] delta rows of the work-list entries before each one
+    int64_t *rowsum;         // [ceil(S / 8192)] block sums while rowpos is formed
+    int32_t *state;          // [VIT_STATE_WORDS] queue heads and the entries of the current and previous round
+    int32_t *err;
     const float *lnbt;  // [K][M][NP] ln B transposed, -inf beyond N
-    const float *lnat;  // [K][N][NP] ln A transposed, lnat[k][j][i] = ln A_k[i][j], -inf beyond N (NP > 64)
-    float *delta;       // [total][NP] delta row of every step but the last, laid out like the symbols
+    const float *lnat;  // [K][N][NP] ln A transposed, lnat[k][j][i] = ln A_k[i][j], -inf beyond N
+    float *delta;       // [cap_rows][NP] delta rows of the round's sequences, each from its rowpos offset
     float *spill;       // [64] target of the delta stores of empty slots (never read)
     float *score;       // [S]
     int32_t *path;      // [total]
+    int64_t cap_rows;   // delta rows the array holds (at least viterbi_min_rows)
+    int64_t half_rows;  // rows of each half when rounds alternate halves (0: one round holds every row)
     int max_grid;       // cap on the persistent grid (0: occupancy limit)
 };
+constexpr int VIT_STATE_WORDS = 9;
 bool viterbi_supported(int NP);
+int64_t viterbi_min_rows(int64_t max_len, int64_t total);
 hipError_t launch_viterbi(const DevPtrs &d, const VitLaunch &v, int cu_count, hipStream_t st);
 
 }  // namespace hmm

@@ -22,7 +22,7 @@ STATUS = {0: "HMM_OK", -1: "HMM_ERR_NULL", -2: "HMM_ERR_SHAPE", -3: "HMM_ERR_WOR
           -4: "HMM_ERR_UNSUPPORTED", -5: "HMM_ERR_HIP", -6: "HMM_ERR_ARG"}
 OP_FORWARD, OP_CLASSIFY, OP_GRAD, OP_VITERBI = 0, 1, 2, 3
 KERNEL_AUTO, KERNEL_PLAIN, KERNEL_BATCHED, KERNEL_TILE16, KERNEL_TILE32, KERNEL_COOP, KERNEL_SCAN = 0, 1, 2, 3, 4, 5, 6
-EXPORTS = ("hmm_workspace_size", "hmm_forward_loglik", "hmm_classify", "hmm_classify_noalloc", "hmm_forward_backward_grad",
+EXPORTS = ("hmm_workspace_size", "hmm_viterbi_workspace_size", "hmm_forward_loglik", "hmm_classify", "hmm_classify_noalloc", "hmm_forward_backward_grad",
            "hmm_viterbi", "hmm_plan_order", "hmm_reestimate_rows", "hmm_softmax_rows", "hmm_logit_grad", "hmm_workspace_error", "hmm_select_kernel",
            "hmm_tune_key_of", "hmm_tune_set", "hmm_tune_get", "hmm_tune_clear", "hmm_call_kernel",
            "hmm_profile_enable", "hmm_profile_read", "hmm_status_string")
@@ -77,6 +77,8 @@ def load_library(path: str = LIB_PATH):
     st = ctypes.c_int
     lib.hmm_workspace_size.restype = ctypes.c_size_t
     lib.hmm_workspace_size.argtypes = [BP, QP, ctypes.c_int]
+    lib.hmm_viterbi_workspace_size.restype = ctypes.c_size_t
+    lib.hmm_viterbi_workspace_size.argtypes = [BP, QP, ctypes.c_int64]
     lib.hmm_forward_loglik.restype = st
     lib.hmm_forward_loglik.argtypes = [BP, QP, P, P, ctypes.c_size_t, P]
     lib.hmm_classify.restype = st
@@ -198,6 +200,17 @@ class Problem:
         n = self.workspace_size(op, batch)
         if n == 0:
             raise HMMError("hmm_workspace_size", -2)
+        return torch.empty(n, dtype=torch.uint8, device=self.pi.device)
+
+    def viterbi_workspace_size(self, rows: int) -> int:
+        """Workspace bytes with which Viterbi decoding keeps `rows` delta rows per round."""
+        return int(load_library().hmm_viterbi_workspace_size(ctypes.byref(self.bank), ctypes.byref(self.batch),
+                                                             int(rows)))
+
+    def viterbi_workspace(self, rows: int) -> torch.Tensor:
+        n = self.viterbi_workspace_size(rows)
+        if n == 0:
+            raise HMMError("hmm_viterbi_workspace_size", -2)
         return torch.empty(n, dtype=torch.uint8, device=self.pi.device)
 
 
@@ -328,7 +341,9 @@ def viterbi(p: Problem, score: Optional[torch.Tensor] = None, path: Optional[tor
             ws: Optional[torch.Tensor] = None, stream=None):
     """Most likely state path of each sequence under its own model.
 
-    Returns (score [S] = max_Q ln P(O, Q), path [total_symbols] int32 in the layout of the symbols)."""
+    Returns (score [S] = max_Q ln P(O, Q), path [total_symbols] int32 in the layout of the symbols).
+    ws: any workspace from p.viterbi_workspace_size(min(max_len, total_symbols)) bytes up; its
+    size sets how many delta rows a decoding round keeps (default p.workspace(OP_VITERBI))."""
     if p.model_of_seq is None:
         raise ValueError("Viterbi decoding needs model_of_seq")
     dev = p.pi.device
@@ -358,7 +373,7 @@ def plan_order(p: Problem, op: int, all_pairs: Optional[bool] = None, ws: Option
     if op == OP_CLASSIFY:
         own = False
     b = p.batch if own else p.batch_without_models()
-    groups = p.K if own else 1
+    groups = p.K if own and op != OP_VITERBI else 1  # Viterbi: all models in one list
     dev = p.pi.device
     order = torch.empty(p.S, dtype=torch.int32, device=dev)
     gstart = torch.empty(groups + 1, dtype=torch.int32, device=dev)

@@ -51,6 +51,14 @@ static void workspace_grid() {
                                 EXPECT(rc == HMM_OK || rc == HMM_ERR_UNSUPPORTED);
                                 hmm_tune_key key;
                                 EXPECT(hmm_tune_key_of(&b, &q, op, &key) == HMM_OK);
+                                if (op == HMM_OP_VITERBI) {
+                                    // the least and the most rows a round may keep
+                                    const int64_t lo = 2 * (int64_t)L < q.total_symbols ? 2 * (int64_t)L : q.total_symbols;
+                                    const size_t a = hmm_viterbi_workspace_size(&b, &q, lo);
+                                    const size_t z = hmm_viterbi_workspace_size(&b, &q, INT64_MAX);
+                                    EXPECT(a > 0 && a <= n && n <= z);
+                                    EXPECT(lo == 0 || hmm_viterbi_workspace_size(&b, &q, lo - 1) == 0);
+                                }
                             }
     // out-of-range shapes size nothing
     const hmm_batch q = batch(100, 50, 5000, false);
@@ -108,8 +116,22 @@ static void argument_checks() {
     EXPECT(hmm_viterbi(&b, &q, out, lab, ws, 1ull << 40, nullptr) == HMM_ERR_NULL);
     EXPECT(hmm_viterbi(&b, &qm, nullptr, lab, ws, 1ull << 40, nullptr) == HMM_ERR_NULL);
     EXPECT(hmm_viterbi(&b, &qm, out, nullptr, ws, 1ull << 40, nullptr) == HMM_ERR_NULL);
-    const size_t vneed = hmm_workspace_size(&b, &qm, HMM_OP_VITERBI);
-    EXPECT(hmm_viterbi(&b, &qm, out, lab, ws, vneed - 1, nullptr) == HMM_ERR_WORKSPACE);
+    const size_t vleast = hmm_viterbi_workspace_size(&b, &qm, 100);
+    EXPECT(vleast > 0 && vleast <= hmm_workspace_size(&b, &qm, HMM_OP_VITERBI));
+    EXPECT(hmm_viterbi(&b, &qm, out, lab, ws, vleast - 1, nullptr) == HMM_ERR_WORKSPACE);
+    EXPECT(hmm_viterbi(&b, &qm, out, lab, nullptr, 1ull << 40, nullptr) == HMM_ERR_WORKSPACE);
+    EXPECT(hmm_viterbi_workspace_size(&b, &qm, 99) == 0);
+    EXPECT(hmm_viterbi_workspace_size(nullptr, &qm, 100) == 0);
+    // work list: operation range, model_of_seq for own-model operations, outputs, workspace
+    int32_t *ord = reinterpret_cast<int32_t *>(0xa000);
+    EXPECT(hmm_plan_order(&b, &qm, 4, ord, lab, ws, 1ull << 40, nullptr) == HMM_ERR_ARG);
+    EXPECT(hmm_plan_order(&b, &qm, -1, ord, lab, ws, 1ull << 40, nullptr) == HMM_ERR_ARG);
+    EXPECT(hmm_plan_order(&b, &q, HMM_OP_GRAD, ord, lab, ws, 1ull << 40, nullptr) == HMM_ERR_NULL);
+    EXPECT(hmm_plan_order(&b, &q, HMM_OP_VITERBI, ord, lab, ws, 1ull << 40, nullptr) == HMM_ERR_NULL);
+    EXPECT(hmm_plan_order(&b, &qm, HMM_OP_FORWARD, nullptr, lab, ws, 1ull << 40, nullptr) == HMM_ERR_NULL);
+    EXPECT(hmm_plan_order(&b, &qm, HMM_OP_FORWARD, ord, nullptr, ws, 1ull << 40, nullptr) == HMM_ERR_NULL);
+    EXPECT(hmm_plan_order(&b, &qm, HMM_OP_FORWARD, ord, lab, ws, 16, nullptr) == HMM_ERR_WORKSPACE);
+    EXPECT(hmm_plan_order(nullptr, &qm, HMM_OP_FORWARD, ord, lab, ws, 1ull << 40, nullptr) == HMM_ERR_NULL);
     // row kernels
     EXPECT(hmm_reestimate_rows(out, out, out, -1, 4, nullptr) == HMM_ERR_SHAPE);
     EXPECT(hmm_reestimate_rows(nullptr, out, out, 3, 4, nullptr) == HMM_ERR_NULL);

@@ -107,22 +107,48 @@ def test_host_side_errors_enqueue_nothing(lib):
     assert lib.hmm_viterbi(ctypes.byref(b), ctypes.byref(q), out, out, ws_al, 1 << 40, None) == -1
     assert lib.hmm_viterbi(ctypes.byref(b), ctypes.byref(qm), None, out, ws_al, 1 << 40, None) == -1
     assert lib.hmm_viterbi(ctypes.byref(b), ctypes.byref(qm), out, None, ws_al, 1 << 40, None) == -1
+    # the default workspace holds every delta row here (5000 symbols x 16 padded states);
+    # anything down to two halves that each hold the longest sequence (2 x max_len = 100) is accepted
     need = lib.hmm_workspace_size(ctypes.byref(b), ctypes.byref(qm), 3)
-    assert need >= 5000 * 16  # one back-pointer byte per padded state and symbol
-    assert lib.hmm_viterbi(ctypes.byref(b), ctypes.byref(qm), out, out, ws_al, need - 1, None) == -3
+    assert need >= 5000 * 16 * 4
+    vws = lambda bank, batch, rows: lib.hmm_viterbi_workspace_size(ctypes.byref(bank), ctypes.byref(batch),
+                                                                   ctypes.c_int64(rows))
+    least = vws(b, qm, 100)
+    assert 0 < least < need
+    assert vws(b, qm, 99) == 0
+    assert vws(b, qm, 5000) == need == vws(b, qm, 10 ** 12)
+    assert lib.hmm_viterbi(ctypes.byref(b), ctypes.byref(qm), out, out, ws_al, least - 1, None) == -3
+    assert lib.hmm_viterbi(ctypes.byref(b), ctypes.byref(qm), out, out, None, need, None) == -3
     # every state count up to HMM_MAX_STATES decodes: the workspace holds the delta rows
-    # (states padded to 128 / 256) and, above 64 states, ln A transposed
+    # (states padded to 128 / 256) and ln A transposed
     for n, np_ in ((65, 128), (256, 256)):
         wide = hmm.Bank(4, n, 32, 0x1000, 0x2000, 0x3000)
         assert lib.hmm_workspace_size(ctypes.byref(wide), ctypes.byref(qm), 3) >= 5000 * np_ * 4 + 4 * n * np_ * 4
-    need = lib.hmm_workspace_size(ctypes.byref(big), ctypes.byref(ql), 3)
-    assert lib.hmm_viterbi(ctypes.byref(big), ctypes.byref(ql), out, out, ws_al, need, None) == -4
     assert lib.hmm_reestimate_rows(out, out, out, -1, 4, None) == -2
     assert lib.hmm_reestimate_rows(None, out, out, 3, 4, None) == -1
     # softmax / logit-grad shape checks
     assert lib.hmm_softmax_rows(out, out, -1, 4, None) == -2
     assert lib.hmm_logit_grad(out, out, out, 4, 0, None) == -2
     assert lib.hmm_workspace_error(None, None, None) == -1
+
+
+def test_viterbi_workspace_is_bounded(lib):
+    """Viterbi's default workspace stays under 2 GB for 16 models of 256 states and 16,384
+    sequences of up to 4096 steps (36 GB of delta rows, decoded in rounds), and grows with
+    the rows a round may keep, up to every row."""
+    b = hmm.Bank(16, 256, 1024, 0x1000, 0x2000, 0x3000)
+    total = 16384 * 2176
+    q = hmm.Batch(16384, 0x4000, 0x5000, 0x6000, 0x7000, 4096, total)
+    vws = lambda rows: lib.hmm_viterbi_workspace_size(ctypes.byref(b), ctypes.byref(q), ctypes.c_int64(rows))
+    dflt = lib.hmm_workspace_size(ctypes.byref(b), ctypes.byref(q), 3)
+    assert 0 < dflt <= 2_000_000_000
+    assert vws(total) >= total * 256 * 4 > dflt
+    prev = 0
+    for rows in (8192, 100_000, 1 << 21, total):
+        n = vws(rows)
+        assert n > prev and n >= rows * 1024
+        prev = n
+    assert vws(8191) == 0
 
 
 def test_kernel_selector(lib):
@@ -267,10 +293,9 @@ def test_call_kernel_resolution(lib):
         assert hmm.call_kernel(hmm.Bank(8, 32, 64, 1, 2, 3), one, hmm.OP_VITERBI) == hmm.KERNEL_BATCHED
         # above 64 states the workgroup decoder (the batched family as well)
         assert hmm.call_kernel(hmm.Bank(8, 100, 64, 1, 2, 3), one, hmm.OP_VITERBI) == hmm.KERNEL_BATCHED
-        with pytest.raises(hmm.HMMError) as e:  # a plan beyond the bin limit
-            hmm.call_kernel(hmm.Bank(64, 100, 64, 1, 2, 3), hmm.Batch(100, 4, 5, 6, 7, 1 << 20, 5000),
-                            hmm.OP_VITERBI)
-        assert e.value.status == -4
+        # one work list for all models: every max_len up to HMM_MAX_LEN fits the planner's bins
+        assert hmm.call_kernel(hmm.Bank(64, 100, 64, 1, 2, 3), hmm.Batch(100, 4, 5, 6, 7, 1 << 20, 5000),
+                               hmm.OP_VITERBI) == hmm.KERNEL_BATCHED
         # the table
         hmm.tune_set(hmm.tune_key(c3b, c3q, hmm.OP_CLASSIFY), hmm.KERNEL_TILE16, 2)
         assert hmm.call_kernel(c3b, c3q, hmm.OP_CLASSIFY) == hmm.KERNEL_TILE16

@@ -243,3 +243,70 @@ def test_viterbi_c5_bank_sampled():
     rng = np.random.default_rng(5)
     pick = np.unique(np.concatenate([order[:2], order[-2:], rng.choice(w.S, 6, replace=False)]))
     _sampled(w, pick, "c5 5% batch, sampled", None)
+
+
+def _decode(p, ws):
+    sc, path = hmm.viterbi(p, ws=ws)
+    return sc.cpu().numpy(), path.cpu().numpy(), hmm.workspace_error(ws)
+
+
+@pytest.mark.parametrize("N", [5, 20, 33, 64, 100, 256])
+def test_viterbi_rounds_match_one_round(N):
+    """A workspace that keeps the delta rows of only a few sequences at once (decoding in
+    many rounds) gives the scores, paths and error word of a workspace with room for every
+    row (one round), bit for bit, for both decoders.  Invalid entries ride along: a bad
+    symbol, a bad model index, lengths 0 and lengths beyond max_len (which store no rows)."""
+    print(f"[case] viterbi rounds N={N}", flush=True)
+    rng = np.random.default_rng(200 + N)
+    lengths = rng.integers(1, 120, size=160).astype(np.int32)
+    lengths[[3, 40]] = 0
+    w = workloads.random_lengths_workload(rng, K=3, N=N, M=6, lengths=lengths, all_pairs=False)
+    max_len = 110                                   # longer sequences are invalid
+    sym = w.symbols.copy()
+    s_sym = int(np.flatnonzero((w.lengths > 5) & (w.lengths <= max_len))[0])
+    sym[w.offsets[s_sym] + 4] = 99                  # invalid symbol
+    owner = w.owner.copy()
+    owner[7] = 3                                    # invalid model index
+    p = hmm.Problem(dev(w.pi), dev(w.A), dev(w.B), dev(sym), dev(w.offsets), dev(w.lengths), dev(owner),
+                    max_len=max_len, total_symbols=w.total_symbols)
+    one = _decode(p, p.viterbi_workspace(w.total_symbols))
+    # sequences whose path range is written: a valid model and length (a bad symbol gives -1s)
+    ok = (owner < w.K) & (w.lengths <= max_len)
+    mask = np.zeros(w.total_symbols, bool)
+    for s in np.flatnonzero(ok):
+        mask[w.offsets[s]:w.offsets[s] + w.lengths[s]] = True
+    bad = {7, s_sym} | set(np.flatnonzero(w.lengths > max_len).tolist())
+    assert set(np.flatnonzero(np.isnan(one[0])).tolist()) == bad
+    assert np.all(one[1][w.offsets[s_sym]:w.offsets[s_sym] + w.lengths[s_sym]] == -1)
+    assert one[2] == min(bad)
+    for rows in (2 * max_len, 2 * max_len + 7, 3 * max_len, w.total_symbols // 4):
+        got = _decode(p, p.viterbi_workspace(rows))
+        assert np.array_equal(got[0], one[0], equal_nan=True), rows
+        assert np.array_equal(got[1][mask], one[1][mask]), rows
+        assert got[2] == one[2], rows
+
+
+def test_viterbi_c5_rounds_bounded_workspace():
+    """A quarter of the c5 batch (4096 sequences of 256..4096 steps, 256 states): the default
+    workspace (1.8 GiB of delta rows, several rounds), one of 1 GiB of rows and one with room
+    for every row (9 GB, one round) give identical scores and paths; sampled sequences
+    against the oracle."""
+    print("[case] viterbi c5 rounds", flush=True)
+    w = workloads.make_workload("c5", scale=0.25)
+    w.all_pairs = False
+    p = problem(w)
+    dflt = p.workspace(hmm.OP_VITERBI)
+    assert dflt.numel() <= 2_000_000_000
+    assert p.viterbi_workspace_size(w.total_symbols) > 4 * dflt.numel()
+    base = _decode(p, dflt)
+    for rows in (1 << 20, w.total_symbols):
+        got = _decode(p, p.viterbi_workspace(rows))
+        assert np.array_equal(got[0], base[0]) and np.array_equal(got[1], base[1]), rows
+        assert got[2] == base[2]
+    order = np.argsort(-w.lengths, kind="stable")
+    rng = np.random.default_rng(6)
+    pick = np.unique(np.concatenate([order[:2], order[-2:], rng.choice(w.S, 4, replace=False)]))
+    sub = w.subset(pick)
+    rs, rp, rm = O.viterbi(sub.pi, sub.A, sub.B, sub.symbols, sub.offsets, sub.lengths, sub.owner)
+    compare(w, pick, base[0].astype(np.float64), base[1], sub, sub.symbols, rs, rp, rm, None,
+            "c5 quarter batch, default workspace, sampled")
