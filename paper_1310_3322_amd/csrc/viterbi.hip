@@ -624,16 +624,18 @@ __device__ void vit_decode_wg(const DevPtrs &d, const VitLaunch &v, const VRound
                 syms[1][tid] = sq[min(WSCH + tid, tlim)];
             }
             __syncthreads();
-            for (int t = 0; t < T; ++t) {
+            // the symbol of step t (< T), checked once, from the staged chunks
+            auto sym_at = [&](int t) {
+                const int o = syms[(t / WSCH) & 1][t % WSCH];
+                symbad |= (o < 0 || o >= M);
+                return ((unsigned)o < (unsigned)M) ? o : 0;
+            };
+            auto step = [&](int t, float lb) {
                 if (t >= WSCH && (t % WSCH) == 0 && tid < WSCH) {
                     // chunk t / WSCH + 1 into the buffer of chunk t / WSCH - 1, whose last
-                    // reader, step t - 1, every thread has passed; read from step t + WSCH on
+                    // symbol was read before step t - 2; read from step t + WSCH - 1 on
                     syms[((t / WSCH) + 1) & 1][tid] = sq[min(t + WSCH + tid, tlim)];
                 }
-                int o = syms[(t / WSCH) & 1][t % WSCH];
-                symbad |= (o < 0 || o >= M);
-                o = ((unsigned)o < (unsigned)M) ? o : 0;
-                const float lb = lbk[(size_t)o * NP + j];
                 if (t == 0) {
                     del = lpi + lb;
                 } else {
@@ -674,6 +676,19 @@ __device__ void vit_decode_wg(const DevPtrs &d, const VitLaunch &v, const VRound
                 dl[t & 1][j + (j / IS) * (SLP - IS)] = del;
                 drow[(size_t)t * NP] = del;
                 lds_barrier();
+            };
+            // The emission term of a step is requested one step ahead (its
+            // gather from the emission table, which the models of a round share
+            // in the cache, then overlaps a step of work), in two registers
+            // that alternate so that no loaded value is copied.
+            float lb0 = lbk[(size_t)sym_at(0) * NP + j], lb1 = 0.0f;
+            for (int t = 0; t < T; t += 2) {
+                if (t + 1 < T) lb1 = lbk[(size_t)sym_at(t + 1) * NP + j];
+                step(t, lb0);
+                if (t + 1 < T) {
+                    if (t + 2 < T) lb0 = lbk[(size_t)sym_at(t + 2) * NP + j];
+                    step(t + 1, lb1);
+                }
             }
         }
         // last state: the first state attaining the maximum of delta_T
