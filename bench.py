@@ -69,33 +69,120 @@ FAMILY_KERNELS = {
     "tile16": ("k_fwd_mfma<2, true, false>", "16-sequence-tile batched forward",
                ["paper_1310_3322_amd/csrc/fwd_mfma.hip"] + _COMMON),
 }
+# The kernels whose HBM traffic profiles/traffic.json records, by workload: the
+# kernel as rocprofv3 names it and the files its code comes from.
+_FWD_COOP = ["paper_1310_3322_amd/csrc/fwd_coop.hip", "paper_1310_3322_amd/csrc/coop_step.cuh"] + _COMMON
+_ADJ_COOP = ["paper_1310_3322_amd/csrc/adj_coop.hip", "paper_1310_3322_amd/csrc/coop_step.cuh"] + _COMMON
+TRAFFIC_KERNELS = {
+    "c3_classify": ("k_fwd_mfma32<1, true>", FAMILY_KERNELS["tile32"][2]),
+    "c4_grad_forward": ("k_fwd_coop<4, 1, true>", _FWD_COOP),
+    "c4_grad_adjoint": ("k_adj_pipe<4>", _ADJ_COOP),
+    "c5_forward": ("k_fwd_coop<16, 2, false>", _FWD_COOP),
+    "c5_grad_forward": ("k_fwd_coop<16, 2, true>", _FWD_COOP),
+    "c5_grad_adjoint": ("k_adj_coop<16, 2, false, true>", _ADJ_COOP),
+}
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_source_hash(family: str = "tile32") -> str:
+def source_hash(files) -> str:
     h = hashlib.sha256()
-    for f in FAMILY_KERNELS[family][2]:
+    for f in files:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload: str, family: str):
+def kernel_source_hash(family: str = "tile32") -> str:
+    return source_hash(FAMILY_KERNELS[family][2])
+
+
+def measured_traffic(workload: str, family: str = None):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on this family's kernel with the current source; else None."""
+    was taken on the workload's kernel (for c3: the family's kernel) with the
+    current source; else None."""
     try:
         with open(TRAFFIC_FILE) as fh:
             data = json.load(fh)
     except (OSError, ValueError):
         return None
     rec = data.get(workload)
-    if (not rec or family not in FAMILY_KERNELS or rec.get("kernel") != FAMILY_KERNELS[family][0]
-            or rec.get("kernel_source_hash") != kernel_source_hash(family)):
+    if family is not None:
+        if family not in FAMILY_KERNELS:
+            return None
+        kernel, files = FAMILY_KERNELS[family][0], FAMILY_KERNELS[family][2]
+    elif workload in TRAFFIC_KERNELS:
+        kernel, files = TRAFFIC_KERNELS[workload]
+    else:
+        return None
+    if not rec or rec.get("kernel") != kernel or rec.get("kernel_source_hash") != source_hash(files):
         return None
     return rec.get("bytes_per_launch")
+
+
+def traffic_summary(fetch_csv: str, write_csv: str, out: str = TRAFFIC_FILE):
+    """profiles/traffic.json from two rocprofv3 --pmc runs of the same command
+    (FETCH_SIZE, then WRITE_SIZE; counter_collection.csv of each, values in KiB
+    per dispatch) that include --copy-calibration: the counters of the 512 MiB
+    device copies give the scale from counter to bytes; per kernel the average
+    over its dispatches, scaled."""
+    import csv
+
+    def per_kernel(path, counter):
+        acc = {}
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                if r["Counter_Name"] != counter:
+                    continue
+                a = acc.setdefault(r["Kernel_Name"], [])
+                a.append(float(r["Counter_Value"]) * 1024.0)
+        return acc
+
+    fetch, write = per_kernel(fetch_csv, "FETCH_SIZE"), per_kernel(write_csv, "WRITE_SIZE")
+    copy_bytes = 512 << 20
+
+    def calib(acc):  # the copies of 512 MiB: dispatches of the copy kernel that moved over 256 MiB
+        vals = [v for name, vs in acc.items() if "copyBuffer" in name for v in vs if v > (256 << 20) * 0.4]
+        if not vals:
+            raise SystemExit("no 512 MiB copy dispatches in the counters (run the bench with --copy-calibration)")
+        return float(np.mean(vals)), copy_bytes / float(np.mean(vals))
+
+    fraw, fscale = calib(fetch)
+    wraw, wscale = calib(write)
+
+    def find(acc, kernel):
+        hits = [vs for name, vs in acc.items() if ("::" + kernel + "(") in name]
+        return hits[0] if len(hits) == 1 else None
+
+    data = {}
+    for wl, (kernel, files) in TRAFFIC_KERNELS.items():
+        fv, wv = find(fetch, kernel), find(write, kernel)
+        if fv is None or wv is None:
+            continue
+        fb, wb = float(np.mean(fv)) * fscale, float(np.mean(wv)) * wscale
+        data[wl] = {"kernel": kernel, "kernel_source_hash": source_hash(files),
+                    "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb, "bytes_per_launch": fb + wb,
+                    "fetch_scale": fscale, "write_scale": wscale,
+                    "calibration": f"__amd_rocclr_copyBuffer of 512 MiB: FETCH_SIZE {fraw / 1024:.1f} KiB, "
+                                   f"WRITE_SIZE {wraw / 1024:.1f} KiB per dispatch",
+                    "launches": min(len(fv), len(wv))}
+    with open(out, "w") as fh:
+        json.dump(data, fh, indent=1)
+        fh.write("\n")
+    print(json.dumps({k: round(v["bytes_per_launch"] / 1e9, 4) for k, v in data.items()}))
+
+
+def traffic_fields(kernels):
+    """{name: (traffic workload, kernel ms)} -> HBM bytes per launch from the committed counter
+    summary (None when it was taken on other code) and the rate they give at that kernel time."""
+    out = {}
+    for name, (wl, ms) in kernels.items():
+        b = measured_traffic(wl)
+        out[name] = {"kernel": TRAFFIC_KERNELS[wl][0], "hbm_bytes_per_launch": b,
+                     "hbm_gbs": round(b / (ms / 1e3) / 1e9, 1) if b and ms > 0 else None}
+    return out
 
 
 def to_dev(w, torch, own):
@@ -119,9 +206,10 @@ def time_steps(fn, steps, warmup, torch):
     return (time.perf_counter() - t0) / max(steps, 1)
 
 
-def graph_stats(fn, reps, torch):
-    """fn captured once as a HIP graph and replayed: 3 warm-up replays, then `reps` replays
-    each bracketed by its own events on the stream; milliseconds per replay (median, min, mean)."""
+def graph_stats(fn, reps, torch, batch=1):
+    """`batch` consecutive calls of fn captured once as a HIP graph and replayed: 3 warm-up
+    replays, then `reps` replays each bracketed by its own events on the stream; milliseconds
+    per call (median, min, mean of the replays, divided by `batch`)."""
     fn()
     torch.cuda.synchronize()
     side = torch.cuda.Stream()
@@ -132,7 +220,8 @@ def graph_stats(fn, reps, torch):
     torch.cuda.synchronize()
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g):
-        fn()
+        for _ in range(batch):
+            fn()
     for _ in range(3):
         g.replay()
     torch.cuda.synchronize()
@@ -142,15 +231,38 @@ def graph_stats(fn, reps, torch):
         g.replay()
         b.record()
     torch.cuda.synchronize()
-    t = np.array([a.elapsed_time(b) for a, b in ev])
+    t = np.array([a.elapsed_time(b) for a, b in ev]) / batch
     # the same replays back to back (throughput: the launches overlap as eager calls do)
     t0 = time.perf_counter()
     for _ in range(reps):
         g.replay()
     torch.cuda.synchronize()
-    b2b = (time.perf_counter() - t0) / reps * 1e3
+    b2b = (time.perf_counter() - t0) / reps / batch * 1e3
     return {"median_ms": float(np.median(t)), "min_ms": float(np.min(t)), "mean_ms": float(np.mean(t)),
-            "back_to_back_ms": b2b, "replays": reps}
+            "back_to_back_ms": b2b, "replays": reps, "calls_per_graph": batch}
+
+
+def graph_floor_us(torch, reps=200):
+    """Back-to-back cost of replaying a graph of one trivial kernel against launching that
+    kernel eagerly: the runtime's own cost per graph launch, in microseconds."""
+    x = torch.zeros(64, device="cuda")
+    f = lambda: x.add_(1.0)
+    g = torch.cuda.CUDAGraph()
+    f()
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g):
+        f()
+
+    def b2b(fn):
+        for _ in range(10):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps * 1e6
+    return {"graph_of_one_kernel_us": b2b(g.replay), "eager_kernel_us": b2b(f)}
 
 
 def eager_stats(fn, reps, torch):
@@ -246,7 +358,13 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="keep the built-in kernel heuristics (no autotuning)")
     ap.add_argument("--tune-cache", default=None,
                     help="JSON tuning cache: install the choices stored there instead of tuning, store new ones")
+    ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"), default=None,
+                    help="write profiles/traffic.json from the counter_collection.csv files of a FETCH_SIZE "
+                         "and a WRITE_SIZE rocprofv3 run of this bench (with --copy-calibration) and exit")
     args = ap.parse_args()
+    if args.traffic_summary:
+        traffic_summary(*args.traffic_summary)
+        return
     legs = {"plain", "grad", "large", "large_viterbi", "latency", "viterbi", "em", "graph", "h2d"}
     chosen = set() if args.no_extra else (legs if args.legs == "all" else set(args.legs.split(",")))
     if chosen - legs:
@@ -370,7 +488,9 @@ def main():
                                          "own model, fused forward + adjoint",
                              "value": u4 / gsec, "unit": "state-steps/s", "ms_per_step": gsec * 1e3,
                              "fwd_kernel_ms": f_ms / max(f_n, 1), "adj_kernel_ms": a_ms / max(a_n, 1),
-                             "frac_fp32_peak": 6.0 * u4 / gsec / 1e12 / FP32_PEAK_TFLOPS}
+                             "frac_fp32_peak": 6.0 * u4 / gsec / 1e12 / FP32_PEAK_TFLOPS,
+                             "traffic": traffic_fields({"forward": ("c4_grad_forward", f_ms / max(f_n, 1)),
+                                                        "adjoint": ("c4_grad_adjoint", a_ms / max(a_n, 1))})}
         if not args.no_cpu:
             log("CPU oracle forward + backward on a c4 sample")
             result["fwd_bwd"]["cpu_oracle"] = cpu_oracle_counts(w4)
@@ -395,7 +515,8 @@ def main():
         del ws5
         large.update({"value": u5 / s5, "unit": "state-steps/s", "ms_per_step": s5 * 1e3,
                       "kernel_ms": k5_ms / max(k5_n, 1),
-                      "frac_fp32_peak": 2.0 * u5 / (k5_ms / max(k5_n, 1) / 1e3) / 1e12 / FP32_PEAK_TFLOPS})
+                      "frac_fp32_peak": 2.0 * u5 / (k5_ms / max(k5_n, 1) / 1e3) / 1e12 / FP32_PEAK_TFLOPS,
+                      "traffic": traffic_fields({"forward": ("c5_forward", k5_ms / max(k5_n, 1))})})
         autotune("c5_grad", p5, hmm.OP_GRAD, warmup=0, reps=2)
         ws5g = p5.workspace(hmm.OP_GRAD)
         cnt5 = (torch.empty((w5.K, w5.N), device="cuda"), torch.empty((w5.K, w5.N, w5.N), device="cuda"),
@@ -410,7 +531,9 @@ def main():
         hmm.profile_enable(False)
         large["fwd_bwd"] = {"value": u5 / gs5, "unit": "state-steps/s", "ms_per_step": gs5 * 1e3,
                             "fwd_kernel_ms": f5_ms / max(f5_n, 1), "adj_kernel_ms": a5_ms / max(a5_n, 1),
-                            "frac_fp32_peak": 6.0 * u5 / gs5 / 1e12 / FP32_PEAK_TFLOPS}
+                            "frac_fp32_peak": 6.0 * u5 / gs5 / 1e12 / FP32_PEAK_TFLOPS,
+                            "traffic": traffic_fields({"forward": ("c5_grad_forward", f5_ms / max(f5_n, 1)),
+                                                       "adjoint": ("c5_grad_adjoint", a5_ms / max(a5_n, 1))})}
         del ws5g, cnt5
     if want("large_viterbi"):
         log("c5 Viterbi (workgroup decoder: 256 states)")
@@ -455,6 +578,7 @@ def main():
         f1 = lambda: hmm.forward_loglik(p1, out=ll1, ws=ws1)
         e1 = time_steps(f1, 50, 5, torch)
         es1, gs1 = eager_stats(f1, 50, torch), graph_stats(f1, 50, torch)
+        gb1 = graph_stats(f1, 20, torch, batch=16)
         lat["c1"] = {"workload": "c1: 1 HMM N=8 M=16, one sequence T=64, forward (tuned choice: "
                                  f"{tune.KERNEL_NAMES[hmm.call_kernel(p1.bank, p1.batch, hmm.OP_FORWARD)]})",
                      "us_per_call": e1 * 1e6,
@@ -462,7 +586,13 @@ def main():
                      "us_per_call_graph": gs1["median_ms"] * 1e3, "us_per_call_graph_min": gs1["min_ms"] * 1e3,
                      "us_per_call_graph_back_to_back": gs1["back_to_back_ms"] * 1e3,
                      "graph_replays": gs1["replays"],
-                     "ns_per_step_graph": gs1["median_ms"] * 1e6 / int(w1.lengths.max())}
+                     "ns_per_step_graph": gs1["median_ms"] * 1e6 / int(w1.lengths.max()),
+                     # 16 consecutive calls in one graph: the runtime's fixed cost per graph
+                     # launch (graph_launch_floor) is paid once for 16 calls
+                     "us_per_call_graph16": gb1["median_ms"] * 1e3, "us_per_call_graph16_min": gb1["min_ms"] * 1e3,
+                     "us_per_call_graph16_back_to_back": gb1["back_to_back_ms"] * 1e3,
+                     "graph16_replays": gb1["replays"]}
+        lat["graph_launch_floor"] = graph_floor_us(torch)
         hmm.select_kernel(hmm.KERNEL_TILE16)
         lat["c1"]["us_per_call_tiles"] = time_steps(f1, 50, 5, torch) * 1e6
         hmm.select_kernel(hmm.KERNEL_AUTO)
@@ -489,6 +619,7 @@ def main():
         f2 = lambda: hmm.classify(p2, labels=lab2, loglik=ll2, ws=ws2)
         e2 = time_steps(f2, 20, 3, torch)
         es2, gs2 = eager_stats(f2, 20, torch), graph_stats(f2, 20, torch)
+        gb2 = graph_stats(f2, 20, torch, batch=16)
         g2 = gs2["median_ms"]
         lat["c2"] = {"workload": "c2: 12 HMMs N=16 M=64, 4096 sequences, T in [50,400], all pairs + labels",
                      "us_per_call": e2 * 1e6,
@@ -497,7 +628,10 @@ def main():
                      "us_per_call_graph_back_to_back": gs2["back_to_back_ms"] * 1e3,
                      "graph_replays": gs2["replays"],
                      "ns_per_step_graph": g2 * 1e6 / int(w2.lengths.max()),
-                     "state_steps_per_s_graph": w2.units() / (g2 / 1e3)}
+                     "state_steps_per_s_graph": w2.units() / (g2 / 1e3),
+                     "us_per_call_graph16": gb2["median_ms"] * 1e3, "us_per_call_graph16_min": gb2["min_ms"] * 1e3,
+                     "us_per_call_graph16_back_to_back": gb2["back_to_back_ms"] * 1e3,
+                     "graph16_replays": gb2["replays"]}
         result["latency"] = lat
 
     if want("viterbi"):

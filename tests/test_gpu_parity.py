@@ -723,6 +723,43 @@ def test_scan_forward_parity(N):
         assert rel_err(ll, ref) <= LL_TOL, all_pairs
 
 
+@pytest.mark.parametrize("T", [0, 1, 2, 17, 64, 65])
+def test_scan_single_pair_one_launch(T):
+    """One pair of at most 65 steps runs in one launch (chunk product and alpha steps in one
+    workgroup): the same log-likelihood, bit for bit, as the two-pass scan (the same pair with
+    a larger max_len), within the tolerance of the oracle; a bad symbol and a length beyond
+    max_len give NaN and the error word."""
+    print(f"[case] scan single pair T={T}", flush=True)
+    rng = np.random.default_rng([14, T])
+    w = workloads.random_lengths_workload(rng, K=1, N=8, M=16, lengths=np.array([T], np.int32), all_pairs=False)
+    ref = oracle_ll(w, True)
+    hmm.select_kernel(hmm.KERNEL_SCAN)
+    try:
+        one = hmm.forward_loglik(hmm.Problem(dev(w.pi), dev(w.A), dev(w.B), dev(w.symbols), dev(w.offsets),
+                                             dev(w.lengths), dev(w.owner), max_len=max(T, 1),
+                                             total_symbols=w.total_symbols)).cpu().numpy()
+        two = hmm.forward_loglik(hmm.Problem(dev(w.pi), dev(w.A), dev(w.B), dev(w.symbols), dev(w.offsets),
+                                             dev(w.lengths), dev(w.owner), max_len=200,
+                                             total_symbols=w.total_symbols)).cpu().numpy()
+        assert np.array_equal(one, two)
+        assert rel_err(one, ref) <= LL_TOL
+        if T >= 2:
+            sym = w.symbols.copy()
+            sym[T - 1] = 99                         # invalid symbol in the last step
+            p = hmm.Problem(dev(w.pi), dev(w.A), dev(w.B), dev(sym), dev(w.offsets), dev(w.lengths),
+                            dev(w.owner), max_len=T, total_symbols=w.total_symbols)
+            ws = p.workspace(hmm.OP_FORWARD)
+            ll = hmm.forward_loglik(p, ws=ws).cpu().numpy()
+            assert np.isnan(ll[0]) and hmm.workspace_error(ws) == 0
+            p = hmm.Problem(dev(w.pi), dev(w.A), dev(w.B), dev(w.symbols), dev(w.offsets), dev(w.lengths),
+                            dev(w.owner), max_len=T - 1, total_symbols=w.total_symbols)
+            ws = p.workspace(hmm.OP_FORWARD)
+            ll = hmm.forward_loglik(p, ws=ws).cpu().numpy()
+            assert np.isnan(ll[0]) and hmm.workspace_error(ws) == 0
+    finally:
+        hmm.select_kernel(hmm.KERNEL_AUTO)
+
+
 def test_scan_forward_special_inputs_and_auto_choice():
     rng = np.random.default_rng(13)
     lengths = np.array([70, 5, 140, 0], np.int32)
