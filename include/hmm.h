@@ -29,7 +29,8 @@
  *    by the caller, dense and row-major as declared.  Probabilities are FP32.
  *  - Calls only enqueue work on `stream` and return; results are valid once
  *    the caller synchronises that stream.  No call allocates device memory,
- *    synchronises, or reads device memory back, except hmm_workspace_error.
+ *    synchronises, or reads device memory back, except hmm_workspace_error
+ *    and hmm_debug_flags.
  *    Calls may therefore be captured into a HIP graph.
  *  - Scratch memory is the caller's workspace `ws` of `ws_bytes` bytes, at
  *    least hmm_workspace_size(...) for the same bank, batch and op (Viterbi
@@ -247,6 +248,23 @@ hmm_status hmm_plan_order(const hmm_bank *bank, const hmm_batch *batch, int32_t 
 /* Synchronises `stream`, then reads the workspace error word: *first_bad_seq
  * is the smallest sequence index the last call flagged, or -1 if none. */
 hmm_status hmm_workspace_error(const void *ws, hipStream_t stream, int32_t *first_bad_seq);
+
+/* Debug build.  The library built with -DHMM_DEBUG (libhmm_mi355x_debug.so)
+ * checks in its kernels the indices it derives for the workspace and the
+ * outputs (the bits below); an index outside its buffer is recorded and the
+ * access kept inside the buffer or skipped, never made.  hmm_debug_flags
+ * synchronises the device, sets *flags to the OR of the bits recorded since
+ * the last call and clears them.  A normal build checks nothing and returns
+ * HMM_ERR_UNSUPPORTED (*flags = 0).  For tests and diagnosis, not for
+ * production: the checks cost time. */
+#define HMM_DEBUG_PLAN_POS 1u     /* work-list position outside [0, S)                        */
+#define HMM_DEBUG_LL_OUT 2u       /* log-likelihood store outside its output or staging buffer */
+#define HMM_DEBUG_CKPT 4u         /* alpha checkpoint outside the sequence's checkpoint slots  */
+#define HMM_DEBUG_SLAB 8u         /* per-tile emission partial outside the slab                */
+#define HMM_DEBUG_SEGMENT 16u     /* recompute segment longer than the segment buffer          */
+#define HMM_DEBUG_VIT_ROWS 32u    /* Viterbi delta rows outside the array (or its half)        */
+#define HMM_DEBUG_VIT_ROUND 64u   /* Viterbi round outside the work list                       */
+hmm_status hmm_debug_flags(uint32_t *flags);
 
 /* Selects the kernel family for later calls (HMM_KERNEL_*).  Any kind other
  * than HMM_KERNEL_AUTO overrides the tuning table below. */

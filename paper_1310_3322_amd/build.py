@@ -14,6 +14,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libhmm_mi355x.so")
+# the same sources with the kernels' bounds checks compiled in (-DHMM_DEBUG)
+LIB_DEBUG = os.path.join(PKG, "libhmm_mi355x_debug.so")
 OBJDIR = os.path.join(ROOT, "_build", "hip")
 
 SOURCES = ["planner.hip", "fwd_plain.hip", "fwd_mfma.hip", "fwd_mfma32.hip", "fwd_coop.hip", "fwd_scan.hip", "adj_mfma.hip", "adj_coop.hip", "viterbi.hip", "abi.hip"]
@@ -27,30 +29,35 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-mllvm", "-amdgpu-mfma-vgpr-form", "-I", INCLUDE]
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(OBJDIR, src.replace(".hip", ".o"))
-    cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+def _compile(src: str, debug: bool = False) -> str:
+    objdir = OBJDIR + ("_debug" if debug else "")
+    obj = os.path.join(objdir, src.replace(".hip", ".o"))
+    cmd = [HIPCC, *FLAGS, *(["-DHMM_DEBUG"] if debug else []), "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")
     return obj
 
 
-def build(verbose: bool = False) -> str:
-    os.makedirs(OBJDIR, exist_ok=True)
+def build(verbose: bool = False, debug: bool = False) -> str:
+    """Builds libhmm_mi355x.so, or with debug=True libhmm_mi355x_debug.so (bounds checks in the kernels)."""
+    lib = LIB_DEBUG if debug else LIB
+    os.makedirs(OBJDIR + ("_debug" if debug else ""), exist_ok=True)
     with concurrent.futures.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
-        objs = list(ex.map(_compile, SOURCES))
-    tmp = LIB + f".tmp{os.getpid()}"
+        objs = list(ex.map(lambda s: _compile(s, debug), SOURCES))
+    tmp = lib + f".tmp{os.getpid()}"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
     if verbose:
-        print("built", LIB)
-    return LIB
+        print("built", lib)
+    return lib
 
 
 if __name__ == "__main__":
     build(verbose=True)
+    if "--debug" in sys.argv[1:]:
+        build(verbose=True, debug=True)
     sys.exit(0)

@@ -495,6 +495,10 @@ hmm_status run_forward(const hmm_bank *b, const hmm_batch *q, int op, float *out
 
 }  // namespace
 
+namespace hmm {
+HMM_DEBUG_TAKE(debug_take_abi)
+}  // namespace hmm
+
 extern "C" {
 
 size_t hmm_workspace_size(const hmm_bank *bank, const hmm_batch *batch, int op) {
@@ -768,6 +772,25 @@ hmm_status hmm_workspace_error(const void *ws, hipStream_t stream, int32_t *firs
     if (hipMemcpy(&v, ws, sizeof(v), hipMemcpyDeviceToHost) != hipSuccess) return HMM_ERR_HIP;
     *first_bad_seq = (v == INT32_MAX) ? -1 : v;
     return HMM_OK;
+}
+
+hmm_status hmm_debug_flags(uint32_t *flags) {
+    if (!flags) return HMM_ERR_NULL;
+    *flags = 0;
+#ifdef HMM_DEBUG
+    if (hipDeviceSynchronize() != hipSuccess) return HMM_ERR_HIP;
+    uint32_t (*const take[])() = {debug_take_planner, debug_take_fwd_plain, debug_take_fwd_mfma,
+                                  debug_take_fwd_mfma32, debug_take_fwd_coop, debug_take_fwd_scan,
+                                  debug_take_adj_mfma, debug_take_adj_coop, debug_take_viterbi,
+                                  debug_take_abi};
+    uint32_t v = 0;
+    for (auto f : take) v |= f();
+    if (v & 0x80000000u) return HMM_ERR_HIP;
+    *flags = v;
+    return HMM_OK;
+#else
+    return HMM_ERR_UNSUPPORTED;
+#endif
 }
 
 hmm_status hmm_select_kernel(int32_t kind) {

@@ -193,6 +193,7 @@ __global__ void __launch_bounds__(R / BO * WAVE) k_adj_coop(DevPtrs d, AdjLaunch
                 bool lane_nan = false;  // a non-finite count (from a non-finite weight) in this lane
                 int L = 1;
                 while (L * L < Tmax) ++L;
+                if (!dbg_in(L - 1, Lcap, HMM_DEBUG_SEGMENT)) return;  // segment buffer too short (debug build)
                 const int nseg = (Tmax + L - 1) / L;
                 const float wgt = act ? (a.weight ? a.weight[seq] : 1.0f) : 0.0f;
                 const int32_t *sbase = T > 0 ? d.symbols + off : d.symbols;
@@ -527,7 +528,8 @@ __global__ void __launch_bounds__(R / BO * WAVE) k_adj_coop(DevPtrs d, AdjLaunch
                 if (NBLDS) {
                     // the tile's emission partial into its slab slot (zeros for an empty tile)
                     __syncthreads();
-                    float *dst = a.slab + (size_t)slab_slot(gbeg, k, tile) * M * NP;
+                    const int64_t slot = slab_slot(gbeg, k, tile);
+                    float *dst = a.slab + (size_t)(dbg_in(slot, slab_slots(a.S, a.K), HMM_DEBUG_SLAB) ? slot : 0) * M * NP;
                     for (int idx = threadIdx.x; idx < M * NP; idx += blockDim.x) {
                         const int o = idx / NP, ic = idx % NP;
                         dst[(size_t)o * NP + (ic ^ (o * 4 & swz))] = nbl[idx];
@@ -660,6 +662,7 @@ __global__ void __launch_bounds__(2 * R * WAVE) k_adj_pipe(DevPtrs d, AdjLaunch 
                 bool lane_nan = false;  // a non-finite count (from a non-finite weight) in this lane
                 int L = 1;
                 while (L * L < Tmax) ++L;
+                if (!dbg_in(L - 1, Lcap, HMM_DEBUG_SEGMENT)) return;  // segment buffer too short (debug build)
                 const int nseg = (Tmax + L - 1) / L;
                 const float wgt = act ? (a.weight ? a.weight[seq] : 1.0f) : 0.0f;
                 const int32_t *sbase = T > 0 ? d.symbols + off : d.symbols;
@@ -907,7 +910,8 @@ __global__ void __launch_bounds__(2 * R * WAVE) k_adj_pipe(DevPtrs d, AdjLaunch 
                 }  // Tmax > 0
                 // the tile's emission partial into its slab slot (zeros for an empty tile)
                 __syncthreads();
-                float *dst = a.slab + (size_t)slab_slot(gbeg, k, tile) * M * NP;
+                const int64_t slot = slab_slot(gbeg, k, tile);
+                float *dst = a.slab + (size_t)(dbg_in(slot, slab_slots(a.S, a.K), HMM_DEBUG_SLAB) ? slot : 0) * M * NP;
                 for (int idx = threadIdx.x; idx < M * NP; idx += blockDim.x) {
                     const int o = idx / NP, ic = idx % NP;
                     dst[(size_t)o * NP + (ic ^ (o * 4 & swz))] = nbl[idx];
@@ -1106,5 +1110,7 @@ hipError_t launch_adj_coop(const DevPtrs &d, const AdjLaunch &a, int cu_count, h
         default: return hipErrorInvalidValue;
     }
 }
+
+HMM_DEBUG_TAKE(debug_take_adj_coop)
 
 }  // namespace hmm

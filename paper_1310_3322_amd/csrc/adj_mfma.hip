@@ -156,6 +156,7 @@ __global__ void __launch_bounds__(WAVES * WAVE) k_adj_mfma(DevPtrs d, AdjLaunch 
                 bool lane_nan = false;
                 int L = 1;
                 while (L * L < Tmax) ++L;
+                if (!dbg_in(L - 1, Lcap, HMM_DEBUG_SEGMENT)) return;  // segment buffer too short (debug build)
                 const int nseg = (Tmax + L - 1) / L;
                 const float wgt = act ? (a.weight ? a.weight[seq] : 1.0f) : 0.0f;
                 const int st_slot = lane >> 2, st_part = lane & 3;
@@ -364,7 +365,8 @@ __global__ void __launch_bounds__(WAVES * WAVE) k_adj_mfma(DevPtrs d, AdjLaunch 
                 if (NBLDS) {
                     // the tile's emission partial into its slab slot (zeros for an empty tile)
                     wave_lds_sync();
-                    float *dst = a.slab + (size_t)slab_slot(gbeg, k, tile) * M * NP;
+                    const int64_t slot = slab_slot(gbeg, k, tile);
+                    float *dst = a.slab + (size_t)(dbg_in(slot, slab_slots(a.S, a.K), HMM_DEBUG_SLAB) ? slot : 0) * M * NP;
                     for (int idx = lane; idx < M * NP; idx += WAVE) {
                         const int o = idx / NP, ic = idx % NP;
                         dst[(size_t)o * NP + (ic ^ (o * 4 & swz))] = nbl[idx];
@@ -474,5 +476,7 @@ hipError_t launch_adj_mfma(const DevPtrs &d, const AdjLaunch &a, int cu_count, h
         default: return hipErrorInvalidValue;
     }
 }
+
+HMM_DEBUG_TAKE(debug_take_adj_mfma)
 
 }  // namespace hmm

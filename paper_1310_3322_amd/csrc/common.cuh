@@ -171,4 +171,35 @@ __device__ __forceinline__ bool seq_bad(int32_t T, int64_t off, int32_t max_len,
     return T < 0 || T > max_len || off < 0 || off + (int64_t)T > total;
 }
 
+// Bounds checks of the debug build (compiled with -DHMM_DEBUG): dbg_in(i, n,
+// bit) is false when 0 <= i < n does not hold and then sets `bit` (one of the
+// HMM_DEBUG_* bits of hmm.h) in the debug word of the translation unit; the
+// caller keeps the access inside its buffer (or skips it).  hmm_debug_flags
+// collects the words.  In a normal build the checks are constant true and
+// vanish.
+#ifdef HMM_DEBUG
+namespace {
+__device__ unsigned int g_debug_word;
+}
+__device__ __forceinline__ bool dbg_in(int64_t i, int64_t n, unsigned int bit) {
+    const bool ok = i >= 0 && i < n;
+    if (!ok) atomicOr(&g_debug_word, bit);
+    return ok;
+}
+// Host side: returns the word of this translation unit and clears it.
+#define HMM_DEBUG_TAKE(fn)                                                            \
+    uint32_t fn() {                                                                 \
+        unsigned int v = 0, z = 0;                                                  \
+        if (hipMemcpyFromSymbol(&v, HIP_SYMBOL(g_debug_word), sizeof(v)) != hipSuccess) \
+            return 0x80000000u;                                                     \
+        if (hipMemcpyToSymbol(HIP_SYMBOL(g_debug_word), &z, sizeof(z)) != hipSuccess)  \
+            return 0x80000000u;                                                     \
+        return v;                                                                   \
+    }
+#else
+__device__ __forceinline__ bool dbg_in(int64_t, int64_t, unsigned int) { return true; }
+#define HMM_DEBUG_TAKE(fn) \
+    uint32_t fn() { return 0; }
+#endif
+
 }  // namespace hmm

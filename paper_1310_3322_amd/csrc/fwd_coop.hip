@@ -132,7 +132,7 @@ __global__ void __launch_bounds__(R / BO * WAVE) k_fwd_coop(DevPtrs d, FwdLaunch
                     }
                     E += e;
                     if (CKPT && t - 1 == ck_t) {  // t - 1 = L ck_c
-                        if (t - 1 < T) {
+                        if (t - 1 < T && dbg_in(ck_c, f.nck, HMM_DEBUG_CKPT)) {
 #pragma unroll
                             for (int b = 0; b < BO; ++b) {
                                 float *dst = f.ckpt + ((size_t)pos * f.nck + ck_c) * NP + 16 * (r0 + b) + 4 * g;
@@ -255,5 +255,7 @@ hipError_t launch_fwd_coop(const DevPtrs &d, const FwdLaunch &f, int cu_count, h
     }
 #undef HMM_COOP_CASE
 }
+
+HMM_DEBUG_TAKE(debug_take_fwd_coop)
 
 }  // namespace hmm

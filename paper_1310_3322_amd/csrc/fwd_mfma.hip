@@ -174,7 +174,7 @@ __global__ void __launch_bounds__(FWD_WAVES * WAVE) k_fwd_mfma(DevPtrs d, FwdLau
                         c_end = cs;
                     }
                     E += e;
-                    if (CKPT && (t % L) == 0 && t < T) {
+                    if (CKPT && (t % L) == 0 && t < T && dbg_in(t / L, f.nck, HMM_DEBUG_CKPT)) {
                         const int c = t / L;
                         float *dst = f.ckpt + ((size_t)ck_base * f.nck + c) * NP;
 #pragma unroll
@@ -243,5 +243,7 @@ hipError_t launch_fwd_mfma(const DevPtrs &d, const FwdLaunch &f, int cu_count, h
     }
 #undef HMM_FWD_CASE
 }
+
+HMM_DEBUG_TAKE(debug_take_fwd_mfma)
 
 }  // namespace hmm

@@ -283,4 +283,6 @@ hipError_t launch_fwd_mfma32(const DevPtrs &d, const FwdLaunch &f, int cu_count,
     }
 }
 
+HMM_DEBUG_TAKE(debug_take_fwd_mfma32)
+
 }  // namespace hmm

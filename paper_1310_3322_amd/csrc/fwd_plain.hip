@@ -102,4 +102,6 @@ hipError_t launch_fwd_plain(const DevPtrs &d, int K, int N, int M, int S, int al
     return hipGetLastError();
 }
 
+HMM_DEBUG_TAKE(debug_take_fwd_plain)
+
 }  // namespace hmm

@@ -315,4 +315,6 @@ hipError_t launch_fwd_scan(const DevPtrs &d, const FwdLaunch &f, const ScanWs &w
     return hipGetLastError();
 }
 
+HMM_DEBUG_TAKE(debug_take_fwd_scan)
+
 }  // namespace hmm

@@ -5,6 +5,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include "common.cuh"
+
 namespace hmm {
 
 // Workspace carve-up for one call (byte offsets into ws, 256-aligned).
@@ -161,10 +163,13 @@ struct FwdLaunch {
 };
 // The log-likelihood of sequence seq (sorted position pos) under model k.
 __device__ __forceinline__ void store_ll(const FwdLaunch &f, int seq, int pos, int k, float r) {
-    if (f.llpos)
-        f.llpos[(size_t)k * f.S + pos] = r;
-    else
-        f.ll[f.all_pairs ? (size_t)seq * f.K + k : (size_t)seq] = r;
+    if (f.llpos) {
+        const int64_t i = (int64_t)k * f.S + pos;
+        if (dbg_in(i, (int64_t)f.S * f.K, HMM_DEBUG_LL_OUT)) f.llpos[i] = r;
+    } else {
+        const int64_t i = f.all_pairs ? (int64_t)seq * f.K + k : (int64_t)seq;
+        if (dbg_in(i, f.all_pairs ? (int64_t)f.S * f.K : (int64_t)f.S, HMM_DEBUG_LL_OUT)) f.ll[i] = r;
+    }
 }
 bool fwd_mfma_supported(int NP);
 hipError_t launch_fwd_mfma(const DevPtrs &d, const FwdLaunch &f, int cu_count, hipStream_t st);
@@ -225,7 +230,7 @@ __host__ __device__ inline int quad_t(int i) { return (i & ~15) | ((i & 3) << 2)
 // Slab slot of tile `tile` of the model whose group starts at gbeg: unique, below
 // S / 16 + K + 1 (the group's tiles follow floor(gbeg / 16) + k).
 __host__ __device__ inline int64_t slab_slot(int gbeg, int k, int tile) { return (int64_t)(gbeg / 16) + k + tile; }
-inline int64_t slab_slots(int S, int K) { return (int64_t)S / 16 + K + 1; }
+__host__ __device__ inline int64_t slab_slots(int S, int K) { return (int64_t)S / 16 + K + 1; }
 bool adj_mfma_supported(int NP);
 // Whether the backward of a shape accumulates emission counts in an LDS partial
 // flushed per tile into the slab (true) or in the global fixed-point counts.
@@ -273,5 +278,17 @@ constexpr int VIT_STATE_WORDS = 9;
 bool viterbi_supported(int NP);
 int64_t viterbi_min_rows(int64_t max_len, int64_t total);
 hipError_t launch_viterbi(const DevPtrs &d, const VitLaunch &v, int cu_count, hipStream_t st);
+
+// Debug build: each translation unit's word of failed bounds checks (taken and cleared).
+uint32_t debug_take_planner();
+uint32_t debug_take_fwd_plain();
+uint32_t debug_take_fwd_mfma();
+uint32_t debug_take_fwd_mfma32();
+uint32_t debug_take_fwd_coop();
+uint32_t debug_take_fwd_scan();
+uint32_t debug_take_adj_mfma();
+uint32_t debug_take_adj_coop();
+uint32_t debug_take_viterbi();
+uint32_t debug_take_abi();
 
 }  // namespace hmm

@@ -296,7 +296,7 @@ __global__ void __launch_bounds__(1024) k_plan_scatter(DevPtrs d, int S, int K, 
                     cntp = mid;
             }
             const int pos = cnt[(int64_t)b * nchunks + c] + (p - first);
-            perm[pos] = base + (int)(kv & 2047);
+            if (dbg_in(pos, S, HMM_DEBUG_PLAN_POS)) perm[pos] = base + (int)(kv & 2047);
             if (p + 1 == n || (int)(key[p + 1] >> 11) != b) {
                 last_bin[h] = b;
                 last_pos[h] = pos + 1;
@@ -339,7 +339,10 @@ __global__ void __launch_bounds__(256) k_plan_scatter_wave(DevPtrs d, int S, int
         if (b == lb) rank = __popcll(m & below);
         todo &= ~m;
     }
-    if (valid) perm[cnt[(int64_t)b * nchunks + c] + rank] = s;
+    if (valid) {
+        const int pos = cnt[(int64_t)b * nchunks + c] + rank;
+        if (dbg_in(pos, S, HMM_DEBUG_PLAN_POS)) perm[pos] = s;
+    }
 }
 
 // cnt_B[k][i][o] for i < N, o < M from the symbol-major emission counts: the
@@ -667,5 +670,7 @@ void launch_reestimate_rows(const float *n, const float *old, float *out, int64_
 void launch_logit_grad(const float *n, const float *p, float *g, int64_t rows, int cols, hipStream_t st) {
     if (rows > 0) hipLaunchKernelGGL(k_logit_grad, dim3(blocks_for(rows, 4)), dim3(256), 0, st, n, p, g, rows, cols);
 }
+
+HMM_DEBUG_TAKE(debug_take_planner)
 
 }  // namespace hmm

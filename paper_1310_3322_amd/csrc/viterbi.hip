@@ -241,6 +241,7 @@ __global__ void __launch_bounds__(WAVE) k_vit_round(VitLaunch v, int gen) {
             const int n = end - start;
             if (n >= gen) end = start + n / gen * gen;
         }
+        if (!dbg_in(end - start, (int64_t)S - start + 1, HMM_DEBUG_VIT_ROUND)) end = start;
     }
     if (lane == 0) {
         v.state[0] = 0;
@@ -297,6 +298,8 @@ __device__ void vit_decode_waves(const DevPtrs &d, const VitLaunch &v, const VRo
             bad |= (mk < 0 || mk >= K);
             if (bad) T = 0;
             k = bad ? 0 : mk;
+            // the entry's rows lie inside the delta array (debug build: else skipped)
+            if (T > 0 && !dbg_in(v.rowpos[pos] + R.roff + T - 1, v.cap_rows, HMM_DEBUG_VIT_ROWS)) T = 0;
         }
         // column j of ln A of this lane's model (states beyond N are impossible)
         float la[NP];
@@ -448,6 +451,7 @@ __device__ void vit_trace_waves(const DevPtrs &d, const VitLaunch &v, const VRou
             const int mk = d.model_of_seq[s];
             if (seq_bad(T, off, v.max_len, v.total) || mk < 0 || mk >= K) T = 0;
             else k = mk;
+            if (T > 0 && !dbg_in(v.rowpos[pos] + R.roff + T - 1, v.cap_rows, HMM_DEBUG_VIT_ROWS)) T = 0;
         }
         int32_t *q = v.path + (T > 0 ? off : 0);
         const float sc = T > 0 ? v.score[s] : 0.0f;
@@ -589,7 +593,8 @@ __device__ void vit_decode_wg(const DevPtrs &d, const VitLaunch &v, const VRound
         const int64_t off = d.offsets[seq];
         const int mk = d.model_of_seq[seq];
         const bool bad = seq_bad(Tin, off, v.max_len, v.total) || mk < 0 || mk >= K;
-        const int32_t T = __builtin_amdgcn_readfirstlane(bad ? 0 : Tin);
+        const bool rows_ok = bad || Tin == 0 || dbg_in(v.rowpos[pos] + R.roff + Tin - 1, v.cap_rows, HMM_DEBUG_VIT_ROWS);
+        const int32_t T = __builtin_amdgcn_readfirstlane((bad || !rows_ok) ? 0 : Tin);
         const int k = __builtin_amdgcn_readfirstlane(bad ? 0 : mk);
         // ln A[i][4 jg + c] for this lane's slice of i (states beyond N are impossible)
         float la[WJ][IS];
@@ -751,6 +756,7 @@ __device__ void vit_trace_wave_wg(const DevPtrs &d, const VitLaunch &v, const VR
         const int mk = d.model_of_seq[s];
         const bool bad = seq_bad(T, off, v.max_len, v.total) || mk < 0 || mk >= K;
         if (bad) T = 0;
+        if (T > 0 && !dbg_in(v.rowpos[pos] + R.roff + T - 1, v.cap_rows, HMM_DEBUG_VIT_ROWS)) T = 0;
         const int k = __builtin_amdgcn_readfirstlane(bad ? 0 : mk);
         const float *lnk = v.lnat + (size_t)k * N * NP;
         int32_t *qp = v.path + (T > 0 ? off : 0);
@@ -954,5 +960,7 @@ hipError_t launch_viterbi(const DevPtrs &d, const VitLaunch &v, int cu_count, hi
         default: return hipErrorInvalidValue;
     }
 }
+
+HMM_DEBUG_TAKE(debug_take_viterbi)
 
 }  // namespace hmm

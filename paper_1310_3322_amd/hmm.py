@@ -16,6 +16,7 @@ import torch
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libhmm_mi355x.so")
+LIB_DEBUG_PATH = os.path.join(_PKG, "libhmm_mi355x_debug.so")  # kernels with bounds checks (-DHMM_DEBUG)
 
 HMM_OK = 0
 STATUS = {0: "HMM_OK", -1: "HMM_ERR_NULL", -2: "HMM_ERR_SHAPE", -3: "HMM_ERR_WORKSPACE",
@@ -23,7 +24,7 @@ STATUS = {0: "HMM_OK", -1: "HMM_ERR_NULL", -2: "HMM_ERR_SHAPE", -3: "HMM_ERR_WOR
 OP_FORWARD, OP_CLASSIFY, OP_GRAD, OP_VITERBI = 0, 1, 2, 3
 KERNEL_AUTO, KERNEL_PLAIN, KERNEL_BATCHED, KERNEL_TILE16, KERNEL_TILE32, KERNEL_COOP, KERNEL_SCAN = 0, 1, 2, 3, 4, 5, 6
 EXPORTS = ("hmm_workspace_size", "hmm_viterbi_workspace_size", "hmm_forward_loglik", "hmm_classify", "hmm_classify_noalloc", "hmm_forward_backward_grad",
-           "hmm_viterbi", "hmm_plan_order", "hmm_reestimate_rows", "hmm_softmax_rows", "hmm_logit_grad", "hmm_workspace_error", "hmm_select_kernel",
+           "hmm_viterbi", "hmm_plan_order", "hmm_reestimate_rows", "hmm_softmax_rows", "hmm_logit_grad", "hmm_workspace_error", "hmm_debug_flags", "hmm_select_kernel",
            "hmm_tune_key_of", "hmm_tune_set", "hmm_tune_get", "hmm_tune_clear", "hmm_call_kernel",
            "hmm_profile_enable", "hmm_profile_read", "hmm_status_string")
 TUNE_MAX, TUNE_MAX_WG = 256, 64
@@ -62,12 +63,15 @@ class TuneChoice(ctypes.Structure):
 
 
 _lib = None
+_lib_path = None
 
 
-def load_library(path: str = LIB_PATH):
-    """Loads and binds the library (no GPU needed for loading)."""
-    global _lib
-    if _lib is not None:
+def load_library(path: str = LIB_PATH, rebind: bool = False):
+    """Loads and binds the library (no GPU needed for loading).  The first call binds
+    `path` for the process; rebind=True binds `path` instead of the bound one (tests
+    that run the debug build beside the normal one)."""
+    global _lib, _lib_path
+    if _lib is not None and not rebind:
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is not built: run __graft_entry__.build() or python -m paper_1310_3322_amd.build")
@@ -99,6 +103,8 @@ def load_library(path: str = LIB_PATH):
     lib.hmm_logit_grad.argtypes = [P, P, P, ctypes.c_int64, ctypes.c_int32, P]
     lib.hmm_workspace_error.restype = st
     lib.hmm_workspace_error.argtypes = [P, P, ctypes.POINTER(ctypes.c_int32)]
+    lib.hmm_debug_flags.restype = st
+    lib.hmm_debug_flags.argtypes = [ctypes.POINTER(ctypes.c_uint32)]
     lib.hmm_select_kernel.restype = st
     lib.hmm_select_kernel.argtypes = [ctypes.c_int32]
     lib.hmm_tune_key_of.restype = st
@@ -117,7 +123,7 @@ def load_library(path: str = LIB_PATH):
     lib.hmm_profile_read.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)]
     lib.hmm_status_string.restype = ctypes.c_char_p
     lib.hmm_status_string.argtypes = [ctypes.c_int]
-    _lib = lib
+    _lib, _lib_path = lib, path
     return lib
 
 
@@ -450,6 +456,19 @@ def workspace_error(ws: torch.Tensor, stream=None) -> int:
     v = ctypes.c_int32(0)
     rc = load_library().hmm_workspace_error(_ptr(ws), _stream(stream), ctypes.byref(v))
     _check("hmm_workspace_error", rc)
+    return int(v.value)
+
+
+def bound_library() -> Optional[str]:
+    """Path of the library the wrappers call (None before the first load)."""
+    return _lib_path
+
+
+def debug_flags() -> int:
+    """HMM_DEBUG_* bits of the bounds checks that failed since the last call (debug build
+    only; synchronises the device).  Raises HMMError(HMM_ERR_UNSUPPORTED) in a normal build."""
+    v = ctypes.c_uint32(0)
+    _check("hmm_debug_flags", load_library().hmm_debug_flags(ctypes.byref(v)))
     return int(v.value)
 
 

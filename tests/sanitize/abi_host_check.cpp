@@ -140,6 +140,9 @@ static void argument_checks() {
     EXPECT(hmm_logit_grad(out, out, out, 4, 0, nullptr) == HMM_ERR_SHAPE);
     EXPECT(hmm_logit_grad(out, nullptr, out, 4, 4, nullptr) == HMM_ERR_NULL);
     EXPECT(hmm_workspace_error(nullptr, nullptr, nullptr) == HMM_ERR_NULL);
+    uint32_t dbg = 5;
+    EXPECT(hmm_debug_flags(nullptr) == HMM_ERR_NULL);
+    EXPECT(hmm_debug_flags(&dbg) == HMM_ERR_UNSUPPORTED && dbg == 0);  // normal build: no checks
     EXPECT(hmm_select_kernel(7) == HMM_ERR_ARG);
     EXPECT(hmm_select_kernel(-1) == HMM_ERR_ARG);
     for (int k = HMM_KERNEL_SCAN; k >= HMM_KERNEL_AUTO; --k) EXPECT(hmm_select_kernel(k) == HMM_OK);

@@ -312,3 +312,20 @@ def test_call_kernel_resolution(lib):
     finally:
         hmm.select_kernel(hmm.KERNEL_AUTO)
         hmm.tune_clear()
+
+
+def test_debug_flags_in_the_normal_build(lib):
+    """The normal build compiles no bounds checks: hmm_debug_flags reports unsupported."""
+    v = ctypes.c_uint32(7)
+    assert lib.hmm_debug_flags(None) == -1
+    assert lib.hmm_debug_flags(ctypes.byref(v)) == -4 and v.value == 0
+
+
+def test_debug_build_exports_the_same_symbols():
+    """The bounds-checked copy of the library exports every declared entry point."""
+    if not os.path.exists(hmm.LIB_DEBUG_PATH):
+        import paper_1310_3322_amd.build as b
+        b.build(debug=True)
+    dbg = ctypes.CDLL(hmm.LIB_DEBUG_PATH)
+    for n in declared_functions():
+        assert hasattr(dbg, n), n

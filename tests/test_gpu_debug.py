@@ -1,0 +1,74 @@
+"""The bounds-checked build (libhmm_mi355x_debug.so, compiled with -DHMM_DEBUG) on the GPU.
+
+Its kernels check the indices they derive for the workspace and the outputs (work-list
+positions, log-likelihood stores, checkpoint slots, slab slots, segment lengths, Viterbi
+rows and rounds) and record a failed check instead of making the access.  On workloads that
+reach every checked index, no check may fail, and every result must equal the normal
+build's bit for bit (the checks change no arithmetic).  The normal build reports the
+debug call as unsupported.
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_1310_3322_amd import hmm, workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def problem(w, own=True):
+    return hmm.Problem(dev(w.pi), dev(w.A), dev(w.B), dev(w.symbols), dev(w.offsets), dev(w.lengths),
+                       dev(w.owner) if own else None, max_len=w.max_len, total_symbols=w.total_symbols)
+
+
+def run_all():
+    """Results of calls that reach each checked index (as numpy arrays)."""
+    out = {}
+    rng = np.random.default_rng(77)
+    w2 = workloads.make_workload("c2", scale=0.1)                  # all pairs, staging by sorted position
+    p2 = problem(w2, own=False)
+    ll = torch.empty((w2.S, w2.K), dtype=torch.float32, device="cuda")
+    lab = hmm.classify(p2, loglik=ll)
+    out["c2_labels"], out["c2_ll"] = lab.cpu().numpy(), ll.cpu().numpy()
+    w3 = workloads.make_workload("c3", scale=0.01)                 # own models, 32-sequence tiles
+    out["c3_own"] = hmm.forward_loglik(problem(w3)).cpu().numpy()
+    w1 = workloads.make_workload("c1")                             # time-parallel forward
+    out["c1"] = hmm.forward_loglik(problem(w1)).cpu().numpy()
+    for name, (K, N, M, S) in {"g16": (3, 16, 9, 70), "g64": (4, 64, 40, 60), "g256": (2, 256, 30, 20)}.items():
+        lengths = rng.integers(1, 200, size=S).astype(np.int32)  # checkpoints, segments, slab or global counts
+        w = workloads.random_lengths_workload(rng, K=K, N=N, M=M, lengths=lengths, all_pairs=False)
+        llg, cnt, _ = hmm.forward_backward_grad(problem(w))
+        out[name + "_ll"] = llg.cpu().numpy()
+        for i, c in enumerate(cnt):
+            out[f"{name}_cnt{i}"] = c.cpu().numpy()
+    for N in (20, 150):                                            # Viterbi in rounds (two halves of 2 max_len rows)
+        lengths = rng.integers(1, 90, size=120).astype(np.int32)
+        w = workloads.random_lengths_workload(rng, K=3, N=N, M=7, lengths=lengths, all_pairs=False)
+        p = problem(w)
+        sc, path = hmm.viterbi(p, ws=p.viterbi_workspace(2 * w.max_len + 5))
+        out[f"vit{N}_score"], out[f"vit{N}_path"] = sc.cpu().numpy(), path.cpu().numpy()
+    torch.cuda.synchronize()
+    return out
+
+
+def test_debug_build_checks_hold_and_change_nothing():
+    print("[case] debug build", flush=True)
+    prev = hmm.bound_library() or hmm.LIB_PATH
+    hmm.load_library(hmm.LIB_PATH, rebind=True)
+    with pytest.raises(hmm.HMMError) as e:
+        hmm.debug_flags()
+    assert e.value.status == -4
+    ref = run_all()
+    hmm.load_library(hmm.LIB_DEBUG_PATH, rebind=True)
+    try:
+        assert hmm.debug_flags() == 0          # nothing recorded yet
+        got = run_all()
+        assert hmm.debug_flags() == 0
+    finally:
+        hmm.load_library(prev, rebind=True)
+    for k in ref:
+        assert np.array_equal(ref[k], got[k], equal_nan=ref[k].dtype.kind == "f"), k
