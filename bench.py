@@ -396,7 +396,8 @@ def main():
         b = p.batch_without_models() if op == hmm.OP_CLASSIFY else p.batch
         got = hmm.tune_get(hmm.tune_key(p.bank, b, op)) if args.tune_cache else None
         if got is not None:
-            tuning[name] = {"choice": {"kernel": tune.KERNEL_NAMES[got[0]], "wg_per_cu": got[1]}, "source": "cache"}
+            tuning[name] = {"choice": {"kernel": tune.KERNEL_NAMES[got[0]], "wg_per_cu": got[1], "flags": got[2]},
+                            "source": "cache"}
             return
         log(f"autotuning {name}")
         r = tune.tune(p, op, **kw)

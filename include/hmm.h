@@ -272,16 +272,19 @@ hmm_status hmm_select_kernel(int32_t kind);
 
 /* Tuning table.  The component configuration of Sec. 4.1 leaves the block size
  * of the HMM stage to the user (16 by default); here the knobs are the kernel
- * family (which fixes the tile: 16 or 32 sequences, or a workgroup per tile)
- * and the size of the persistent grid, picked per call shape by measurement.  While
+ * family (which fixes the tile: 16 or 32 sequences, or a workgroup per tile),
+ * the size of the persistent grid and the flags below (where the tile kernels
+ * keep the emission table, whether all-pairs tiles are split over the XCDs),
+ * picked per call shape by measurement.  While
  * hmm_select_kernel is HMM_KERNEL_AUTO, a call whose shape has an entry takes
  * the entry's choice instead of the built-in heuristics; hmm_workspace_size
  * applies the same entry, so query it after tuning (a choice can need a larger
  * workspace; a call then returns HMM_ERR_WORKSPACE rather than run).  The table
  * lives in host memory, process-wide, at most HMM_TUNE_MAX entries; calls read
  * it on the host only, so they stay capturable into graphs.  Every choice runs
- * kernels held to the same accuracy; the grid cap changes no result, the
- * family may change the rounding of log-likelihoods within that accuracy.  Thread-safe; a call that races with a
+ * kernels held to the same accuracy; the grid cap and the flags change no
+ * result, the family may change the rounding of log-likelihoods within that
+ * accuracy.  Thread-safe; a call that races with a
  * change of its own entry takes either the old or the new choice. */
 #define HMM_TUNE_MAX 256
 #define HMM_TUNE_MAX_WG 64
@@ -298,7 +301,16 @@ typedef struct {
                            BATCHED (those ops have one family per shape)             */
     int32_t wg_per_cu;  /* cap on resident workgroups per compute unit of the persistent
                            launches, 0..HMM_TUNE_MAX_WG; 0 = as many as occupancy allows */
+    int32_t flags;      /* OR of HMM_TUNE_* below (0 = the built-in rules); they act on the
+                           tile forwards (16 and 32 sequences), including the gradient's
+                           checkpointing forward                                       */
 } hmm_tune_choice;
+#define HMM_TUNE_XCD_OFF 1    /* all-pairs tiles not split over the XCDs: each model's tiles in one
+                                 queue (default: one queue per XCD when the grid allows)     */
+#define HMM_TUNE_BT_GLOBAL 2  /* emission table read from global memory (default: copied into
+                                 LDS when it takes at most 48 KB)                             */
+#define HMM_TUNE_BT_LDS 4     /* emission table copied into LDS up to 128 KB (fewer workgroups
+                                 per CU); not together with HMM_TUNE_BT_GLOBAL                */
 
 /* The key of a call (host only; pointers in bank/batch may be NULL).
  * HMM_ERR_SHAPE / HMM_ERR_ARG for shapes or ops the calls would reject. */

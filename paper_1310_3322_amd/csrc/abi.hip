@@ -97,9 +97,10 @@ hmm_tune_key key_of(const hmm_bank *b, const hmm_batch *q, int op) {
 struct CallChoice {
     int kind;
     int wg_per_cu;
+    int flags;
 };
 CallChoice call_choice(const hmm_bank *b, const hmm_batch *q, int op) {
-    CallChoice c{g_kernel_kind.load(std::memory_order_relaxed), 0};
+    CallChoice c{g_kernel_kind.load(std::memory_order_relaxed), 0, 0};
     if (c.kind != HMM_KERNEL_AUTO) return c;
     const hmm_tune_key k = key_of(b, q, op);
     std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -107,6 +108,7 @@ CallChoice call_choice(const hmm_bank *b, const hmm_batch *q, int op) {
         if (same_key(g_tune[i].key, k)) {
             c.kind = g_tune[i].choice.kernel;
             c.wg_per_cu = g_tune[i].choice.wg_per_cu;
+            c.flags = g_tune[i].choice.flags;
             break;
         }
     return c;
@@ -258,6 +260,7 @@ Layout make_layout(const hmm_bank *b, const hmm_batch *q, int op, int64_t vit_ro
     const CallChoice cc = call_choice(b, q, op);
     L.kind = cc.kind;
     L.wg_per_cu = cc.wg_per_cu;
+    L.tune_flags = cc.flags;
     L.err = take(64);
     // all pairs: staging buffer of the sorted-position values (or the rows, without a caller buffer)
     if (op == HMM_OP_CLASSIFY || (op == HMM_OP_FORWARD && q->model_of_seq == nullptr))
@@ -482,6 +485,7 @@ hmm_status run_forward(const hmm_bank *b, const hmm_batch *q, int op, float *out
     f.llpos = staging;
     f.bmin = (const uint32_t *)(ws + L.bmin);
     f.max_grid = max_grid(L.wg_per_cu, cus);
+    f.tune_flags = L.tune_flags;
     if (S == 0) return HMM_OK;
     const int pr = prof_begin(st, HMM_PROF_FWD_BATCHED);
     const hipError_t e = fam == HMM_KERNEL_COOP    ? launch_fwd_coop(d, f, cus, st)
@@ -584,6 +588,7 @@ hmm_status hmm_forward_backward_grad(const hmm_bank *bank, const hmm_batch *batc
         f.flag = (int32_t *)(w + L.flag);
         f.nck = L.nck;
         f.max_grid = max_grid(L.wg_per_cu, cus);
+        f.tune_flags = L.tune_flags;
         if (S > 0) {
             const int pr = prof_begin(stream, HMM_PROF_FWD_BATCHED);
             const hipError_t e = grad_uses_coop(NP) ? launch_fwd_coop(d, f, cus, stream) : launch_fwd_mfma(d, f, cus, stream);
@@ -842,6 +847,8 @@ hmm_status hmm_tune_set(const hmm_tune_key *key, const hmm_tune_choice *choice) 
             choice->kernel != HMM_KERNEL_BATCHED)
             return HMM_ERR_ARG;
         if (choice->wg_per_cu < 0 || choice->wg_per_cu > HMM_TUNE_MAX_WG) return HMM_ERR_ARG;
+        if (choice->flags & ~(HMM_TUNE_XCD_OFF | HMM_TUNE_BT_GLOBAL | HMM_TUNE_BT_LDS)) return HMM_ERR_ARG;
+        if ((choice->flags & HMM_TUNE_BT_GLOBAL) && (choice->flags & HMM_TUNE_BT_LDS)) return HMM_ERR_ARG;
     }
     std::lock_guard<std::mutex> lk(g_tune_mu);
     int at = -1;

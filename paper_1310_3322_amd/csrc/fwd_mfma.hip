@@ -225,7 +225,7 @@ hipError_t launch_t(const DevPtrs &d, const FwdLaunch &f, int cu_count, hipStrea
 bool fwd_mfma_supported(int NP) { return NP == 16 || NP == 32 || NP == 48 || NP == 64; }
 
 hipError_t launch_fwd_mfma(const DevPtrs &d, const FwdLaunch &f, int cu_count, hipStream_t st) {
-    const bool blds = (size_t)f.M * f.NP * sizeof(float) <= 48 * 1024;
+    const bool blds = bt_in_lds(f);
     const bool ck = f.ckpt != nullptr;
 #define HMM_FWD_CASE(R)                                                                  \
     case R:                                                                              \

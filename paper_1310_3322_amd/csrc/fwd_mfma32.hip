@@ -51,7 +51,7 @@ k_fwd_mfma32(DevPtrs d, FwdLaunch f) {
     // XCD b mod 8): slice x takes tiles x, x + 8, ... of every model, so each
     // tile's symbols are read into one XCD's L2 and serve all the models there.
     // Own-model calls keep one model per workgroup.
-    const int XS = xcd_slices(f.all_pairs, gridDim.x, K);
+    const int XS = xcd_slices(f.all_pairs && !(f.tune_flags & HMM_TUNE_XCD_OFF), gridDim.x, K);
     const int x = (int)(blockIdx.x % XS);
     const int G = (int)gridDim.x / XS, gi = (int)blockIdx.x / XS;
     const int k_first = G >= K ? gi % K : gi;
@@ -275,7 +275,7 @@ bool fwd_mfma32_supported(int NP) { return NP == 32 || NP == 64; }
 
 hipError_t launch_fwd_mfma32(const DevPtrs &d, const FwdLaunch &f, int cu_count, hipStream_t st) {
     if (f.ckpt != nullptr) return hipErrorInvalidValue;
-    const bool blds = (size_t)f.M * f.NP * sizeof(float) <= 48 * 1024;
+    const bool blds = bt_in_lds(f);
     switch (f.NP) {
         case 32: return blds ? launch_t<1, true>(d, f, cu_count, st) : launch_t<1, false>(d, f, cu_count, st);
         case 64: return blds ? launch_t<2, true>(d, f, cu_count, st) : launch_t<2, false>(d, f, cu_count, st);

@@ -41,6 +41,7 @@ struct Layout {
     int32_t scan_nch;    // chunks per pair of the time-parallel forward (0: not used)
     int32_t kind;        // kernel family of the call (HMM_KERNEL_*, after the tuning table)
     int32_t wg_per_cu;   // cap on resident workgroups per CU of persistent launches (0: none)
+    int32_t tune_flags;  // HMM_TUNE_* of the call's tuning entry
     size_t total;
     int32_t plan_chunk;    // sequences per chunk of the stable counting sort
     int32_t plan_nchunks;  // chunks of the stable counting sort
@@ -160,7 +161,14 @@ struct FwdLaunch {
     int32_t *flag;    // [S] per sorted position: 1 = no finite likelihood (gradient only)
     int nck;
     int max_grid;     // cap on the persistent grid (0: occupancy limit)
+    int tune_flags;   // HMM_TUNE_* of the call
 };
+// Whether a tile forward copies the emission table (M x NP floats) into LDS.
+inline bool bt_in_lds(const FwdLaunch &f) {
+    const size_t bytes = (size_t)f.M * f.NP * sizeof(float);
+    if (f.tune_flags & HMM_TUNE_BT_GLOBAL) return false;
+    return bytes <= ((f.tune_flags & HMM_TUNE_BT_LDS) ? (size_t)128 * 1024 : (size_t)48 * 1024);
+}
 // The log-likelihood of sequence seq (sorted position pos) under model k.
 __device__ __forceinline__ void store_ll(const FwdLaunch &f, int seq, int pos, int k, float r) {
     if (f.llpos) {

@@ -28,6 +28,7 @@ EXPORTS = ("hmm_workspace_size", "hmm_viterbi_workspace_size", "hmm_forward_logl
            "hmm_tune_key_of", "hmm_tune_set", "hmm_tune_get", "hmm_tune_clear", "hmm_call_kernel",
            "hmm_profile_enable", "hmm_profile_read", "hmm_status_string")
 TUNE_MAX, TUNE_MAX_WG = 256, 64
+TUNE_XCD_OFF, TUNE_BT_GLOBAL, TUNE_BT_LDS = 1, 2, 4  # HMM_TUNE_* flags
 STATIC_SCRATCH_BYTES = 32 << 20  # HMM_STATIC_SCRATCH_BYTES
 PROF_FWD_BATCHED, PROF_ADJ_BATCHED, PROF_FWD_PLAIN, PROF_VITERBI = 0, 1, 2, 3
 
@@ -59,7 +60,7 @@ class TuneKey(ctypes.Structure):
 
 
 class TuneChoice(ctypes.Structure):
-    _fields_ = [("kernel", ctypes.c_int32), ("wg_per_cu", ctypes.c_int32)]
+    _fields_ = [("kernel", ctypes.c_int32), ("wg_per_cu", ctypes.c_int32), ("flags", ctypes.c_int32)]
 
 
 _lib = None
@@ -232,18 +233,19 @@ def tune_key(bank: Bank, batch: Batch, op: int) -> TuneKey:
     return k
 
 
-def tune_set(key: TuneKey, kernel: Optional[int], wg_per_cu: int = 0):
-    """Installs the choice (kernel family, workgroups per CU) for `key`; kernel None removes the entry."""
-    c = None if kernel is None else ctypes.byref(TuneChoice(int(kernel), int(wg_per_cu)))
+def tune_set(key: TuneKey, kernel: Optional[int], wg_per_cu: int = 0, flags: int = 0):
+    """Installs the choice (kernel family, workgroups per CU, TUNE_* flags) for `key`;
+    kernel None removes the entry."""
+    c = None if kernel is None else ctypes.byref(TuneChoice(int(kernel), int(wg_per_cu), int(flags)))
     _check("hmm_tune_set", load_library().hmm_tune_set(ctypes.byref(key), c))
 
 
 def tune_get(key: TuneKey) -> Optional[tuple]:
-    """(kernel, wg_per_cu) installed for `key`, or None."""
+    """(kernel, wg_per_cu, flags) installed for `key`, or None."""
     c = TuneChoice()
     found = ctypes.c_int32(0)
     _check("hmm_tune_get", load_library().hmm_tune_get(ctypes.byref(key), ctypes.byref(c), ctypes.byref(found)))
-    return (int(c.kernel), int(c.wg_per_cu)) if found.value else None
+    return (int(c.kernel), int(c.wg_per_cu), int(c.flags)) if found.value else None
 
 
 def tune_clear():

@@ -9,7 +9,12 @@ measurement, per call shape:
     tile shape, and
   * the cap on resident workgroups per compute unit of the persistent launches
     (forward, gradient and Viterbi decoding), which sets how many queue
-    consumers share a CU and its L2 slice.
+    consumers share a CU and its L2 slice, and
+  * for the tile forwards (recognition, log-likelihoods and the gradient's
+    checkpointing forward), where the emission table lives (copied into LDS up
+    to 48 KB by default, up to 128 KB, or read from global memory) and whether
+    all-pairs tiles are split over the XCDs: tried on the best family and cap
+    of the first stage.
 
 For one call shape, `tune` runs the library's default choice first and keeps
 its outputs as the reference, then runs every candidate the library accepts for
@@ -176,8 +181,8 @@ def _time(call: _Call, ws: torch.Tensor, warmup: int, reps: int) -> float:
 def tune(p: hmm.Problem, op: int, warmup: int = 1, reps: int = 3, stream=None, log=None) -> dict:
     """Tunes the calls of `op` on problem `p`'s shape and installs the fastest
     accepted choice.  Sets the kernel selector to HMM_KERNEL_AUTO (the table
-    applies only then).  Returns a record with the key, the chosen kernel and
-    grid cap, and every candidate's time and verdict."""
+    applies only then).  Returns a record with the key, the chosen kernel, grid
+    cap and flags, and every candidate's time and verdict."""
     if stream is None:
         stream = torch.cuda.current_stream()
     hmm.select_kernel(hmm.KERNEL_AUTO)
@@ -190,11 +195,15 @@ def tune(p: hmm.Problem, op: int, warmup: int = 1, reps: int = 3, stream=None, l
     torch.cuda.synchronize()
     ref = call.snapshot()
     base_ms = _time(call, ws, warmup, reps)
-    cands = [{"kernel": KERNEL_NAMES[hmm.KERNEL_AUTO], "wg_per_cu": 0, "ms": base_ms, "ok": True, "reason": "default"}]
-    best = (base_ms, hmm.KERNEL_AUTO, 0)
-    for kind, cap in _candidates(op):
-        hmm.tune_set(key, kind, cap)
-        rec = {"kernel": KERNEL_NAMES[kind], "wg_per_cu": cap, "ms": None, "ok": False, "reason": ""}
+    cands = [{"kernel": KERNEL_NAMES[hmm.KERNEL_AUTO], "wg_per_cu": 0, "flags": 0, "ms": base_ms, "ok": True,
+              "reason": "default"}]
+    best = [base_ms, hmm.KERNEL_AUTO, 0, 0]
+
+    def attempt(kind, cap, flags):
+        hmm.tune_set(key, kind, cap, flags)
+        rec = {"kernel": KERNEL_NAMES[kind], "wg_per_cu": cap, "flags": flags, "ms": None, "ok": False,
+               "reason": ""}
+        cands.append(rec)
         try:
             ws = call.workspace()
             for t in call.outs:
@@ -206,21 +215,29 @@ def tune(p: hmm.Problem, op: int, warmup: int = 1, reps: int = 3, stream=None, l
                 hmm.tune_set(key, None)
                 raise
             rec["reason"] = "unsupported"
-            cands.append(rec)
-            continue
+            return
         why = _mismatch(op, call.outs, ref)
         if why:
             rec["reason"] = why
-            cands.append(rec)
-            continue
+            return
         ms = _time(call, ws, warmup, reps)
         rec.update(ms=ms, ok=True)
-        cands.append(rec)
         if ms < best[0]:
-            best = (ms, kind, cap)
-    hmm.tune_set(key, best[1], best[2])
+            best[:] = [ms, kind, cap, flags]
+
+    for kind, cap in _candidates(op):
+        attempt(kind, cap, 0)
+    # second stage: the flags on the best family and cap (they act on the tile forwards)
+    if best[1] in (hmm.KERNEL_AUTO, hmm.KERNEL_BATCHED, hmm.KERNEL_TILE16, hmm.KERNEL_TILE32):
+        kind, cap = best[1], best[2]
+        sets = [hmm.TUNE_BT_GLOBAL, hmm.TUNE_BT_LDS]
+        if call.batch.model_of_seq is None:  # all pairs
+            sets += [hmm.TUNE_XCD_OFF, hmm.TUNE_XCD_OFF | hmm.TUNE_BT_LDS]
+        for flags in sets:
+            attempt(kind, cap, flags)
+    hmm.tune_set(key, best[1], best[2], best[3])
     result = {"op": OP_NAMES[op], "key": key.as_dict(),
-              "choice": {"kernel": KERNEL_NAMES[best[1]], "wg_per_cu": best[2]},
+              "choice": {"kernel": KERNEL_NAMES[best[1]], "wg_per_cu": best[2], "flags": best[3]},
               "ms": best[0], "default_ms": base_ms, "candidates": cands}
     if log is not None:
         log(result)
@@ -260,6 +277,7 @@ def load_cache(path: str, arch: Optional[str] = None) -> int:
         if e.get("arch") != arch:
             continue
         key = hmm.TuneKey(**{f: int(e["key"][f]) for f, _ in hmm.TuneKey._fields_})
-        hmm.tune_set(key, _KERNEL_IDS[e["choice"]["kernel"]], int(e["choice"]["wg_per_cu"]))
+        hmm.tune_set(key, _KERNEL_IDS[e["choice"]["kernel"]], int(e["choice"]["wg_per_cu"]),
+                     int(e["choice"].get("flags", 0)))
         n += 1
     return n

@@ -163,7 +163,7 @@ static hmm_tune_key key(int op, int all_pairs, int K, int N, int M, int sb, int 
 
 static void tuning_table() {
     EXPECT(hmm_tune_clear() == HMM_OK);
-    const hmm_tune_choice c16{HMM_KERNEL_TILE16, 1}, c32{HMM_KERNEL_TILE32, 2};
+    const hmm_tune_choice c16{HMM_KERNEL_TILE16, 1, 0}, c32{HMM_KERNEL_TILE32, 2, HMM_TUNE_XCD_OFF | HMM_TUNE_BT_LDS};
     for (int i = 0; i < HMM_TUNE_MAX; ++i) {
         const hmm_tune_key k = key(HMM_OP_FORWARD, 1, i + 1, 16, 32, 7, 6);
         EXPECT(hmm_tune_set(&k, &c16) == HMM_OK);
@@ -172,10 +172,10 @@ static void tuning_table() {
     EXPECT(hmm_tune_set(&over, &c16) == HMM_ERR_UNSUPPORTED);
     const hmm_tune_key k5 = key(HMM_OP_FORWARD, 1, 5, 16, 32, 7, 6);
     EXPECT(hmm_tune_set(&k5, &c32) == HMM_OK);
-    hmm_tune_choice got{0, 0};
+    hmm_tune_choice got{0, 0, 0};
     int32_t found = 0;
     EXPECT(hmm_tune_get(&k5, &got, &found) == HMM_OK && found == 1 && got.kernel == HMM_KERNEL_TILE32 &&
-           got.wg_per_cu == 2);
+           got.wg_per_cu == 2 && got.flags == (HMM_TUNE_XCD_OFF | HMM_TUNE_BT_LDS));
     const hmm_tune_key k7 = key(HMM_OP_FORWARD, 1, 7, 16, 32, 7, 6);
     EXPECT(hmm_tune_set(&k7, nullptr) == HMM_OK);
     EXPECT(hmm_tune_set(&over, &c16) == HMM_OK);
@@ -187,9 +187,12 @@ static void tuning_table() {
     EXPECT(hmm_tune_set(&bad_pairs, &c16) == HMM_ERR_ARG);
     EXPECT(hmm_tune_set(&bad_n, &c16) == HMM_ERR_ARG);
     EXPECT(hmm_tune_set(&bad_sb, &c16) == HMM_ERR_ARG);
-    const hmm_tune_choice bad_kind{7, 0}, bad_cap{HMM_KERNEL_AUTO, HMM_TUNE_MAX_WG + 1};
+    const hmm_tune_choice bad_kind{7, 0, 0}, bad_cap{HMM_KERNEL_AUTO, HMM_TUNE_MAX_WG + 1, 0};
+    const hmm_tune_choice bad_bit{HMM_KERNEL_AUTO, 0, 8}, bad_pair{HMM_KERNEL_AUTO, 0, HMM_TUNE_BT_GLOBAL | HMM_TUNE_BT_LDS};
     EXPECT(hmm_tune_set(&k5, &bad_kind) == HMM_ERR_ARG);
     EXPECT(hmm_tune_set(&k5, &bad_cap) == HMM_ERR_ARG);
+    EXPECT(hmm_tune_set(&k5, &bad_bit) == HMM_ERR_ARG);
+    EXPECT(hmm_tune_set(&k5, &bad_pair) == HMM_ERR_ARG);
     const hmm_tune_key kg = key(HMM_OP_GRAD, 0, 8, 64, 512, 14, 10);
     EXPECT(hmm_tune_set(&kg, &c16) == HMM_ERR_ARG);
     EXPECT(hmm_tune_set(nullptr, nullptr) == HMM_ERR_NULL);
@@ -201,7 +204,7 @@ static void tuning_table() {
     const size_t plain = hmm_workspace_size(&b, &q, HMM_OP_FORWARD);
     hmm_tune_key kq;
     EXPECT(hmm_tune_key_of(&b, &q, HMM_OP_FORWARD, &kq) == HMM_OK);
-    const hmm_tune_choice scan{HMM_KERNEL_SCAN, 0};
+    const hmm_tune_choice scan{HMM_KERNEL_SCAN, 0, 0};
     EXPECT(hmm_tune_set(&kq, &scan) == HMM_OK);
     EXPECT(hmm_workspace_size(&b, &q, HMM_OP_FORWARD) > plain);
     int32_t kern = -1;

@@ -186,10 +186,10 @@ def test_tune_table_set_get_remove(lib):
     hmm.tune_clear()
     k = _key()
     assert hmm.tune_get(k) is None
-    hmm.tune_set(k, hmm.KERNEL_TILE32, 2)
-    assert hmm.tune_get(k) == (hmm.KERNEL_TILE32, 2)
+    hmm.tune_set(k, hmm.KERNEL_TILE32, 2, hmm.TUNE_XCD_OFF | hmm.TUNE_BT_LDS)
+    assert hmm.tune_get(k) == (hmm.KERNEL_TILE32, 2, hmm.TUNE_XCD_OFF | hmm.TUNE_BT_LDS)
     hmm.tune_set(k, hmm.KERNEL_COOP, 0)  # replaces
-    assert hmm.tune_get(k) == (hmm.KERNEL_COOP, 0)
+    assert hmm.tune_get(k) == (hmm.KERNEL_COOP, 0, 0)
     other = _key(sb=8)
     assert hmm.tune_get(other) is None
     hmm.tune_set(k, None)
@@ -204,6 +204,10 @@ def test_tune_table_set_get_remove(lib):
     for key, kind, cap in bad:
         with pytest.raises(hmm.HMMError) as e:
             hmm.tune_set(key, kind, cap)
+        assert e.value.status == -6
+    for flags in (8, -1, hmm.TUNE_BT_GLOBAL | hmm.TUNE_BT_LDS):  # unknown bits, both table placements
+        with pytest.raises(hmm.HMMError) as e:
+            hmm.tune_set(_key(), hmm.KERNEL_TILE32, 0, flags)
         assert e.value.status == -6
     hmm.tune_set(_key(op=hmm.OP_GRAD, all_pairs=0), hmm.KERNEL_BATCHED, 4)
     assert lib.hmm_tune_set(None, None) == -1
@@ -220,10 +224,10 @@ def test_tune_table_capacity(lib):
         hmm.tune_set(_key(K=hmm.TUNE_MAX + 1), hmm.KERNEL_TILE16, 1)
     assert e.value.status == -4
     hmm.tune_set(_key(K=5), hmm.KERNEL_TILE32, 2)  # replacing still works when full
-    assert hmm.tune_get(_key(K=5)) == (hmm.KERNEL_TILE32, 2)
+    assert hmm.tune_get(_key(K=5)) == (hmm.KERNEL_TILE32, 2, 0)
     hmm.tune_set(_key(K=7), None)
     hmm.tune_set(_key(K=hmm.TUNE_MAX + 1), hmm.KERNEL_TILE16, 1)  # a freed slot is reused
-    assert hmm.tune_get(_key(K=hmm.TUNE_MAX + 1)) == (hmm.KERNEL_TILE16, 1)
+    assert hmm.tune_get(_key(K=hmm.TUNE_MAX + 1)) == (hmm.KERNEL_TILE16, 1, 0)
     assert hmm.tune_get(_key(K=7)) is None
     hmm.tune_clear()
 
@@ -265,10 +269,11 @@ def test_tune_cache_roundtrip(lib, tmp_path):
     tune.save_cache(path, [r1], arch="gfx950")
     tune.save_cache(path, [r2], arch="gfx950")          # merged
     tune.save_cache(path, [dict(r1, choice={"kernel": "coop", "wg_per_cu": 0})], arch="gfx942")  # other arch
-    tune.save_cache(path, [dict(r1, choice={"kernel": "tile16", "wg_per_cu": 4})], arch="gfx950")  # replaces r1
+    tune.save_cache(path, [dict(r1, choice={"kernel": "tile16", "wg_per_cu": 4, "flags": hmm.TUNE_BT_GLOBAL})],
+                    arch="gfx950")  # replaces r1
     assert tune.load_cache(path, arch="gfx950") == 2
-    assert hmm.tune_get(_key()) == (hmm.KERNEL_TILE16, 4)
-    assert hmm.tune_get(_key(op=hmm.OP_VITERBI, all_pairs=0)) == (hmm.KERNEL_BATCHED, 1)
+    assert hmm.tune_get(_key()) == (hmm.KERNEL_TILE16, 4, hmm.TUNE_BT_GLOBAL)
+    assert hmm.tune_get(_key(op=hmm.OP_VITERBI, all_pairs=0)) == (hmm.KERNEL_BATCHED, 1, 0)  # no flags: 0
     hmm.tune_clear()
     assert tune.load_cache(path, arch="gfx90a") == 0
     assert hmm.tune_get(_key()) is None

@@ -142,11 +142,14 @@ def test_tune_installs_an_accepted_choice(op):
     p = problem(w, own)
     r = tune.tune(p, op, warmup=1, reps=2)
     assert r["op"] == tune.OP_NAMES[op]
-    chosen = (tune._KERNEL_IDS[r["choice"]["kernel"]], r["choice"]["wg_per_cu"])
+    chosen = (tune._KERNEL_IDS[r["choice"]["kernel"]], r["choice"]["wg_per_cu"], r["choice"]["flags"])
     key = hmm.TuneKey(**r["key"])
     assert hmm.tune_get(key) == chosen
     ok = [c for c in r["candidates"] if c["ok"]]
-    assert any((c["kernel"], c["wg_per_cu"]) == (r["choice"]["kernel"], r["choice"]["wg_per_cu"]) for c in ok)
+    assert any((c["kernel"], c["wg_per_cu"], c["flags"]) ==
+               (r["choice"]["kernel"], r["choice"]["wg_per_cu"], r["choice"]["flags"]) for c in ok)
+    if op in (hmm.OP_FORWARD, hmm.OP_CLASSIFY, hmm.OP_GRAD):  # the second stage tried the flags
+        assert any(c["flags"] != 0 for c in r["candidates"])
     assert r["ms"] == min(c["ms"] for c in ok)
     assert all(c["reason"] in ("unsupported", "default", "") for c in r["candidates"]), r["candidates"]
     # a call after tuning takes the installed choice and still matches the oracle
@@ -169,6 +172,58 @@ def test_tune_installs_an_accepted_choice(op):
     else:
         rs, _, _ = O.viterbi(w.pi, w.A, w.B, w.symbols, w.offsets, w.lengths, w.owner)
         assert rel_err(hmm.viterbi(p)[0].cpu().numpy(), rs) <= LL_TOL
+
+
+@pytest.mark.parametrize("kind,N,M,all_pairs,S", [(hmm.KERNEL_TILE32, 32, 500, True, 20000),
+                                                 (hmm.KERNEL_TILE16, 16, 1000, True, 20000),
+                                                 (hmm.KERNEL_TILE32, 32, 500, False, 3000),
+                                                 (hmm.KERNEL_TILE16, 48, 300, False, 3000)])
+def test_tune_flags_change_no_result(kind, N, M, all_pairs, S):
+    """Where the tile kernels keep the emission table (LDS up to 128 KB, global memory) and
+    whether all-pairs tiles are split over the XCDs (20,000 sequences of 4 models fill a
+    grid that allows the split) change no result: log-likelihoods bit-identical to the
+    built-in choice (the tables here take 64-75 KB, so the default reads them from global
+    memory), and within the oracle's tolerance."""
+    print(f"[case] tune flags kind={kind} N={N} all_pairs={all_pairs}", flush=True)
+    w = short_workload(300 + N, K=4, N=N, M=M, S=S, tmax=24, all_pairs=all_pairs)
+    p = problem(w, not all_pairs)
+    key = hmm.tune_key(p.bank, p.batch, hmm.OP_FORWARD)
+    sets = [0, hmm.TUNE_BT_GLOBAL, hmm.TUNE_BT_LDS]
+    if all_pairs:
+        sets += [hmm.TUNE_XCD_OFF, hmm.TUNE_XCD_OFF | hmm.TUNE_BT_LDS]
+    base = None
+    try:
+        for flags in sets:
+            hmm.tune_set(key, kind, 0, flags)
+            ll = hmm.forward_loglik(p).cpu().numpy()
+            if base is None:
+                base = ll
+                ref = O.forward(w.pi, w.A, w.B, w.symbols, w.offsets, w.lengths, None if all_pairs else w.owner)
+                assert rel_err(ll, ref) <= LL_TOL
+            else:
+                assert np.array_equal(ll, base, equal_nan=True), flags
+    finally:
+        hmm.tune_set(key, None)
+
+
+def test_tune_flags_gradient_counts_identical():
+    """The gradient's checkpointing forward (16-sequence tiles, N = 32) with its emission
+    table in LDS or in global memory: identical log-likelihoods and counts."""
+    print("[case] tune flags gradient", flush=True)
+    w = short_workload(5, K=3, N=32, M=700, S=400, tmax=60, all_pairs=False)
+    p = problem(w, True)
+    key = hmm.tune_key(p.bank, p.batch, hmm.OP_GRAD)
+    outs = []
+    try:
+        for flags in (0, hmm.TUNE_BT_LDS, hmm.TUNE_BT_GLOBAL):
+            hmm.tune_set(key, hmm.KERNEL_BATCHED, 0, flags)
+            ll, cnt, _ = hmm.forward_backward_grad(p)
+            outs.append([ll.cpu().numpy()] + [c.cpu().numpy() for c in cnt])
+    finally:
+        hmm.tune_set(key, None)
+    for o in outs[1:]:
+        for a, b in zip(o, outs[0]):
+            assert np.array_equal(a, b, equal_nan=True)
 
 
 def test_selector_overrides_table():
