@@ -81,6 +81,17 @@ TRAFFIC_KERNELS = {
     "c5_grad_forward": ("k_fwd_coop<16, 2, true>", _FWD_COOP),
     "c5_grad_adjoint": ("k_adj_coop<16, 2, false, true>", _ADJ_COOP),
 }
+# The bench leg whose tuned choice (kernel family, workgroups-per-CU cap, flags)
+# launched each recorded kernel: a figure holds only for the choice it was taken on.
+TRAFFIC_LEGS = {"c3_classify": "c3_classify", "c4_grad_forward": "c4_grad", "c4_grad_adjoint": "c4_grad",
+                "c5_forward": "c5_forward", "c5_grad_forward": "c5_grad", "c5_grad_adjoint": "c5_grad"}
+DEFAULT_CHOICE = {"kernel": "auto", "wg_per_cu": 0, "flags": 0}
+
+
+def leg_choice(tuning: dict, leg: str) -> dict:
+    """The choice a leg ran with: its tuned one, else the library's heuristics."""
+    c = (tuning or {}).get(leg, {}).get("choice")
+    return {k: c.get(k, 0) for k in DEFAULT_CHOICE} if c else dict(DEFAULT_CHOICE)
 
 
 def log(msg):
@@ -99,16 +110,15 @@ def kernel_source_hash(family: str = "tile32") -> str:
     return source_hash(FAMILY_KERNELS[family][2])
 
 
-def measured_traffic(workload: str, family: str = None):
+def measured_traffic(workload: str, choice: dict, family: str = None, path: str = TRAFFIC_FILE):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the workload's kernel (for c3: the family's kernel) with the
-    current source; else None."""
+    holds a record taken on the workload's kernel (for c3: the family's kernel)
+    with the current source and the same tuned choice; else None."""
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(path) as fh:
             data = json.load(fh)
     except (OSError, ValueError):
         return None
-    rec = data.get(workload)
     if family is not None:
         if family not in FAMILY_KERNELS:
             return None
@@ -117,18 +127,31 @@ def measured_traffic(workload: str, family: str = None):
         kernel, files = TRAFFIC_KERNELS[workload]
     else:
         return None
-    if not rec or rec.get("kernel") != kernel or rec.get("kernel_source_hash") != source_hash(files):
-        return None
-    return rec.get("bytes_per_launch")
+    h = source_hash(files)
+    for rec in data.get(workload, []):
+        if rec.get("kernel") == kernel and rec.get("kernel_source_hash") == h and rec.get("choice") == choice:
+            return rec.get("bytes_per_launch")
+    return None
 
 
-def traffic_summary(fetch_csv: str, write_csv: str, out: str = TRAFFIC_FILE):
-    """profiles/traffic.json from two rocprofv3 --pmc runs of the same command
-    (FETCH_SIZE, then WRITE_SIZE; counter_collection.csv of each, values in KiB
-    per dispatch) that include --copy-calibration: the counters of the 512 MiB
-    device copies give the scale from counter to bytes; per kernel the average
-    over its dispatches, scaled."""
+def traffic_summary(fetch_csv: str, write_csv: str, bench_out: str, out: str = TRAFFIC_FILE):
+    """Records in profiles/traffic.json from two rocprofv3 --pmc runs of the same
+    command (FETCH_SIZE, then WRITE_SIZE; counter_collection.csv of each, values
+    in KiB per dispatch) that include --copy-calibration: the counters of the
+    512 MiB device copies give the scale from counter to bytes; per kernel the
+    average over its dispatches, scaled.  `bench_out` is the output of one of
+    those runs (its JSON line names the tuned choice each leg ran with, which
+    the record keeps).  Per workload the file holds one record per choice:
+    a new record replaces the one of the same choice, and records taken on
+    other source are dropped."""
     import csv
+
+    tuning = {}
+    with open(bench_out) as fh:
+        for line in fh:
+            line = line.strip()
+            if line.startswith("{"):
+                tuning = json.loads(line).get("tuning", {})
 
     def per_kernel(path, counter):
         acc = {}
@@ -156,30 +179,43 @@ def traffic_summary(fetch_csv: str, write_csv: str, out: str = TRAFFIC_FILE):
         hits = [vs for name, vs in acc.items() if ("::" + kernel + "(") in name]
         return hits[0] if len(hits) == 1 else None
 
-    data = {}
+    try:
+        with open(out) as fh:
+            old = json.load(fh)
+    except (OSError, ValueError):
+        old = {}
+    data, new = {}, {}
     for wl, (kernel, files) in TRAFFIC_KERNELS.items():
+        h = source_hash(files)
+        choice = leg_choice(tuning, TRAFFIC_LEGS[wl])
+        kept = [r for r in (old.get(wl) if isinstance(old.get(wl), list) else [])
+                if r.get("kernel") == kernel and r.get("kernel_source_hash") == h]
         fv, wv = find(fetch, kernel), find(write, kernel)
         if fv is None or wv is None:
+            if kept:
+                data[wl] = kept
             continue
         fb, wb = float(np.mean(fv)) * fscale, float(np.mean(wv)) * wscale
-        data[wl] = {"kernel": kernel, "kernel_source_hash": source_hash(files),
-                    "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb, "bytes_per_launch": fb + wb,
-                    "fetch_scale": fscale, "write_scale": wscale,
-                    "calibration": f"__amd_rocclr_copyBuffer of 512 MiB: FETCH_SIZE {fraw / 1024:.1f} KiB, "
-                                   f"WRITE_SIZE {wraw / 1024:.1f} KiB per dispatch",
-                    "launches": min(len(fv), len(wv))}
+        new[wl] = {"kernel": kernel, "kernel_source_hash": h, "choice": choice,
+                   "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb, "bytes_per_launch": fb + wb,
+                   "fetch_scale": fscale, "write_scale": wscale,
+                   "calibration": f"__amd_rocclr_copyBuffer of 512 MiB: FETCH_SIZE {fraw / 1024:.1f} KiB, "
+                                  f"WRITE_SIZE {wraw / 1024:.1f} KiB per dispatch",
+                   "launches": min(len(fv), len(wv))}
+        data[wl] = [r for r in kept if r.get("choice") != choice] + [new[wl]]
     with open(out, "w") as fh:
         json.dump(data, fh, indent=1)
         fh.write("\n")
-    print(json.dumps({k: round(v["bytes_per_launch"] / 1e9, 4) for k, v in data.items()}))
+    print(json.dumps({k: round(v["bytes_per_launch"] / 1e9, 4) for k, v in new.items()}))
 
 
-def traffic_fields(kernels):
+def traffic_fields(kernels, tuning):
     """{name: (traffic workload, kernel ms)} -> HBM bytes per launch from the committed counter
-    summary (None when it was taken on other code) and the rate they give at that kernel time."""
+    summary (None when it was taken on other code or another tuned choice) and the rate they
+    give at that kernel time."""
     out = {}
     for name, (wl, ms) in kernels.items():
-        b = measured_traffic(wl)
+        b = measured_traffic(wl, leg_choice(tuning, TRAFFIC_LEGS[wl]))
         out[name] = {"kernel": TRAFFIC_KERNELS[wl][0], "hbm_bytes_per_launch": b,
                      "hbm_gbs": round(b / (ms / 1e3) / 1e9, 1) if b and ms > 0 else None}
     return out
@@ -317,7 +353,7 @@ def cpu_oracle_counts(w, target_s: float = 5.0):
     O.counts(sample.pi, sample.A, sample.B, sample.symbols, sample.offsets, sample.lengths, sample.owner)
     dt = time.perf_counter() - t0
     return {"value": sample.units() / dt, "unit": "state-steps/s", "cores": O.max_threads(), "kind": "oracle",
-            "sample": f"every {stride}th sequence in length order ({sample.S} of {w.S}), own model, "
+            "sample": f"one sequence in {stride} in length order ({sample.S} of {w.S}), own model, "
                       f"{sample.units():.3e} state-steps in {dt:.1f} s, FP64 forward + backward counts"}
 
 
@@ -338,7 +374,7 @@ def cpu_baseline(w, target_s: float = 15.0):
     O.forward(sample.pi, sample.A, sample.B, sample.symbols, sample.offsets, sample.lengths, None)
     dt = time.perf_counter() - t0
     return {"value": sample.units() / dt, "unit": "state-steps/s", "cores": threads, "kind": "oracle",
-            "sample": f"every {stride}th sequence in length order ({sample.S} of {w.S}) x all {w.K} models, "
+            "sample": f"one sequence in {stride} in length order ({sample.S} of {w.S}) x all {w.K} models, "
                       f"{sample.units():.3e} state-steps in {dt:.1f} s, FP64, OpenMP over pairs"}
 
 
@@ -358,9 +394,10 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="keep the built-in kernel heuristics (no autotuning)")
     ap.add_argument("--tune-cache", default=None,
                     help="JSON tuning cache: install the choices stored there instead of tuning, store new ones")
-    ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"), default=None,
+    ap.add_argument("--traffic-summary", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "BENCH_JSON"), default=None,
                     help="write profiles/traffic.json from the counter_collection.csv files of a FETCH_SIZE "
-                         "and a WRITE_SIZE rocprofv3 run of this bench (with --copy-calibration) and exit")
+                         "and a WRITE_SIZE rocprofv3 run of this bench (with --copy-calibration and the "
+                         "--tune-cache of the bench run whose output line BENCH_JSON holds) and exit")
     args = ap.parse_args()
     if args.traffic_summary:
         traffic_summary(*args.traffic_summary)
@@ -436,7 +473,7 @@ def main():
     kern_s = kern_ms / 1e3 / max(launches, 1)
     flops = 2.0 * units
     achieved = flops / kern_s / 1e12
-    traffic = measured_traffic("c3_classify", family)
+    traffic = measured_traffic("c3_classify", leg_choice(tuning, "c3_classify"), family)
     kname = " ".join(FAMILY_KERNELS[family][:2]) if family in FAMILY_KERNELS else family
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / FP32_PEAK_TFLOPS, 4), "traffic": traffic,
@@ -491,7 +528,8 @@ def main():
                              "fwd_kernel_ms": f_ms / max(f_n, 1), "adj_kernel_ms": a_ms / max(a_n, 1),
                              "frac_fp32_peak": 6.0 * u4 / gsec / 1e12 / FP32_PEAK_TFLOPS,
                              "traffic": traffic_fields({"forward": ("c4_grad_forward", f_ms / max(f_n, 1)),
-                                                        "adjoint": ("c4_grad_adjoint", a_ms / max(a_n, 1))})}
+                                                        "adjoint": ("c4_grad_adjoint", a_ms / max(a_n, 1))},
+                                                       tuning)}
         if not args.no_cpu:
             log("CPU oracle forward + backward on a c4 sample")
             result["fwd_bwd"]["cpu_oracle"] = cpu_oracle_counts(w4)
@@ -517,7 +555,7 @@ def main():
         large.update({"value": u5 / s5, "unit": "state-steps/s", "ms_per_step": s5 * 1e3,
                       "kernel_ms": k5_ms / max(k5_n, 1),
                       "frac_fp32_peak": 2.0 * u5 / (k5_ms / max(k5_n, 1) / 1e3) / 1e12 / FP32_PEAK_TFLOPS,
-                      "traffic": traffic_fields({"forward": ("c5_forward", k5_ms / max(k5_n, 1))})})
+                      "traffic": traffic_fields({"forward": ("c5_forward", k5_ms / max(k5_n, 1))}, tuning)})
         autotune("c5_grad", p5, hmm.OP_GRAD, warmup=0, reps=2)
         ws5g = p5.workspace(hmm.OP_GRAD)
         cnt5 = (torch.empty((w5.K, w5.N), device="cuda"), torch.empty((w5.K, w5.N, w5.N), device="cuda"),
@@ -534,7 +572,8 @@ def main():
                             "fwd_kernel_ms": f5_ms / max(f5_n, 1), "adj_kernel_ms": a5_ms / max(a5_n, 1),
                             "frac_fp32_peak": 6.0 * u5 / gs5 / 1e12 / FP32_PEAK_TFLOPS,
                             "traffic": traffic_fields({"forward": ("c5_grad_forward", f5_ms / max(f5_n, 1)),
-                                                       "adjoint": ("c5_grad_adjoint", a5_ms / max(a5_n, 1))})}
+                                                       "adjoint": ("c5_grad_adjoint", a5_ms / max(a5_n, 1))},
+                                                      tuning)}
         del ws5g, cnt5
     if want("large_viterbi"):
         log("c5 Viterbi (workgroup decoder: 256 states)")

@@ -48,9 +48,12 @@ k_fwd_mfma32(DevPtrs d, FwdLaunch f) {
     int32_t *sym = sym_all + wave * SYM32;
 
     // Scoring all pairs, the tiles are split over the XCDs (workgroup b runs on
-    // XCD b mod 8): slice x takes tiles x, x + 8, ... of every model, so each
-    // tile's symbols are read into one XCD's L2 and serve all the models there.
-    // Own-model calls keep one model per workgroup.
+    // XCD b mod 8): slice x takes one tile of every group of 8 consecutive tiles
+    // of every model, so each tile's symbols are read into one XCD's L2 and serve
+    // all the models there.  The tiles come longest first; the slice takes the
+    // x-th tile from the front of even groups and from the back of odd ones, so
+    // the slices' shares of work differ by at most one group's spread instead of
+    // the sum of them.  Own-model calls keep one model per workgroup.
     const int XS = xcd_slices(f.all_pairs && !(f.tune_flags & HMM_TUNE_XCD_OFF), gridDim.x, K);
     const int x = (int)(blockIdx.x % XS);
     const int G = (int)gridDim.x / XS, gi = (int)blockIdx.x / XS;
@@ -60,7 +63,8 @@ k_fwd_mfma32(DevPtrs d, FwdLaunch f) {
         const int grp = f.all_pairs ? 0 : k;
         const int gbeg = f.gstart[grp], gend = f.gstart[grp + 1];
         const int ntiles_all = (gend - gbeg + T32 - 1) / T32;
-        const int ntiles = (ntiles_all - x + XS - 1) / XS;  // tiles x, x + XS, ... of this slice
+        const int full = ntiles_all / XS, rem = ntiles_all % XS;
+        const int ntiles = full + (((full & 1) ? XS - 1 - x : x) < rem ? 1 : 0);  // this slice's tiles
         const float *btk = f.bt + (size_t)k * M * NP;
         if (BLDS) {
             __syncthreads();
@@ -98,7 +102,7 @@ k_fwd_mfma32(DevPtrs d, FwdLaunch f) {
         for (;;) {
             const int jt = wave_pop(&f.queue[k * XS + x]);
             if (jt >= ntiles) break;
-            const int tile = x + XS * jt;
+            const int tile = XS * jt + ((jt & 1) ? XS - 1 - x : x);
 
             const int pos = gbeg + tile * T32 + sl;
             const bool has = pos < gend;

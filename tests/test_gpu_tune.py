@@ -150,7 +150,8 @@ def test_tune_installs_an_accepted_choice(op):
                (r["choice"]["kernel"], r["choice"]["wg_per_cu"], r["choice"]["flags"]) for c in ok)
     if op in (hmm.OP_FORWARD, hmm.OP_CLASSIFY, hmm.OP_GRAD):  # the second stage tried the flags
         assert any(c["flags"] != 0 for c in r["candidates"])
-    assert r["ms"] == min(c["ms"] for c in ok)
+    # no accepted candidate beat the choice by more than the tuner's margin
+    assert min(c["ms"] for c in ok) >= r["ms"] * (1.0 - tune.MIN_GAIN)
     assert all(c["reason"] in ("unsupported", "default", "") for c in r["candidates"]), r["candidates"]
     # a call after tuning takes the installed choice and still matches the oracle
     if op == hmm.OP_FORWARD:
