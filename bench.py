@@ -128,8 +128,9 @@ def measured_traffic(workload: str, choice: dict, family: str = None, path: str 
     else:
         return None
     h = source_hash(files)
-    for rec in data.get(workload, []):
-        if rec.get("kernel") == kernel and rec.get("kernel_source_hash") == h and rec.get("choice") == choice:
+    recs = data.get(workload)
+    for rec in recs if isinstance(recs, list) else []:
+        if isinstance(rec, dict) and rec.get("kernel") == kernel and rec.get("kernel_source_hash") == h and rec.get("choice") == choice:
             return rec.get("bytes_per_launch")
     return None
 
