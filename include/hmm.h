@@ -34,7 +34,8 @@
  *    Calls may therefore be captured into a HIP graph.
  *  - Scratch memory is the caller's workspace `ws` of `ws_bytes` bytes, at
  *    least hmm_workspace_size(...) for the same bank, batch and op (Viterbi
- *    decoding also takes less, see hmm_viterbi), 256-byte aligned.  Two calls
+ *    decoding and the gradient also take less, see hmm_viterbi and
+ *    hmm_forward_backward_grad), 256-byte aligned.  Two calls
  *    in flight at once need two workspaces.
  *  - Host-checkable problems (null pointer, shape out of range, workspace too
  *    small) return a negative status and enqueue nothing.
@@ -160,21 +161,41 @@ hmm_status hmm_classify_noalloc(const hmm_bank *bank, const hmm_batch *batch, in
  *   sum_s w_s E[ [q_1 = i] ], sum_s w_s E[ #(i -> j) ], sum_s w_s E[ #(i emits o) ]
  * (the gradient of sum_s w_s loglik_s w.r.t. ln pi, ln A, ln B).
  * phase: 0 = forward and backward in one call;
- *        1 = forward only, writing loglik and keeping alpha checkpoints in ws
- *            (counts untouched, may be NULL);
- *        2 = backward only, from the checkpoints a phase-1 call with the same
- *            bank, batch and ws left behind (loglik untouched, may be NULL).
- * The forward pass keeps alpha every ceil(sqrt(T)) steps (T the longest
- * sequence of the length-sorted tile of 16 sequences) and the backward pass
- * recomputes each segment, so memory grows with sqrt(T).
+ *        1 = forward only, writing loglik and keeping the scaled alpha the
+ *            backward pass needs in ws (counts untouched, may be NULL);
+ *        2 = backward only, from what a phase-1 call with the same bank,
+ *            batch, ws and ws_bytes left behind (loglik untouched, may be NULL).
+ * Storage of the scaled alpha (the forward variables of Sec. 2.7, rescaled
+ * per step) between the passes, chosen by ws_bytes:
+ *  - every step: the forward pass stores alphahat_t of every step of every
+ *    sequence (one row of NP = padded N floats per step) and the backward pass
+ *    reads it back.  Needs a workspace with room for the rows of the batch:
+ *    hmm_grad_workspace_size(bank, batch, rows) with rows >= the sum of the
+ *    lengths (total_symbols when the sequences do not overlap in `symbols`).
+ *    Served for N >= 49; a workspace with fewer rows than the batch needs is
+ *    used as below, found on the device without a host synchronisation.
+ *  - checkpoints: the forward pass keeps alpha every ceil(sqrt(T)) steps (T
+ *    the longest sequence of the length-sorted tile of 16 sequences) and the
+ *    backward pass recomputes each segment, so memory grows with sqrt(T) at
+ *    the price of a second forward step per step.
+ * hmm_workspace_size(..., HMM_OP_GRAD) gives room for every step when the rows
+ * take at most 4 GiB, else for checkpoints only.  Both storages give the same
+ * counts and log-likelihoods bit for bit.
  * The counts are deterministic: the same bank, batch and weights give the same
- * counts bit for bit, whatever the tuning choice or the order in which the
- * device runs the work.  A non-finite weight makes every count of its
- * sequence's model NaN. */
+ * counts bit for bit, whatever the tuning choice, the storage or the order in
+ * which the device runs the work.  A non-finite weight makes every count of
+ * its sequence's model NaN. */
 hmm_status hmm_forward_backward_grad(const hmm_bank *bank, const hmm_batch *batch,
                                      const float *seq_weight, float *loglik, float *cnt_pi,
                                      float *cnt_A, float *cnt_B, int32_t phase, void *ws,
                                      size_t ws_bytes, hipStream_t stream);
+
+/* Bytes of workspace with which hmm_forward_backward_grad stores the scaled
+ * alpha of `rows` steps (0: checkpoints only; requests above S max_len count
+ * as S max_len; ignored below 49 states, where the gradient keeps
+ * checkpoints).  Returns 0 if the shapes are out of range or rows < 0.
+ * Host only. */
+size_t hmm_grad_workspace_size(const hmm_bank *bank, const hmm_batch *batch, int64_t rows);
 
 /* Viterbi decoding (Sec. 2.7 "Viterbi"): the most likely state path of each
  * sequence under its own model (batch->model_of_seq is required), in the log
@@ -264,6 +285,7 @@ hmm_status hmm_workspace_error(const void *ws, hipStream_t stream, int32_t *firs
 #define HMM_DEBUG_SEGMENT 16u     /* recompute segment longer than the segment buffer          */
 #define HMM_DEBUG_VIT_ROWS 32u    /* Viterbi delta rows outside the array (or its half)        */
 #define HMM_DEBUG_VIT_ROUND 64u   /* Viterbi round outside the work list                       */
+#define HMM_DEBUG_GRAD_ROWS 128u  /* stored alphahat row of the gradient outside its rows      */
 hmm_status hmm_debug_flags(uint32_t *flags);
 
 /* Selects the kernel family for later calls (HMM_KERNEL_*).  Any kind other

@@ -246,7 +246,25 @@ int64_t vit_default_rows(const hmm_bank *b, const hmm_batch *q) {
     return rows > vit_min_rows(q) ? rows : vit_min_rows(q);
 }
 
-Layout make_layout(const hmm_bank *b, const hmm_batch *q, int op, int64_t vit_rows = -1) {
+// Alphahat rows of the full-storage gradient (cooperative shapes).  The
+// sequences of a batch whose sequences do not overlap in the symbol array need
+// at most total_symbols rows; overlapping ones up to S max_len, beyond which
+// no request grows.  By default every row of a non-overlapping batch when they
+// take at most GRAD_FULL_BYTES, else none (checkpoints only).
+constexpr size_t GRAD_FULL_BYTES = (size_t)4 << 30;  // 4 GiB
+
+int64_t grad_max_rows(const hmm_bank *b, const hmm_batch *q) {
+    return grad_uses_coop(padded_states(b->N)) ? (int64_t)q->S * q->max_len : 0;
+}
+
+int64_t grad_default_rows(const hmm_bank *b, const hmm_batch *q) {
+    const int64_t mx = grad_max_rows(b, q);
+    const int64_t rows = q->total_symbols < mx ? q->total_symbols : mx;
+    const size_t row_bytes = (size_t)padded_states(b->N) * sizeof(float) + sizeof(int32_t);
+    return (size_t)rows * row_bytes <= GRAD_FULL_BYTES ? rows : 0;
+}
+
+Layout make_layout(const hmm_bank *b, const hmm_batch *q, int op, int64_t vit_rows = -1, int64_t grad_rows = -1) {
     Layout L;
     memset(&L, 0, sizeof(L));
     size_t o = 0;
@@ -306,6 +324,15 @@ Layout make_layout(const hmm_bank *b, const hmm_batch *q, int op, int64_t vit_ro
             L.nanflag = take((size_t)K * sizeof(int32_t));
             L.wmax = take(sizeof(uint32_t));
             if (coop && adj_coop_streams(NP)) L.frag = take((size_t)K * 2 * NP * NP * sizeof(float));
+            const int64_t mx = grad_max_rows(b, q);
+            L.grad_rows = grad_rows < 0 ? grad_default_rows(b, q) : (grad_rows < mx ? grad_rows : mx);
+            if (L.grad_rows > 0) {
+                L.arow = take((size_t)L.grad_rows * NP * sizeof(float));
+                L.aexp = take((size_t)L.grad_rows * sizeof(int32_t));
+                L.mlast = take((size_t)S * sizeof(float));
+                L.rowpos = take(((size_t)S + 1) * sizeof(int64_t));
+                L.rowsum = take(((size_t)S + ROW_PREFIX_BLOCK - 1) / ROW_PREFIX_BLOCK * sizeof(int64_t) + sizeof(int64_t));
+            }
         }
     }
     bool scan = false;
@@ -543,6 +570,28 @@ hmm_status hmm_classify(const hmm_bank *bank, const hmm_batch *batch, int32_t *l
     return run_forward(bank, batch, HMM_OP_CLASSIFY, loglik_opt, labels, (unsigned char *)ws, L, stream);
 }
 
+// Alphahat rows of the largest gradient layout that fits ws_bytes (0 when only
+// the checkpoint layout fits, -1 when not even that does).
+int64_t grad_rows_for(const hmm_bank *b, const hmm_batch *q, size_t ws_bytes) {
+    int64_t lo = 0, hi = grad_max_rows(b, q);
+    if (make_layout(b, q, HMM_OP_GRAD, -1, lo).total > ws_bytes) return -1;
+    if (make_layout(b, q, HMM_OP_GRAD, -1, hi).total <= ws_bytes) return hi;
+    while (hi - lo > 1) {  // the layout grows with the rows: fits at lo, not at hi
+        const int64_t mid = lo + (hi - lo) / 2;
+        if (make_layout(b, q, HMM_OP_GRAD, -1, mid).total <= ws_bytes)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+size_t hmm_grad_workspace_size(const hmm_bank *bank, const hmm_batch *batch, int64_t rows) {
+    if (check_shapes(bank, batch) != HMM_OK) return 0;
+    if (rows < 0) return 0;
+    return make_layout(bank, batch, HMM_OP_GRAD, -1, rows).total;
+}
+
 hmm_status hmm_forward_backward_grad(const hmm_bank *bank, const hmm_batch *batch, const float *seq_weight,
                                      float *loglik, float *cnt_pi, float *cnt_A, float *cnt_B, int32_t phase,
                                      void *ws, size_t ws_bytes, hipStream_t stream) {
@@ -552,7 +601,9 @@ hmm_status hmm_forward_backward_grad(const hmm_bank *bank, const hmm_batch *batc
     if ((rc = check_pointers(bank, batch)) != HMM_OK) return rc;
     if (batch->S > 0 && !batch->model_of_seq) return HMM_ERR_NULL;
     if (phase != 1 && (!cnt_pi || !cnt_A || !cnt_B)) return HMM_ERR_NULL;
-    const Layout L = make_layout(bank, batch, HMM_OP_GRAD);
+    // the stored alphahat rows: as many as the workspace holds
+    const int64_t rows = grad_rows_for(bank, batch, ws ? ws_bytes : 0);
+    const Layout L = make_layout(bank, batch, HMM_OP_GRAD, -1, rows < 0 ? 0 : rows);
     if ((rc = check_ws(ws, ws_bytes, L)) != HMM_OK) return rc;
     bool batched = false;
     if ((rc = choose(bank, batch, HMM_OP_GRAD, L.kind, &batched)) != HMM_OK) return rc;
@@ -567,6 +618,11 @@ hmm_status hmm_forward_backward_grad(const hmm_bank *bank, const hmm_batch *batc
         const TransposeJob tj{bank->B, (float *)(w + L.bt), N, M, NP, 0, nullptr};
         launch_plan(d, K, S, K, batch->max_len, batch->total_symbols, nbins, w, L, stream, &tj);
         if (hipGetLastError() != hipSuccess) return HMM_ERR_HIP;
+        if (L.grad_rows > 0) {  // first stored row of each sorted position
+            const RowPrefix rp{(const int32_t *)(w + L.perm), S, batch->max_len, batch->total_symbols,
+                               (int64_t *)(w + L.rowpos), (int64_t *)(w + L.rowsum), nullptr, 0};
+            if (launch_row_prefix(d, rp, stream) != hipSuccess) return HMM_ERR_HIP;
+        }
         FwdLaunch f;
         memset(&f, 0, sizeof(f));
         f.K = K;
@@ -587,6 +643,13 @@ hmm_status hmm_forward_backward_grad(const hmm_bank *bank, const hmm_batch *batc
         f.ckexp = (int32_t *)(w + L.ckexp);
         f.flag = (int32_t *)(w + L.flag);
         f.nck = L.nck;
+        if (L.grad_rows > 0) {
+            f.arow = (float *)(w + L.arow);
+            f.aexp = (int32_t *)(w + L.aexp);
+            f.mlast = (float *)(w + L.mlast);
+            f.rowpos = (const int64_t *)(w + L.rowpos);
+            f.grad_rows = L.grad_rows;
+        }
         f.max_grid = max_grid(L.wg_per_cu, cus);
         f.tune_flags = L.tune_flags;
         if (S > 0) {
@@ -637,6 +700,13 @@ hmm_status hmm_forward_backward_grad(const hmm_bank *bank, const hmm_batch *batc
     a.nanflag = (int32_t *)(w + L.nanflag);
     a.wmax = (const uint32_t *)(w + L.wmax);
     a.max_grid = max_grid(L.wg_per_cu, cus);
+    if (L.grad_rows > 0) {
+        a.arow = (const float *)(w + L.arow);
+        a.aexp = (const int32_t *)(w + L.aexp);
+        a.mlast = (const float *)(w + L.mlast);
+        a.rowpos = (const int64_t *)(w + L.rowpos);
+        a.grad_rows = L.grad_rows;
+    }
     if (S > 0) {
         if (coop && adj_coop_streams(NP)) {
             float *frag = (float *)(w + L.frag);

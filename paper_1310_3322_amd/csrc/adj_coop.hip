@@ -102,8 +102,10 @@ struct AdjFrags<R, BO, true> {
     }
 };
 
-template <int R, int BO, bool NBLDS, bool STREAM>
+template <int R, int BO, bool NBLDS, bool STREAM, bool FULL>
 __global__ void __launch_bounds__(R / BO * WAVE) k_adj_coop(DevPtrs d, AdjLaunch a) {
+    // the kernel of the other storage mode serves the call (a uniform exit before any barrier)
+    if (FULL != grad_full(a.arow, a.rowpos, a.S, a.grad_rows)) return;
     using SH = AdjCoopShape<R, BO>;
     // emission counts into the LDS partial one step late, overlapped with the next step's MFMAs
     static_assert(!(NBLDS && STREAM), "the LDS partial serves one-block waves");
@@ -191,14 +193,36 @@ __global__ void __launch_bounds__(R / BO * WAVE) k_adj_coop(DevPtrs d, AdjLaunch
 #pragma unroll
                     for (int rj = 0; rj < R; ++rj) C[b][rj] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
                 bool lane_nan = false;  // a non-finite count (from a non-finite weight) in this lane
+                // checkpoints: segments of about sqrt(Tmax) steps, each recomputed
+                // before it is walked; full storage: one walk over the stored rows
                 int L = 1;
-                while (L * L < Tmax) ++L;
-                if (!dbg_in(L - 1, Lcap, HMM_DEBUG_SEGMENT)) return;  // segment buffer too short (debug build)
+                if (FULL) {
+                    L = Tmax;
+                } else {
+                    while (L * L < Tmax) ++L;
+                    if (!dbg_in(L - 1, Lcap, HMM_DEBUG_SEGMENT)) return;  // segment buffer too short (debug build)
+                }
                 const int nseg = (Tmax + L - 1) / L;
                 const float wgt = act ? (a.weight ? a.weight[seq] : 1.0f) : 0.0f;
                 const int32_t *sbase = T > 0 ? d.symbols + off : d.symbols;
                 const int tlim = T > 0 ? T - 1 : 0;
                 float m_last = 1.0f;  // m_T of this lane's sequence (set in the last segment)
+                int64_t rb = 0;       // first stored row of the sequence (full storage)
+                if (FULL && T > 0) {
+                    rb = a.rowpos[pos];
+                    m_last = a.mlast[pos];
+                }
+                // alphahat, exponent and symbol of step t from the stored rows (steps past
+                // the sequence's end read its last row; they are not used)
+                auto fetch_full = [&](int t, float4 (&aq)[BO], int &et, int &ot) {
+                    int64_t row = T > 0 ? rb + min(t, T - 1) : 0;
+                    if (!dbg_in(row, a.grad_rows, HMM_DEBUG_GRAD_ROWS)) row = 0;
+#pragma unroll
+                    for (int b = 0; b < BO; ++b) aq[b] = *(const float4 *)&a.arow[(size_t)row * NP + 16 * (r0 + b) + 4 * g];
+                    et = a.aexp[row];
+                    const int o = sbase[min(t, tlim)];
+                    ot = ((unsigned)o < (unsigned)M) ? o : 0;
+                };
                 // gamma_1 of this lane's states, added to n_pi after the tile (a global atomic
                 // inside the step would make every step wait for all outstanding loads)
                 float gpi[BO][4] = {};
@@ -252,90 +276,96 @@ __global__ void __launch_bounds__(R / BO * WAVE) k_adj_coop(DevPtrs d, AdjLaunch
                         return ((unsigned)o < (unsigned)M) ? o : 0;
                     };
                     __syncthreads();
-                    stage_syms(t0);
-                    // ---- recompute alphahat over [t0, t1) from checkpoint j
-                    float x[BO][4];
-#pragma unroll
-                    for (int b = 0; b < BO; ++b) {
-                        if (t0 < T) {
-                            const float4 q =
-                                *(const float4 *)&a.ckpt[((size_t)pos * a.nck + j) * NP + 16 * (r0 + b) + 4 * g];
-                            x[b][0] = q.x;
-                            x[b][1] = q.y;
-                            x[b][2] = q.z;
-                            x[b][3] = q.w;
-                        } else {
-                            x[b][0] = x[b][1] = x[b][2] = x[b][3] = 0.0f;
-                        }
-                    }
-                    int e_prev = (t0 < T) ? a.ckexp[(size_t)pos * a.nck + j] : 0;
-#pragma unroll
-                    for (int b = 0; b < BO; ++b) {
-                        *(float4 *)&xbuf[(t0 & 1) * TILE * XROW + sl * XROW + 16 * (r0 + b) + 4 * g] =
-                            float4{x[b][0], x[b][1], x[b][2], x[b][3]};
-                        // block shares of sum_i alphahat_{t0}(i), in the forward's summation order
-                        float part;
-                        {
-#pragma clang fp contract(off)
-                            part = ((x[b][0] + x[b][1]) + x[b][2]) + x[b][3];
-                        }
-                        part = sum_row_groups(part);
-                        if (g == 0) psum[(t0 & 1) * R * TILE + (r0 + b) * TILE + sl] = part;
-                    }
-                    __syncthreads();
-#pragma unroll
-                    for (int b = 0; b < BO; ++b) seg_alpha[aidx(0, b)] = float4{x[b][0], x[b][1], x[b][2], x[b][3]};
-                    seg_e[sidx(0)] = e_prev;
-                    seg_o[sidx(0)] = read_sym(t0);
-                    if (t0 == T - 1) m_last = coop_step_sum<R>(psum + (t0 & 1) * R * TILE, sl);
-                    for (int t = t0 + 1; t <= t1; ++t) {
-                        // first operand of this step's product, requested with the block sums
-                        const float *xprev = xbuf + ((t - 1) & 1) * TILE * XROW;
-                        const float4 q0 = *(const float4 *)&xprev[sl * XROW + 4 * g];
-                        int e = 0;
-                        if (t > t0 + 1) {
-                            // finish step t - 1: its sum and exponent, store alphahat_{t-1}
-                            const float cs = coop_step_sum<R>(psum + ((t - 1) & 1) * R * TILE, sl);
-                            e = frexp_exp(cs);
-#pragma unroll
-                            for (int b = 0; b < BO; ++b)
-                                seg_alpha[aidx(t - 1 - t0, b)] = float4{ldexp_f(x[b][0], -e), ldexp_f(x[b][1], -e),
-                                                                        ldexp_f(x[b][2], -e), ldexp_f(x[b][3], -e)};
-                            seg_e[sidx(t - 1 - t0)] = e;
-                            if (t - 1 == T - 1) m_last = ldexp_f(cs, -e);
-                        }
-                        if (t == t1) break;
-                        if (((t - t0) % SSEG) == 0) {  // segments longer than SSEG steps
-                            __syncthreads();
-                            stage_syms(t);
-                            __syncthreads();
-                        }
-                        const int o = read_sym(t);
-                        seg_o[sidx(t - t0)] = o;
-                        // the emission row is requested before the matvec, which hides its latency
-                        float4 bb[BO];
-#pragma unroll
-                        for (int b = 0; b < BO; ++b) bb[b] = *(const float4 *)&btk[(size_t)o * NP + 16 * (r0 + b) + 4 * g];
-                        floatx4 u[BO];
-                        // the checkpoint row enters unscaled (exponent 0), later rows by 2^-e
-                        fr.fwd(xprev, q0, (t == t0 + 1) ? 0 : e, g, sl, u);
+                    if constexpr (!FULL) {
+                        stage_syms(t0);
+                        // ---- recompute alphahat over [t0, t1) from checkpoint j
+                        float x[BO][4];
 #pragma unroll
                         for (int b = 0; b < BO; ++b) {
-                            const float part = coop_emit(u[b], bb[b], x[b]);
-                            *(float4 *)&xbuf[(t & 1) * TILE * XROW + sl * XROW + 16 * (r0 + b) + 4 * g] =
-                                float4{x[b][0], x[b][1], x[b][2], x[b][3]};
-                            if (g == 0) psum[(t & 1) * R * TILE + (r0 + b) * TILE + sl] = part;
+                            if (t0 < T) {
+                                const float4 q =
+                                    *(const float4 *)&a.ckpt[((size_t)pos * a.nck + j) * NP + 16 * (r0 + b) + 4 * g];
+                                x[b][0] = q.x;
+                                x[b][1] = q.y;
+                                x[b][2] = q.z;
+                                x[b][3] = q.w;
+                            } else {
+                                x[b][0] = x[b][1] = x[b][2] = x[b][3] = 0.0f;
+                            }
                         }
-                        lds_barrier();  // LDS exchange only; segment entries are the wave's own
-                    }
+                        int e_prev = (t0 < T) ? a.ckexp[(size_t)pos * a.nck + j] : 0;
+#pragma unroll
+                        for (int b = 0; b < BO; ++b) {
+                            *(float4 *)&xbuf[(t0 & 1) * TILE * XROW + sl * XROW + 16 * (r0 + b) + 4 * g] =
+                                float4{x[b][0], x[b][1], x[b][2], x[b][3]};
+                            // block shares of sum_i alphahat_{t0}(i), in the forward's summation order
+                            float part;
+                            {
+#pragma clang fp contract(off)
+                                part = ((x[b][0] + x[b][1]) + x[b][2]) + x[b][3];
+                            }
+                            part = sum_row_groups(part);
+                            if (g == 0) psum[(t0 & 1) * R * TILE + (r0 + b) * TILE + sl] = part;
+                        }
+                        __syncthreads();
+#pragma unroll
+                        for (int b = 0; b < BO; ++b) seg_alpha[aidx(0, b)] = float4{x[b][0], x[b][1], x[b][2], x[b][3]};
+                        seg_e[sidx(0)] = e_prev;
+                        seg_o[sidx(0)] = read_sym(t0);
+                        if (t0 == T - 1) m_last = coop_step_sum<R>(psum + (t0 & 1) * R * TILE, sl);
+                        for (int t = t0 + 1; t <= t1; ++t) {
+                            // first operand of this step's product, requested with the block sums
+                            const float *xprev = xbuf + ((t - 1) & 1) * TILE * XROW;
+                            const float4 q0 = *(const float4 *)&xprev[sl * XROW + 4 * g];
+                            int e = 0;
+                            if (t > t0 + 1) {
+                                // finish step t - 1: its sum and exponent, store alphahat_{t-1}
+                                const float cs = coop_step_sum<R>(psum + ((t - 1) & 1) * R * TILE, sl);
+                                e = frexp_exp(cs);
+#pragma unroll
+                                for (int b = 0; b < BO; ++b)
+                                    seg_alpha[aidx(t - 1 - t0, b)] = float4{ldexp_f(x[b][0], -e), ldexp_f(x[b][1], -e),
+                                                                            ldexp_f(x[b][2], -e), ldexp_f(x[b][3], -e)};
+                                seg_e[sidx(t - 1 - t0)] = e;
+                                if (t - 1 == T - 1) m_last = ldexp_f(cs, -e);
+                            }
+                            if (t == t1) break;
+                            if (((t - t0) % SSEG) == 0) {  // segments longer than SSEG steps
+                                __syncthreads();
+                                stage_syms(t);
+                                __syncthreads();
+                            }
+                            const int o = read_sym(t);
+                            seg_o[sidx(t - t0)] = o;
+                            // the emission row is requested before the matvec, which hides its latency
+                            float4 bb[BO];
+#pragma unroll
+                            for (int b = 0; b < BO; ++b) bb[b] = *(const float4 *)&btk[(size_t)o * NP + 16 * (r0 + b) + 4 * g];
+                            floatx4 u[BO];
+                            // the checkpoint row enters unscaled (exponent 0), later rows by 2^-e
+                            fr.fwd(xprev, q0, (t == t0 + 1) ? 0 : e, g, sl, u);
+#pragma unroll
+                            for (int b = 0; b < BO; ++b) {
+                                const float part = coop_emit(u[b], bb[b], x[b]);
+                                *(float4 *)&xbuf[(t & 1) * TILE * XROW + sl * XROW + 16 * (r0 + b) + 4 * g] =
+                                    float4{x[b][0], x[b][1], x[b][2], x[b][3]};
+                                if (g == 0) psum[(t & 1) * R * TILE + (r0 + b) * TILE + sl] = part;
+                            }
+                            lds_barrier();  // LDS exchange only; segment entries are the wave's own
+                        }
+                    }  // !FULL
                     // ---- backward through the segment; the segment entries of step t - 1
                     // are requested during step t, and the emission row of step t at its start
                     float4 aq_n[BO];
                     int et_n = 0, ot_n = 0;
+                    if constexpr (FULL) {
+                        fetch_full(t1 - 1, aq_n, et_n, ot_n);
+                    } else {
 #pragma unroll
-                    for (int b = 0; b < BO; ++b) aq_n[b] = seg_alpha[aidx(t1 - 1 - t0, b)];
-                    et_n = seg_e[sidx(t1 - 1 - t0)];
-                    ot_n = seg_o[sidx(t1 - 1 - t0)];
+                        for (int b = 0; b < BO; ++b) aq_n[b] = seg_alpha[aidx(t1 - 1 - t0, b)];
+                        et_n = seg_e[sidx(t1 - 1 - t0)];
+                        ot_n = seg_o[sidx(t1 - 1 - t0)];
+                    }
                     for (int t = t1 - 1; t >= t0; --t) {
                         const int tl = t - t0;
                         float al[BO][4];
@@ -355,10 +385,14 @@ __global__ void __launch_bounds__(R / BO * WAVE) k_adj_coop(DevPtrs d, AdjLaunch
                             // unconditional (index clamped at the segment start), so that the
                             // wait for the emission row above can leave these loads in flight
                             const int tp = tl > 0 ? tl - 1 : 0;
+                            if constexpr (FULL) {
+                                fetch_full(t0 + tp, aq_n, et_n, ot_n);
+                            } else {
 #pragma unroll
-                            for (int b = 0; b < BO; ++b) aq_n[b] = seg_alpha[aidx(tp, b)];
-                            et_n = seg_e[sidx(tp)];
-                            ot_n = seg_o[sidx(tp)];
+                                for (int b = 0; b < BO; ++b) aq_n[b] = seg_alpha[aidx(tp, b)];
+                                et_n = seg_e[sidx(tp)];
+                                ot_n = seg_o[sidx(tp)];
+                            }
                         }
                         const bool live = act && t < T;
                         const bool trans = act && t + 1 < T;
@@ -556,6 +590,8 @@ __global__ void __launch_bounds__(R / BO * WAVE) k_adj_coop(DevPtrs d, AdjLaunch
 // quantity is formed by the same operations in the same order as in k_adj_coop.
 template <int R>
 __global__ void __launch_bounds__(2 * R * WAVE) k_adj_pipe(DevPtrs d, AdjLaunch a) {
+    // full storage: the walk over the stored rows serves the call
+    if (grad_full(a.arow, a.rowpos, a.S, a.grad_rows)) return;
     using SH = AdjCoopShape<R, 1>;
     constexpr int NP = SH::NP;
     constexpr int XROW = SH::XROW;
@@ -972,11 +1008,11 @@ int grid_pipe(int M, int cu_count, int K) {
     }
 }
 
-template <int R, bool NBLDS>
+template <int R, bool NBLDS, bool FULL = false>
 int grid_t(int M, int cu_count, int K) {
     constexpr int BO = adj_bo(R);
     if constexpr (NBLDS && BO > 1) return 0;  // not instantiated: the partial serves one-block waves
-    auto kern = k_adj_coop<R, BO, NBLDS && BO == 1, (BO > 1)>;
+    auto kern = k_adj_coop<R, BO, NBLDS && BO == 1, (BO > 1), FULL>;
     const size_t dyn = NBLDS ? nb_lds_bytes<R>(M) : 0;
     if (dyn > 0) (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
     int per_cu = 0;
@@ -1001,6 +1037,29 @@ hipError_t launch_r(const DevPtrs &d, const AdjLaunch &a, int cu_count, hipStrea
     const int grid =
         persistent_grid(grid_r<R>(a.M, a.S, cu_count, a.K), tile_bound(a.S, a.K, false, TILE), 1, a.K, a.max_grid);
     if (grid > a.seg_slots) return hipErrorInvalidValue;
+    // Full storage possible: its walk runs first and exits unless the rows of
+    // every sequence fit; the checkpoint kernel below exits when they do.  The
+    // walk keeps the emission counts where the checkpoint kernel of the shape
+    // keeps them (LDS partial and slab, or the global sums).
+    if (a.arow != nullptr) {
+        const bool slab_shape = use_pipe<R>(a.M, a.S, a.K) || (!STREAM && use_nb_lds<R>(a.M, a.S, a.K));
+        if (slab_shape && (STREAM || a.slab == nullptr)) return hipErrorInvalidValue;
+        if (!slab_shape && a.B64 == nullptr) return hipErrorInvalidValue;
+        if constexpr (!STREAM) {
+            if (slab_shape) {
+                const int gf = persistent_grid(grid_t<R, true, true>(a.M, cu_count, a.K), tile_bound(a.S, a.K, false, TILE),
+                                               1, a.K, a.max_grid);
+                k_adj_coop<R, BO, true, false, true><<<gf, R / BO * WAVE, nb_lds_bytes<R>(a.M), st>>>(d, a);
+            }
+        }
+        if (!slab_shape) {
+            const int gf = persistent_grid(grid_t<R, false, true>(a.M, cu_count, a.K), tile_bound(a.S, a.K, false, TILE),
+                                           1, a.K, a.max_grid);
+            k_adj_coop<R, BO, false, STREAM, true><<<gf, R / BO * WAVE, 0, st>>>(d, a);
+        }
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     if constexpr (R == 4) {
         if (use_pipe<R>(a.M, a.S, a.K)) {
             if (a.slab == nullptr) return hipErrorInvalidValue;
@@ -1011,12 +1070,12 @@ hipError_t launch_r(const DevPtrs &d, const AdjLaunch &a, int cu_count, hipStrea
     if constexpr (!STREAM) {
         if (use_nb_lds<R>(a.M, a.S, a.K)) {
             if (a.slab == nullptr) return hipErrorInvalidValue;
-            k_adj_coop<R, BO, true, false><<<grid, R / BO * WAVE, nb_lds_bytes<R>(a.M), st>>>(d, a);
+            k_adj_coop<R, BO, true, false, false><<<grid, R / BO * WAVE, nb_lds_bytes<R>(a.M), st>>>(d, a);
             return hipGetLastError();
         }
     }
     if (a.B64 == nullptr) return hipErrorInvalidValue;
-    k_adj_coop<R, BO, false, STREAM><<<grid, R / BO * WAVE, 0, st>>>(d, a);
+    k_adj_coop<R, BO, false, STREAM, false><<<grid, R / BO * WAVE, 0, st>>>(d, a);
     return hipGetLastError();
 }
 

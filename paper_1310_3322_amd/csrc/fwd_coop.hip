@@ -35,6 +35,8 @@ __global__ void __launch_bounds__(R / BO * WAVE) k_fwd_coop(DevPtrs d, FwdLaunch
     const int K = f.K, N = f.N, M = f.M;
     float *xbuf = xch;                       // [2][16][XROW]
     float *psum = xch + SH::x_floats;        // [2][R][16]
+    // full-storage gradient: every step's alphahat in place of the checkpoints
+    const bool full = CKPT && grad_full(f.arow, f.rowpos, f.S, f.grad_rows);
 
     const int G = gridDim.x;
     const int k_first = G >= K ? (int)(blockIdx.x % K) : (int)blockIdx.x;
@@ -82,8 +84,9 @@ __global__ void __launch_bounds__(R / BO * WAVE) k_fwd_coop(DevPtrs d, FwdLaunch
                 continue;
             }
             int L = 1;
-            if (CKPT)
+            if (CKPT && !full)
                 while (L * L < Tmax) ++L;
+            const int64_t rb = (full && T > 0) ? f.rowpos[pos] : 0;  // first stored row of the sequence
             // symbols: wave 0 stages chunks (register prefetch, chunk c lives in sym[c & 1])
             const int32_t *sbase = T > 0 ? d.symbols + off : d.symbols;
             const int tlim = T > 0 ? T - 1 : 0;
@@ -131,7 +134,21 @@ __global__ void __launch_bounds__(R / BO * WAVE) k_fwd_coop(DevPtrs d, FwdLaunch
                         c_end = cs;
                     }
                     E += e;
-                    if (CKPT && t - 1 == ck_t) {  // t - 1 = L ck_c
+                    if (full) {
+                        if (t - 1 < T) {
+                            const int64_t row = rb + (t - 1);
+                            if (dbg_in(row, f.grad_rows, HMM_DEBUG_GRAD_ROWS)) {
+#pragma unroll
+                                for (int b = 0; b < BO; ++b) {
+                                    float *dst = f.arow + (size_t)row * NP + 16 * (r0 + b) + 4 * g;
+                                    *(float4 *)dst = float4{ldexp_f(x[b][0], -e), ldexp_f(x[b][1], -e),
+                                                            ldexp_f(x[b][2], -e), ldexp_f(x[b][3], -e)};
+                                }
+                                if (w == 0 && g == 0) f.aexp[row] = e;
+                            }
+                            if (t - 1 == T - 1 && w == 0 && g == 0) f.mlast[pos] = ldexp_f(cs, -e);
+                        }
+                    } else if (CKPT && t - 1 == ck_t) {  // t - 1 = L ck_c
                         if (t - 1 < T && dbg_in(ck_c, f.nck, HMM_DEBUG_CKPT)) {
 #pragma unroll
                             for (int b = 0; b < BO; ++b) {

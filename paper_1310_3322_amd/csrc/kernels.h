@@ -34,8 +34,12 @@ struct Layout {
     size_t frag;     // float4 [K][2][NP^2 / 4] streamed MFMA fragments (cooperative gradient, NP > 128)
     size_t delta;    // float [vit_rows][NP] Viterbi delta rows of one round (bt then holds ln B transposed), then 64 spare floats
     size_t lnat;     // float [K][N][NP] ln A transposed (Viterbi)
-    size_t rowpos;   // int64 [S + 1] rows stored before each work-list entry (Viterbi)
-    size_t rowsum;   // int64 [ceil(S / 8192)] block sums of that prefix (Viterbi)
+    size_t rowpos;   // int64 [S + 1] rows stored before each work-list entry (Viterbi, full-storage gradient)
+    size_t rowsum;   // int64 [ceil(S / 8192)] block sums of that prefix
+    int64_t grad_rows;   // alphahat rows the gradient may store (0: checkpoints only)
+    size_t arow;     // float [grad_rows][NP] alphahat of every step, rows of sorted position p from rowpos[p]
+    size_t aexp;     // int32 [grad_rows] exponents of those steps
+    size_t mlast;    // float [S] m_T of each sorted position (full-storage gradient)
     int64_t vit_rows;    // delta rows one Viterbi round may store
     size_t scan;     // time-parallel forward: chunk products, exponents, flags (ScanWs)
     int32_t scan_nch;    // chunks per pair of the time-parallel forward (0: not used)
@@ -137,6 +141,21 @@ void launch_rows_from_sorted(const float *llpos, const int32_t *perm, int S, int
                              hipStream_t st);
 void launch_fill_f32(float *p, size_t n, float v, hipStream_t st);
 void launch_fill_i32(int32_t *p, size_t n, int32_t v, hipStream_t st);
+// Row prefix of a work list (perm[0..S)): rowpos[p] = the lengths of the
+// entries before p (0 for an invalid sequence), rowpos[S] = their sum; rowsum
+// holds ceil(S / ROW_PREFIX_BLOCK) scratch words; the last kernel also sets
+// zero[0..nzero) to 0 (nzero <= 1024).
+constexpr int ROW_PREFIX_BLOCK = 8192;
+struct RowPrefix {
+    const int32_t *perm;
+    int S, max_len;
+    int64_t total;
+    int64_t *rowpos;
+    int64_t *rowsum;
+    int32_t *zero;
+    int nzero;
+};
+hipError_t launch_row_prefix(const DevPtrs &d, const RowPrefix &r, hipStream_t st);
 void launch_copy_i32(const int32_t *src, int32_t *dst, size_t n, hipStream_t st);
 void launch_softmax_rows(const float *z, float *p, int64_t rows, int cols, hipStream_t st);
 void launch_logit_grad(const float *n, const float *p, float *g, int64_t rows, int cols, hipStream_t st);
@@ -160,6 +179,14 @@ struct FwdLaunch {
     int32_t *ckexp;
     int32_t *flag;    // [S] per sorted position: 1 = no finite likelihood (gradient only)
     int nck;
+    // Full-storage gradient (arow NULL: checkpoints only): when the rows of all
+    // sorted positions fit (rowpos[S] <= grad_rows), every step's alphahat and
+    // exponent are stored in place of the checkpoints, and m_T per position.
+    float *arow;
+    int32_t *aexp;
+    float *mlast;
+    const int64_t *rowpos;
+    int64_t grad_rows;
     int max_grid;     // cap on the persistent grid (0: occupancy limit)
     int tune_flags;   // HMM_TUNE_* of the call
 };
@@ -229,7 +256,19 @@ struct AdjLaunch {
     const uint32_t *wmax;      // bits of max_s |w_s| (the fixed-point scale)
     const float *frag;  // pre-arranged fragments when the cooperative kernel streams them
     int max_grid;       // cap on the persistent grid (0: occupancy limit)
+    // Full-storage gradient (as in FwdLaunch; arow NULL: checkpoints only)
+    const float *arow;
+    const int32_t *aexp;
+    const float *mlast;
+    const int64_t *rowpos;
+    int64_t grad_rows;
 };
+// Whether a gradient call stores every step's alphahat (decided on the device
+// from the row prefix, so that overlapping sequences whose rows exceed the
+// workspace fall back to checkpoints).
+__device__ __forceinline__ bool grad_full(const float *arow, const int64_t *rowpos, int S, int64_t grad_rows) {
+    return arow != nullptr && S > 0 && rowpos[S] <= grad_rows;
+}
 // Quad-transposed position of state i in a row of the global emission counts:
 // within each 16-state block, i = 4 g + v goes to 4 v + g.  A lane of the
 // backward kernels holds states 4 g + v (v = 0..3) of a sequence, so the four

@@ -537,6 +537,84 @@ __global__ void k_reestimate_rows(const float *n, const float *old, float *out, 
 
 inline int blocks_for(int64_t n, int bs) { return (int)((n + bs - 1) / bs); }
 
+
+// Row prefix over a work list: rowpos[p] = rows stored before entry p (the
+// lengths of the entries before it, 0 for an invalid sequence), rowpos[S] =
+// all rows.  Multi-workgroup form: block sums, their exclusive scan, then each
+// workgroup scans its own entries from its block's offset.
+constexpr int RP_PER = 8;  // entries per thread
+static_assert(ROW_PREFIX_BLOCK == 1024 * RP_PER, "entries per workgroup of the row prefix");
+
+__device__ __forceinline__ int64_t entry_rows(const DevPtrs &d, const RowPrefix &r, int p) {
+    const int s = r.perm[p];
+    const int32_t T = d.lengths[s];
+    return seq_bad(T, d.offsets[s], r.max_len, r.total) ? 0 : (int64_t)T;
+}
+
+// Inclusive scan over the 1024 threads of a workgroup; *total gets the sum.
+__device__ int64_t block_scan64(int64_t *part, int64_t x, int64_t *total) {
+    const int tid = threadIdx.x;
+    part[tid] = x;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const int64_t y = tid >= off ? part[tid - off] : 0;
+        __syncthreads();
+        part[tid] += y;
+        __syncthreads();
+    }
+    const int64_t res = part[tid];
+    *total = part[1023];
+    __syncthreads();  // part is free again
+    return res;
+}
+
+__global__ void __launch_bounds__(1024) k_rows_reduce(DevPtrs d, RowPrefix r) {
+    __shared__ int64_t part[1024];
+    const int64_t p0 = (int64_t)blockIdx.x * ROW_PREFIX_BLOCK + threadIdx.x;
+    int64_t x = 0;
+    for (int u = 0; u < RP_PER; ++u) {
+        const int64_t p = p0 + (int64_t)u * 1024;
+        if (p < r.S) x += entry_rows(d, r, (int)p);
+    }
+    int64_t tot;
+    block_scan64(part, x, &tot);
+    if (threadIdx.x == 0) r.rowsum[blockIdx.x] = tot;
+}
+
+__global__ void __launch_bounds__(1024) k_rows_top(RowPrefix r, int nb) {
+    __shared__ int64_t part[1024];
+    int64_t carry = 0;
+    for (int b0 = 0; b0 < nb; b0 += 1024) {
+        const int b = b0 + (int)threadIdx.x;
+        const int64_t x = b < nb ? r.rowsum[b] : 0;
+        int64_t tot;
+        const int64_t inc = block_scan64(part, x, &tot);
+        if (b < nb) r.rowsum[b] = carry + inc - x;
+        carry += tot;
+    }
+}
+
+__global__ void __launch_bounds__(1024) k_rows_apply(DevPtrs d, RowPrefix r, int nb) {
+    __shared__ int64_t part[1024];
+    const int64_t p0 = (int64_t)blockIdx.x * ROW_PREFIX_BLOCK + (int64_t)threadIdx.x * RP_PER;
+    int64_t rows[RP_PER];
+    int64_t x = 0;
+#pragma unroll
+    for (int u = 0; u < RP_PER; ++u) {
+        rows[u] = p0 + u < r.S ? entry_rows(d, r, (int)(p0 + u)) : 0;
+        x += rows[u];
+    }
+    int64_t tot;
+    int64_t run = block_scan64(part, x, &tot) - x + (nb > 1 ? r.rowsum[blockIdx.x] : 0);
+#pragma unroll
+    for (int u = 0; u < RP_PER; ++u) {
+        if (p0 + u < r.S) r.rowpos[p0 + u] = run;
+        run += rows[u];
+    }
+    if (p0 <= r.S - 1 && r.S - 1 < p0 + RP_PER) r.rowpos[r.S] = run;
+    if (blockIdx.x == 0 && (int)threadIdx.x < r.nzero) r.zero[threadIdx.x] = 0;
+}
+
 }  // namespace
 
 void plan_chunking(int S, int64_t nbins, int *chunk, int *nchunks) {
@@ -669,6 +747,17 @@ void launch_reestimate_rows(const float *n, const float *old, float *out, int64_
 
 void launch_logit_grad(const float *n, const float *p, float *g, int64_t rows, int cols, hipStream_t st) {
     if (rows > 0) hipLaunchKernelGGL(k_logit_grad, dim3(blocks_for(rows, 4)), dim3(256), 0, st, n, p, g, rows, cols);
+}
+
+hipError_t launch_row_prefix(const DevPtrs &d, const RowPrefix &r, hipStream_t st) {
+    if (r.S <= 0 || r.nzero < 0 || r.nzero > 1024) return r.S == 0 ? hipSuccess : hipErrorInvalidValue;
+    const int nb = (int)((r.S + (int64_t)ROW_PREFIX_BLOCK - 1) / ROW_PREFIX_BLOCK);
+    if (nb > 1) {
+        hipLaunchKernelGGL(k_rows_reduce, dim3(nb), dim3(1024), 0, st, d, r);
+        hipLaunchKernelGGL(k_rows_top, dim3(1), dim3(1024), 0, st, r, nb);
+    }
+    hipLaunchKernelGGL(k_rows_apply, dim3(nb), dim3(1024), 0, st, d, r, nb);
+    return hipGetLastError();
 }
 
 HMM_DEBUG_TAKE(debug_take_planner)

@@ -108,86 +108,6 @@ __device__ __forceinline__ int group_max_key(int k) {
     return k;
 }
 
-// Rows stored for work-list entry p: its length, 0 for an invalid sequence
-// (a decoder row of a sequence with an invalid model is never written, but
-// counting it keeps the sum an upper bound).
-__device__ __forceinline__ int64_t entry_rows(const DevPtrs &d, const VitLaunch &v, int p) {
-    const int s = v.perm[p];
-    const int32_t T = d.lengths[s];
-    return seq_bad(T, d.offsets[s], v.max_len, v.total) ? 0 : (int64_t)T;
-}
-
-constexpr int RP_PER = 8;                 // work-list entries per thread of the row prefix
-constexpr int RP_BLOCK = 1024 * RP_PER;   // per workgroup
-
-// Inclusive scan over the 1024 threads of a workgroup; *total gets the sum.
-__device__ int64_t block_scan64(int64_t *part, int64_t x, int64_t *total) {
-    const int tid = threadIdx.x;
-    part[tid] = x;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        const int64_t y = tid >= off ? part[tid - off] : 0;
-        __syncthreads();
-        part[tid] += y;
-        __syncthreads();
-    }
-    const int64_t r = part[tid];
-    *total = part[1023];
-    __syncthreads();  // part is free again
-    return r;
-}
-
-// Row prefix, multi-workgroup form: block sums, their exclusive scan, then
-// each workgroup scans its own entries from its block's offset.
-__global__ void __launch_bounds__(1024) k_vit_rows_reduce(DevPtrs d, VitLaunch v) {
-    __shared__ int64_t part[1024];
-    const int64_t p0 = (int64_t)blockIdx.x * RP_BLOCK + threadIdx.x;
-    int64_t x = 0;
-    for (int u = 0; u < RP_PER; ++u) {
-        const int64_t p = p0 + (int64_t)u * 1024;
-        if (p < v.S) x += entry_rows(d, v, (int)p);
-    }
-    int64_t tot;
-    block_scan64(part, x, &tot);
-    if (threadIdx.x == 0) v.rowsum[blockIdx.x] = tot;
-}
-
-__global__ void __launch_bounds__(1024) k_vit_rows_top(VitLaunch v, int nb) {
-    __shared__ int64_t part[1024];
-    int64_t carry = 0;
-    for (int b0 = 0; b0 < nb; b0 += 1024) {
-        const int b = b0 + (int)threadIdx.x;
-        const int64_t x = b < nb ? v.rowsum[b] : 0;
-        int64_t tot;
-        const int64_t inc = block_scan64(part, x, &tot);
-        if (b < nb) v.rowsum[b] = carry + inc - x;
-        carry += tot;
-    }
-}
-
-// rowpos[p] = rows of the entries before p, rowpos[S] = all rows.
-__global__ void __launch_bounds__(1024) k_vit_rows_apply(DevPtrs d, VitLaunch v, int nb) {
-    __shared__ int64_t part[1024];
-    int64_t *rowpos = const_cast<int64_t *>(v.rowpos);
-    const int64_t p0 = (int64_t)blockIdx.x * RP_BLOCK + (int64_t)threadIdx.x * RP_PER;
-    int64_t r[RP_PER];
-    int64_t x = 0;
-#pragma unroll
-    for (int u = 0; u < RP_PER; ++u) {
-        r[u] = p0 + u < v.S ? entry_rows(d, v, (int)(p0 + u)) : 0;
-        x += r[u];
-    }
-    int64_t tot;
-    int64_t run = block_scan64(part, x, &tot) - x + (nb > 1 ? v.rowsum[blockIdx.x] : 0);
-#pragma unroll
-    for (int u = 0; u < RP_PER; ++u) {
-        if (p0 + u < v.S) rowpos[p0 + u] = run;
-        run += r[u];
-    }
-    if (p0 <= v.S - 1 && v.S - 1 < p0 + RP_PER) rowpos[v.S] = run;
-    if (blockIdx.x == 0 && threadIdx.x < VIT_STATE_WORDS) v.state[threadIdx.x] = 0;  // no round yet
-}
-
 // Round bookkeeping, in the int32 words of v.state:
 //   [0] decoder head, [1] traceback head,
 //   [2] start, [3] end, [4] half of the round being decoded,
@@ -943,13 +863,12 @@ hipError_t launch_viterbi(const DevPtrs &d, const VitLaunch &v, int cu_count, hi
     if (v.S == 0) return hipSuccess;
     if (!viterbi_supported(v.NP)) return hipErrorInvalidValue;
     if (v.cap_rows < viterbi_min_rows(v.max_len, v.total)) return hipErrorInvalidValue;
-    const int nb = (int)((v.S + (int64_t)RP_BLOCK - 1) / RP_BLOCK);
-    if (nb > 1) {
-        hipLaunchKernelGGL(k_vit_rows_reduce, dim3(nb), dim3(1024), 0, st, d, v);
-        hipLaunchKernelGGL(k_vit_rows_top, dim3(1), dim3(1024), 0, st, v, nb);
-    }
-    hipLaunchKernelGGL(k_vit_rows_apply, dim3(nb), dim3(1024), 0, st, d, v, nb);
-    const hipError_t e = hipGetLastError();
+    // rows of every entry before it (a decoder row of a sequence with an invalid
+    // model is never written, but counting it keeps the sum an upper bound); the
+    // round state starts at zero (no round yet)
+    const RowPrefix rp{v.perm, v.S, v.max_len, v.total, const_cast<int64_t *>(v.rowpos), v.rowsum, v.state,
+                       VIT_STATE_WORDS};
+    const hipError_t e = launch_row_prefix(d, rp, st);
     if (e != hipSuccess) return e;
     switch (v.NP) {
         case 16: return launch_rounds<16>(d, v, cu_count, st);

@@ -23,7 +23,7 @@ STATUS = {0: "HMM_OK", -1: "HMM_ERR_NULL", -2: "HMM_ERR_SHAPE", -3: "HMM_ERR_WOR
           -4: "HMM_ERR_UNSUPPORTED", -5: "HMM_ERR_HIP", -6: "HMM_ERR_ARG"}
 OP_FORWARD, OP_CLASSIFY, OP_GRAD, OP_VITERBI = 0, 1, 2, 3
 KERNEL_AUTO, KERNEL_PLAIN, KERNEL_BATCHED, KERNEL_TILE16, KERNEL_TILE32, KERNEL_COOP, KERNEL_SCAN = 0, 1, 2, 3, 4, 5, 6
-EXPORTS = ("hmm_workspace_size", "hmm_viterbi_workspace_size", "hmm_forward_loglik", "hmm_classify", "hmm_classify_noalloc", "hmm_forward_backward_grad",
+EXPORTS = ("hmm_workspace_size", "hmm_viterbi_workspace_size", "hmm_grad_workspace_size", "hmm_forward_loglik", "hmm_classify", "hmm_classify_noalloc", "hmm_forward_backward_grad",
            "hmm_viterbi", "hmm_plan_order", "hmm_reestimate_rows", "hmm_softmax_rows", "hmm_logit_grad", "hmm_workspace_error", "hmm_debug_flags", "hmm_select_kernel",
            "hmm_tune_key_of", "hmm_tune_set", "hmm_tune_get", "hmm_tune_clear", "hmm_call_kernel",
            "hmm_profile_enable", "hmm_profile_read", "hmm_status_string")
@@ -84,6 +84,8 @@ def load_library(path: str = LIB_PATH, rebind: bool = False):
     lib.hmm_workspace_size.argtypes = [BP, QP, ctypes.c_int]
     lib.hmm_viterbi_workspace_size.restype = ctypes.c_size_t
     lib.hmm_viterbi_workspace_size.argtypes = [BP, QP, ctypes.c_int64]
+    lib.hmm_grad_workspace_size.restype = ctypes.c_size_t
+    lib.hmm_grad_workspace_size.argtypes = [BP, QP, ctypes.c_int64]
     lib.hmm_forward_loglik.restype = st
     lib.hmm_forward_loglik.argtypes = [BP, QP, P, P, ctypes.c_size_t, P]
     lib.hmm_classify.restype = st
@@ -214,6 +216,19 @@ class Problem:
         return int(load_library().hmm_viterbi_workspace_size(ctypes.byref(self.bank), ctypes.byref(self.batch),
                                                              int(rows)))
 
+    def grad_workspace_size(self, rows: int) -> int:
+        """Workspace bytes with which the gradient stores the scaled alpha of `rows`
+        steps (0: checkpoints only; every step of the batch needs rows >= the sum of
+        its lengths)."""
+        return int(load_library().hmm_grad_workspace_size(ctypes.byref(self.bank), ctypes.byref(self.batch),
+                                                          int(rows)))
+
+    def grad_workspace(self, rows: int) -> torch.Tensor:
+        n = self.grad_workspace_size(rows)
+        if n == 0:
+            raise HMMError("hmm_grad_workspace_size", -2)
+        return torch.empty(n, dtype=torch.uint8, device=self.pi.device)
+
     def viterbi_workspace(self, rows: int) -> torch.Tensor:
         n = self.viterbi_workspace_size(rows)
         if n == 0:
@@ -320,6 +335,10 @@ def forward_backward_grad(p: Problem, seq_weight: Optional[torch.Tensor] = None,
                           stream=None):
     """Expected counts (gradient w.r.t. ln pi, ln A, ln B) and log-likelihoods.
 
+    ws: the workspace, p.workspace(OP_GRAD) by default (the scaled alpha of every
+    step stored between the passes when that takes at most 4 GiB, else
+    checkpoints); p.grad_workspace(rows) sets the stored rows (0: checkpoints).
+    Phases 1 and 2 of one gradient take the same ws.
     Returns (loglik [S], (n_pi [K][N], n_A [K][N][N], n_B [K][N][M]), ws).
     """
     if p.model_of_seq is None:

@@ -151,6 +151,37 @@ def test_viterbi_workspace_is_bounded(lib):
     assert vws(8191) == 0
 
 
+def test_grad_workspace_storage(lib):
+    """The gradient's workspace: checkpoints only at rows = 0; each stored step adds a
+    row of NP floats and an exponent; requests clamp at S max_len; negative rows are
+    refused.  The default stores every step when that takes at most 4 GiB (the c4 shape)
+    and keeps checkpoints only above (the c5 shape: 36 GB of rows); below 49 states the
+    gradient keeps checkpoints whatever the request."""
+    gws = lambda b, q, rows: lib.hmm_grad_workspace_size(ctypes.byref(b), ctypes.byref(q), ctypes.c_int64(rows))
+    dflt = lambda b, q: lib.hmm_workspace_size(ctypes.byref(b), ctypes.byref(q), 2)
+    b4 = hmm.Bank(8, 64, 512, 0x1000, 0x2000, 0x3000)
+    tot4 = 8192 * 550
+    q4 = hmm.Batch(8192, 0x4000, 0x5000, 0x6000, 0x7000, 1000, tot4)
+    base = gws(b4, q4, 0)
+    assert base > 0 and gws(b4, q4, -1) == 0
+    assert gws(b4, q4, tot4) >= base + tot4 * (64 * 4 + 4)
+    assert dflt(b4, q4) == gws(b4, q4, tot4)
+    assert gws(b4, q4, 8192 * 1000) == gws(b4, q4, 1 << 40) > gws(b4, q4, tot4)
+    prev = base
+    for rows in (1, 1000, 1 << 20, tot4):
+        n = gws(b4, q4, rows)
+        assert n > prev
+        prev = n
+    b5 = hmm.Bank(16, 256, 1024, 0x1000, 0x2000, 0x3000)
+    tot5 = 16384 * 2176
+    q5 = hmm.Batch(16384, 0x4000, 0x5000, 0x6000, 0x7000, 4096, tot5)
+    assert dflt(b5, q5) == gws(b5, q5, 0) < 2_000_000_000
+    assert gws(b5, q5, tot5) >= tot5 * (256 * 4 + 4)
+    b2 = hmm.Bank(4, 40, 64, 0x1000, 0x2000, 0x3000)
+    q2 = hmm.Batch(100, 0x4000, 0x5000, 0x6000, 0x7000, 50, 2500)
+    assert gws(b2, q2, 0) == gws(b2, q2, 2500) == gws(b2, q2, 1 << 30) == dflt(b2, q2) > 0
+
+
 def test_kernel_selector(lib):
     assert lib.hmm_select_kernel(7) == -6
     assert lib.hmm_select_kernel(-1) == -6
