@@ -15,9 +15,12 @@ time.  Printed as one JSON line, with:
   plain         the plain per-pair kernel on the same workload (batched / plain speedup);
   fwd_bwd       forward + adjoint (expected counts) on the gradient workload
                 (8 models, N=64, M=512, 8192 sequences, T in [100, 1000]),
-                6 algorithmic FLOPs per state-step;
+                6 algorithmic FLOPs per state-step, with the scaled alpha of
+                every step stored between the passes when the device has room
+                (`storage`), and the checkpoint storage timed beside it;
   large_states  the N=256 bank (16 models, M=1024, 16,384 sequences, T in
-                [256, 4096], own model): forward, and forward + adjoint, on the
+                [256, 4096], own model): forward, and forward + adjoint (storage
+                as above: 38 GB of workspace for every step), on the
                 cooperative kernels, and Viterbi decoding on the workgroup
                 decoder;
   latency       the small workloads, whose time is the serial chain of steps
@@ -76,10 +79,10 @@ _ADJ_COOP = ["paper_1310_3322_amd/csrc/adj_coop.hip", "paper_1310_3322_amd/csrc/
 TRAFFIC_KERNELS = {
     "c3_classify": ("k_fwd_mfma32<1, true>", FAMILY_KERNELS["tile32"][2]),
     "c4_grad_forward": ("k_fwd_coop<4, 1, true>", _FWD_COOP),
-    "c4_grad_adjoint": ("k_adj_pipe<4>", _ADJ_COOP),
+    "c4_grad_adjoint": ("k_adj_coop<4, 1, true, false, true>", _ADJ_COOP),
     "c5_forward": ("k_fwd_coop<16, 2, false>", _FWD_COOP),
     "c5_grad_forward": ("k_fwd_coop<16, 2, true>", _FWD_COOP),
-    "c5_grad_adjoint": ("k_adj_coop<16, 2, false, true>", _ADJ_COOP),
+    "c5_grad_adjoint": ("k_adj_coop<16, 2, false, true, true>", _ADJ_COOP),
 }
 # The bench leg whose tuned choice (kernel family, workgroups-per-CU cap, flags)
 # launched each recorded kernel: a figure holds only for the choice it was taken on.
@@ -230,6 +233,29 @@ def to_dev(w, torch, own):
 
     return hmm.Problem(d(w.pi), d(w.A), d(w.B), d(w.symbols), d(w.offsets), d(w.lengths),
                        d(w.owner) if own else None, max_len=w.max_len, total_symbols=w.total_symbols)
+
+
+def grad_rows(p, w, torch) -> int:
+    """Scaled-alpha rows the gradient legs store: every step of the workload when that
+    workspace fits the device's free memory with 2 GiB to spare, else none (checkpoints)."""
+    free, _ = torch.cuda.mem_get_info()
+    return w.total_symbols if p.grad_workspace_size(w.total_symbols) + (2 << 30) <= free else 0
+
+
+def time_grad_storage(p, rows, reps, torch):
+    """ms per gradient call and per forward / adjoint kernel with `rows` stored steps."""
+    from paper_1310_3322_amd import hmm
+
+    ws = p.grad_workspace(rows)
+    ll, cnt, _ = hmm.forward_backward_grad(p, ws=ws)
+    torch.cuda.synchronize()
+    hmm.profile_enable(True)
+    sec = time_steps(lambda: hmm.forward_backward_grad(p, loglik=ll, counts=cnt, ws=ws), reps, 0, torch)
+    f_ms, f_n = hmm.profile_read(hmm.PROF_FWD_BATCHED)
+    a_ms, a_n = hmm.profile_read(hmm.PROF_ADJ_BATCHED)
+    hmm.profile_enable(False)
+    return {"ms_per_step": sec * 1e3, "fwd_kernel_ms": f_ms / max(f_n, 1), "adj_kernel_ms": a_ms / max(a_n, 1),
+            "workspace_bytes": ws.numel()}
 
 
 def time_steps(fn, steps, warmup, torch):
@@ -393,6 +419,9 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run 4 device copies of 512 MiB (reference kernel for HBM counter scaling)")
     ap.add_argument("--no-tune", action="store_true", help="keep the built-in kernel heuristics (no autotuning)")
+    ap.add_argument("--no-storage-compare", action="store_true",
+                    help="skip the gradient legs' second timing with checkpoints (profiled runs: the kernels of "
+                         "both storages have the same names)")
     ap.add_argument("--tune-cache", default=None,
                     help="JSON tuning cache: install the choices stored there instead of tuning, store new ones")
     ap.add_argument("--traffic-summary", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "BENCH_JSON"), default=None,
@@ -500,8 +529,9 @@ def main():
     if want("grad"):
         log("forward + adjoint on the gradient workload (8 models, N=64, M=512, 8192 sequences)")
         p4 = to_dev(w4, torch, own=True)
-        autotune("c4_grad", p4, hmm.OP_GRAD)
-        ws4 = p4.workspace(hmm.OP_GRAD)
+        rows4 = grad_rows(p4, w4, torch)
+        autotune("c4_grad", p4, hmm.OP_GRAD, grad_rows=rows4)
+        ws4 = p4.grad_workspace(rows4)
         ll4 = torch.empty(w4.S, dtype=torch.float32, device="cuda")
         cnt = (torch.empty((w4.K, w4.N), device="cuda"), torch.empty((w4.K, w4.N, w4.N), device="cuda"),
                torch.empty((w4.K, w4.N, w4.M), device="cuda"))
@@ -528,9 +558,12 @@ def main():
                              "value": u4 / gsec, "unit": "state-steps/s", "ms_per_step": gsec * 1e3,
                              "fwd_kernel_ms": f_ms / max(f_n, 1), "adj_kernel_ms": a_ms / max(a_n, 1),
                              "frac_fp32_peak": 6.0 * u4 / gsec / 1e12 / FP32_PEAK_TFLOPS,
+                             "storage": "every step" if rows4 else "checkpoints", "workspace_bytes": ws4.numel(),
                              "traffic": traffic_fields({"forward": ("c4_grad_forward", f_ms / max(f_n, 1)),
                                                         "adjoint": ("c4_grad_adjoint", a_ms / max(a_n, 1))},
                                                        tuning)}
+        if rows4 and not args.no_storage_compare:
+            result["fwd_bwd"]["checkpoints"] = time_grad_storage(p4, 0, 10, torch)
         if not args.no_cpu:
             log("CPU oracle forward + backward on a c4 sample")
             result["fwd_bwd"]["cpu_oracle"] = cpu_oracle_counts(w4)
@@ -557,8 +590,9 @@ def main():
                       "kernel_ms": k5_ms / max(k5_n, 1),
                       "frac_fp32_peak": 2.0 * u5 / (k5_ms / max(k5_n, 1) / 1e3) / 1e12 / FP32_PEAK_TFLOPS,
                       "traffic": traffic_fields({"forward": ("c5_forward", k5_ms / max(k5_n, 1))}, tuning)})
-        autotune("c5_grad", p5, hmm.OP_GRAD, warmup=0, reps=2)
-        ws5g = p5.workspace(hmm.OP_GRAD)
+        rows5 = grad_rows(p5, w5, torch)
+        autotune("c5_grad", p5, hmm.OP_GRAD, warmup=0, reps=2, grad_rows=rows5)
+        ws5g = p5.grad_workspace(rows5)
         cnt5 = (torch.empty((w5.K, w5.N), device="cuda"), torch.empty((w5.K, w5.N, w5.N), device="cuda"),
                 torch.empty((w5.K, w5.N, w5.M), device="cuda"))
         g5 = lambda: hmm.forward_backward_grad(p5, phase=0, loglik=ll5, counts=cnt5, ws=ws5g)
@@ -572,10 +606,14 @@ def main():
         large["fwd_bwd"] = {"value": u5 / gs5, "unit": "state-steps/s", "ms_per_step": gs5 * 1e3,
                             "fwd_kernel_ms": f5_ms / max(f5_n, 1), "adj_kernel_ms": a5_ms / max(a5_n, 1),
                             "frac_fp32_peak": 6.0 * u5 / gs5 / 1e12 / FP32_PEAK_TFLOPS,
+                            "storage": "every step" if rows5 else "checkpoints", "workspace_bytes": ws5g.numel(),
                             "traffic": traffic_fields({"forward": ("c5_grad_forward", f5_ms / max(f5_n, 1)),
                                                        "adjoint": ("c5_grad_adjoint", a5_ms / max(a5_n, 1))},
                                                       tuning)}
         del ws5g, cnt5
+        if rows5 and not args.no_storage_compare:
+            log("c5 gradient with checkpoints (the bounded-memory storage)")
+            large["fwd_bwd"]["checkpoints"] = time_grad_storage(p5, 0, 2, torch)
     if want("large_viterbi"):
         log("c5 Viterbi (workgroup decoder: 256 states)")
         wsv5 = p5.workspace(hmm.OP_VITERBI)

@@ -77,8 +77,8 @@ def _candidates(op: int):
 class _Call:
     """One call shape with its output buffers; run(ws) enqueues the call."""
 
-    def __init__(self, p: hmm.Problem, op: int, stream):
-        self.p, self.op, self.stream = p, op, stream
+    def __init__(self, p: hmm.Problem, op: int, stream, grad_rows: Optional[int] = None):
+        self.p, self.op, self.stream, self.grad_rows = p, op, stream, grad_rows
         dev = p.pi.device
         if op == hmm.OP_FORWARD:
             self.batch = p.batch
@@ -103,13 +103,18 @@ class _Call:
         self._ws = None
 
     def workspace(self) -> torch.Tensor:
-        n = self.p.workspace_size(self.op, self.batch)
+        """A workspace of exactly the call's size (the gradient's storage of the
+        scaled alpha follows the workspace size, so every candidate gets the same)."""
+        if self.op == hmm.OP_GRAD and self.grad_rows is not None:
+            n = self.p.grad_workspace_size(self.grad_rows)
+        else:
+            n = self.p.workspace_size(self.op, self.batch)
         if n == 0:
             raise hmm.HMMError("hmm_workspace_size", -2)
         if self._ws is None or self._ws.numel() < n:
             self._ws = None
             self._ws = torch.empty(n, dtype=torch.uint8, device=self.p.pi.device)
-        return self._ws
+        return self._ws[:n]
 
     def run(self, ws: torch.Tensor):
         p, o, st = self.p, self.outs, self.stream
@@ -185,15 +190,18 @@ def _time(call: _Call, ws: torch.Tensor, warmup: int, reps: int) -> float:
     return statistics.median(times)
 
 
-def tune(p: hmm.Problem, op: int, warmup: int = 1, reps: int = 3, stream=None, log=None) -> dict:
+def tune(p: hmm.Problem, op: int, warmup: int = 1, reps: int = 3, stream=None, log=None,
+         grad_rows: Optional[int] = None) -> dict:
     """Tunes the calls of `op` on problem `p`'s shape and installs the fastest
     accepted choice.  Sets the kernel selector to HMM_KERNEL_AUTO (the table
-    applies only then).  Returns a record with the key, the chosen kernel, grid
-    cap and flags, and every candidate's time and verdict."""
+    applies only then).  grad_rows: the gradient's workspace stores that many
+    steps of the scaled alpha (p.grad_workspace_size), else the default
+    workspace.  Returns a record with the key, the chosen kernel, grid cap and
+    flags, and every candidate's time and verdict."""
     if stream is None:
         stream = torch.cuda.current_stream()
     hmm.select_kernel(hmm.KERNEL_AUTO)
-    call = _Call(p, op, stream)
+    call = _Call(p, op, stream, grad_rows)
     key = hmm.tune_key(p.bank, call.batch, op)
     hmm.tune_set(key, None)
     # the library's default choice: reference outputs and baseline time
