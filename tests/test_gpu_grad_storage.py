@@ -184,3 +184,32 @@ def test_every_step_benchmark_shapes(cfg, scale):
     ev = grad(p, w.total_symbols, wts)
     assert_same(ck[:2], ev[:2], cfg)
     assert torch.isfinite(ev[0]).all()
+
+
+def test_every_step_c5_full_size_masked_weights():
+    """The N=256 gradient as the benchmark runs it: all 16,384 sequences with every step
+    stored (38 GB of workspace), sequence weights nonzero on 32 sampled sequences only, so
+    that the counts are the sample's and the oracle computes them; the checkpoint storage
+    gives the same counts bit for bit."""
+    print("[case] grad storage c5 full size, masked weights", flush=True)
+    w = workloads.make_workload("c5")
+    rng = np.random.default_rng(39)
+    order = np.argsort(-w.lengths, kind="stable")
+    pick = np.unique(np.concatenate([order[:6], order[-6:], rng.choice(w.S, 20, replace=False)]))
+    wts = np.zeros(w.S, np.float32)
+    wts[pick] = rng.uniform(0.5, 1.5, size=pick.size).astype(np.float32)
+    p = problem(w)
+    ev = grad(p, w.total_symbols, wts)
+    ll = ev[0].cpu().numpy()
+    assert np.all(np.isfinite(ll))
+    sub = w.subset(pick)
+    rll, rpi, rA, rB = O.counts(sub.pi, sub.A, sub.B, sub.symbols, sub.offsets, sub.lengths, sub.owner,
+                                weights=wts[pick])
+    assert rel_err(ll[pick], rll) <= LL_TOL
+    for got, ref in zip(ev[1], (rpi, rA, rB)):
+        assert counts_err(got.cpu().numpy(), ref) <= GRAD_TOL
+    ws_bytes = ev[2].numel()
+    ev = ev[:2]  # the 38 GB workspace is released
+    ck = grad(p, 0, wts)
+    assert ck[2].numel() < ws_bytes
+    assert_same(ck[:2], ev, "c5 full size")
