@@ -60,11 +60,14 @@ struct AdjCoopShape {
     static constexpr int small_bytes = (xch_floats + w_floats + at_floats) * 4 + SSEG * TILE * 4;
 };
 
-// LDS partial of the emission counts: state i of symbol o at o * NP + (i ^ (4 o & 12)).
-// The XOR rotates the 4-state groups inside each 16-state block (spreading banks
-// across symbols) and never moves a state out of its block, so the wave that owns
-// a block owns all of that block's addresses.
-__host__ __device__ inline int nb_swz(int) { return 12; }
+// LDS partial of the emission counts: state i of symbol o at o * NP + (i ^ (4 o & swz)),
+// swz = P - 4 for P the largest power of two dividing NP.  Rows start on the same
+// bank (NP is a multiple of 32), so without the XOR the 16 slots of a step would
+// all add into the same banks; with it the rows of different symbols land on
+// different ones.  The XOR keeps 4-state groups aligned (float4 adds) and every
+// state within its row, and it permutes each row, so the waves, which own
+// disjoint states, also own disjoint addresses.
+__host__ __device__ inline int nb_swz(int NP) { return (NP & -NP) - 4; }
 
 // The two fragment sets of a wave: resident in registers, or streamed.
 template <int R, int BO, bool STREAM>
