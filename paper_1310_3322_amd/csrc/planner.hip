@@ -348,37 +348,40 @@ __global__ void __launch_bounds__(256) k_plan_scatter_wave(DevPtrs d, int S, int
 // cnt_B[k][i][o] for i < N, o < M from the symbol-major emission counts: the
 // per-tile partials of model k's tiles summed in tile order (slab), or the
 // fixed-point sums; NaN for a model flagged as having received a non-finite
-// count.  32 x 32 tiles through LDS, so both sides are read and written in rows.
+// count.  Tiles of 32 states x 8 symbols through LDS, so both sides are read
+// and written in rows; one element per thread, the slab's partials requested 8
+// at a time (the sum still takes them in tile order).
 __global__ void k_counts_finish_b(AdjLaunch a, int slab, float *cnt_B) {
-    __shared__ float tile[32][33];
+    __shared__ float tile[8][33];
     const int k = blockIdx.z;
     const int N = a.N, M = a.M, NP = a.NP;
-    const int i0 = blockIdx.x * 32, o0 = blockIdx.y * 32;
-    const int F = fixed_exponent(*a.wmax, a.S, a.max_len);
-    const int gb = a.gstart[k], ge = a.gstart[k + 1];
-    const int nt = (ge - gb + TILE - 1) / TILE;
-    for (int r = threadIdx.y; r < 32; r += 8) {
-        const int o = o0 + r, i = i0 + threadIdx.x;
+    const int i0 = blockIdx.x * 32, o0 = blockIdx.y * 8;
+    const int tx = threadIdx.x, ty = threadIdx.y;
+    {
+        const int o = o0 + ty, i = i0 + tx;
         float v = 0.0f;
         if (o < M && i < N) {
             if (slab) {
+                const int gb = a.gstart[k], ge = a.gstart[k + 1];
+                const int nt = (ge - gb + TILE - 1) / TILE;
                 const float *src = a.slab + (size_t)slab_slot(gb, k, 0) * M * NP + (size_t)o * NP + i;
                 double acc = 0.0;
+#pragma unroll 8
                 for (int t = 0; t < nt; ++t) acc += (double)src[(size_t)t * M * NP];
                 v = (float)acc;
             } else {
+                const int F = fixed_exponent(*a.wmax, a.S, a.max_len);
                 v = from_fixed(a.B64[((size_t)k * M + o) * NP + quad_t(i)], F);
             }
         }
-        tile[r][threadIdx.x] = v;
+        tile[ty][tx] = v;
     }
     __syncthreads();
     const bool bad = a.nanflag[k] != 0;
     float *dst = cnt_B + (size_t)k * N * M;
-    for (int r = threadIdx.y; r < 32; r += 8) {
-        const int i = i0 + r, o = o0 + threadIdx.x;
-        if (i < N && o < M) dst[(size_t)i * M + o] = bad ? __builtin_nanf("") : tile[threadIdx.x][r];
-    }
+    const int f = ty * 32 + tx;  // 256 threads: state i0 + f / 8, symbol o0 + f % 8
+    const int i = i0 + f / 8, o = o0 + f % 8;
+    if (i < N && o < M) dst[(size_t)i * M + o] = bad ? __builtin_nanf("") : tile[f % 8][f / 8];
 }
 
 // cnt_pi [K][N] and cnt_A [K][N][N] from their fixed-point sums.
@@ -688,7 +691,7 @@ void launch_counts_finish(const AdjLaunch &a, bool slab, float *cnt_pi, float *c
     int nb = blocks_for(n, 256);
     if (nb > 8192) nb = 8192;
     hipLaunchKernelGGL(k_counts_finish_pa, dim3(nb), dim3(256), 0, st, a, cnt_pi, cnt_A);
-    dim3 grid((a.N + 31) / 32, (a.M + 31) / 32, a.K);
+    dim3 grid((a.N + 31) / 32, (a.M + 7) / 8, a.K);
     hipLaunchKernelGGL(k_counts_finish_b, grid, dim3(32, 8), 0, st, a, slab ? 1 : 0, cnt_B);
 }
 
