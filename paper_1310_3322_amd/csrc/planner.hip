@@ -162,26 +162,35 @@ __global__ void __launch_bounds__(1024) k_plan_scan_top(int32_t *bsum, int nb) {
     }
 }
 
-// Small matrices (up to PLAN_SCAN_ONE entries): one workgroup, each thread a
-// contiguous run of at most 32 entries, in one launch.
+// Small matrices (up to PLAN_SCAN_ONE entries): one workgroup, in one launch.
+// The matrix is staged through LDS with coalesced loads and stores (one pad word
+// after every 32 entries, so that the threads' runs start on different banks);
+// each thread scans a contiguous run of at most 32 entries there.
 constexpr int64_t PLAN_SCAN_ONE = 32768;
+__host__ __device__ inline int64_t scan_one_pos(int64_t e) { return e + (e >> 5); }
+inline size_t scan_one_lds(int64_t n) { return (size_t)(scan_one_pos(n) + 1) * sizeof(int32_t); }
 
 __global__ void __launch_bounds__(1024) k_plan_scan_one(int32_t *cnt, int64_t n, int nchunks, int bins_per_group,
                                                         int groups, int32_t *gstart) {
     __shared__ int32_t part[1024];
+    extern __shared__ int32_t stage[];  // entry e at scan_one_pos(e)
+    for (int64_t e = threadIdx.x; e < n; e += 1024) stage[scan_one_pos(e)] = cnt[e];
+    __syncthreads();
     const int64_t per = (n + 1023) / 1024;
     const int64_t e0 = min(n, (int64_t)threadIdx.x * per), e1 = min(n, e0 + per);
     int32_t local = 0;
-    for (int64_t e = e0; e < e1; ++e) local += cnt[e];
+    for (int64_t e = e0; e < e1; ++e) local += stage[scan_one_pos(e)];
     int32_t run = block_inclusive_scan(part, local) - local;
     for (int64_t e = e0; e < e1; ++e) {
-        const int32_t c = cnt[e];
-        cnt[e] = run;
+        const int32_t c = stage[scan_one_pos(e)];
+        stage[scan_one_pos(e)] = run;
         const int64_t b = e / nchunks;
         if (e % nchunks == 0 && b % bins_per_group == 0) gstart[b / bins_per_group] = run;
         run += c;
     }
     if (threadIdx.x == 1023) gstart[groups] = part[1023];
+    __syncthreads();
+    for (int64_t e = threadIdx.x; e < n; e += 1024) cnt[e] = stage[scan_one_pos(e)];
 }
 
 __global__ void __launch_bounds__(1024) k_plan_scan_apply(int32_t *cnt, int64_t n, const int32_t *bsum, int nchunks,
@@ -662,7 +671,10 @@ void launch_plan(const DevPtrs &d, int K, int S, int groups, int max_len, int64_
         hipLaunchKernelGGL(k_plan_count, dim3(count_blocks + tblocks), dim3(256), 0, st, d, S, K, groups, max_len,
                            total, chunk, nchunks, cnt, err, count_blocks, j);
     if (n <= PLAN_SCAN_ONE) {
-        hipLaunchKernelGGL(k_plan_scan_one, dim3(1), dim3(1024), 0, st, cnt, n, nchunks, max_len + 1, groups, gstart);
+        const size_t dyn = scan_one_lds(n);
+        if (dyn > 64 * 1024)
+            (void)hipFuncSetAttribute((const void *)k_plan_scan_one, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
+        hipLaunchKernelGGL(k_plan_scan_one, dim3(1), dim3(1024), dyn, st, cnt, n, nchunks, max_len + 1, groups, gstart);
     } else {
         const int nscan = (int)((n + PLAN_SCAN - 1) / PLAN_SCAN);
         int32_t *bsum = (int32_t *)(ws + L.scanb);
