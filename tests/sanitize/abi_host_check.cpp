@@ -59,6 +59,14 @@ static void workspace_grid() {
                                     EXPECT(a > 0 && a <= n && n <= z);
                                     EXPECT(lo == 0 || hmm_viterbi_workspace_size(&b, &q, lo - 1) == 0);
                                 }
+                                if (op == HMM_OP_GRAD) {
+                                    // checkpoints only, the default, and every step of S max_len rows
+                                    const size_t c = hmm_grad_workspace_size(&b, &q, 0);
+                                    const size_t f = hmm_grad_workspace_size(&b, &q, INT64_MAX);
+                                    EXPECT(c > 0 && c <= n && n <= f);
+                                    EXPECT(hmm_grad_workspace_size(&b, &q, (int64_t)S * L) == f);
+                                    EXPECT(hmm_grad_workspace_size(&b, &q, -1) == 0);
+                                }
                             }
     // out-of-range shapes size nothing
     const hmm_batch q = batch(100, 50, 5000, false);
