@@ -213,3 +213,29 @@ def test_every_step_c5_full_size_masked_weights():
     ck = grad(p, 0, wts)
     assert ck[2].numel() < ws_bytes
     assert_same(ck[:2], ev, "c5 full size")
+
+
+def test_every_step_invalid_model_index():
+    """Sequences whose model index is out of range (K and -1) take NaN log-likelihoods, add
+    no counts and set the error word (the smallest such index) in both storages; the counts
+    are the valid sequences' (the oracle on that subset)."""
+    rng = np.random.default_rng(41)
+    lengths = rng.integers(1, 120, size=23).astype(np.int32)
+    w = workloads.random_lengths_workload(rng, K=3, N=70, M=9, lengths=lengths, all_pairs=False)
+    owner = w.owner.copy()
+    owner[5] = 3
+    owner[9] = -1
+    p = hmm.Problem(dev(w.pi), dev(w.A), dev(w.B), dev(w.symbols), dev(w.offsets), dev(w.lengths), dev(owner),
+                    max_len=w.max_len, total_symbols=w.total_symbols)
+    ck = grad(p, 0)
+    ev = grad(p, w.total_symbols)
+    assert_same(ck[:2], ev[:2], "invalid model index")
+    assert hmm.workspace_error(ck[2]) == 5 and hmm.workspace_error(ev[2]) == 5
+    ll = ev[0].cpu().numpy()
+    assert np.isnan(ll[5]) and np.isnan(ll[9])
+    valid = np.array([s for s in range(w.S) if s not in (5, 9)])
+    sub = w.subset(valid)
+    rll, rpi, rA, rB = O.counts(sub.pi, sub.A, sub.B, sub.symbols, sub.offsets, sub.lengths, sub.owner)
+    assert rel_err(ll[valid], rll) <= LL_TOL
+    for got, ref in zip(ev[1], (rpi, rA, rB)):
+        assert counts_err(got.cpu().numpy(), ref) <= GRAD_TOL
