@@ -41,10 +41,12 @@ def run_all():
     for name, (K, N, M, S) in {"g16": (3, 16, 9, 70), "g64": (4, 64, 40, 60), "g256": (2, 256, 30, 20)}.items():
         lengths = rng.integers(1, 200, size=S).astype(np.int32)  # checkpoints, segments, slab or global counts
         w = workloads.random_lengths_workload(rng, K=K, N=N, M=M, lengths=lengths, all_pairs=False)
-        llg, cnt, _ = hmm.forward_backward_grad(problem(w))
-        out[name + "_ll"] = llg.cpu().numpy()
-        for i, c in enumerate(cnt):
-            out[f"{name}_cnt{i}"] = c.cpu().numpy()
+        p = problem(w)
+        for tag, rows in (("ck", 0), ("ev", w.total_symbols)):  # checkpoints; every step stored
+            llg, cnt, _ = hmm.forward_backward_grad(p, ws=p.grad_workspace(rows))
+            out[f"{name}_{tag}_ll"] = llg.cpu().numpy()
+            for i, c in enumerate(cnt):
+                out[f"{name}_{tag}_cnt{i}"] = c.cpu().numpy()
     for N in (20, 150):                                            # Viterbi in rounds (two halves of 2 max_len rows)
         lengths = rng.integers(1, 90, size=120).astype(np.int32)
         w = workloads.random_lengths_workload(rng, K=3, N=N, M=7, lengths=lengths, all_pairs=False)
