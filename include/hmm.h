@@ -180,7 +180,10 @@ hmm_status hmm_classify_noalloc(const hmm_bank *bank, const hmm_batch *batch, in
  *    the price of a second forward step per step.
  * hmm_workspace_size(..., HMM_OP_GRAD) gives room for every step when the rows
  * take at most 4 GiB, else for checkpoints only.  Both storages give the same
- * counts and log-likelihoods bit for bit.
+ * counts and log-likelihoods bit for bit.  With every step stored, a phase-0
+ * call may overwrite the stored rows during its backward pass (above 128
+ * states, or when the emission counts do not fit a workgroup's LDS); phase 2
+ * leaves them, so several phase-2 calls may follow one phase-1 call.
  * The counts are deterministic: the same bank, batch and weights give the same
  * counts bit for bit, whatever the tuning choice, the storage or the order in
  * which the device runs the work.  A non-finite weight makes every count of

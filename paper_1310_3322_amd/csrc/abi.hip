@@ -332,6 +332,15 @@ Layout make_layout(const hmm_bank *b, const hmm_batch *q, int op, int64_t vit_ro
                 L.mlast = take((size_t)S * sizeof(float));
                 L.rowpos = take(((size_t)S + 1) * sizeof(int64_t));
                 L.rowsum = take(((size_t)S + ROW_PREFIX_BLOCK - 1) / ROW_PREFIX_BLOCK * sizeof(int64_t) + sizeof(int64_t));
+                // global-count shapes: emission counts summed from the stored gamma rows by
+                // (model, symbol) bucket instead of per-step atomics (32-bit row indices,
+                // at most 2^20 buckets)
+                const int64_t nbk = (int64_t)K * M;
+                if (!L.slab_on && L.grad_rows <= INT32_MAX && nbk <= ((int64_t)1 << 20)) {
+                    L.srows = take((size_t)L.grad_rows * sizeof(uint32_t));
+                    L.bucket = take(((size_t)nbk + 1) * sizeof(int32_t));
+                    L.cursor = take((size_t)nbk * sizeof(int32_t));
+                }
             }
         }
     }
@@ -701,7 +710,14 @@ hmm_status hmm_forward_backward_grad(const hmm_bank *bank, const hmm_batch *batc
     a.wmax = (const uint32_t *)(w + L.wmax);
     a.max_grid = max_grid(L.wg_per_cu, cus);
     if (L.grad_rows > 0) {
-        a.arow = (const float *)(w + L.arow);
+        a.arow = (float *)(w + L.arow);
+        // the walk overwrites the rows with gamma, so only a call that ran its own
+        // forward does (a phase-2 call leaves them for the next phase 2)
+        if (L.srows && phase == 0) {
+            a.srows = (uint32_t *)(w + L.srows);
+            a.bucket = (int32_t *)(w + L.bucket);
+            a.cursor = (int32_t *)(w + L.cursor);
+        }
         a.aexp = (const int32_t *)(w + L.aexp);
         a.mlast = (const float *)(w + L.mlast);
         a.rowpos = (const int64_t *)(w + L.rowpos);
@@ -714,7 +730,8 @@ hmm_status hmm_forward_backward_grad(const hmm_bank *bank, const hmm_batch *batc
             a.frag = frag;
         }
         const int pr = prof_begin(stream, HMM_PROF_ADJ_BATCHED);
-        const hipError_t e = coop ? launch_adj_coop(d, a, cus, stream) : launch_adj_mfma(d, a, cus, stream);
+        hipError_t e = coop ? launch_adj_coop(d, a, cus, stream) : launch_adj_mfma(d, a, cus, stream);
+        if (e == hipSuccess && coop) e = launch_counts_from_rows(d, a, stream);
         prof_end(stream, pr);
         if (e != hipSuccess) return HMM_ERR_HIP;
     }

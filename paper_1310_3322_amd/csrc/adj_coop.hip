@@ -431,18 +431,39 @@ __global__ void __launch_bounds__(R / BO * WAVE) k_adj_coop(DevPtrs d, AdjLaunch
                             // (the counts' quad-transposed layout puts the four lanes of a
                             // sequence on four adjacent words in each instruction)
                             const int ib = 16 * r0 + 4 * g;
-                            unsigned long long *dst = B64k + (uint32_t)(ot * NP + 16 * r0 + g);
+                            if (FULL && a.srows != nullptr) {
+                                // the weighted gamma of this step into its stored row (already read
+                                // for this step), summed by symbol after the walk
+                                float gmv[BO][4];
 #pragma unroll
-                            for (int b = 0; b < BO; ++b)
+                                for (int b = 0; b < BO; ++b)
 #pragma unroll
-                                for (int v = 0; v < 4; ++v) {
-                                    const int i = ib + 16 * b + v;
-                                    const float gm = wgt * al[b][v] * be[b][v];
-                                    const bool fin = __builtin_isfinite(gm);
-                                    lane_nan |= !fin;
-                                    if (i < N) atomicAdd(dst + 16 * b + 4 * v, to_fixed(fin ? gm : 0.0f, F));
-                                    if (t == 0) gpi[b][v] = gm;
-                                }
+                                    for (int v = 0; v < 4; ++v) {
+                                        const float gm = wgt * al[b][v] * be[b][v];
+                                        lane_nan |= !__builtin_isfinite(gm);
+                                        gmv[b][v] = gm;
+                                        if (t == 0) gpi[b][v] = gm;
+                                    }
+                                int64_t row = rb + t;
+                                if (!dbg_in(row, a.grad_rows, HMM_DEBUG_GRAD_ROWS)) row = 0;
+#pragma unroll
+                                for (int b = 0; b < BO; ++b)
+                                    *(float4 *)&a.arow[(size_t)row * NP + 16 * (r0 + b) + 4 * g] =
+                                        float4{gmv[b][0], gmv[b][1], gmv[b][2], gmv[b][3]};
+                            } else {
+                                unsigned long long *dst = B64k + (uint32_t)(ot * NP + 16 * r0 + g);
+#pragma unroll
+                                for (int b = 0; b < BO; ++b)
+#pragma unroll
+                                    for (int v = 0; v < 4; ++v) {
+                                        const int i = ib + 16 * b + v;
+                                        const float gm = wgt * al[b][v] * be[b][v];
+                                        const bool fin = __builtin_isfinite(gm);
+                                        lane_nan |= !fin;
+                                        if (i < N) atomicAdd(dst + 16 * b + 4 * v, to_fixed(fin ? gm : 0.0f, F));
+                                        if (t == 0) gpi[b][v] = gm;
+                                    }
+                            }
                         }
                         if (more) {
                             // C[own rows][all] += X^T W: X (own blocks) through the wave's tiles
@@ -1082,6 +1103,113 @@ hipError_t launch_r(const DevPtrs &d, const AdjLaunch &a, int cu_count, hipStrea
     return hipGetLastError();
 }
 
+// ---- Emission counts from the stored gamma rows.  A position whose rows hold
+// gamma is one the backward pass walked with a finite likelihood (its "act"):
+// a valid sequence with steps, a valid model and flag 0.  Buckets are (model,
+// symbol); the rows of a bucket are summed as 64-bit fixed-point values, the
+// same values the per-step atomics add, so the counts are the same bit for bit
+// whatever order the rows take in their bucket.
+__device__ __forceinline__ bool gamma_rows_of(const DevPtrs &d, const AdjLaunch &a, int p, int *mk, int32_t *T,
+                                              int64_t *off) {
+    const int seq = a.perm[p];
+    *T = d.lengths[seq];
+    *off = d.offsets[seq];
+    *mk = d.model_of_seq[seq];
+    const bool bad = seq_bad(*T, *off, a.max_len, a.total) || *mk < 0 || *mk >= a.K;
+    return !bad && *T > 0 && a.flag[p] == 0;
+}
+
+// One wave per position: the rows of each bucket.
+__global__ void __launch_bounds__(256) k_grows_hist(DevPtrs d, AdjLaunch a) {
+    if (!grad_full(a.arow, a.rowpos, a.S, a.grad_rows)) return;
+    const int p = (int)(blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE);
+    const int lane = threadIdx.x & (WAVE - 1);
+    int mk;
+    int32_t T;
+    int64_t off;
+    if (p >= a.S || !gamma_rows_of(d, a, p, &mk, &T, &off)) return;
+    for (int t = lane; t < T; t += WAVE) {
+        const int o = d.symbols[off + t];
+        atomicAdd(&a.cursor[(size_t)mk * a.M + ((unsigned)o < (unsigned)a.M ? o : 0)], 1);
+    }
+}
+
+// One workgroup: bucket[b] = rows of the buckets before b, bucket[KM] = all;
+// the counts become the scatter cursors.
+__global__ void __launch_bounds__(1024) k_grows_scan(AdjLaunch a, int nb) {
+    if (!grad_full(a.arow, a.rowpos, a.S, a.grad_rows)) return;
+    __shared__ int32_t part[1024];
+    const int per = (nb + 1023) / 1024;
+    const int e0 = min(nb, (int)threadIdx.x * per), e1 = min(nb, e0 + per);
+    int32_t local = 0;
+    for (int e = e0; e < e1; ++e) local += a.cursor[e];
+    part[threadIdx.x] = local;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const int32_t y = (int)threadIdx.x >= off ? part[threadIdx.x - off] : 0;
+        __syncthreads();
+        part[threadIdx.x] += y;
+        __syncthreads();
+    }
+    int32_t run = part[threadIdx.x] - local;
+    for (int e = e0; e < e1; ++e) {
+        const int32_t c = a.cursor[e];
+        a.bucket[e] = run;
+        a.cursor[e] = run;
+        run += c;
+    }
+    if (threadIdx.x == 1023) a.bucket[nb] = part[1023];
+}
+
+// One wave per position: each row index into its bucket.
+__global__ void __launch_bounds__(256) k_grows_scatter(DevPtrs d, AdjLaunch a) {
+    if (!grad_full(a.arow, a.rowpos, a.S, a.grad_rows)) return;
+    const int p = (int)(blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE);
+    const int lane = threadIdx.x & (WAVE - 1);
+    int mk;
+    int32_t T;
+    int64_t off;
+    if (p >= a.S || !gamma_rows_of(d, a, p, &mk, &T, &off)) return;
+    const int64_t rb = a.rowpos[p];
+    const int64_t nrows = a.bucket[(size_t)a.K * a.M];
+    for (int t = lane; t < T; t += WAVE) {
+        const int o = d.symbols[off + t];
+        const int slot = atomicAdd(&a.cursor[(size_t)mk * a.M + ((unsigned)o < (unsigned)a.M ? o : 0)], 1);
+        if (dbg_in(slot, nrows, HMM_DEBUG_GRAD_ROWS)) a.srows[slot] = (uint32_t)(rb + t);
+    }
+}
+
+// One wave per bucket (model k, symbol o): its rows' gamma, lane l holding
+// states 4 l .. 4 l + 3, into the symbol-major fixed-point counts.
+__global__ void __launch_bounds__(256) k_grows_reduce(AdjLaunch a) {
+    if (!grad_full(a.arow, a.rowpos, a.S, a.grad_rows)) return;
+    const int b = (int)(blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE);
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int NP = a.NP;
+    if (b >= a.K * a.M || 4 * lane >= NP) return;
+    const int F = fixed_exponent(*a.wmax, a.S, a.max_len);
+    const int e0 = a.bucket[b], e1 = a.bucket[b + 1];
+    unsigned long long acc[4] = {0ull, 0ull, 0ull, 0ull};
+#pragma unroll 4
+    for (int e = e0; e < e1; ++e) {
+        int64_t r = a.srows[e];
+        if (!dbg_in(r, a.grad_rows, HMM_DEBUG_GRAD_ROWS)) r = 0;
+        const float4 q = *(const float4 *)&a.arow[(size_t)r * NP + 4 * lane];
+        const float qv[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const float gm = qv[v];
+            acc[v] += to_fixed(__builtin_isfinite(gm) ? gm : 0.0f, F);
+        }
+    }
+    unsigned long long *dst = a.B64 + (size_t)b * NP;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int i = 4 * lane + v;
+        dst[quad_t(i)] = i < a.N ? acc[v] : 0ull;
+    }
+}
+
 // Streamed fragments of model k: set 0 (A_k^T, recompute) and set 1 (A_k,
 // beta), float4 index (((set * NW + w) * R + rp) * 64 + lane) * BO + b with
 // components v = 0..3:
@@ -1171,6 +1299,19 @@ hipError_t launch_adj_coop(const DevPtrs &d, const AdjLaunch &a, int cu_count, h
         case 16: return launch_r<16>(d, a, cu_count, st);
         default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_counts_from_rows(const DevPtrs &d, const AdjLaunch &a, hipStream_t st) {
+    if (a.srows == nullptr || a.S == 0) return hipSuccess;
+    if (a.B64 == nullptr || a.NP > 4 * WAVE) return hipErrorInvalidValue;
+    const int nb = a.K * a.M;
+    launch_fill_i32(a.cursor, (size_t)nb, 0, st);
+    const unsigned pos_blocks = (unsigned)((a.S + 3) / 4);
+    hipLaunchKernelGGL(k_grows_hist, dim3(pos_blocks), dim3(256), 0, st, d, a);
+    hipLaunchKernelGGL(k_grows_scan, dim3(1), dim3(1024), 0, st, a, nb);
+    hipLaunchKernelGGL(k_grows_scatter, dim3(pos_blocks), dim3(256), 0, st, d, a);
+    hipLaunchKernelGGL(k_grows_reduce, dim3((unsigned)((nb + 3) / 4)), dim3(256), 0, st, a);
+    return hipGetLastError();
 }
 
 HMM_DEBUG_TAKE(debug_take_adj_coop)

@@ -40,6 +40,13 @@ struct Layout {
     size_t arow;     // float [grad_rows][NP] alphahat of every step, rows of sorted position p from rowpos[p]
     size_t aexp;     // int32 [grad_rows] exponents of those steps
     size_t mlast;    // float [S] m_T of each sorted position (full-storage gradient)
+    // Emission counts from the stored rows (full storage, global-count shapes): the
+    // backward pass leaves each live step's weighted gamma in its row, and the rows
+    // are grouped by (model, symbol) and summed bucket by bucket instead of with
+    // per-step atomics.
+    size_t srows;    // uint32 [grad_rows] row indices grouped by bucket
+    size_t bucket;   // int32 [K M + 1] first entry of each bucket in srows, then the total
+    size_t cursor;   // int32 [K M] rows per bucket, then the scatter cursors
     int64_t vit_rows;    // delta rows one Viterbi round may store
     size_t scan;     // time-parallel forward: chunk products, exponents, flags (ScanWs)
     int32_t scan_nch;    // chunks per pair of the time-parallel forward (0: not used)
@@ -257,7 +264,9 @@ struct AdjLaunch {
     const float *frag;  // pre-arranged fragments when the cooperative kernel streams them
     int max_grid;       // cap on the persistent grid (0: occupancy limit)
     // Full-storage gradient (as in FwdLaunch; arow NULL: checkpoints only)
-    const float *arow;
+    float *arow;          // the backward pass writes gamma into the rows when srows is set
+    uint32_t *srows;      // rows grouped by (model, symbol) (NULL: emission counts by atomics)
+    int32_t *bucket, *cursor;
     const int32_t *aexp;
     const float *mlast;
     const int64_t *rowpos;
@@ -298,6 +307,10 @@ int adj_coop_slots(int NP, int M, int S, int K, int cu_count);
 int64_t adj_coop_seg_stride(int NP, int M, int S, int K, int max_len);
 bool adj_coop_pipelined(int NP, int M, int S, int K);  // the two-group pipelined backward serves this shape
 hipError_t launch_adj_coop(const DevPtrs &d, const AdjLaunch &a, int cu_count, hipStream_t st);
+// Emission counts of the full-storage backward from its gamma rows (a.srows set):
+// buckets by (model, symbol), then one wave per bucket sums its rows' fixed-point
+// values into a.B64.  Every kernel exits when the call kept checkpoints.
+hipError_t launch_counts_from_rows(const DevPtrs &d, const AdjLaunch &a, hipStream_t st);
 int adj_mfma_slots(int NP, int M, int S, int K, int cu_count);
 int64_t adj_mfma_seg_stride(int NP, int max_len);
 hipError_t launch_adj_mfma(const DevPtrs &d, const AdjLaunch &a, int cu_count, hipStream_t st);
