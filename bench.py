@@ -83,11 +83,13 @@ TRAFFIC_KERNELS = {
     "c5_forward": ("k_fwd_coop<16, 2, false>", _FWD_COOP),
     "c5_grad_forward": ("k_fwd_coop<16, 2, true>", _FWD_COOP),
     "c5_grad_adjoint": ("k_adj_coop<16, 2, false, true, true>", _ADJ_COOP),
+    "c5_grad_counts": ("k_grows_reduce", _ADJ_COOP),
 }
 # The bench leg whose tuned choice (kernel family, workgroups-per-CU cap, flags)
 # launched each recorded kernel: a figure holds only for the choice it was taken on.
 TRAFFIC_LEGS = {"c3_classify": "c3_classify", "c4_grad_forward": "c4_grad", "c4_grad_adjoint": "c4_grad",
-                "c5_forward": "c5_forward", "c5_grad_forward": "c5_grad", "c5_grad_adjoint": "c5_grad"}
+                "c5_forward": "c5_forward", "c5_grad_forward": "c5_grad", "c5_grad_adjoint": "c5_grad",
+                "c5_grad_counts": "c5_grad"}
 DEFAULT_CHOICE = {"kernel": "auto", "wg_per_cu": 0, "flags": 0}
 
 
