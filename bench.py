@@ -15,12 +15,14 @@ time.  Printed as one JSON line, with:
   plain         the plain per-pair kernel on the same workload (batched / plain speedup);
   fwd_bwd       forward + adjoint (expected counts) on the gradient workload
                 (8 models, N=64, M=512, 8192 sequences, T in [100, 1000]),
-                6 algorithmic FLOPs per state-step, with the scaled alpha of
-                every step stored between the passes when the device has room
-                (`storage`), and the checkpoint storage timed beside it;
+                6 algorithmic FLOPs per state-step, with alpha checkpointed
+                every ceil(sqrt(T)) steps as that configuration states
+                (`storage`); `every_step` times the same call with the scaled
+                alpha of every step stored between the passes;
   large_states  the N=256 bank (16 models, M=1024, 16,384 sequences, T in
-                [256, 4096], own model): forward, and forward + adjoint (storage
-                as above: 38 GB of workspace for every step), on the
+                [256, 4096], own model): forward, and forward + adjoint with
+                every step stored when the device has room (38 GB of
+                workspace) and the checkpoint storage timed beside it, on the
                 cooperative kernels, and Viterbi decoding on the workgroup
                 decoder;
   latency       the small workloads, whose time is the serial chain of steps
@@ -79,7 +81,7 @@ _ADJ_COOP = ["paper_1310_3322_amd/csrc/adj_coop.hip", "paper_1310_3322_amd/csrc/
 TRAFFIC_KERNELS = {
     "c3_classify": ("k_fwd_mfma32<1, true>", FAMILY_KERNELS["tile32"][2]),
     "c4_grad_forward": ("k_fwd_coop<4, 1, true>", _FWD_COOP),
-    "c4_grad_adjoint": ("k_adj_coop<4, 1, true, false, true>", _ADJ_COOP),
+    "c4_grad_adjoint": ("k_adj_pipe<4>", _ADJ_COOP),
     "c5_forward": ("k_fwd_coop<16, 2, false>", _FWD_COOP),
     "c5_grad_forward": ("k_fwd_coop<16, 2, true>", _FWD_COOP),
     "c5_grad_adjoint": ("k_adj_coop<16, 2, false, true, true>", _ADJ_COOP),
@@ -531,7 +533,9 @@ def main():
     if want("grad"):
         log("forward + adjoint on the gradient workload (8 models, N=64, M=512, 8192 sequences)")
         p4 = to_dev(w4, torch, own=True)
-        rows4 = grad_rows(p4, w4, torch)
+        # the gradient configuration keeps alpha every ceil(sqrt(T)) steps; every step stored
+        # is timed beside it
+        rows4 = 0
         autotune("c4_grad", p4, hmm.OP_GRAD, grad_rows=rows4)
         ws4 = p4.grad_workspace(rows4)
         ll4 = torch.empty(w4.S, dtype=torch.float32, device="cuda")
@@ -564,8 +568,8 @@ def main():
                              "traffic": traffic_fields({"forward": ("c4_grad_forward", f_ms / max(f_n, 1)),
                                                         "adjoint": ("c4_grad_adjoint", a_ms / max(a_n, 1))},
                                                        tuning)}
-        if rows4 and not args.no_storage_compare:
-            result["fwd_bwd"]["checkpoints"] = time_grad_storage(p4, 0, 10, torch)
+        if grad_rows(p4, w4, torch) and not args.no_storage_compare:
+            result["fwd_bwd"]["every_step"] = time_grad_storage(p4, w4.total_symbols, 10, torch)
         if not args.no_cpu:
             log("CPU oracle forward + backward on a c4 sample")
             result["fwd_bwd"]["cpu_oracle"] = cpu_oracle_counts(w4)
