@@ -9,11 +9,13 @@
 //   n_A = A o C.
 // One workgroup of R / BO waves per tile of 16 length-sorted sequences of one
 // model; wave w owns the BO 16-state blocks BO w .. BO w + BO - 1 (the
-// partition of the checkpointing forward, fwd_coop.hip).  For each sqrt(T)
-// segment, last to first, the workgroup recomputes alphahat from the
-// checkpoint with the cooperative forward step (bit-identical to the
-// checkpointing forward), keeps each lane's own states in a per-workgroup
-// buffer in global memory, then walks the segment backwards: per step one
+// partition of the gradient's forward, fwd_coop.hip).  When the forward stored
+// every step's alphahat (FULL), the workgroup walks the tile back once over
+// the stored rows.  With checkpoints, for each sqrt(T) segment, last to first,
+// the workgroup recomputes alphahat from the checkpoint with the cooperative
+// forward step (bit-identical to the checkpointing forward), keeps each lane's
+// own states in a per-workgroup buffer in global memory, then walks the
+// segment backwards.  Per step of a walk: one
 // barrier; w_{t+1} of all NP states is exchanged through LDS; wave w forms
 // betahat for its rows (4 R BO MFMAs), adds its rows of C += X^T W (4 R BO
 // MFMAs, the 16 sequences as the contraction axis, X transposed through a
@@ -28,7 +30,10 @@
 // floats per model, resident in the XCD's L2) a few blocks ahead of use.
 // Emission counts go to an LDS partial [M][NP] when it fits (one 16-state block
 // per wave), written after each tile to the tile's slot of a slab of per-tile
-// partials, else straight to the symbol-major global counts.  Every global count
+// partials; else, in a FULL walk of a call that ran its own forward, each live
+// step's weighted gamma overwrites the row just read and k_grows_* sum the rows
+// by (model, symbol) afterwards; else they go straight to the symbol-major
+// global counts with atomics.  Every global count
 // is a 64-bit fixed-point sum (common.cuh), and every sum inside a tile is formed
 // in an order fixed by the tile's data (MFMA accumulation in step order; adds to
 // the LDS partial in slot-rank rounds), so the counts do not depend on which

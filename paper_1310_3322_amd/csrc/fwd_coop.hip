@@ -8,7 +8,10 @@
 // data movement).  Per step and workgroup: 4 R^2 MFMAs of 16x16x4 FP32, one
 // barrier, one exchange of 16 x NP floats through LDS.  Emission rows B^T[o][.] come from L2 (B^T of one model is up to
 // 1 MiB and stays resident in its XCD's L2); the symbol and row of step t+1
-// are fetched during step t.
+// are fetched during step t.  The gradient's variant (CKPT) keeps alphahat for
+// the backward pass: every step's row and exponent when the workspace's rows
+// hold the batch (decided on the device from the row prefix), else a
+// checkpoint every ceil(sqrt(Tmax)) steps.
 #include <climits>
 
 #include "common.cuh"
