@@ -13,6 +13,7 @@
 // 16-sequence tiles.  Used for recognition and log-likelihoods when tiles are
 // plentiful; the gradient keeps the 16-sequence kernels.
 #include <climits>
+#include <type_traits>
 
 #include "common.cuh"
 #include "kernels.h"
@@ -24,12 +25,16 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 
 constexpr int T32 = 32;              // sequences per tile
 constexpr int CH32 = 16;             // symbols per staging chunk (8 per lane)
-constexpr int SYM32 = CH32 * T32;    // ints per wave buffer
+constexpr int SYM32 = CH32 * T32;    // symbols per wave buffer
 constexpr int WAVES32 = 4;           // waves per workgroup
 
-// B^T rows in LDS: float4 chunk c of row o at position c ^ (o & mask).
-template <int R>
-__device__ __forceinline__ int swz32(int o) { return o & (R == 1 ? 7 : 15); }
+// B^T rows in LDS, row o at byte o * row_stride32(NP): a row of NP floats and 16
+// bytes of padding.  With the padding, the float4 chunk c of row o starts in bank
+// group (o (NP / 4 + 1) + c) mod 16 of the 16 groups of four 4-byte banks, so the
+// 16 lanes of one 16-byte LDS pass, which read one chunk of 16 random rows, spread
+// over all 16 groups; a lane's chunks of one row are at fixed offsets from the
+// row's start, which takes one address computation per step.
+__host__ __device__ constexpr int row_stride32(int NP) { return NP * 4 + 16; }
 
 // With one 32-state block (R = 1) the step fits 128 VGPRs, which allows four
 // waves per SIMD; R = 2 needs about twice that.
@@ -38,14 +43,17 @@ __global__ void __launch_bounds__(WAVES32 * WAVE) __attribute__((amdgpu_waves_pe
 k_fwd_mfma32(DevPtrs d, FwdLaunch f) {
     constexpr int NP = 32 * R;
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ int32_t sym_all[WAVES32 * SYM32];
+    // 16-bit symbols when B^T fits in LDS (M <= 1024 there), which leaves room for the
+    // padded rows at four workgroups per CU
+    typedef typename std::conditional<BLDS, uint16_t, int32_t>::type sym_t;
+    __shared__ sym_t sym_all[WAVES32 * SYM32];
     const int lane = threadIdx.x & (WAVE - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     const int sl = lane & 31;        // sequence slot
     const int h = lane >> 5;         // half: states 32 r + 8 q + 4 h + 0..3
     const int K = f.K, N = f.N, M = f.M;
-    float *btl = (float *)smem;
-    int32_t *sym = sym_all + wave * SYM32;
+    unsigned char *btl = smem;
+    sym_t *sym = sym_all + wave * SYM32;
 
     // Scoring all pairs, the tiles are split over the XCDs (workgroup b runs on
     // XCD b mod 8): slice x takes one tile of every group of 8 consecutive tiles
@@ -71,7 +79,7 @@ k_fwd_mfma32(DevPtrs d, FwdLaunch f) {
             const int n4 = M * NP / 4;
             for (int i = threadIdx.x; i < n4; i += blockDim.x) {
                 const int o = i / (NP / 4), c = i % (NP / 4);
-                ((float4 *)btl)[o * (NP / 4) + (c ^ swz32<R>(o))] = ((const float4 *)btk)[i];
+                *(float4 *)(btl + o * row_stride32(NP) + 16 * c) = ((const float4 *)btk)[i];
             }
             __syncthreads();
         }
@@ -139,7 +147,7 @@ k_fwd_mfma32(DevPtrs d, FwdLaunch f) {
                     const int o = nxt[u];
                     const bool ok = (unsigned)o < (unsigned)M;
                     symbad |= (t0 + 2 * u + h < T) && !ok;
-                    sym[u * WAVE + lane] = ok ? o : 0;
+                    sym[u * WAVE + lane] = (sym_t)(ok ? o : 0);
                 }
                 wave_lds_sync();
             };
@@ -148,12 +156,13 @@ k_fwd_mfma32(DevPtrs d, FwdLaunch f) {
                 return sym[(pp / 2) * WAVE + 32 * (pp % 2) + sl];
             };
             auto gather = [&](int o, float4 (&b)[R][4]) {
+                const unsigned char *row = btl + o * row_stride32(NP) + 16 * h;
 #pragma unroll
                 for (int r = 0; r < R; ++r)
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
                         const int c = 8 * r + 2 * q + h;  // float4 chunk of states 32 r + 8 q + 4 h
-                        b[r][q] = BLDS ? ((const float4 *)btl)[o * (NP / 4) + (c ^ swz32<R>(o))]
+                        b[r][q] = BLDS ? *(const float4 *)(row + 16 * (8 * r + 2 * q))
                                        : ((const float4 *)btk)[(size_t)o * (NP / 4) + c];
                     }
             };
@@ -258,7 +267,7 @@ k_fwd_mfma32(DevPtrs d, FwdLaunch f) {
 
 template <int R, bool BLDS>
 hipError_t launch_t(const DevPtrs &d, const FwdLaunch &f, int cu_count, hipStream_t st) {
-    const size_t lds = BLDS ? (size_t)f.M * 32 * R * sizeof(float) : 0;
+    const size_t lds = BLDS ? (size_t)f.M * row_stride32(32 * R) : 0;
     auto kern = k_fwd_mfma32<R, BLDS>;
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
