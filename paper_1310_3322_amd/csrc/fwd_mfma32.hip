@@ -14,6 +14,7 @@
 // plentiful; the gradient keeps the 16-sequence kernels.
 #include <climits>
 #include <type_traits>
+#include <type_traits>
 
 #include "common.cuh"
 #include "kernels.h"
@@ -130,15 +131,29 @@ k_fwd_mfma32(DevPtrs d, FwdLaunch f) {
             }
             const int Tmax = __builtin_amdgcn_readfirstlane(wave_max_int(T));
             const int Tmin = __builtin_amdgcn_readfirstlane(-wave_max_int(T > 0 ? -T : INT_MIN + 1));
-            // Symbol chunks: nxt[u] = symbol of sequence sl at step t0 + 2 u + h,
-            // stored as sym[u][lane]; checked and clamped when a chunk enters LDS.
+            // Symbol chunks: nxt[u] = symbol of sequence sl at step t0 + 8 h + u (the
+            // lane's half of the chunk, consecutive, so that a chunk inside the
+            // sequence takes one address; the steps past its end repeat the last
+            // symbol), stored as sym[u][lane]; checked and clamped when a chunk
+            // enters LDS.
             const int32_t *sbase = T > 0 ? d.symbols + off : d.symbols;
             const int tlim = T > 0 ? T - 1 : 0;
             int32_t nxt[CH32 / 2];
             bool symbad = false;
             auto load_chunk = [&](int t0) {
+                const int tb = t0 + (CH32 / 2) * h;
+                if (__builtin_amdgcn_ballot_w64(tb + CH32 / 2 - 1 > tlim) == 0) {  // every lane's half inside
+                    // two 16-byte loads (symbols are 4-byte aligned; global loads take any
+                    // 4-byte-aligned address)
+                    int4 v0, v1;
+                    __builtin_memcpy(&v0, sbase + tb, 16);
+                    __builtin_memcpy(&v1, sbase + tb + 4, 16);
+                    nxt[0] = v0.x; nxt[1] = v0.y; nxt[2] = v0.z; nxt[3] = v0.w;
+                    nxt[4] = v1.x; nxt[5] = v1.y; nxt[6] = v1.z; nxt[7] = v1.w;
+                } else {
 #pragma unroll
-                for (int u = 0; u < CH32 / 2; ++u) nxt[u] = sbase[min(t0 + 2 * u + h, tlim)];
+                    for (int u = 0; u < CH32 / 2; ++u) nxt[u] = sbase[min(tb + u, tlim)];
+                }
             };
             auto store_chunk = [&](int t0) {
                 wave_lds_sync();
@@ -146,14 +161,14 @@ k_fwd_mfma32(DevPtrs d, FwdLaunch f) {
                 for (int u = 0; u < CH32 / 2; ++u) {
                     const int o = nxt[u];
                     const bool ok = (unsigned)o < (unsigned)M;
-                    symbad |= (t0 + 2 * u + h < T) && !ok;
+                    symbad |= (t0 + (CH32 / 2) * h + u < T) && !ok;
                     sym[u * WAVE + lane] = (sym_t)(ok ? o : 0);
                 }
                 wave_lds_sync();
             };
             auto read_sym = [&](int t) {
                 const int pp = t % CH32;
-                return sym[(pp / 2) * WAVE + 32 * (pp % 2) + sl];
+                return sym[(pp % (CH32 / 2)) * WAVE + 32 * (pp / (CH32 / 2)) + sl];
             };
             auto gather = [&](int o, float4 (&b)[R][4]) {
                 const unsigned char *row = btl + o * row_stride32(NP) + 16 * h;
@@ -175,9 +190,10 @@ k_fwd_mfma32(DevPtrs d, FwdLaunch f) {
                 store_chunk(0);
                 load_chunk(CH32);
                 // one step: bcur holds the emission row of step t, bnext receives the
-                // one of step t + 1 (the loop below alternates the two buffers, so no
-                // copy is needed between steps)
-                auto step = [&](int t, const float4 (&bcur)[R][4], float4 (&bnext)[R][4], bool full) {
+                // one of step t + 1 (the loops below alternate the two buffers, so no
+                // copy is needed between steps); cap: whether a sequence of the tile may
+                // end at this step (then its sum is kept)
+                auto step = [&](auto cap, int t, const float4 (&bcur)[R][4], float4 (&bnext)[R][4], bool full) {
                     const int tn = t + 1;
                     if (tn < Tmax) {
                         if ((tn % CH32) == 0) {
@@ -240,17 +256,28 @@ k_fwd_mfma32(DevPtrs d, FwdLaunch f) {
                     for (int r = 0; r < R; ++r)
 #pragma unroll
                         for (int v = 0; v < 16; ++v) acur[r][v] = ldexp_f(x[r][v], -e);
-                    if (t + 1 >= Tmin && t == T - 1) {
-                        E_end = E;
-                        c_end = cs;
+                    if constexpr (decltype(cap)::value) {
+                        if (t == T - 1) {
+                            E_end = E;
+                            c_end = cs;
+                        }
                     }
                     E += e;
                 };
                 float4 bA[R][4], bB[R][4];
                 gather(read_sym(0), bA);
-                for (int t = 0; t < Tmax; t += 2) {
-                    step(t, bA, bB, !lazy || t + 1 >= Tmin);
-                    if (t + 1 < Tmax) step(t + 1, bB, bA, true);
+                // steps before Tmin - 1, where no sequence of the tile ends, then the
+                // rest, where the sums of ending sequences are kept (the same steps
+                // rescale in both loops: every odd one, and every step from Tmin - 1 on
+                // or without the lazy rule)
+                int t = 0;
+                for (; t + 2 < Tmin; t += 2) {
+                    step(std::false_type{}, t, bA, bB, !lazy);
+                    step(std::false_type{}, t + 1, bB, bA, true);
+                }
+                for (; t < Tmax; t += 2) {
+                    step(std::true_type{}, t, bA, bB, !lazy || t + 1 >= Tmin);
+                    if (t + 1 < Tmax) step(std::true_type{}, t + 1, bB, bA, true);
                 }
             }
             int sb = symbad ? 1 : 0;
