@@ -190,17 +190,24 @@ k_fwd_mfma32(DevPtrs d, FwdLaunch f) {
                 store_chunk(0);
                 load_chunk(CH32);
                 // one step: bcur holds the emission row of step t, bnext receives the
-                // one of step t + 1 (the loops below alternate the two buffers, so no
-                // copy is needed between steps); cap: whether a sequence of the tile may
-                // end at this step (then its sum is kept)
-                auto step = [&](auto cap, int t, const float4 (&bcur)[R][4], float4 (&bnext)[R][4], bool full) {
+                // one of step t + 1, whose symbol o1 was read from LDS a step earlier,
+                // and o2 receives the symbol of step t + 2 (the loops below alternate
+                // the buffers, so no copy is needed between steps); cap: whether a
+                // sequence of the tile may end at this step (then its sum is kept).  A
+                // chunk enters LDS at the step that reads its first symbol, after the
+                // last read of the chunk before.
+                auto step = [&](auto cap, int t, const float4 (&bcur)[R][4], float4 (&bnext)[R][4], int o1, int &o2,
+                                bool full) {
                     const int tn = t + 1;
                     if (tn < Tmax) {
-                        if ((tn % CH32) == 0) {
-                            store_chunk(tn);
-                            load_chunk(tn + CH32);
+                        gather(o1, bnext);
+                        if (tn + 1 < Tmax) {
+                            if (((tn + 1) % CH32) == 0) {
+                                store_chunk(tn + 1);
+                                load_chunk(tn + 1 + CH32);
+                            }
+                            o2 = read_sym(tn + 1);
                         }
-                        gather(read_sym(tn), bnext);
                     }
                     float x[R][16];
                     float part;
@@ -266,18 +273,19 @@ k_fwd_mfma32(DevPtrs d, FwdLaunch f) {
                 };
                 float4 bA[R][4], bB[R][4];
                 gather(read_sym(0), bA);
+                int oA = 0, oB = read_sym(1);  // symbols of the next even and odd steps
                 // steps before Tmin - 1, where no sequence of the tile ends, then the
                 // rest, where the sums of ending sequences are kept (the same steps
                 // rescale in both loops: every odd one, and every step from Tmin - 1 on
                 // or without the lazy rule)
                 int t = 0;
                 for (; t + 2 < Tmin; t += 2) {
-                    step(std::false_type{}, t, bA, bB, !lazy);
-                    step(std::false_type{}, t + 1, bB, bA, true);
+                    step(std::false_type{}, t, bA, bB, oB, oA, !lazy);
+                    step(std::false_type{}, t + 1, bB, bA, oA, oB, true);
                 }
                 for (; t < Tmax; t += 2) {
-                    step(std::true_type{}, t, bA, bB, !lazy || t + 1 >= Tmin);
-                    if (t + 1 < Tmax) step(std::true_type{}, t + 1, bB, bA, true);
+                    step(std::true_type{}, t, bA, bB, oB, oA, !lazy || t + 1 >= Tmin);
+                    if (t + 1 < Tmax) step(std::true_type{}, t + 1, bB, bA, oA, oB, true);
                 }
             }
             int sb = symbad ? 1 : 0;
