@@ -219,6 +219,53 @@ def test_c5_subset_and_full_size_sample():
     assert rel_err(llf[pick], oracle_ll(sub, True)) <= LL_TOL
 
 
+@pytest.mark.parametrize("N,own", [(32, False), (32, True), (64, False)])
+def test_tile32_symbol_staging_edges(N, own):
+    """The 32-sequence-tile forward stages each lane's eight consecutive steps of a symbol
+    chunk with two 16-byte loads when they lie inside the sequence and with clamped loads
+    otherwise, reads each step's symbol one step ahead, and runs the steps before the
+    shortest sequence of a tile can end in a loop of their own.  Lengths around multiples
+    of 8 and 16, tiles of mixed lengths (the split falls at many steps), the longest
+    sequence last in the symbol array; symbols out of range at the first step, inside a
+    half loaded whole, at the last step (a clamped half) and negative give NaN and the error
+    word (the smallest such sequence), every other
+    sequence matches the oracle; the emission table in LDS and in global memory give
+    bit-identical results."""
+    print(f"[case] tile32 symbol staging N={N} own={own}", flush=True)
+    rng = np.random.default_rng([43, N, int(own)])
+    edges = [0, 1, 2, 7, 8, 9, 15, 16, 17, 23, 24, 25, 31, 32, 33, 47, 48, 49, 63, 64, 65, 100]
+    lengths = np.concatenate([edges, rng.integers(1, 120, size=150), [301]]).astype(np.int32)
+    bad = {40: 0, 41: 5, 42: 99, 43: 47, 44: 60}  # sequence -> step of the bad symbol
+    lengths[[40, 41, 42, 43, 44]] = [50, 60, 110, 70, 61]
+    w = workloads.random_lengths_workload(rng, K=3, N=N, M=11, lengths=lengths, all_pairs=not own, conc=0.7)
+    assert w.offsets[-1] + w.lengths[-1] == w.total_symbols  # the longest sequence ends the array
+    ref = oracle_ll(w, own)
+    sym = w.symbols.copy()
+    for s, t in bad.items():
+        assert w.lengths[s] > t
+        sym[w.offsets[s] + t] = w.M if s != 43 else -3
+    p = hmm.Problem(dev(w.pi), dev(w.A), dev(w.B), dev(sym), dev(w.offsets), dev(w.lengths),
+                    dev(w.owner) if own else None, max_len=w.max_len, total_symbols=w.total_symbols)
+    key = hmm.tune_key(p.bank, p.batch, hmm.OP_FORWARD)
+    outs = []
+    try:
+        for flags in (0, hmm.TUNE_BT_GLOBAL):
+            hmm.tune_set(key, hmm.KERNEL_TILE32, 0, flags)
+            ws = p.workspace(hmm.OP_FORWARD)
+            ll = hmm.forward_loglik(p, ws=ws).cpu().numpy()
+            assert hmm.workspace_error(ws) == min(bad), flags
+            outs.append(ll)
+    finally:
+        hmm.tune_set(key, None)
+    assert np.array_equal(outs[0], outs[1], equal_nan=True)
+    ll = outs[0]
+    badrows = np.array(sorted(bad))
+    assert np.all(np.isnan(ll[badrows]))
+    good = np.setdiff1d(np.arange(w.S), badrows)
+    assert rel_err(ll[good], ref[good]) <= LL_TOL
+    assert np.all(ll[w.lengths == 0] == 0.0)
+
+
 def test_ragged_edge_lengths():
     rng = np.random.default_rng(11)
     # ragged tail, all-equal runs, one very long sequence among short ones, T = 0/1/2
