@@ -25,6 +25,7 @@
 // queue (longest first), so uneven lengths are balanced inside one launch.
 // With K a multiple of 8 all workgroups of a model land on one XCD.
 #include <climits>
+#include <type_traits>
 
 #include "common.cuh"
 #include "fwd_step.cuh"
@@ -96,18 +97,33 @@ __global__ void __launch_bounds__(FWD_WAVES * WAVE) k_fwd_mfma(DevPtrs d, FwdLau
             // Shortest sequence of the tile: only its last steps can end a sequence.
             const int Tmin = __builtin_amdgcn_readfirstlane(-wave_max_int(T > 0 ? -T : INT_MIN + 1));
             // Symbols travel in chunks of CH steps: the next chunk is loaded into
-            // registers (nxt[u] = symbol of sequence sl at step t0 + 4 u + g) while
-            // the current one is read from the wave's LDS buffer, laid out as
-            // sym[u][lane] for the same (u, lane).  Past a sequence's end the
-            // loads repeat its last symbol (a valid address; never used).  Symbols
-            // are checked and clamped to [0, M) once, when a chunk enters LDS.
+            // registers (nxt[u] = symbol of sequence sl at step t0 + (CH / 4) g + u,
+            // consecutive, so that a quarter inside the sequence takes 16-byte loads
+            // from one address) while the current one is read from the wave's LDS
+            // buffer, laid out as sym[u][lane] for the same (u, lane).  Past a
+            // sequence's end the loads repeat its last symbol (a valid address;
+            // never used).  Symbols are checked and clamped to [0, M) once, when a
+            // chunk enters LDS.
             const int32_t *sbase = T > 0 ? d.symbols + off : d.symbols;
             const int tlim = T > 0 ? T - 1 : 0;
             int32_t nxt[CH / 4];
             bool symbad = false;
             auto load_chunk = [&](int t0) {
+                const int tb = t0 + (CH / 4) * g;
+                if (__builtin_amdgcn_ballot_w64(tb + CH / 4 - 1 > tlim) == 0) {  // every lane's quarter inside
 #pragma unroll
-                for (int u = 0; u < CH / 4; ++u) nxt[u] = sbase[min(t0 + 4 * u + g, tlim)];
+                    for (int u = 0; u < CH / 4; u += 4) {
+                        int4 v;
+                        __builtin_memcpy(&v, sbase + tb + u, 16);  // 4-byte aligned: any global address
+                        nxt[u] = v.x;
+                        nxt[u + 1] = v.y;
+                        nxt[u + 2] = v.z;
+                        nxt[u + 3] = v.w;
+                    }
+                } else {
+#pragma unroll
+                    for (int u = 0; u < CH / 4; ++u) nxt[u] = sbase[min(tb + u, tlim)];
+                }
             };
             auto store_chunk = [&](int t0) {
                 wave_lds_sync();
@@ -115,16 +131,16 @@ __global__ void __launch_bounds__(FWD_WAVES * WAVE) k_fwd_mfma(DevPtrs d, FwdLau
                 for (int u = 0; u < CH / 4; ++u) {
                     const int o = nxt[u];
                     const bool ok = (unsigned)o < (unsigned)M;
-                    symbad |= (t0 + 4 * u + g < T) && !ok;
+                    symbad |= (t0 + (CH / 4) * g + u < T) && !ok;
                     sym[u * WAVE + lane] = ok ? o : 0;
                 }
                 wave_lds_sync();
             };
             auto read_sym = [&](int t) {
                 const int pp = t % CH;
-                return sym[(pp / 4) * WAVE + 16 * (pp % 4) + sl];
+                return sym[(pp % (CH / 4)) * WAVE + 16 * (pp / (CH / 4)) + sl];
             };
-            int L = 1, ck_base = 0;
+            int L = 1, ck_base = 0, ck_t = 0;  // ck_t: next checkpointed step
             if (CKPT) {
                 while (L * L < Tmax) ++L;
                 ck_base = pos;
@@ -138,29 +154,38 @@ __global__ void __launch_bounds__(FWD_WAVES * WAVE) k_fwd_mfma(DevPtrs d, FwdLau
                 load_chunk(0);
                 store_chunk(0);
                 load_chunk(CH);
-                // the symbol and emission row of step t + 1 are fetched during step t
-                const int o_nx = read_sym(0);
+                // the emission row of step t + 1 and the symbol of step t + 2 are
+                // fetched during step t; a chunk enters LDS at the step that reads its
+                // first symbol, after the last read of the chunk before
                 float4 b_nx[R];
-                if (BLDS)
-                    gather_b_swz<R>(btl, o_nx, g, b_nx);
-                else
-                    gather_b<R>(&btk[(size_t)o_nx * NP], g, b_nx);
-                for (int t = 0; t < Tmax; ++t) {
+                {
+                    const int o0 = read_sym(0);
+                    if (BLDS)
+                        gather_b_swz<R>(btl, o0, g, b_nx);
+                    else
+                        gather_b<R>(&btk[(size_t)o0 * NP], g, b_nx);
+                }
+                int o_nx = read_sym(1);
+                // cap: whether a sequence of the tile may end at step t (then its sum
+                // is kept); the steps before Tmin - 1 run without that bookkeeping
+                auto step = [&](auto cap, int t) {
                     float4 bcur[R];
 #pragma unroll
                     for (int r = 0; r < R; ++r) bcur[r] = b_nx[r];
                     const int tn = t + 1;
                     if (tn < Tmax) {
-                        if ((tn % CH) == 0) {
-                            // chunk tn / CH was prefetched a chunk ago
-                            store_chunk(tn);
-                            load_chunk(tn + CH);
-                        }
-                        const int o = read_sym(tn);
                         if (BLDS)
-                            gather_b_swz<R>(btl, o, g, b_nx);
+                            gather_b_swz<R>(btl, o_nx, g, b_nx);
                         else
-                            gather_b<R>(&btk[(size_t)o * NP], g, b_nx);
+                            gather_b<R>(&btk[(size_t)o_nx * NP], g, b_nx);
+                        if (tn + 1 < Tmax) {
+                            if (((tn + 1) % CH) == 0) {
+                                // chunk (tn + 1) / CH was prefetched a chunk ago
+                                store_chunk(tn + 1);
+                                load_chunk(tn + 1 + CH);
+                            }
+                            o_nx = read_sym(tn + 1);
+                        }
                     }
                     floatx4 u[R];
                     if (t == 0)
@@ -169,21 +194,29 @@ __global__ void __launch_bounds__(FWD_WAVES * WAVE) k_fwd_mfma(DevPtrs d, FwdLau
                         tile_matvec<R>(af, acur, u);
                     int e;
                     const float cs = emit_and_rescale<R>(u, bcur, acur, e);
-                    if (t + 1 >= Tmin && t == T - 1) {
-                        E_end = E;
-                        c_end = cs;
+                    if constexpr (decltype(cap)::value) {
+                        if (t == T - 1) {
+                            E_end = E;
+                            c_end = cs;
+                        }
                     }
                     E += e;
-                    if (CKPT && (t % L) == 0 && t < T && dbg_in(t / L, f.nck, HMM_DEBUG_CKPT)) {
+                    if (CKPT && t == ck_t) {  // t = L c
                         const int c = t / L;
-                        float *dst = f.ckpt + ((size_t)ck_base * f.nck + c) * NP;
+                        if (t < T && dbg_in(c, f.nck, HMM_DEBUG_CKPT)) {
+                            float *dst = f.ckpt + ((size_t)ck_base * f.nck + c) * NP;
 #pragma unroll
-                        for (int r = 0; r < R; ++r)
-                            *(float4 *)&dst[16 * r + 4 * g] =
-                                float4{acur[r][0], acur[r][1], acur[r][2], acur[r][3]};
-                        if (g == 0) f.ckexp[(size_t)ck_base * f.nck + c] = e;
+                            for (int r = 0; r < R; ++r)
+                                *(float4 *)&dst[16 * r + 4 * g] =
+                                    float4{acur[r][0], acur[r][1], acur[r][2], acur[r][3]};
+                            if (g == 0) f.ckexp[(size_t)ck_base * f.nck + c] = e;
+                        }
+                        ck_t += L;
                     }
-                }
+                };
+                int t = 0;
+                for (; t + 1 < Tmin; ++t) step(std::false_type{}, t);
+                for (; t < Tmax; ++t) step(std::true_type{}, t);
             }
             // symbols were checked by the lane that loaded them: combine the four
             // lanes of each sequence
