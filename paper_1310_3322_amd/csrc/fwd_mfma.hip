@@ -37,6 +37,14 @@ namespace {
 constexpr int CH = 32;               // symbols per staging chunk (multiple of 4)
 constexpr int SYM_INTS = CH * TILE;  // one chunk buffer per wave
 constexpr int FWD_WAVES = 4;         // waves per workgroup
+constexpr size_t LDS_CU = 160 * 1024;
+
+// B^T rows in LDS, row o at byte o * row_stride16(NP): NP floats and 16 bytes of
+// padding, an odd number of 16-byte chunks per row, so that chunk c of row o starts
+// in bank group (o (NP / 4 + 1) + c) mod 16 and the 16 lanes of one 16-byte LDS
+// pass, which read one chunk of 16 random rows, spread over all 16 groups; a lane's
+// chunks of a row sit at fixed offsets from one address.
+__host__ __device__ constexpr int row_stride16(int NP) { return NP * 4 + 16; }
 
 template <int R, bool BLDS, bool CKPT>
 __global__ void __launch_bounds__(FWD_WAVES * WAVE) k_fwd_mfma(DevPtrs d, FwdLaunch f) {
@@ -47,7 +55,7 @@ __global__ void __launch_bounds__(FWD_WAVES * WAVE) k_fwd_mfma(DevPtrs d, FwdLau
     const int sl = lane & 15;        // sequence slot in the tile
     const int g = lane >> 4;         // row group: states 16r + 4g + 0..3
     const int K = f.K, N = f.N, M = f.M;
-    float *btl = (float *)smem;      // [M][NP] when BLDS
+    unsigned char *btl = smem;       // padded rows of B^T when BLDS
     __shared__ int32_t sym_all[FWD_WAVES * SYM_INTS];   // separate object: never aliases btl
     int32_t *sym = sym_all + wave * SYM_INTS;
 
@@ -64,7 +72,7 @@ __global__ void __launch_bounds__(FWD_WAVES * WAVE) k_fwd_mfma(DevPtrs d, FwdLau
             const int n4 = M * NP / 4;
             for (int i = threadIdx.x; i < n4; i += blockDim.x) {
                 const int o = i / (NP / 4), c = i % (NP / 4);
-                ((float4 *)btl)[o * (NP / 4) + (c ^ (o & chunk_swizzle_mask<R>()))] = ((const float4 *)btk)[i];
+                *(float4 *)(btl + o * row_stride16(NP) + 16 * c) = ((const float4 *)btk)[i];
             }
             __syncthreads();
         }
@@ -140,6 +148,12 @@ __global__ void __launch_bounds__(FWD_WAVES * WAVE) k_fwd_mfma(DevPtrs d, FwdLau
                 const int pp = t % CH;
                 return sym[(pp % (CH / 4)) * WAVE + 16 * (pp / (CH / 4)) + sl];
             };
+            // chunks 4 r + g of row o of B^T in LDS
+            auto gather_lds = [&](int o, float4 (&b)[R]) {
+                const unsigned char *row = btl + o * row_stride16(NP) + 16 * g;
+#pragma unroll
+                for (int r = 0; r < R; ++r) b[r] = *(const float4 *)(row + 64 * r);
+            };
             int L = 1, ck_base = 0, ck_t = 0;  // ck_t: next checkpointed step
             if (CKPT) {
                 while (L * L < Tmax) ++L;
@@ -161,7 +175,7 @@ __global__ void __launch_bounds__(FWD_WAVES * WAVE) k_fwd_mfma(DevPtrs d, FwdLau
                 {
                     const int o0 = read_sym(0);
                     if (BLDS)
-                        gather_b_swz<R>(btl, o0, g, b_nx);
+                        gather_lds(o0, b_nx);
                     else
                         gather_b<R>(&btk[(size_t)o0 * NP], g, b_nx);
                 }
@@ -175,7 +189,7 @@ __global__ void __launch_bounds__(FWD_WAVES * WAVE) k_fwd_mfma(DevPtrs d, FwdLau
                     const int tn = t + 1;
                     if (tn < Tmax) {
                         if (BLDS)
-                            gather_b_swz<R>(btl, o_nx, g, b_nx);
+                            gather_lds(o_nx, b_nx);
                         else
                             gather_b<R>(&btk[(size_t)o_nx * NP], g, b_nx);
                         if (tn + 1 < Tmax) {
@@ -238,7 +252,7 @@ __global__ void __launch_bounds__(FWD_WAVES * WAVE) k_fwd_mfma(DevPtrs d, FwdLau
 
 template <int R, bool BLDS, bool CKPT>
 hipError_t launch_t(const DevPtrs &d, const FwdLaunch &f, int cu_count, hipStream_t st) {
-    const size_t lds = BLDS ? (size_t)f.M * 16 * R * sizeof(float) : 0;  // + static symbol buffers
+    const size_t lds = BLDS ? (size_t)f.M * row_stride16(16 * R) : 0;  // + static symbol buffers
     auto kern = k_fwd_mfma<R, BLDS, CKPT>;
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -258,7 +272,9 @@ hipError_t launch_t(const DevPtrs &d, const FwdLaunch &f, int cu_count, hipStrea
 bool fwd_mfma_supported(int NP) { return NP == 16 || NP == 32 || NP == 48 || NP == 64; }
 
 hipError_t launch_fwd_mfma(const DevPtrs &d, const FwdLaunch &f, int cu_count, hipStream_t st) {
-    const bool blds = bt_in_lds(f);
+    // the padded rows and the symbol buffers must fit a CU's LDS (the largest table the
+    // tuning flag allows, 128 KB, does not with 16 states)
+    const bool blds = bt_in_lds(f) && (size_t)f.M * row_stride16(f.NP) + FWD_WAVES * SYM_INTS * sizeof(int32_t) <= LDS_CU;
     const bool ck = f.ckpt != nullptr;
 #define HMM_FWD_CASE(R)                                                                  \
     case R:                                                                              \

@@ -105,21 +105,4 @@ __device__ __forceinline__ void gather_b(const float *row, int g, float4 (&b)[R]
     for (int r = 0; r < R; ++r) b[r] = *(const float4 *)&row[16 * r + 4 * g];
 }
 
-// LDS copy of B^T: the float4 chunks of row o are XOR-permuted by
-// chunk_swizzle(o) so that the 16 different rows a tile reads in one step fall
-// into different banks.  The mask stays inside an aligned group of chunks, so
-// the permuted index stays inside the row.
-template <int R>
-__host__ __device__ constexpr int chunk_swizzle_mask() {
-    return (R % 2 == 0) ? 7 : 3;   // NP / 4 = 4 R chunks per row
-}
-
-template <int R>
-__device__ __forceinline__ void gather_b_swz(const float *lds_bt, int o, int g, float4 (&b)[R]) {
-    const int m = o & chunk_swizzle_mask<R>();
-    const float4 *row = (const float4 *)lds_bt + o * (4 * R);
-#pragma unroll
-    for (int r = 0; r < R; ++r) b[r] = row[(4 * r + g) ^ m];
-}
-
 }  // namespace hmm
