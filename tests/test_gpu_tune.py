@@ -177,6 +177,7 @@ def test_tune_installs_an_accepted_choice(op):
 
 @pytest.mark.parametrize("kind,N,M,all_pairs,S", [(hmm.KERNEL_TILE32, 32, 500, True, 20000),
                                                  (hmm.KERNEL_TILE16, 16, 1000, True, 20000),
+                                                 (hmm.KERNEL_TILE16, 16, 2000, True, 4000),
                                                  (hmm.KERNEL_TILE32, 32, 500, False, 3000),
                                                  (hmm.KERNEL_TILE16, 48, 300, False, 3000)])
 def test_tune_flags_change_no_result(kind, N, M, all_pairs, S):
@@ -184,7 +185,9 @@ def test_tune_flags_change_no_result(kind, N, M, all_pairs, S):
     whether all-pairs tiles are split over the XCDs (20,000 sequences of 4 models fill a
     grid that allows the split) change no result: log-likelihoods bit-identical to the
     built-in choice (the tables here take 64-75 KB, so the default reads them from global
-    memory), and within the oracle's tolerance."""
+    memory; with 2000 symbols and 16 states the padded table would not fit beside the symbol
+    buffers, and the LDS flag falls back to global memory), and within the oracle's
+    tolerance."""
     print(f"[case] tune flags kind={kind} N={N} all_pairs={all_pairs}", flush=True)
     w = short_workload(300 + N, K=4, N=N, M=M, S=S, tmax=24, all_pairs=all_pairs)
     p = problem(w, not all_pairs)
