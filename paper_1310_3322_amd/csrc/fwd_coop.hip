@@ -174,23 +174,28 @@ __global__ void __launch_bounds__(R / BO * WAVE) k_fwd_coop(DevPtrs d, FwdLaunch
             // compiler would wait for every outstanding load there); the load
             // into bnext is issued every step (a valid row when t + 1 = Tmax) so
             // that the wait before its use in the next step can count it.
+            // The symbol of step s is read from LDS at step s - 2 (o2), so that the
+            // emission rows of step t + 1 (symbol o1, any value at t + 1 = Tmax,
+            // clamped below) are requested before anything else of step t.
             // Chunk c + 1 >= 2 is loaded by wave 0 at step 32 c (always the first
             // step of a pair) and stored at step 32 c + 1 (the second), into the
-            // buffer of chunk c - 1, whose last reader, step 32 c - 2, every wave
+            // buffer of chunk c - 1, whose last reader, step 32 c - 3, every wave
             // has passed; the barrier of step 32 c + 1 publishes it long before
-            // its first reader, step 32 c + 31.  Loading and storing inside one
+            // its first reader, step 32 c + 30.  Loading and storing inside one
             // iteration keeps the staging registers out of the loop latch.
-            auto step = [&](int t, const float4 (&bcur)[BO], float4 (&bnext)[BO], bool chunk_ld, bool chunk_st) {
+            auto step = [&](int t, const float4 (&bcur)[BO], float4 (&bnext)[BO], int o1, int &o2, bool chunk_ld,
+                            bool chunk_st) {
+                int on = o1;
+                symbad |= (t + 1 < T) && (on < 0 || on >= M);
+                on = ((unsigned)on < (unsigned)M) ? on : 0;
+#pragma unroll
+                for (int b = 0; b < BO; ++b) bnext[b] = *(const float4 *)&btk[(size_t)on * NP + 16 * (r0 + b) + 4 * g];
                 // first operand of this step's product, requested with the block sums
                 const float *xprev = xbuf + ((t - 1) & 1) * TILE * XROW;
                 const float4 q0 = *(const float4 *)&xprev[sl * XROW + 4 * g];
                 const int e = read_phase(t);
                 if (chunk_ld) load_chunk(t + CCH);
-                int on = read_sym(t + 1);  // any value at t + 1 = Tmax, clamped below
-                symbad |= (t + 1 < T) && (on < 0 || on >= M);
-                on = ((unsigned)on < (unsigned)M) ? on : 0;
-#pragma unroll
-                for (int b = 0; b < BO; ++b) bnext[b] = *(const float4 *)&btk[(size_t)on * NP + 16 * (r0 + b) + 4 * g];
+                o2 = read_sym(t + 2);
                 floatx4 u[BO];
                 if (t == 0) {
 #pragma unroll
@@ -215,13 +220,14 @@ __global__ void __launch_bounds__(R / BO * WAVE) k_fwd_coop(DevPtrs d, FwdLaunch
                 // symbols requested for the next steps stay in flight across the barrier
                 lds_barrier();
             };
+            int oA = 0, oB = read_sym(1);  // symbols of the next even and odd steps
             int t = 0;
             for (; t + 1 < Tmax; t += 2) {
                 const bool chunk = w == 0 && t > 0 && (t % CCH) == 0;
-                step(t, bA, bB, chunk, false);
-                step(t + 1, bB, bA, false, chunk);
+                step(t, bA, bB, oB, oA, chunk, false);
+                step(t + 1, bB, bA, oA, oB, false, chunk);
             }
-            if (t < Tmax) step(t++, bA, bB, false, false);
+            if (t < Tmax) step(t++, bA, bB, oB, oA, false, false);
             read_phase(t);
             if (has && g == 0 && w == 0) {
                 float r = (float)((double)E_end * LN2 + (double)logf(c_end));
