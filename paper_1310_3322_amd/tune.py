@@ -242,11 +242,18 @@ def tune(p: hmm.Problem, op: int, warmup: int = 1, reps: int = 3, stream=None, l
 
     for kind, cap in _candidates(op):
         attempt(kind, cap, 0)
-    # second stage: the flags on the best family and cap (they act on the tile forwards)
-    if best[1] in (hmm.KERNEL_AUTO, hmm.KERNEL_BATCHED, hmm.KERNEL_TILE16, hmm.KERNEL_TILE32):
+    # second stage: the flags on the best family and cap, where the kernels that
+    # choice resolves to read them (the emission-table placement acts on the tile
+    # forwards, the XCD split on the 32-sequence tiles of an all-pairs call); a flag
+    # that changes no kernel would only let timing noise pick between equal choices
+    if best[1] in (hmm.KERNEL_AUTO, hmm.KERNEL_BATCHED, hmm.KERNEL_TILE16, hmm.KERNEL_TILE32) and op != hmm.OP_VITERBI:
         kind, cap = best[1], best[2]
-        sets = [hmm.TUNE_BT_GLOBAL, hmm.TUNE_BT_LDS]
-        if call.batch.model_of_seq is None:  # all pairs
+        hmm.tune_set(key, kind, cap, 0)
+        fam = hmm.call_kernel(p.bank, call.batch, op)
+        sets = []
+        if fam in (hmm.KERNEL_TILE16, hmm.KERNEL_TILE32):
+            sets += [hmm.TUNE_BT_GLOBAL, hmm.TUNE_BT_LDS]
+        if fam == hmm.KERNEL_TILE32 and call.batch.model_of_seq is None:  # all pairs
             sets += [hmm.TUNE_XCD_OFF, hmm.TUNE_XCD_OFF | hmm.TUNE_BT_LDS]
         for flags in sets:
             attempt(kind, cap, flags)

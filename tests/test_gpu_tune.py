@@ -148,8 +148,13 @@ def test_tune_installs_an_accepted_choice(op):
     ok = [c for c in r["candidates"] if c["ok"]]
     assert any((c["kernel"], c["wg_per_cu"], c["flags"]) ==
                (r["choice"]["kernel"], r["choice"]["wg_per_cu"], r["choice"]["flags"]) for c in ok)
-    if op in (hmm.OP_FORWARD, hmm.OP_CLASSIFY, hmm.OP_GRAD):  # the second stage tried the flags
-        assert any(c["flags"] != 0 for c in r["candidates"])
+    # the second stage tried the flags exactly where the chosen family reads them (the tile
+    # forwards; the gradient with 64 states runs the cooperative kernels, Viterbi its own)
+    fam = hmm.call_kernel(p.bank, p.batch, op)
+    tile = fam in (hmm.KERNEL_TILE16, hmm.KERNEL_TILE32) and op != hmm.OP_VITERBI
+    assert any(c["flags"] != 0 for c in r["candidates"]) == tile, (fam, r["candidates"])
+    if op in (hmm.OP_FORWARD, hmm.OP_CLASSIFY):
+        assert tile
     # no accepted candidate beat the choice by more than the tuner's margin
     assert min(c["ms"] for c in ok) >= r["ms"] * (1.0 - tune.MIN_GAIN)
     assert all(c["reason"] in ("unsupported", "default", "") for c in r["candidates"]), r["candidates"]
